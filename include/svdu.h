@@ -1,0 +1,142 @@
+/* svdu.h -- rank-1 SVD update on one AMD MI355X (gfx950), C ABI.
+ *
+ * Method: Gandhi & Rajgor, "Updating Singular Value Decomposition for Rank
+ * One Matrix Perturbation". Given A = U diag(sigma) V^T (U m x m, V n x n,
+ * m <= n) and vectors a (m), b (n), return the SVD of A^ = A + a b^T
+ * (Section 3, equation APurturbation1; Section 6.1, the algorithm "Update SVD
+ * of rank-1 modified matrix"). The update runs the four symmetric rank-one
+ * eigen-updates of A^ A^T and A^T A^ (equations U+D+U+T and V+D+V+T, Section
+ * 6.2 RankOneUpdate): a secular-equation solve (equation
+ * GolubEigenvalUpdate), the Cauchy eigenvector matrix C~ (equation
+ * CTildeFinalForm1) and the product X C~ (equation UCTildeProduct).
+ *
+ * Conventions for every entry point:
+ *  - Matrices are row-major float64 with an explicit leading dimension
+ *    (element (r, c) of X is X[r * ldx + c]).
+ *  - Every pointer argument is a DEVICE pointer owned by the caller, unless
+ *    the comment says "host". The library never allocates device memory in
+ *    these calls; scratch space comes from the caller's workspace.
+ *  - `stream` is a hipStream_t (NULL: the default stream). Calls only enqueue
+ *    work and return; results are valid once the stream has reached them.
+ *  - Return value: 0 on success; a negative SVDU_E* code for an argument
+ *    error found on the host (nothing is enqueued then). Errors found on the
+ *    device (non-finite input, unsorted sigma, secular iteration cap) are
+ *    recorded in the workspace and reported by svdu_get_status().
+ */
+#ifndef SVDU_H
+#define SVDU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SVDU_OK 0
+#define SVDU_EINVAL (-1)        /* an argument is out of range, NULL or aliased */
+#define SVDU_ENOMEM (-2)        /* workspace smaller than svdu_*_workspace_bytes() */
+#define SVDU_EHIP (-3)          /* a HIP runtime call failed */
+#define SVDU_ENONFINITE (-4)    /* NaN or Inf in U, sigma, V, a or b (device check) */
+#define SVDU_EBADSIGMA (-5)     /* sigma not descending or negative (device check) */
+#define SVDU_ENOCONV (-6)       /* a secular root reached the iteration cap */
+#define SVDU_ENOTSUP (-7)       /* path / precision combination not available */
+
+/* product path for X C~ */
+#define SVDU_PATH_DIRECT 0      /* dense FP64 MFMA GEMM, C~ generated in LDS */
+#define SVDU_PATH_FMM 1         /* row-batched 1-D fast multipole (Section 5, Appendix D) */
+
+/* arithmetic of the product X C~ (roots, deflation and norms are always FP64) */
+#define SVDU_PREC_FP64 0
+#define SVDU_PREC_SPLIT32 1     /* split FP32 hi/lo, three MFMA passes */
+
+/* options for svdu_set_option */
+#define SVDU_OPT_SECULAR_MAXIT 1 /* iteration cap of the secular solver (default 200) */
+#define SVDU_OPT_TIMING 2        /* 1: record phase timings of svdu_rank1_update (resets the record) */
+
+/* Bytes of device workspace svdu_rank1_update needs for (m, n, path, precision). */
+size_t svdu_workspace_bytes(int m, int n, int path, int precision);
+
+/* Rank-1 SVD update (Section 6.1, Steps 1-8).
+ *  m, n        1 <= m <= n.
+ *  U, ldu      m x m orthogonal, ldu >= m.            (input, not modified)
+ *  sigma       m singular values, descending, >= 0.    (input)
+ *  V, ldv      n x n orthogonal, ldv >= n.             (input, not modified)
+ *  a, b        update vectors of length m and n.       (input)
+ *  eps         FMM tolerance (ignored by SVDU_PATH_DIRECT), 0 < eps < 1.
+ *  path        SVDU_PATH_DIRECT or SVDU_PATH_FMM.
+ *  precision   SVDU_PREC_FP64 or SVDU_PREC_SPLIT32.
+ *  U_out       m x m, ldu_out >= m: left singular vectors of A^, columns by
+ *              descending singular value. Must not overlap U.
+ *  sigma_out   m singular values of A^, descending.
+ *  V_out       n x n, ldv_out >= n: right singular vectors; column i pairs with
+ *              column i of U_out (signs chosen so that U^ S^ V^^T = A^), and
+ *              columns m..n-1 span the null space of A^. Must not overlap V.
+ *  defl        NULL, or 4*n int8 deflation flags, one row of n per eigen-update
+ *              in the order (left, rho+), (left, rho-), (right, rho+),
+ *              (right, rho-); entry j of a row describes input column j of that
+ *              update (left side: entries m..n-1 are 0): 0 kept, 1 zero
+ *              component dropped, 2 merged into an exactly repeated pole.
+ *  workspace   device buffer of workspace_bytes >= svdu_workspace_bytes(...),
+ *              256-byte aligned; it also holds the device status word, so one
+ *              workspace serves one call in flight at a time.
+ * Returns 0 or a negative SVDU_E* code (see the conventions above). */
+int svdu_rank1_update(int m, int n, const double* U, int ldu, const double* sigma, const double* V, int ldv,
+                      const double* a, const double* b, double eps, int path, int precision, double* U_out,
+                      int ldu_out, double* sigma_out, double* V_out, int ldv_out, int8_t* defl,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/* Waits for `stream` and returns the device-side status of the last call that
+ * used `workspace`: SVDU_OK, SVDU_ENONFINITE, SVDU_EBADSIGMA or SVDU_ENOCONV
+ * (the first that applies, in that order), or SVDU_EHIP. */
+int svdu_get_status(const void* workspace, void* stream);
+
+/* Bytes of workspace svdu_eig_update needs. */
+size_t svdu_eig_update_workspace_bytes(int R, int N);
+
+/* One symmetric rank-one eigen-update (Section 6.2, RankOneUpdate Steps 2-7)
+ * of X diag(lam) X^T + rho X z z^T X^T, with the projection z = X^T v already
+ * formed (Step 1):
+ *  R, N        X is R x N (R >= 0, N >= 1), ldx >= N.
+ *  lam         N eigenvalues of the columns of X, ascending.
+ *  z           N projected components.
+ *  rho         host scalar, nonzero.
+ *  X_out, ldo  R x N, ldo >= N: X C~, columns by ascending new eigenvalue.
+ *  lam_out     N new eigenvalues, ascending.
+ *  defl        NULL or N int8 flags (as for svdu_rank1_update).
+ *  workspace   >= svdu_eig_update_workspace_bytes(R, N) bytes. */
+int svdu_eig_update(int R, int N, const double* X, int ldx, const double* lam, const double* z, double rho,
+                    double* X_out, int ldo, double* lam_out, int8_t* defl, void* workspace,
+                    size_t workspace_bytes, void* stream);
+
+/* Roots of the secular equation w(mu) = 1 + rho sum_k z_k^2 / (d_k - mu)
+ * (equation GolubEigenvalUpdate) for K distinct poles d (ascending) and
+ * nonzero z, rho nonzero (host scalar). Root i is returned pole-relative:
+ * mu_i = d[org[i]] + tau[i], with org[i] the nearer end of its interval.
+ * iters (may be NULL) receives the iteration count per root.
+ * workspace >= svdu_secular_workspace_bytes(K). */
+size_t svdu_secular_workspace_bytes(int K);
+int svdu_secular(int K, const double* d, const double* z, double rho, int* org, double* tau, int* iters,
+                 void* workspace, size_t workspace_bytes, void* stream);
+
+/* Process-wide tuning/test options (host); returns the previous value. */
+int svdu_set_option(int option, int value);
+
+/* Phase timings recorded while SVDU_OPT_TIMING is on (at most 256 calls since
+ * it was switched on). For call c, ms[7 c + k] (host array of 7 max_calls
+ * doubles) receives the milliseconds of phase k, measured with HIP events on
+ * the call's stream: 0 projections and checks, 1 the O(n^2) eigen-update work
+ * of all four updates (deflation, secular roots, weights, signs), 2..5 the
+ * products X C~ of the updates (left rho+, left rho-, right rho+, right rho-;
+ * one kernel each), 6 the flag copies. Waits for those events. Returns the
+ * number of calls filled, or SVDU_EHIP. */
+int svdu_timing_read(double* ms, int max_calls);
+
+/* Static description of a status code (host). */
+const char* svdu_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVDU_H */

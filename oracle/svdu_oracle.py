@@ -301,8 +301,12 @@ def rank_one_update(X: np.ndarray, lam: np.ndarray, v: np.ndarray, rho: float) -
     X has orthonormal columns with eigenvalues lam (any order). Returns the new
     basis X C~ and eigenvalues, both ascending.
     """
+    return rank_one_update_z(X, lam, X.T @ v, rho)   # Step 1: a_bar = X^T v
+
+
+def rank_one_update_z(X: np.ndarray, lam: np.ndarray, z: np.ndarray, rho: float) -> StageResult:
+    """RankOneUpdate Steps 2-7 for a given projection z = a_bar (Step 1 done)."""
     N = lam.shape[0]
-    z = X.T @ v                                      # Step 1: a_bar = X^T v
     order = np.argsort(lam, kind="stable")
     lam_s, z_s = lam[order], z[order]
     defl = deflate(lam_s, z_s, rho)

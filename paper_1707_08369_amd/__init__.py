@@ -1,0 +1,266 @@
+"""Python binding of libsvdu, the rank-1 SVD update library for MI355X (gfx950).
+
+Argument marshalling only: every step of the update runs in the HIP kernels
+of ``libsvdu.so``. Tensors are torch CUDA (HIP) float64 tensors, row-major with
+unit column stride; torch provides device memory and the stream.
+
+The functions named ``svdu_*`` mirror the C ABI in ``include/svdu.h`` one to
+one. ``rank1_update``, ``eig_update`` and ``secular`` allocate outputs and a
+workspace and raise on a non-zero status.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsvdu.so")
+
+SVDU_OK = 0
+SVDU_EINVAL = -1
+SVDU_ENOMEM = -2
+SVDU_EHIP = -3
+SVDU_ENONFINITE = -4
+SVDU_EBADSIGMA = -5
+SVDU_ENOCONV = -6
+SVDU_ENOTSUP = -7
+SVDU_PATH_DIRECT = 0
+SVDU_PATH_FMM = 1
+SVDU_PREC_FP64 = 0
+SVDU_PREC_SPLIT32 = 1
+SVDU_OPT_SECULAR_MAXIT = 1
+SVDU_OPT_TIMING = 2
+
+EXPORTS = ("svdu_workspace_bytes", "svdu_rank1_update", "svdu_get_status", "svdu_eig_update_workspace_bytes",
+           "svdu_eig_update", "svdu_secular_workspace_bytes", "svdu_secular", "svdu_set_option",
+           "svdu_status_string", "svdu_timing_read")
+
+_lib = None
+
+
+class SvduError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {svdu_status_string(code)} ({code})")
+        self.code = code
+
+
+def load():
+    """Load libsvdu.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    c_int, c_size, c_dbl, c_vp = ctypes.c_int, ctypes.c_size_t, ctypes.c_double, ctypes.c_void_p
+    lib.svdu_workspace_bytes.argtypes = [c_int, c_int, c_int, c_int]
+    lib.svdu_workspace_bytes.restype = c_size
+    lib.svdu_rank1_update.argtypes = [c_int, c_int, c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_vp, c_dbl, c_int, c_int,
+                                      c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_vp, c_size, c_vp]
+    lib.svdu_rank1_update.restype = c_int
+    lib.svdu_get_status.argtypes = [c_vp, c_vp]
+    lib.svdu_get_status.restype = c_int
+    lib.svdu_eig_update_workspace_bytes.argtypes = [c_int, c_int]
+    lib.svdu_eig_update_workspace_bytes.restype = c_size
+    lib.svdu_eig_update.argtypes = [c_int, c_int, c_vp, c_int, c_vp, c_vp, c_dbl, c_vp, c_int, c_vp, c_vp, c_vp,
+                                    c_size, c_vp]
+    lib.svdu_eig_update.restype = c_int
+    lib.svdu_secular_workspace_bytes.argtypes = [c_int]
+    lib.svdu_secular_workspace_bytes.restype = c_size
+    lib.svdu_secular.argtypes = [c_int, c_vp, c_vp, c_dbl, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]
+    lib.svdu_secular.restype = c_int
+    lib.svdu_set_option.argtypes = [c_int, c_int]
+    lib.svdu_set_option.restype = c_int
+    lib.svdu_timing_read.argtypes = [c_vp, c_int]
+    lib.svdu_timing_read.restype = c_int
+    lib.svdu_status_string.argtypes = [c_int]
+    lib.svdu_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------------------------
+# one-to-one wrappers of the C ABI (raw pointers / ints)
+# ---------------------------------------------------------------------------
+def svdu_workspace_bytes(m, n, path=SVDU_PATH_DIRECT, precision=SVDU_PREC_FP64) -> int:
+    return int(load().svdu_workspace_bytes(m, n, path, precision))
+
+
+def svdu_rank1_update(m, n, U, ldu, sigma, V, ldv, a, b, eps, path, precision, U_out, ldu_out, sigma_out, V_out,
+                      ldv_out, defl, workspace, workspace_bytes, stream) -> int:
+    return int(load().svdu_rank1_update(m, n, U, ldu, sigma, V, ldv, a, b, eps, path, precision, U_out, ldu_out,
+                                        sigma_out, V_out, ldv_out, defl, workspace, workspace_bytes, stream))
+
+
+def svdu_get_status(workspace, stream) -> int:
+    return int(load().svdu_get_status(workspace, stream))
+
+
+def svdu_eig_update_workspace_bytes(R, N) -> int:
+    return int(load().svdu_eig_update_workspace_bytes(R, N))
+
+
+def svdu_eig_update(R, N, X, ldx, lam, z, rho, X_out, ldo, lam_out, defl, workspace, workspace_bytes,
+                    stream) -> int:
+    return int(load().svdu_eig_update(R, N, X, ldx, lam, z, rho, X_out, ldo, lam_out, defl, workspace,
+                                      workspace_bytes, stream))
+
+
+def svdu_secular_workspace_bytes(K) -> int:
+    return int(load().svdu_secular_workspace_bytes(K))
+
+
+def svdu_secular(K, d, z, rho, org, tau, iters, workspace, workspace_bytes, stream) -> int:
+    return int(load().svdu_secular(K, d, z, rho, org, tau, iters, workspace, workspace_bytes, stream))
+
+
+def svdu_set_option(option, value) -> int:
+    return int(load().svdu_set_option(option, value))
+
+
+def svdu_timing_read(ms, max_calls) -> int:
+    return int(load().svdu_timing_read(ms, max_calls))
+
+
+def timing_read(max_calls=256):
+    """Phase timings (ms) of the calls recorded since SVDU_OPT_TIMING was set: list of 7-tuples."""
+    buf = (ctypes.c_double * (7 * max_calls))()
+    n = svdu_timing_read(ctypes.cast(buf, ctypes.c_void_p), max_calls)
+    if n < 0:
+        raise SvduError(n, "svdu_timing_read")
+    return [tuple(buf[7 * c + k] for k in range(7)) for c in range(n)]
+
+
+def svdu_status_string(code) -> str:
+    return load().svdu_status_string(code).decode()
+
+
+# ---------------------------------------------------------------------------
+# tensor-level helpers
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_mat(x, rows, cols, name):
+    torch = _torch()
+    if x.dtype != torch.float64 or not x.is_cuda or x.dim() != 2:
+        raise ValueError(f"{name} must be a 2-D float64 device tensor")
+    if x.shape[0] != rows or x.shape[1] != cols or (cols > 1 and x.stride(1) != 1):
+        raise ValueError(f"{name} must be {rows} x {cols} with unit column stride")
+    return max(x.stride(0), cols)
+
+
+def _check_vec(x, n, name):
+    torch = _torch()
+    if x.dtype != torch.float64 or not x.is_cuda or x.dim() != 1 or x.shape[0] != n or x.stride(0) != 1:
+        raise ValueError(f"{name} must be a contiguous float64 device vector of length {n}")
+
+
+def new_workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+
+
+def _aligned(ws):
+    p = ws.data_ptr()
+    off = (-p) % 256
+    return ctypes.c_void_p(p + off), ws.numel() - off
+
+
+def rank1_update(U, sigma, V, a, b, eps=1e-10, path=SVDU_PATH_DIRECT, precision=SVDU_PREC_FP64, out=None,
+                 workspace=None, want_defl=True, stream=None, check=True):
+    """SVD of U diag(sigma) V^T + a b^T. Returns (U^, sigma^, V^, defl flags or None).
+
+    ``out`` may pass preallocated (U_out, sigma_out, V_out); ``workspace`` a uint8
+    device tensor of at least svdu_workspace_bytes(m, n) + 256 bytes.
+    """
+    torch = _torch()
+    m, n = U.shape[0], V.shape[0]
+    ldu = _check_mat(U, m, m, "U")
+    ldv = _check_mat(V, n, n, "V")
+    _check_vec(sigma, m, "sigma")
+    _check_vec(a, m, "a")
+    _check_vec(b, n, "b")
+    dev = U.device
+    if out is None:
+        Uo = torch.empty((m, m), dtype=torch.float64, device=dev)
+        so = torch.empty(m, dtype=torch.float64, device=dev)
+        Vo = torch.empty((n, n), dtype=torch.float64, device=dev)
+    else:
+        Uo, so, Vo = out
+    lduo = _check_mat(Uo, m, m, "U_out")
+    ldvo = _check_mat(Vo, n, n, "V_out")
+    _check_vec(so, m, "sigma_out")
+    need = svdu_workspace_bytes(m, n, path, precision)
+    if workspace is None:
+        workspace = new_workspace(need, dev)
+    wp, wb = _aligned(workspace)
+    defl = torch.empty((4, n), dtype=torch.int8, device=dev) if want_defl else None
+    sh = _stream_handle(stream)
+    rc = svdu_rank1_update(m, n, _ptr(U), ldu, _ptr(sigma), _ptr(V), ldv, _ptr(a), _ptr(b), float(eps), path,
+                           precision, _ptr(Uo), lduo, _ptr(so), _ptr(Vo), ldvo, _ptr(defl), wp, wb, sh)
+    if rc != SVDU_OK:
+        raise SvduError(rc, "svdu_rank1_update")
+    if check:
+        rc = svdu_get_status(wp, sh)
+        if rc != SVDU_OK:
+            raise SvduError(rc, "svdu_rank1_update (device)")
+    return Uo, so, Vo, defl
+
+
+def eig_update(X, lam, z, rho, stream=None, check=True):
+    """One RankOneUpdate: returns (X C~, new eigenvalues ascending, flags)."""
+    torch = _torch()
+    R, N = X.shape
+    ldx = _check_mat(X, R, N, "X")
+    _check_vec(lam, N, "lam")
+    _check_vec(z, N, "z")
+    Xo = torch.empty((R, N), dtype=torch.float64, device=X.device)
+    lo = torch.empty(N, dtype=torch.float64, device=X.device)
+    fl = torch.empty(N, dtype=torch.int8, device=X.device)
+    ws = new_workspace(svdu_eig_update_workspace_bytes(R, N), X.device)
+    wp, wb = _aligned(ws)
+    sh = _stream_handle(stream)
+    rc = svdu_eig_update(R, N, _ptr(X), ldx, _ptr(lam), _ptr(z), float(rho), _ptr(Xo), max(N, 1), _ptr(lo),
+                         _ptr(fl), wp, wb, sh)
+    if rc != SVDU_OK:
+        raise SvduError(rc, "svdu_eig_update")
+    if check:
+        rc = svdu_get_status(wp, sh)
+        if rc != SVDU_OK:
+            raise SvduError(rc, "svdu_eig_update (device)")
+    return Xo, lo, fl
+
+
+def secular(d, z, rho, stream=None, check=True):
+    """Roots of 1 + rho sum z^2/(d - mu) for distinct ascending d: (org, tau, iters)."""
+    torch = _torch()
+    K = d.shape[0]
+    _check_vec(d, K, "d")
+    _check_vec(z, K, "z")
+    org = torch.empty(K, dtype=torch.int32, device=d.device)
+    tau = torch.empty(K, dtype=torch.float64, device=d.device)
+    its = torch.empty(K, dtype=torch.int32, device=d.device)
+    ws = new_workspace(svdu_secular_workspace_bytes(K), d.device)
+    wp, wb = _aligned(ws)
+    sh = _stream_handle(stream)
+    rc = svdu_secular(K, _ptr(d), _ptr(z), float(rho), _ptr(org), _ptr(tau), _ptr(its), wp, wb, sh)
+    if rc != SVDU_OK:
+        raise SvduError(rc, "svdu_secular")
+    if check:
+        rc = svdu_get_status(wp, sh)
+        if rc != SVDU_OK:
+            raise SvduError(rc, "svdu_secular (device)")
+    return org, tau, its

@@ -1,0 +1,89 @@
+// Device helpers shared by the svdu kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace svdu {
+
+constexpr double kU = 1.1102230246251565e-16;  // unit roundoff 2^-53
+
+// 1/x to within an ulp: hardware reciprocal (about 2^-24 relative) refined by
+// two Newton steps. Inputs too small for the hardware estimate use the IEEE
+// divide.
+__device__ __forceinline__ double recip(double x) {
+  if (__builtin_fabs(x) < 0x1p-1000) return 1.0 / x;
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// Butterfly reductions over a full wave of 64 lanes. IEEE addition and
+// multiplication commute, so every lane ends with the same bits.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_prod(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = __builtin_fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block-wide inclusive scan of one int per thread (blockDim a multiple of 64,
+// at most 4096). `sh` holds at least 64 ints of shared memory. Returns the
+// inclusive prefix; *total receives the block total.
+__device__ inline int block_scan_incl(int v, int* sh, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  if (lane == 63) sh[w] = v;
+  __syncthreads();
+  if (w == 0) {
+    int s = (lane < nw) ? sh[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int t = __shfl_up(s, o, 64);
+      if (lane >= o) s += t;
+    }
+    if (lane < nw) sh[lane] = s;
+  }
+  __syncthreads();
+  if (w > 0) v += sh[w - 1];
+  *total = sh[nw - 1];
+  __syncthreads();
+  return v;
+}
+
+// Block-wide sum of one double per thread; every thread gets the result.
+__device__ inline double block_sum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < nw; ++k) s += sh[k];  // fixed order: deterministic
+  __syncthreads();
+  return s;
+}
+
+// Counter-based hash to a double in [-1, 1) (splitmix64 finaliser).
+__device__ __forceinline__ double hash_unit(uint64_t i, uint64_t stream) {
+  uint64_t x = i * 0x9E3779B97F4A7C15ull + stream * 0xD1B54A32D192ED03ull + 0x632BE59BD9B4E019ull;
+  x ^= x >> 30; x *= 0xBF58476D1CE4E5B9ull;
+  x ^= x >> 27; x *= 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return (double)(x >> 11) * 0x1p-52 - 1.0;
+}
+
+}  // namespace svdu

@@ -1,0 +1,485 @@
+// One symmetric rank-one eigen-update up to (not including) the product:
+// deflation, the secular roots, the eigenvector weights and the descriptors
+// of C~. Section 6.2 of the paper (RankOneUpdate Steps 2, 3, 5 and 7),
+// Section 3.1 (deflation cases) and equation GolubEigenvalUpdate.
+//
+// Readings where the paper is silent:
+//  * a component z_j is dropped when |z_j| <= 8 u sqrt(N) |z| (rounding noise
+//    of a projection); exactly repeated poles merge into one pole whose weight
+//    is the norm of their z entries, and a Householder reflection supplies
+//    the group's other eigenvectors. Close but distinct poles stay separate.
+//  * each root is stored as (origin pole, offset tau), the origin being the
+//    nearer pole, so that every difference d_j - mu_i is formed as
+//    (d_j - d_origin) - tau without cancellation.
+//  * the eigenvector weights are recomputed from the roots (Loewner formula),
+//    which keeps C~ orthogonal to working precision.
+#include <math.h>
+
+#include "device_util.h"
+#include "svdu_internal.h"
+
+namespace svdu {
+
+// ---------------------------------------------------------------------------
+// Deflation: one block of 1024 threads walks the N sorted poles.
+// ---------------------------------------------------------------------------
+constexpr int kDeflThreads = 1024;
+
+__global__ __launch_bounds__(kDeflThreads) void deflate_kernel(Stage s) {
+  __shared__ int shi[64];
+  __shared__ double shd[64];
+  if (*s.status & kStFatal) return;
+  const int N = s.N;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double loc = 0.0;
+  int bad = 0;
+  for (int t = tid; t < N; t += nt) {
+    const int j = s.col_of[t];
+    const double zz = s.z[j];
+    const double dd = s.lam_in[j];
+    s.dsort[t] = dd;
+    s.zs[t] = zz;
+    loc += zz * zz;
+    if (!isfinite(dd) || !isfinite(zz)) bad |= kStNonFinite;
+    if (t > 0 && !(s.lam_in[s.col_of[t - 1]] <= dd)) bad |= kStBadSigma;
+  }
+  const double znorm = sqrt(block_sum(loc, shd));
+  const double rho = *s.rho;
+  if (!isfinite(znorm) || !isfinite(rho) || rho == 0.0) bad |= kStNonFinite;
+  // every thread learns whether any thread saw bad data
+  __shared__ int shbad;
+  if (tid == 0) shbad = 0;
+  __syncthreads();
+  if (bad) atomicOr(&shbad, bad);
+  __syncthreads();
+  bad = shbad;
+  if (bad) {
+    // record the error and describe C~ = I (everything deflated, in order), so
+    // that nothing downstream can derive an index from the bad data
+    if (tid == 0) {
+      atomicOr(s.status, bad);
+      s.counts[0] = 0;
+      s.counts[1] = N;
+      s.counts[2] = 0;
+    }
+    for (int t = tid; t < N; t += nt) {
+      const int j = s.col_of[t];
+      s.clu[t] = -1;
+      s.dlist[t] = t;
+      s.dval[t] = 0.0;
+      s.rg[j] = 0.0;
+      s.rh[j] = 0.0;
+      s.rcl[j] = t;
+      s.flags[j] = 1;
+    }
+    return;
+  }
+  const double tol = 8.0 * kU * sqrt((double)(N > 0 ? N : 1)) * znorm;
+  __syncthreads();
+  // kept components -> Llist
+  int carry = 0;
+  for (int base = 0; base < N; base += nt) {
+    const int t = base + tid;
+    const bool keep = (t < N) && !(fabs(s.zs[t]) <= tol);
+    int tot;
+    const int incl = block_scan_incl(keep ? 1 : 0, shi, &tot);
+    if (keep) s.Llist[carry + incl - 1] = t;
+    if (t < N && !keep) s.clu[t] = -1;
+    carry += tot;
+  }
+  const int Nl = carry;
+  __syncthreads();
+  // clusters of exactly equal poles among the kept components
+  carry = 0;
+  for (int base = 0; base < Nl; base += nt) {
+    const int k = base + tid;
+    bool nc = false;
+    if (k < Nl) nc = (k == 0) || (s.dsort[s.Llist[k]] != s.dsort[s.Llist[k - 1]]);
+    int tot;
+    const int incl = block_scan_incl(nc ? 1 : 0, shi, &tot);
+    if (k < Nl) {
+      const int cid = carry + incl - 1;
+      s.clu[s.Llist[k]] = cid;
+      if (nc) s.cfirst[cid] = k;
+    }
+    carry += tot;
+  }
+  const int K = carry;
+  __syncthreads();
+  // per cluster: pole, weight, Householder vector, row descriptors of members
+  for (int c = tid; c < K; c += nt) {
+    const int f = s.cfirst[c];
+    const int e = (c + 1 < K) ? s.cfirst[c + 1] : Nl;
+    const int sz = e - f;
+    s.csize[c] = sz;
+    const double gc = s.dsort[s.Llist[f]];
+    s.g[c] = gc;
+    double w2 = 0.0;
+    for (int k = f; k < e; ++k) {
+      const double zz = s.zs[s.Llist[k]];
+      w2 += zz * zz;
+    }
+    const double w = sqrt(w2);
+    s.W2[c] = w2;
+    s.W[c] = w;
+    double sg = 1.0, hn = 1.0;
+    if (sz >= 2) {
+      const double v0 = s.zs[s.Llist[f]] / w;
+      sg = (v0 >= 0.0) ? 1.0 : -1.0;
+      hn = sqrt(2.0 * (1.0 + fabs(v0)));
+    }
+    for (int k = f; k < e; ++k) {
+      const int t = s.Llist[k];
+      const int j = s.col_of[t];
+      s.rg[j] = gc;
+      s.rcl[j] = c;
+      s.flags[j] = (k == f) ? 0 : 2;
+      s.rh[j] = (sz >= 2) ? (s.zs[t] / w + (k == f ? sg : 0.0)) / hn : 0.0;
+    }
+  }
+  __syncthreads();
+  // deflated list: dropped components and non-first cluster members
+  carry = 0;
+  for (int base = 0; base < N; base += nt) {
+    const int t = base + tid;
+    bool dfl = false;
+    if (t < N) {
+      const int c = s.clu[t];
+      dfl = (c < 0) || (s.Llist[s.cfirst[c]] != t);
+    }
+    int tot;
+    const int incl = block_scan_incl(dfl ? 1 : 0, shi, &tot);
+    if (dfl) {
+      const int kd = carry + incl - 1;
+      s.dlist[kd] = t;
+      s.dval[kd] = s.dsort[t];
+      if (s.clu[t] < 0) {
+        const int j = s.col_of[t];
+        s.rg[j] = 0.0;
+        s.rh[j] = 0.0;
+        s.rcl[j] = K + kd;   // a group of its own
+        s.flags[j] = 1;
+      }
+    }
+    carry += tot;
+  }
+  if (tid == 0) {
+    s.counts[0] = K;
+    s.counts[1] = carry;
+    s.counts[2] = Nl;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Secular equation, one root per wave of 64 lanes (lanes stride over poles).
+// Works in the reflected problem when rho < 0 so that the iteration always
+// sees rho > 0 and roots to the right of their left pole.
+// ---------------------------------------------------------------------------
+struct Reflect {
+  const double* g;
+  const double* W2;
+  int K;
+  bool refl;
+  __device__ __forceinline__ double pole(int k) const { return refl ? -g[K - 1 - k] : g[k]; }
+  __device__ __forceinline__ double wt(int k) const { return refl ? W2[K - 1 - k] : W2[k]; }
+};
+
+struct SecSums {
+  double psi, dpsi, phi, dphi;
+};
+
+// Sums over poles at x = P(o) + tau: psi/dpsi over poles k <= i, phi/dphi over k > i.
+__device__ inline SecSums secular_sums(const Reflect& R, int i, double po, double tau, int lane) {
+  double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+  for (int k = lane; k < R.K; k += 64) {
+    const double del = (R.pole(k) - po) - tau;
+    const double r = recip(del);
+    const double t = R.wt(k) * r;
+    if (k <= i) {
+      psi += t;
+      dpsi += t * r;
+    } else {
+      phi += t;
+      dphi += t * r;
+    }
+  }
+  return SecSums{wave_sum(psi), wave_sum(dpsi), wave_sum(phi), wave_sum(dphi)};
+}
+
+// Root of c x^2 - a x + b = 0 inside (lo, hi); returns false when none is.
+__device__ inline bool quad_root_in(double c, double a, double b, double lo, double hi, double* x) {
+  double r1, r2;
+  if (c == 0.0) {
+    if (a == 0.0) return false;
+    r1 = r2 = b / a;
+  } else {
+    double disc = a * a - 4.0 * b * c;
+    if (disc < 0.0) disc = 0.0;
+    const double q = 0.5 * (a + copysign(sqrt(disc), a));
+    if (q == 0.0) return false;
+    r1 = q / c;
+    r2 = b / q;
+  }
+  const bool in1 = (r1 > lo) && (r1 < hi);
+  const bool in2 = (r2 > lo) && (r2 < hi);
+  if (in1 && in2) {
+    *x = (fabs(r1) < fabs(r2)) ? r1 : r2;
+    return true;
+  }
+  if (in1) { *x = r1; return true; }
+  if (in2) { *x = r2; return true; }
+  return false;
+}
+
+__global__ __launch_bounds__(256) void secular_kernel(const int* __restrict__ Kdev, const double* __restrict__ g,
+                                                      const double* __restrict__ W2,
+                                                      const double* __restrict__ rhop, int* __restrict__ org,
+                                                      double* __restrict__ tau_out, int* __restrict__ iters,
+                                                      int* status, int maxit) {
+  if (*status & kStFatal) return;
+  const int K = *Kdev;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wave >= K) return;
+  const double rho0 = *rhop;
+  Reflect R{g, W2, K, rho0 < 0.0};
+  const double rho = fabs(rho0);
+  const double rinv = 1.0 / rho;
+  const int i = R.refl ? K - 1 - wave : wave;  // root index in the reflected problem
+
+  int o;
+  double lo, hi, tau;
+  if (i < K - 1) {
+    const double pi = R.pole(i), pi1 = R.pole(i + 1);
+    const double gap = pi1 - pi;
+    const double half = 0.5 * gap;
+    const SecSums m = secular_sums(R, i, pi, half, lane);
+    const double fmid = rinv + m.psi + m.phi;
+    const double qi = R.wt(i), qi1 = R.wt(i + 1);
+    // two-pole model at the midpoint: c + qi/(pi - x) + qi1/(pi1 - x)
+    const double c = fmid + qi / half - qi1 / half;
+    double a, b;
+    if (fmid >= 0.0) {
+      o = i;
+      lo = 0.0;
+      hi = half;
+      a = c * gap + qi + qi1;
+      b = qi * gap;
+    } else {
+      o = i + 1;
+      lo = -half;
+      hi = 0.0;
+      a = -c * gap + qi + qi1;
+      b = -qi1 * gap;
+    }
+    if (!quad_root_in(c, a, b, lo, hi, &tau)) tau = 0.5 * (lo + hi);
+    if (fmid == 0.0) tau = (o == i) ? half : -half;
+  } else {
+    o = K - 1;
+    double w = 0.0;
+    for (int k = lane; k < K; k += 64) w += R.wt(k);
+    w = wave_sum(w);
+    lo = 0.0;
+    hi = rho * w;
+    tau = 0.5 * hi;
+  }
+  const double po = R.pole(o);
+  const double dl = (i < K - 1 || true) ? (R.pole(i) - po) : 0.0;       // left pole offset
+  const double dr = (i < K - 1) ? (R.pole(i + 1) - po) : 0.0;          // right pole offset
+  bool done = false;
+  int it = 0;
+  for (; it < maxit; ++it) {
+    const SecSums s = secular_sums(R, i, po, tau, lane);
+    const double f = rinv + s.psi + s.phi;
+    if (f < 0.0) lo = tau; else hi = tau;
+    const double err = 8.0 * (s.phi - s.psi) + 2.0 * rinv + 3.0 * fabs(f) + fabs(tau) * (s.dpsi + s.dphi);
+    if (fabs(f) <= kU * err || f == 0.0) { done = true; break; }
+    if (hi - lo <= 4.0 * kU * fmax(fabs(lo), fabs(hi))) { done = true; break; }
+    double eta;
+    bool ok;
+    const double dL = dl - tau;
+    if (i < K - 1) {
+      const double dR = dr - tau;
+      const double c = f - dL * s.dpsi - dR * s.dphi;
+      const double a = f * (dL + dR) - dL * dR * (s.dpsi + s.dphi);
+      const double b = dL * dR * f;
+      ok = quad_root_in(c, a, b, lo - tau, hi - tau, &eta);
+    } else {
+      const double c = f - dL * s.dpsi;
+      ok = c > 0.0;
+      eta = ok ? dL + dL * dL * s.dpsi / c : 0.0;
+    }
+    if (!ok || f * eta >= 0.0) eta = -f / (s.dpsi + s.dphi);
+    double tn = tau + eta;
+    if (!(tn > lo && tn < hi) || it >= 40) tn = 0.5 * (lo + hi);
+    if (tn == tau) { done = true; break; }
+    tau = tn;
+  }
+  if (!isfinite(tau)) {  // keeps mu inside its interval whatever happened
+    tau = 0.0;
+    done = false;
+  }
+  if (lane == 0) {
+    if (!done) atomicOr(status, (int)kStNoConv);
+    const int ow = R.refl ? K - 1 - o : o;
+    org[wave] = ow;
+    tau_out[wave] = R.refl ? -tau : tau;
+    if (iters) iters[wave] = it + 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Loewner weights, one pole per wave (lanes over roots), reflected for rho<0:
+// |w_j|^2 = prod_i (mu_i - d_j) / (rho prod_{k != j} (d_k - d_j)), as K ratios
+// in (0, 1] pairing root i with pole i (i < j) or i+1 (i >= j), last with rho.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void loewner_kernel(const int* __restrict__ Kdev, const double* __restrict__ g,
+                                                      const double* __restrict__ rhop,
+                                                      const int* __restrict__ org, const double* __restrict__ tau,
+                                                      double* __restrict__ what, const int* status) {
+  if (*status & kStFatal) return;
+  const int K = *Kdev;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wave >= K) return;
+  const double rho0 = *rhop;
+  const bool refl = rho0 < 0.0;
+  const double rho = fabs(rho0);
+  Reflect R{g, nullptr, K, refl};
+  const int jr = refl ? K - 1 - wave : wave;  // pole index in the reflected problem
+  const double pj = R.pole(jr);
+  double prod = 1.0;
+  for (int ir = lane; ir < K; ir += 64) {
+    const int io = refl ? K - 1 - ir : ir;
+    const int orr = refl ? K - 1 - org[io] : org[io];
+    const double tr = refl ? -tau[io] : tau[io];
+    const double num = (R.pole(orr) - pj) + tr;
+    double ratio;
+    if (ir == K - 1) {
+      ratio = num / rho;
+    } else {
+      const int pr = (ir < jr) ? ir : ir + 1;
+      ratio = num / (R.pole(pr) - pj);
+    }
+    prod *= ratio;
+  }
+  prod = wave_prod(prod);
+  if (lane == 0) what[wave] = sqrt(fabs(prod));
+}
+
+// ---------------------------------------------------------------------------
+// Column scales 1/|c_i| with |c_i|^2 = sum_k what_k^2 / delta_ki^2, and mu.
+// One root per wave, two passes (max, then scaled sum of squares).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void colnorm_kernel(const int* __restrict__ Kdev, const double* __restrict__ g,
+                                                      const double* __restrict__ what,
+                                                      const int* __restrict__ org,
+                                                      const double* __restrict__ tau, double* __restrict__ cs,
+                                                      double* __restrict__ mu, const int* status) {
+  if (*status & kStFatal) return;
+  const int K = *Kdev;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= K) return;
+  const double go = g[org[i]];
+  const double ti = tau[i];
+  double mx = 0.0;
+  for (int k = lane; k < K; k += 64) mx = fmax(mx, fabs(what[k] * recip((g[k] - go) - ti)));
+  mx = wave_max(mx);
+  const double inv = (mx > 0.0) ? 1.0 / mx : 1.0;
+  double ss = 0.0;
+  for (int k = lane; k < K; k += 64) {
+    const double t = what[k] * recip((g[k] - go) - ti) * inv;
+    ss += t * t;
+  }
+  ss = wave_sum(ss);
+  if (lane == 0) {
+    cs[i] = (mx > 0.0) ? inv / sqrt(ss) : 0.0;
+    mu[i] = go + ti;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Output positions and descriptors: merge the ascending roots with the
+// ascending deflated eigenvalues (ties: root first), then write the column
+// descriptors at their output positions and the per-row weights zeta.
+// ---------------------------------------------------------------------------
+__device__ inline int count_less(const double* a, int n, double v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+__device__ inline int count_leq(const double* a, int n, double v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] <= v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void merge_kernel(Stage s) {
+  if (*s.status & kStFatal) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = s.N;
+  const int K = s.counts[0], Kd = s.counts[1];
+  if (idx < N) {
+    // row weight zeta_j = what_c z_j / W_c (zero for dropped components)
+    const int t = idx;
+    const int j = s.col_of[t];
+    const int c = s.clu[t];
+    s.rzeta[j] = (c >= 0) ? s.what[c] * (s.zs[t] / s.W[c]) : 0.0;
+  }
+  if (idx < K) {
+    const double v = s.mu[idx];
+    const int pos = idx + count_less(s.dval, Kd, v);
+    const int P = s.descending ? N - 1 - pos : pos;
+    s.lam_out[P] = v;
+    s.ctype[P] = 0;
+    s.co[P] = s.g[s.org[idx]];
+    s.ctau[P] = s.tau[idx];
+    s.ccs[P] = s.cs[idx];
+    s.ccl[P] = -1;
+    s.cmem[P] = -1;
+    s.ch[P] = 0.0;
+  } else if (idx < K + Kd) {
+    const int kd = idx - K;
+    const double v = s.dval[kd];
+    const int pos = kd + count_leq(s.mu, K, v);
+    const int P = s.descending ? N - 1 - pos : pos;
+    const int t = s.dlist[kd];
+    const int j = s.col_of[t];
+    s.lam_out[P] = v;
+    s.ctype[P] = 1;
+    s.co[P] = 0.0;
+    s.ctau[P] = 0.0;
+    s.ccs[P] = 0.0;
+    s.ccl[P] = s.rcl[j];
+    s.cmem[P] = j;
+    s.ch[P] = s.rh[j];
+  }
+}
+
+void launch_secular(int K_max, const int* Kdev, const double* g, const double* W2, const double* rho, int* org,
+                    double* tau, int* iters, int* status, int maxit, hipStream_t st) {
+  if (K_max <= 0) return;
+  hipLaunchKernelGGL(secular_kernel, dim3((K_max + 3) / 4), dim3(256), 0, st, Kdev, g, W2, rho, org, tau, iters,
+                     status, maxit);
+}
+
+void launch_stage_small(Stage& s, int maxit, hipStream_t st) {
+  const int N = s.N;
+  if (N <= 0) return;
+  hipLaunchKernelGGL(deflate_kernel, dim3(1), dim3(kDeflThreads), 0, st, s);
+  launch_secular(N, s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, st);
+  hipLaunchKernelGGL(loewner_kernel, dim3((N + 3) / 4), dim3(256), 0, st, s.counts, s.g, s.rho, s.org, s.tau,
+                     s.what, s.status);
+  hipLaunchKernelGGL(colnorm_kernel, dim3((N + 3) / 4), dim3(256), 0, st, s.counts, s.g, s.what, s.org, s.tau,
+                     s.cs, s.mu, s.status);
+  hipLaunchKernelGGL(merge_kernel, dim3((N + 255) / 256), dim3(256), 0, st, s);
+}
+
+}  // namespace svdu

@@ -1,0 +1,123 @@
+// Internal interfaces of libsvdu: per-stage device buffers and kernel launchers.
+//
+// One symmetric rank-one eigen-update (the paper's RankOneUpdate, Section 6.2)
+// is a "stage". Its input is a basis X whose columns carry eigenvalues lam_in
+// (storage order), the projected vector z = X^T v and rho. Its output is the
+// description of the orthogonal matrix C~ (equation CTildeFinalForm1) as
+// per-row and per-output-column data, from which every kernel that needs an
+// entry of C~ regenerates it:
+//
+//   live column c (a secular root mu_c = d_org + tau):
+//     C~[j, c] = zeta_j * s_c / ((rg_j - o_c) - tau_c)      (0 where zeta_j == 0)
+//   deflated column c (a kept pole, member `mem` of cluster `cl`):
+//     C~[j, c] = (rcl_j == cl) ? ([j == mem] - 2 rh_j h_c) : 0
+//
+// where rg_j is the (merged) pole of row j, zeta_j its Loewner weight with the
+// sign of z_j, s_c = 1/|c_c| the column scale, and rh the Householder vector
+// of an exactly repeated pole group (zero for single poles and dropped rows).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace svdu {
+
+enum StatusBits : int {
+  kStNoConv = 1,      // a secular root hit the iteration cap
+  kStNonFinite = 2,   // NaN or Inf in an input (or produced from one)
+  kStBadSigma = 4,    // sigma / eigenvalues not in the required order, or negative sigma
+};
+// Once a fatal bit is set every later kernel of the call returns at entry, so
+// no index is ever derived from invalid data.
+constexpr int kStFatal = kStNonFinite | kStBadSigma;
+
+struct Stage {
+  int N = 0;              // dimension of the eigenproblem
+  int* status = nullptr;  // device status word of the call
+  int cap = 0;            // allocated length of every per-index array
+  double* rho = nullptr;  // device scalar
+  bool descending = false;  // output columns by descending eigenvalue
+  // inputs
+  const double* lam_in = nullptr;  // N, storage order of X's columns
+  int* col_of = nullptr;           // N, sorted position -> storage column
+  double* z = nullptr;             // N, storage order
+  // deflation (sorted positions t)
+  double* dsort = nullptr;
+  double* zs = nullptr;
+  int* clu = nullptr;      // cluster id, -1 for a dropped component
+  int* Llist = nullptr;    // sorted positions of kept components
+  double* g = nullptr;     // per cluster: pole
+  double* W = nullptr;     // per cluster: norm of z over the cluster
+  double* W2 = nullptr;    // per cluster: W^2
+  int* cfirst = nullptr;   // per cluster: first index into Llist
+  int* csize = nullptr;    // per cluster: member count
+  int* dlist = nullptr;    // deflated sorted positions (dropped or non-first member)
+  double* dval = nullptr;  // their eigenvalues
+  int* counts = nullptr;   // [0] K clusters (= roots), [1] Kd deflated, [2] kept count
+  // roots and weights (per cluster / root index)
+  int* org = nullptr;
+  double* tau = nullptr;
+  double* mu = nullptr;
+  double* what = nullptr;
+  double* cs = nullptr;    // 1 / column norm
+  int* iters = nullptr;    // secular iterations per root
+  // row descriptors (storage order)
+  double* rg = nullptr;
+  double* rzeta = nullptr;
+  double* rh = nullptr;
+  int* rcl = nullptr;
+  int8_t* flags = nullptr;  // 0 kept, 1 dropped (zero component), 2 merged repeated pole
+  // column descriptors (output position)
+  int8_t* ctype = nullptr;  // 0 live, 1 deflated
+  double* co = nullptr;
+  double* ctau = nullptr;
+  double* ccs = nullptr;
+  int* ccl = nullptr;
+  int* cmem = nullptr;
+  double* ch = nullptr;
+  double* lam_out = nullptr;  // eigenvalue per output column
+  double* hx = nullptr;       // per cluster x 3: Householder dot products for C~^T x
+};
+
+// Descriptor view handed to the product kernels.
+struct CauchyDesc {
+  int N;
+  const double* rg;
+  const double* rzeta;
+  const double* rh;
+  const int* rcl;
+  const int8_t* ctype;
+  const double* co;
+  const double* ctau;
+  const double* ccs;
+  const int* ccl;
+  const int* cmem;
+  const double* ch;
+  const double* colscale;  // optional per-output-column sign (nullptr: none)
+  const int* status;       // device status word; fatal bits make the kernels return
+};
+
+inline CauchyDesc desc_of(const Stage& s, const double* colscale = nullptr) {
+  return CauchyDesc{s.N, s.rg, s.rzeta, s.rh, s.rcl, s.ctype, s.co, s.ctau, s.ccs, s.ccl, s.cmem, s.ch,
+                    colscale, s.status};
+}
+
+// ---- launchers (each enqueues on `st`, no host synchronisation) ----------------
+// Projections: part/out = X^T [v0 v1 v2] (nv of them), X row-major R x N.
+void launch_gemv_t(int R, int N, const double* X, int ldx, int nv, const double* v0, const double* v1,
+                   const double* v2, double* out0, double* out1, double* out2, double* scratch,
+                   size_t scratch_elems, hipStream_t st);
+size_t gemv_t_scratch_elems(int R, int N, int nv);
+
+// Deflation, secular roots, Loewner weights, column norms, descriptors.
+void launch_stage_small(Stage& s, int maxit, hipStream_t st);
+// The secular solve alone, for distinct ascending poles g with weights W2 (K of them).
+void launch_secular(int K_max, const int* Kdev, const double* g, const double* W2, const double* rho,
+                    int* org, double* tau, int* iters, int* status, int maxit, hipStream_t st);
+// y_k = C~^T x_k for up to 3 vectors (storage order in, output positions out).
+void launch_cauchy_tmatvec(const Stage& s, int nv, const double* const* x, double* const* y, hipStream_t st);
+// X_out = X * C~ (R x N times N x N), FP64 MFMA with C~ tiles generated in LDS.
+void launch_gemm_cauchy_f64(int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo,
+                            hipStream_t st);
+
+}  // namespace svdu
