@@ -28,12 +28,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
-GEMM_SRC = os.path.join(ROOT, "paper_1707_08369_amd", "csrc", "k_cauchy.hip")
+CSRC = os.path.join(ROOT, "paper_1707_08369_amd", "csrc")
+GEMM_SRCS = [os.path.join(CSRC, f) for f in ("k_gemm_f64.hip", "cauchy_tile.h", "device_util.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_cauchy_f64_traffic.json")
 
 
 def gemm_source_hash() -> str:
-    return hashlib.sha256(open(GEMM_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the product kernel's source and the headers it includes."""
+    h = hashlib.sha256()
+    for f in GEMM_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(m: int, n: int):
@@ -106,6 +111,35 @@ def cpu_baseline(n_s: int = 3072, seed: int = 77):
     }
 
 
+def measure_forms(svdu, torch, U, sigma, V, A_vecs, B_vecs, Uo, so, Vo, ws, stream, fp64_ms, check, steps=4):
+    """The precision form on the same inputs: updates/s, speedup over the plain
+    FP64 path, and its reconstruction / orthogonality error."""
+    import numpy as np
+    res = {}
+    m, n = U.shape[0], V.shape[0]
+    for name, prec in (("split32", svdu.SVDU_PREC_SPLIT32),):
+        def run(k):
+            svdu.rank1_update(U, sigma, V, A_vecs[k], B_vecs[k], precision=prec, out=(Uo, so, Vo), workspace=ws,
+                              want_defl=False, stream=stream, check=False)
+        run(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(1, steps + 1):
+            run(k % A_vecs.shape[0])
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        rec = dict(updates_per_s=1e3 / ms, ms_per_update=ms, speedup_vs_fp64=fp64_ms / ms)
+        if check:
+            k = steps % A_vecs.shape[0]
+            Ah = (U * sigma[None, :]) @ V[:, :m].T + torch.outer(A_vecs[k], B_vecs[k])
+            rec["recon"] = ((Uo * so[None, :]) @ Vo[:, :m].T - Ah).norm().item() / Ah.norm().item()
+            rec["orth_U"] = (Uo.T @ Uo - torch.eye(m, dtype=Uo.dtype, device=Uo.device)).abs().max().item()
+            rec["orth_V"] = (Vo.T @ Vo - torch.eye(n, dtype=Vo.dtype, device=Vo.device)).abs().max().item()
+            rec["bound"] = 1e-10
+        res[name] = rec
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +149,12 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--seed", type=int, default=2026)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--haar", choices=("device", "host"), default="device",
+                    help="where the Haar factors are drawn: torch QR on the GPU, or numpy QR on the host "
+                         "(no library kernels besides libsvdu's run on the GPU then; for counter runs)")
+    ap.add_argument("--no-check", action="store_true", help="skip the reconstruction spot check")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the short measurements of the other forms (precision form) on the same inputs")
     ap.add_argument("--profile-copy", type=int, default=0,
                     help="run only N plain 1 GiB device copies (counter calibration) and exit")
     args = ap.parse_args()
@@ -147,8 +187,12 @@ def main():
 
     m, n, K, W = args.m, args.n, args.steps, args.warmup
     rng = np.random.default_rng(args.seed)
-    U = S.haar_torch(m, seed=args.seed + 1, device="cuda")
-    V = S.haar_torch(n, seed=args.seed + 2, device="cuda")
+    if args.haar == "device":
+        U = S.haar_torch(m, seed=args.seed + 1, device="cuda")
+        V = S.haar_torch(n, seed=args.seed + 2, device="cuda")
+    else:
+        U = torch.as_tensor(S.haar(m, S.rng_for(args.seed + 1)), device=dev)
+        V = torch.as_tensor(S.haar(n, S.rng_for(args.seed + 2)), device=dev)
     sigma = torch.as_tensor(S.sigma_uniform(m, 1e-3, 1.0, rng), device=dev)
     A_vecs = torch.as_tensor(rng.standard_normal((W + K, m)) / np.sqrt(n), device=dev)
     B_vecs = torch.as_tensor(rng.standard_normal((W + K, n)) / np.sqrt(n), device=dev)
@@ -183,9 +227,11 @@ def main():
     print(f"[bench] timed {K} steps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
 
     # correctness spot check of the last timed update (not timed)
-    k = W + K - 1
-    Ah = (U * sigma[None, :]) @ V[:, :m].T + torch.outer(A_vecs[k], B_vecs[k])
-    recon = ((Uo * so[None, :]) @ Vo[:, :m].T - Ah).norm().item() / Ah.norm().item()
+    recon = None
+    if not args.no_check:
+        k = W + K - 1
+        Ah = (U * sigma[None, :]) @ V[:, :m].T + torch.outer(A_vecs[k], B_vecs[k])
+        recon = ((Uo * so[None, :]) @ Vo[:, :m].T - Ah).norm().item() / Ah.norm().item()
 
     ph = np.asarray(phases)                       # K x 7 ms
     per_update = ph.sum(axis=1)
@@ -230,6 +276,9 @@ def main():
             "mean_launch_ms": mean_gemm_ms,
         },
     }
+    if not args.no_forms:
+        out["forms"] = measure_forms(svdu, torch, U, sigma, V, A_vecs, B_vecs, Uo, so, Vo, ws, stream,
+                                     fp64_ms=1e3 * (t1 - t0) / K, check=not args.no_check)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -49,11 +49,13 @@ extern "C" {
 
 /* arithmetic of the product X C~ (roots, deflation and norms are always FP64) */
 #define SVDU_PREC_FP64 0
-#define SVDU_PREC_SPLIT32 1     /* split FP32 hi/lo, three MFMA passes */
+#define SVDU_PREC_SPLIT32 1     /* split FP32 hi/lo, three FP32 MFMA passes, FP32 accumulation drained to
+                                   FP64 every 16 k; then every column of U^ and V^ rescaled to unit FP64 norm */
 
 /* options for svdu_set_option */
 #define SVDU_OPT_SECULAR_MAXIT 1 /* iteration cap of the secular solver (default 200) */
 #define SVDU_OPT_TIMING 2        /* 1: record phase timings of svdu_rank1_update (resets the record) */
+#define SVDU_OPT_GEMM_VARIANT 3  /* product kernel: 2 (default, X in registers) or 1 (both operands via LDS) */
 
 /* Bytes of device workspace svdu_rank1_update needs for (m, n, path, precision). */
 size_t svdu_workspace_bytes(int m, int n, int path, int precision);

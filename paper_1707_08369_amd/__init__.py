@@ -30,6 +30,7 @@ SVDU_PREC_FP64 = 0
 SVDU_PREC_SPLIT32 = 1
 SVDU_OPT_SECULAR_MAXIT = 1
 SVDU_OPT_TIMING = 2
+SVDU_OPT_GEMM_VARIANT = 3
 
 EXPORTS = ("svdu_workspace_bytes", "svdu_rank1_update", "svdu_get_status", "svdu_eig_update_workspace_bytes",
            "svdu_eig_update", "svdu_secular_workspace_bytes", "svdu_secular", "svdu_set_option",

@@ -1,0 +1,104 @@
+// Cauchy tile generation shared by the kernels that need entries of C~
+// (see svdu_internal.h for the descriptor layout).
+#pragma once
+#include "device_util.h"
+#include "svdu_internal.h"
+
+namespace svdu {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Block tile of the product kernels: 128 x 128 outputs, K step 16.
+constexpr int kBM = 128, kBN = 128, kBK = 16;
+constexpr int kLDA = kBK + 1;  // padded LDS row of the LDS-staged X tile
+
+// Entry C~[j, c] from the descriptors (see svdu_internal.h).
+struct ColDesc {
+  int type;   // -1 out of range, 0 live, 1 deflated
+  double o, t, s, h;
+  int cl, mem;
+};
+
+__device__ __forceinline__ ColDesc load_col(const CauchyDesc& d, int c) {
+  ColDesc r{-1, 0.0, 0.0, 0.0, 0.0, -1, -1};
+  if (c < d.N) {
+    r.type = d.ctype[c];
+    r.o = d.co[c];
+    r.t = d.ctau[c];
+    r.s = d.ccs[c];
+    r.h = d.ch[c];
+    r.cl = d.ccl[c];
+    r.mem = d.cmem[c];
+  }
+  return r;
+}
+
+__device__ __forceinline__ double cauchy_entry(const CauchyDesc& d, int j, const ColDesc& c) {
+  if (j >= d.N || c.type < 0) return 0.0;
+  if (c.type == 0) {
+    const double z = d.rzeta[j];
+    if (z == 0.0) return 0.0;
+    return (z * c.s) * recip((d.rg[j] - c.o) - c.t);
+  }
+  if (d.rcl[j] != c.cl) return 0.0;
+  return ((j == c.mem) ? 1.0 : 0.0) - 2.0 * d.rh[j] * c.h;
+}
+
+struct RowVals {
+  double z, g, h;
+  int cl;
+};
+
+__device__ __forceinline__ double live_entry(double z, double g, const ColDesc& c, double* absd) {
+  const double del = (g - c.o) - c.t;
+  *absd = __builtin_fabs(del);
+  double r = __builtin_amdgcn_rcp(del);
+  double e = __builtin_fma(-del, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-del, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  const double v = (z * c.s) * r;
+  return (z == 0.0) ? 0.0 : v;
+}
+
+__device__ __forceinline__ double general_entry(int j, const RowVals& rv, const ColDesc& c) {
+  if (c.type == 0) {
+    if (rv.z == 0.0) return 0.0;
+    return (rv.z * c.s) / ((rv.g - c.o) - c.t);
+  }
+  if (c.type < 0 || rv.cl != c.cl) return 0.0;
+  return ((j == c.mem) ? 1.0 : 0.0) - 2.0 * rv.h * c.h;
+}
+
+template <bool LIVE>
+__device__ __forceinline__ double gen_entry(const CauchyDesc& d, int j, int N, const ColDesc& c, double* mind) {
+  const int jj = j < N ? j : N - 1;
+  const double zl = d.rzeta[jj];   // unconditional load (index clamped), then select
+  const double z = (j < N) ? zl : 0.0;
+  const double g = d.rg[jj];
+  if (LIVE) {
+    double ad;
+    const double v = live_entry(z, g, c, &ad);
+    *mind = __builtin_fmin(*mind, ad);
+    return v;
+  } else {
+    RowVals rv{z, g, d.rh[jj], (j < N) ? d.rcl[jj] : -2};
+    return general_entry(j, rv, c);
+  }
+}
+
+
+// XCD-aware order of the 2-D tile grid: blocks are dealt to the 8 XCDs in
+// turn, so consecutive tiles of one block row (sharing an X panel) land on
+// the same XCD and its L2.
+__device__ __forceinline__ void tile_origin(int N, int* m0, int* n0) {
+  const int tiles_n = (N + kBN - 1) / kBN;
+  const int G = gridDim.x;
+  const int bid = blockIdx.x;
+  const int full = (G / 8) * 8;
+  const int lid = (bid < full) ? (bid % 8) * (G / 8) + bid / 8 : bid;
+  *m0 = (lid / tiles_n) * kBM;
+  *n0 = (lid % tiles_n) * kBN;
+}
+
+}  // namespace svdu

@@ -1,47 +1,11 @@
-// Products with the Cauchy eigenvector matrix C~ of one eigen-update.
-//
-//  * cauchy_tmatvec: y = C~^T x for up to three vectors. It carries the
-//    projected vectors between the two eigen-updates of one side in core
-//    space (z for the second update is C~^T of the first applied to U^T b1,
-//    since U~^T b1 = C~^T U^T b1) and maps the sign probes.
-//  * gemm_cauchy_f64: X_out = X C~ (RankOneUpdate Steps 4-7, equation
-//    UCTildeProduct), FP64 MFMA with C~ regenerated tile by tile into LDS.
-#include "device_util.h"
-#include "svdu_internal.h"
+// Products with the Cauchy eigenvector matrix C~ of one eigen-update:
+// y = C~^T x for up to three vectors. It carries the projected vectors between
+// the two eigen-updates of one side in core space (z for the second update is
+// C~^T of the first applied to U^T b1, since U~^T b1 = C~^T U^T b1) and maps
+// the sign probes.
+#include "cauchy_tile.h"
 
 namespace svdu {
-
-// Entry C~[j, c] from the descriptors (see svdu_internal.h).
-struct ColDesc {
-  int type;   // -1 out of range, 0 live, 1 deflated
-  double o, t, s, h;
-  int cl, mem;
-};
-
-__device__ __forceinline__ ColDesc load_col(const CauchyDesc& d, int c) {
-  ColDesc r{-1, 0.0, 0.0, 0.0, 0.0, -1, -1};
-  if (c < d.N) {
-    r.type = d.ctype[c];
-    r.o = d.co[c];
-    r.t = d.ctau[c];
-    r.s = d.ccs[c];
-    r.h = d.ch[c];
-    r.cl = d.ccl[c];
-    r.mem = d.cmem[c];
-  }
-  return r;
-}
-
-__device__ __forceinline__ double cauchy_entry(const CauchyDesc& d, int j, const ColDesc& c) {
-  if (j >= d.N || c.type < 0) return 0.0;
-  if (c.type == 0) {
-    const double z = d.rzeta[j];
-    if (z == 0.0) return 0.0;
-    return (z * c.s) * recip((d.rg[j] - c.o) - c.t);
-  }
-  if (d.rcl[j] != c.cl) return 0.0;
-  return ((j == c.mem) ? 1.0 : 0.0) - 2.0 * d.rh[j] * c.h;
-}
 
 // ---------------------------------------------------------------------------
 // y = C~^T x
@@ -113,117 +77,6 @@ void launch_cauchy_tmatvec(const Stage& s, int nv, const double* const* x, doubl
   hipLaunchKernelGGL(householder_dots, dim3((N + 255) / 256), dim3(256), 0, st, s, nv, x[0], x1, x2);
   hipLaunchKernelGGL(cauchy_tmatvec_kernel, dim3((N + 3) / 4), dim3(256), 0, st, desc_of(s), s.hx, nv, x[0], x1,
                      x2, y[0], y1, y2);
-}
-
-// ---------------------------------------------------------------------------
-// X_out = X C~, FP64 MFMA (v_mfma_f64_16x16x4f64).
-//
-// Block tile 128 x 128, 4 waves in a 2 x 2 grid, each wave 64 x 64 = 4 x 4
-// MFMA blocks. K advances 16 at a time: the X tile (128 x 16) is loaded from
-// HBM into registers one step ahead, the C~ tile (16 x 128) is generated by
-// the VALU from O(N) descriptors (it never exists in HBM), both are staged in
-// LDS, then 64 MFMAs per wave consume them.
-//
-// MFMA operand layout (lane l): A[l % 16][l / 16], B[l / 16][l % 16];
-// result register v holds D[l / 16 + 4 v][l % 16].
-// ---------------------------------------------------------------------------
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-constexpr int kBM = 128, kBN = 128, kBK = 16;
-constexpr int kLDA = kBK + 1;  // As[m][k], padded: conflict-free column reads
-
-__global__ __launch_bounds__(256, 2) void gemm_cauchy_f64_kernel(int R, const double* __restrict__ X, int ldx,
-                                                                 CauchyDesc d, double* __restrict__ Xo,
-                                                                 int ldo) {
-  __shared__ double As[kBM * kLDA];
-  __shared__ double Bs[kBK * kBN];
-  if (*d.status & kStFatal) return;
-  const int N = d.N;
-  const int tiles_n = (N + kBN - 1) / kBN;
-  // XCD-aware order: consecutive tiles of one block row land on one XCD
-  const int G = gridDim.x;
-  const int bid = blockIdx.x;
-  const int full = (G / 8) * 8;
-  const int lid = (bid < full) ? (bid % 8) * (G / 8) + bid / 8 : bid;
-  const int m0 = (lid / tiles_n) * kBM;
-  const int n0 = (lid % tiles_n) * kBN;
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int ar = tid >> 1, ak = (tid & 1) * 8;      // X tile: row, k offset
-  const int bn = tid & 127, bk = (tid >> 7) * 8;    // C~ tile: column, k offset
-  const ColDesc cd = load_col(d, n0 + bn);
-
-  d4 acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-
-  double ra[8], rb[8];
-  const int arow = m0 + ar;
-  const double* xrow = X + (size_t)(arow < R ? arow : 0) * ldx;
-  auto loadA = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int k = k0 + ak + q;
-      ra[q] = (arow < R && k < N) ? xrow[k] : 0.0;
-    }
-  };
-  auto genB = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) rb[q] = cauchy_entry(d, k0 + bk + q, cd);
-  };
-
-  const int nk = (N + kBK - 1) / kBK;
-  loadA(0);
-  genB(0);
-  for (int kc = 0; kc < nk; ++kc) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      As[ar * kLDA + ak + q] = ra[q];
-      Bs[(bk + q) * kBN + bn] = rb[q];
-    }
-    __syncthreads();
-    if (kc + 1 < nk) loadA((kc + 1) * kBK);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      double af[4], bf[4];
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) af[mb] = As[(wm * 64 + mb * 16 + (lane & 15)) * kLDA + s * 4 + (lane >> 4)];
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) bf[nb] = Bs[(s * 4 + (lane >> 4)) * kBN + wn * 64 + nb * 16 + (lane & 15)];
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb)
-          acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mb], bf[nb], acc[mb][nb], 0, 0, 0);
-    }
-    if (kc + 1 < nk) genB((kc + 1) * kBK);
-  }
-
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-    const int col = n0 + wn * 64 + nb * 16 + (lane & 15);
-    if (col >= N) continue;
-    const double sc = d.colscale ? d.colscale[col] : 1.0;
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm * 64 + mb * 16 + (lane >> 4) + 4 * v;
-        if (row < R) Xo[(size_t)row * ldo + col] = sc * acc[mb][nb][v];
-      }
-    }
-  }
-}
-
-void launch_gemm_cauchy_f64(int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo,
-                            hipStream_t st) {
-  if (R <= 0 || d.N <= 0) return;
-  const int tm = (R + kBM - 1) / kBM, tn = (d.N + kBN - 1) / kBN;
-  hipLaunchKernelGGL(gemm_cauchy_f64_kernel, dim3(tm * tn), dim3(256), 0, st, R, X, ldx, d, Xo, ldo);
 }
 
 }  // namespace svdu

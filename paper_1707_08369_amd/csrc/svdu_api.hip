@@ -121,6 +121,7 @@ struct Layout {
   double *lamLp, *lamRp, *signs;
   double* gemv_scratch;
   size_t gemv_elems;
+  double* renorm_scratch;
   double* T;  // n x n intermediate basis
   Stage st[4];
   size_t bytes;
@@ -158,6 +159,7 @@ Layout carve_update(void* base, int m, int n) {
   L.signs = c.take<double>(n);
   L.gemv_elems = std::max(gemv_t_scratch_elems(m, m, 1), gemv_t_scratch_elems(n, n, 3));
   L.gemv_scratch = c.take<double>(L.gemv_elems);
+  L.renorm_scratch = c.take<double>(std::max(renorm_scratch_elems(m, m), renorm_scratch_elems(n, n)));
   for (int k = 0; k < 4; ++k) carve_stage(c, L.st[k], k < 2 ? m : n);
   L.T = c.take<double>((size_t)n * n);
   L.bytes = c.off + 256;
@@ -340,7 +342,7 @@ int svdu_rank1_update(int m, int n, const double* U, int ldu, const double* sigm
   if (path != SVDU_PATH_DIRECT && path != SVDU_PATH_FMM) return SVDU_EINVAL;
   if (precision != SVDU_PREC_FP64 && precision != SVDU_PREC_SPLIT32) return SVDU_EINVAL;
   if (path == SVDU_PATH_FMM && !(eps > 0.0 && eps < 1.0)) return SVDU_EINVAL;
-  if (path != SVDU_PATH_DIRECT || precision != SVDU_PREC_FP64) return SVDU_ENOTSUP;
+  if (path != SVDU_PATH_DIRECT) return SVDU_ENOTSUP;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return SVDU_EINVAL;
   const size_t ub = ((size_t)(m - 1) * ldu + m) * 8, vb = ((size_t)(n - 1) * ldv + n) * 8;
   const size_t uob = ((size_t)(m - 1) * ldu_out + m) * 8, vob = ((size_t)(n - 1) * ldv_out + n) * 8;
@@ -405,14 +407,25 @@ int svdu_rank1_update(int m, int n, const double* U, int ldu, const double* sigm
   hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, st, m, n, sLm.lam_out, L.fL1, L.fL2,
                      L.fR1, L.fR2, sigma_out, L.signs);
   ring_mark(tcall, 2, st);
-  // 6. products
-  launch_gemm_cauchy_f64(m, U, ldu, desc_of(sLp), L.T, m, st);
+  // 6. products (FP64 MFMA, or the split-FP32 precision form plus an FP64
+  //    column renormalisation of the final factors)
+  auto product = [&](int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo) {
+    if (precision == SVDU_PREC_SPLIT32)
+      launch_gemm_cauchy_split32(R, X, ldx, d, Xo, ldo, st);
+    else
+      launch_gemm_cauchy_f64(R, X, ldx, d, Xo, ldo, st);
+  };
+  product(m, U, ldu, desc_of(sLp), L.T, m);
   ring_mark(tcall, 3, st);
-  launch_gemm_cauchy_f64(m, L.T, m, desc_of(sLm), U_out, ldu_out, st);
+  product(m, L.T, m, desc_of(sLm), U_out, ldu_out);
   ring_mark(tcall, 4, st);
-  launch_gemm_cauchy_f64(n, V, ldv, desc_of(sRp), L.T, n, st);
+  product(n, V, ldv, desc_of(sRp), L.T, n);
   ring_mark(tcall, 5, st);
-  launch_gemm_cauchy_f64(n, L.T, n, desc_of(sRm, L.signs), V_out, ldv_out, st);
+  product(n, L.T, n, desc_of(sRm, L.signs), V_out, ldv_out);
+  if (precision == SVDU_PREC_SPLIT32) {
+    launch_column_renorm(m, m, U_out, ldu_out, L.renorm_scratch, L.status, st);
+    launch_column_renorm(n, n, V_out, ldv_out, L.renorm_scratch, L.status, st);
+  }
   ring_mark(tcall, 6, st);
   if (defl) {
     for (int k = 0; k < 4; ++k) {
@@ -529,6 +542,10 @@ int svdu_set_option(int option, int value) {
     const int old = g_maxit;
     g_maxit = value < 1 ? 1 : value;
     return old;
+  }
+  if (option == SVDU_OPT_GEMM_VARIANT) {
+    if (value < 1 || value > 2) return SVDU_EINVAL;
+    return set_gemm_variant(value);
   }
   if (option == SVDU_OPT_TIMING) {
     const int old = g_ring.on ? 1 : 0;

@@ -119,5 +119,12 @@ void launch_cauchy_tmatvec(const Stage& s, int nv, const double* const* x, doubl
 // X_out = X * C~ (R x N times N x N), FP64 MFMA with C~ tiles generated in LDS.
 void launch_gemm_cauchy_f64(int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo,
                             hipStream_t st);
+int set_gemm_variant(int v);  // 1: LDS for both operands, 2: X in registers (default)
+// Precision form: X_out = X * C~ as split-FP32 products with FP32 accumulation drained to FP64.
+void launch_gemm_cauchy_split32(int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo,
+                                hipStream_t st);
+// Rescales every column of X (R x N) to unit FP64 norm; scratch >= renorm_scratch_elems(R, N) doubles.
+size_t renorm_scratch_elems(int R, int N);
+void launch_column_renorm(int R, int N, double* X, int ldx, double* scratch, const int* status, hipStream_t st);
 
 }  // namespace svdu

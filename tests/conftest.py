@@ -27,3 +27,16 @@ def lib():
         pytest.skip("no GPU")
     import paper_1707_08369_amd as svdu
     return svdu
+
+
+@pytest.fixture(autouse=True)
+def _gemm_variant_from_env(request):
+    """SVDU_TEST_GEMM_VARIANT=k runs the GPU tests with product-kernel variant k."""
+    v = os.environ.get("SVDU_TEST_GEMM_VARIANT")
+    if not v or request.node.get_closest_marker("gpu") is None:
+        yield
+        return
+    import paper_1707_08369_amd as svdu
+    old = svdu.svdu_set_option(svdu.SVDU_OPT_GEMM_VARIANT, int(v))
+    yield
+    svdu.svdu_set_option(svdu.SVDU_OPT_GEMM_VARIANT, old)

@@ -285,3 +285,26 @@ def test_bitwise_deterministic_and_stream_ordered(lib):
     s.synchronize()
     for x, y in zip(r1, r2):
         assert torch.equal(x, y)
+
+
+# ---------------------------------------------------------------------------
+# precision form (split FP32 products): same roots, flags and sigma as FP64;
+# vectors within the FP32-accumulation error
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n,kind", [(256, 256, "uniform"), (300, 457, "uniform"), (512, 512, "geometric")])
+def test_precision_form_keeps_roots_and_reports_its_error(lib, m, n, kind):
+    P = S.make_problem(m, n, kind, seed=4)
+    args = (dev(P.U), dev(P.sigma), dev(P.V), dev(P.a), dev(P.b))
+    U64_, s64, V64, f64 = lib.rank1_update(*args)
+    U32, s32, V32, f32 = lib.rank1_update(*args, precision=lib.SVDU_PREC_SPLIT32)
+    assert torch.equal(s64, s32)            # no form touches roots ...
+    assert torch.equal(f64, f32)            # ... or deflation decisions
+    Ug, Vg, sg = host(U32), host(V32), host(s32)
+    Ah = O.dense_ahat(P.U, P.sigma, P.V, P.a, P.b)
+    recon = O.recon_error(Ah, Ug, sg, Vg)
+    orth = max(O.orth_error(Ug), O.orth_error(Vg))
+    # FP32 accumulation limits this form to about 1e-7 (the 1e-10 target is not
+    # reachable this way); the bound checked here is what it delivers
+    assert recon <= 5e-6 and orth <= 5e-6, (recon, orth)
+    assert np.max(np.abs(np.linalg.norm(Ug, axis=0) - 1)) <= 1e-14   # the FP64 renormalisation sweep
+    print(f"split32 m={m} n={n} {kind}: recon {recon:.2e} orth {orth:.2e}")
