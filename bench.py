@@ -117,10 +117,18 @@ def measure_forms(svdu, torch, U, sigma, V, A_vecs, B_vecs, Uo, so, Vo, ws, stre
     import numpy as np
     res = {}
     m, n = U.shape[0], V.shape[0]
-    for name, prec in (("split32", svdu.SVDU_PREC_SPLIT32),):
+    ref = None
+    if check:   # the FP64 direct result of the inputs the forms end on, for the FMM comparison
+        k = steps % A_vecs.shape[0]
+        ref = svdu.rank1_update(U, sigma, V, A_vecs[k], B_vecs[k], workspace=ws, want_defl=False, stream=stream)
+    for name, prec, path in (("split32", svdu.SVDU_PREC_SPLIT32, svdu.SVDU_PATH_DIRECT),
+                             ("fmm_eps1e-10", svdu.SVDU_PREC_FP64, svdu.SVDU_PATH_FMM)):
+        wsf = ws if path == svdu.SVDU_PATH_DIRECT else svdu.new_workspace(svdu.svdu_workspace_bytes(m, n, path),
+                                                                          U.device)
+
         def run(k):
-            svdu.rank1_update(U, sigma, V, A_vecs[k], B_vecs[k], precision=prec, out=(Uo, so, Vo), workspace=ws,
-                              want_defl=False, stream=stream, check=False)
+            svdu.rank1_update(U, sigma, V, A_vecs[k], B_vecs[k], eps=1e-10, path=path, precision=prec,
+                              out=(Uo, so, Vo), workspace=wsf, want_defl=False, stream=stream, check=False)
         run(0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -135,8 +143,12 @@ def measure_forms(svdu, torch, U, sigma, V, A_vecs, B_vecs, Uo, so, Vo, ws, stre
             rec["recon"] = ((Uo * so[None, :]) @ Vo[:, :m].T - Ah).norm().item() / Ah.norm().item()
             rec["orth_U"] = (Uo.T @ Uo - torch.eye(m, dtype=Uo.dtype, device=Uo.device)).abs().max().item()
             rec["orth_V"] = (Vo.T @ Vo - torch.eye(n, dtype=Vo.dtype, device=Vo.device)).abs().max().item()
-            rec["bound"] = 1e-10
+            rec["bound"] = 1e-10 if path == svdu.SVDU_PATH_DIRECT else 1e-9
+            if path == svdu.SVDU_PATH_FMM:
+                rec["max_abs_diff_vs_direct_U"] = (Uo - ref[0]).abs().max().item()
+                rec["max_abs_diff_vs_direct_V"] = (Vo - ref[2]).abs().max().item()
         res[name] = rec
+        del wsf
     return res
 
 

@@ -66,8 +66,12 @@ size_t svdu_workspace_bytes(int m, int n, int path, int precision);
  *  sigma       m singular values, descending, >= 0.    (input)
  *  V, ldv      n x n orthogonal, ldv >= n.             (input, not modified)
  *  a, b        update vectors of length m and n.       (input)
- *  eps         FMM tolerance (ignored by SVDU_PATH_DIRECT), 0 < eps < 1.
- *  path        SVDU_PATH_DIRECT or SVDU_PATH_FMM.
+ *  eps         FMM tolerance (ignored by SVDU_PATH_DIRECT), 0 < eps < 1; the
+ *              expansion order is p = ceil(log_5(1/eps)), at most 16.
+ *  path        SVDU_PATH_DIRECT or SVDU_PATH_FMM. The FMM path copies the
+ *              roots to the host once per call to build its trees (the call
+ *              then returns after that synchronisation of `stream`); it works
+ *              with SVDU_PREC_FP64 only.
  *  precision   SVDU_PREC_FP64 or SVDU_PREC_SPLIT32.
  *  U_out       m x m, ldu_out >= m: left singular vectors of A^, columns by
  *              descending singular value. Must not overlap U.
@@ -94,8 +98,8 @@ int svdu_rank1_update(int m, int n, const double* U, int ldu, const double* sigm
  * (the first that applies, in that order), or SVDU_EHIP. */
 int svdu_get_status(const void* workspace, void* stream);
 
-/* Bytes of workspace svdu_eig_update needs. */
-size_t svdu_eig_update_workspace_bytes(int R, int N);
+/* Bytes of workspace svdu_eig_update needs for an R x N basis and `path`. */
+size_t svdu_eig_update_workspace_bytes(int R, int N, int path);
 
 /* One symmetric rank-one eigen-update (Section 6.2, RankOneUpdate Steps 2-7)
  * of X diag(lam) X^T + rho X z z^T X^T, with the projection z = X^T v already
@@ -104,12 +108,14 @@ size_t svdu_eig_update_workspace_bytes(int R, int N);
  *  lam         N eigenvalues of the columns of X, ascending.
  *  z           N projected components.
  *  rho         host scalar, nonzero.
+ *  path, eps   SVDU_PATH_DIRECT, or SVDU_PATH_FMM with tolerance 0 < eps < 1
+ *              (the FMM path synchronises `stream` once to build its tree).
  *  X_out, ldo  R x N, ldo >= N: X C~, columns by ascending new eigenvalue.
  *  lam_out     N new eigenvalues, ascending.
  *  defl        NULL or N int8 flags (as for svdu_rank1_update).
- *  workspace   >= svdu_eig_update_workspace_bytes(R, N) bytes. */
+ *  workspace   >= svdu_eig_update_workspace_bytes(R, N, path) bytes. */
 int svdu_eig_update(int R, int N, const double* X, int ldx, const double* lam, const double* z, double rho,
-                    double* X_out, int ldo, double* lam_out, int8_t* defl, void* workspace,
+                    int path, double eps, double* X_out, int ldo, double* lam_out, int8_t* defl, void* workspace,
                     size_t workspace_bytes, void* stream);
 
 /* Roots of the secular equation w(mu) = 1 + rho sum_k z_k^2 / (d_k - mu)

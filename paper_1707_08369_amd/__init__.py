@@ -61,10 +61,10 @@ def load():
     lib.svdu_rank1_update.restype = c_int
     lib.svdu_get_status.argtypes = [c_vp, c_vp]
     lib.svdu_get_status.restype = c_int
-    lib.svdu_eig_update_workspace_bytes.argtypes = [c_int, c_int]
+    lib.svdu_eig_update_workspace_bytes.argtypes = [c_int, c_int, c_int]
     lib.svdu_eig_update_workspace_bytes.restype = c_size
-    lib.svdu_eig_update.argtypes = [c_int, c_int, c_vp, c_int, c_vp, c_vp, c_dbl, c_vp, c_int, c_vp, c_vp, c_vp,
-                                    c_size, c_vp]
+    lib.svdu_eig_update.argtypes = [c_int, c_int, c_vp, c_int, c_vp, c_vp, c_dbl, c_int, c_dbl, c_vp, c_int, c_vp,
+                                    c_vp, c_vp, c_size, c_vp]
     lib.svdu_eig_update.restype = c_int
     lib.svdu_secular_workspace_bytes.argtypes = [c_int]
     lib.svdu_secular_workspace_bytes.restype = c_size
@@ -97,13 +97,13 @@ def svdu_get_status(workspace, stream) -> int:
     return int(load().svdu_get_status(workspace, stream))
 
 
-def svdu_eig_update_workspace_bytes(R, N) -> int:
-    return int(load().svdu_eig_update_workspace_bytes(R, N))
+def svdu_eig_update_workspace_bytes(R, N, path=SVDU_PATH_DIRECT) -> int:
+    return int(load().svdu_eig_update_workspace_bytes(R, N, path))
 
 
-def svdu_eig_update(R, N, X, ldx, lam, z, rho, X_out, ldo, lam_out, defl, workspace, workspace_bytes,
+def svdu_eig_update(R, N, X, ldx, lam, z, rho, path, eps, X_out, ldo, lam_out, defl, workspace, workspace_bytes,
                     stream) -> int:
-    return int(load().svdu_eig_update(R, N, X, ldx, lam, z, rho, X_out, ldo, lam_out, defl, workspace,
+    return int(load().svdu_eig_update(R, N, X, ldx, lam, z, rho, path, eps, X_out, ldo, lam_out, defl, workspace,
                                       workspace_bytes, stream))
 
 
@@ -221,7 +221,7 @@ def rank1_update(U, sigma, V, a, b, eps=1e-10, path=SVDU_PATH_DIRECT, precision=
     return Uo, so, Vo, defl
 
 
-def eig_update(X, lam, z, rho, stream=None, check=True):
+def eig_update(X, lam, z, rho, path=SVDU_PATH_DIRECT, eps=1e-10, stream=None, check=True):
     """One RankOneUpdate: returns (X C~, new eigenvalues ascending, flags)."""
     torch = _torch()
     R, N = X.shape
@@ -231,11 +231,11 @@ def eig_update(X, lam, z, rho, stream=None, check=True):
     Xo = torch.empty((R, N), dtype=torch.float64, device=X.device)
     lo = torch.empty(N, dtype=torch.float64, device=X.device)
     fl = torch.empty(N, dtype=torch.int8, device=X.device)
-    ws = new_workspace(svdu_eig_update_workspace_bytes(R, N), X.device)
+    ws = new_workspace(svdu_eig_update_workspace_bytes(R, N, path), X.device)
     wp, wb = _aligned(ws)
     sh = _stream_handle(stream)
-    rc = svdu_eig_update(R, N, _ptr(X), ldx, _ptr(lam), _ptr(z), float(rho), _ptr(Xo), max(N, 1), _ptr(lo),
-                         _ptr(fl), wp, wb, sh)
+    rc = svdu_eig_update(R, N, _ptr(X), ldx, _ptr(lam), _ptr(z), float(rho), path, float(eps), _ptr(Xo), max(N, 1),
+                         _ptr(lo), _ptr(fl), wp, wb, sh)
     if rc != SVDU_OK:
         raise SvduError(rc, "svdu_eig_update")
     if check:

@@ -1,0 +1,591 @@
+// The product X C~ through the 1-D fast multipole method (Section 5 and
+// Appendix D of the paper), batched over all R rows of X.
+//
+// For every row r the live columns of X C~ are a Cauchy sum
+//   Y[r, c] = s_c f_r(mu_c),  f_r(y) = sum_k B[r, k] / (g_k - y),
+// over the K merged poles g_k with charges B[r, k] = sum_{j in group k}
+// zeta_j X[r, j], evaluated at the K roots mu_c. All expansion operators
+// depend on the geometry only, so they are shared by the R rows and every
+// step below is a row-batched small matrix product (rows contiguous in memory).
+//
+// Tree: count-balanced over the sorted poles (leaf size s ~ 2p, Appendix D
+// Step 2); root i sits in the leaf of pole i (the roots interlace the poles).
+// Box intervals cover the box's poles and roots. Far field: the Chebyshev
+// interpolation of Appendix D (nodes t_i = cos((2i-1) pi / 2p), Lagrange
+// basis u_j, Steps 3-4) applied with each box's own centre and radius, which
+// is what an adaptive tree needs (uniform levels fail on spectra spanning many
+// decades):
+//   P2M  W_k = sum_j B_j u_k((g_j - c)/r)                  (anterpolation)
+//   M2M  W^P_k += sum_k' W^C_k' u_k((x^C_k' - c_P)/r_P)
+//   M2L  L^T_k += sum_k' W^S_k' / (x^S_k' - y^T_k)
+//   L2L  L^C_k += sum_k' L^P_k' u_k'((y^C_k - c_P)/r_P)
+//   L2P  f_far(y) = sum_k L^T_k u_k((y - c_T)/r_T)
+// Two boxes interact through M2L when the gap between their intervals is at
+// least the larger of their widths, so every interpolation sees its nearest
+// singularity at >= 3 radii (error ~ (3 + sqrt 8)^-p per interpolation).
+// Leaf pairs that never become admissible are summed directly (P2P) with the
+// pole-relative differences (g_k - d_org) - tau of the direct path.
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "device_util.h"
+#include "fmm_plan.h"
+#include "svdu_internal.h"
+
+namespace svdu {
+
+constexpr int kP = 16;  // padded expansion length (p <= 16)
+
+// ---------------------------------------------------------------------------
+// host plan
+// ---------------------------------------------------------------------------
+__host__ __device__ static inline int box_id(int l, int k) { return (1 << l) - 1 + k; }
+
+int fmm_order(double eps) {
+  // p = ceil(log_5(1/eps)), clamped to [8, 16] (leaves of 16 to 32 poles)
+  const double p = ceil(log(1.0 / eps) / log(5.0));
+  return (int)std::min(16.0, std::max(8.0, p));
+}
+
+static void build_plan(int K, const double* g, const double* mu, int p, FmmHostPlan* P) {
+  P->p = p;
+  P->K = K;
+  P->s = 2 * p;
+  const int s = P->s;
+  const int nleaf = (K + s - 1) / s;
+  int nlev = 0;
+  while ((1 << nlev) < nleaf) ++nlev;
+  P->nlev = nlev;
+  P->nbox = (1 << (nlev + 1)) - 1;
+  P->lo.assign(P->nbox, 0.0);
+  P->hi.assign(P->nbox, 0.0);
+  P->s0.assign(P->nbox, 0);
+  P->s1.assign(P->nbox, 0);
+  P->lev_off.resize(nlev + 2);
+  for (int l = 0; l <= nlev + 1; ++l) P->lev_off[l] = (1 << l) - 1;
+  for (int b = 0; b < (1 << nlev); ++b) {
+    const int id = box_id(nlev, b);
+    const int a0 = std::min(K, b * s), a1 = std::min(K, (b + 1) * s);
+    P->s0[id] = a0;
+    P->s1[id] = a1;
+    if (a0 < a1) {
+      double lo = g[a0], hi = g[a0];
+      for (int i = a0; i < a1; ++i) {
+        lo = std::min(lo, std::min(g[i], mu[i]));
+        hi = std::max(hi, std::max(g[i], mu[i]));
+      }
+      P->lo[id] = lo;
+      P->hi[id] = hi;
+    }
+  }
+  for (int l = nlev - 1; l >= 0; --l) {
+    for (int b = 0; b < (1 << l); ++b) {
+      const int id = box_id(l, b), c0 = box_id(l + 1, 2 * b), c1 = box_id(l + 1, 2 * b + 1);
+      P->s0[id] = P->s0[c0];
+      P->s1[id] = std::max(P->s1[c0], P->s1[c1]);
+      if (P->s1[c1] > P->s0[c1] && P->s1[c0] > P->s0[c0]) {
+        P->lo[id] = std::min(P->lo[c0], P->lo[c1]);
+        P->hi[id] = std::max(P->hi[c0], P->hi[c1]);
+      } else if (P->s1[c0] > P->s0[c0]) {
+        P->lo[id] = P->lo[c0];
+        P->hi[id] = P->hi[c0];
+      }
+      if (P->s1[c1] > P->s0[c1] && P->s1[c0] <= P->s0[c0]) P->s0[id] = P->s0[c1];
+    }
+  }
+  // dual traversal: M2L lists for every box, near lists for leaves
+  std::vector<std::vector<int>> m2l(P->nbox), nearl(P->nbox);
+  auto empty = [&](int id) { return P->s1[id] <= P->s0[id]; };
+  auto adm = [&](int a, int b) {
+    if (a == b) return false;
+    const double wa = P->hi[a] - P->lo[a], wb = P->hi[b] - P->lo[b];
+    const double gap = std::max(P->lo[b] - P->hi[a], P->lo[a] - P->hi[b]);
+    return gap > 0.0 && gap >= std::max(wa, wb);
+  };
+  std::vector<std::pair<int, int>> stack;
+  stack.push_back({0, 0});
+  std::vector<int> level_of(P->nbox);
+  for (int l = 0; l <= nlev; ++l)
+    for (int b = 0; b < (1 << l); ++b) level_of[box_id(l, b)] = l;
+  while (!stack.empty()) {
+    auto [a, b] = stack.back();
+    stack.pop_back();
+    if (empty(a) || empty(b)) continue;
+    if (adm(a, b)) {
+      m2l[a].push_back(b);
+      continue;
+    }
+    const int l = level_of[a];
+    if (l == nlev) {
+      nearl[a].push_back(b);
+      continue;
+    }
+    const int ka = a - P->lev_off[l], kb = b - P->lev_off[l];
+    for (int ca = 0; ca < 2; ++ca)
+      for (int cb = 0; cb < 2; ++cb) stack.push_back({box_id(l + 1, 2 * ka + ca), box_id(l + 1, 2 * kb + cb)});
+  }
+  P->m2l_ptr.assign(P->nbox + 1, 0);
+  P->near_ptr.assign(P->nbox + 1, 0);
+  for (int i = 0; i < P->nbox; ++i) {
+    std::sort(m2l[i].begin(), m2l[i].end());
+    std::sort(nearl[i].begin(), nearl[i].end());
+    P->m2l_ptr[i + 1] = P->m2l_ptr[i] + (int)m2l[i].size();
+    P->near_ptr[i + 1] = P->near_ptr[i] + (int)nearl[i].size();
+  }
+  P->m2l_src.clear();
+  P->near_src.clear();
+  for (int i = 0; i < P->nbox; ++i) {
+    P->m2l_src.insert(P->m2l_src.end(), m2l[i].begin(), m2l[i].end());
+    P->near_src.insert(P->near_src.end(), nearl[i].begin(), nearl[i].end());
+  }
+}
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+struct FmmDev {
+  int p, s, K, nlev, nbox, R;
+  const double* lo;
+  const double* hi;
+  const int* s0;
+  const int* s1;
+  const int* m2l_ptr;
+  const int* m2l_src;
+  const int* near_ptr;
+  const int* near_src;
+  double* B;   // [K][R] charges
+  double* W;   // [nbox][kP][R] far-field coefficients
+  double* L;   // [nbox][kP][R] local coefficients
+};
+
+__device__ __forceinline__ double cheb_node(int k, int p) { return cos((2.0 * k + 1.0) * M_PI / (2.0 * p)); }
+
+// Chebyshev nodes t_k (Appendix D Step 3) and the inverse node differences
+// 1/(t_k - t_m), built once per block in LDS; then each Lagrange basis value
+// u_k(t) = prod_{m != k} (t - t_m) / (t_k - t_m) (Step 4) costs p multiplies.
+struct ChebTab {
+  double t[kP];
+  double inv[kP * kP];
+};
+
+__device__ __forceinline__ void cheb_fill(ChebTab* T, int p) {
+  for (int e = threadIdx.x; e < p; e += blockDim.x) T->t[e] = cheb_node(e, p);
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int k = e / p, m = e - k * p;
+    T->inv[k * kP + m] = (k == m) ? 0.0 : 1.0 / (cheb_node(k, p) - cheb_node(m, p));
+  }
+}
+
+__device__ __forceinline__ double lagrange(const ChebTab& T, int k, int p, double x) {
+  double v = 1.0;
+  for (int m = 0; m < p; ++m)
+    if (m != k) v *= (x - T.t[m]) * T.inv[k * kP + m];
+  return v;
+}
+
+__device__ __forceinline__ void box_cr(const FmmDev& F, int id, double* c, double* r) {
+  const double lo = F.lo[id], hi = F.hi[id];
+  *c = 0.5 * (lo + hi);
+  *r = fmax(0.5 * (hi - lo), fmax(fabs(*c) * 1e-14, 1e-300));
+}
+
+// ---------------------------------------------------------------------------
+// charges B[k][r] = sum_{j in group k} zeta_j X[r, j]  (transpose through LDS)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fmm_charges(int R, const double* __restrict__ X, int ldx, Stage s,
+                                                   double* __restrict__ B) {
+  __shared__ double tile[32][33];
+  if (*s.status & kStFatal) return;
+  const int K = s.counts[0];
+  const int k0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int rr = ty; rr < 32; rr += 8) {
+    const int r = r0 + rr, k = k0 + tx;
+    double v = 0.0;
+    if (r < R && k < K) {
+      const int f = s.cfirst[k], sz = s.csize[k];
+      for (int q = f; q < f + sz; ++q) {
+        const int j = s.col_of[s.Llist[q]];
+        v += s.rzeta[j] * X[(size_t)r * ldx + j];
+      }
+    }
+    tile[rr][tx] = v;
+  }
+  __syncthreads();
+  for (int kk = ty; kk < 32; kk += 8) {
+    const int k = k0 + kk, r = r0 + tx;
+    if (k < K && r < R) B[(size_t)k * R + r] = tile[tx][kk];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// P2M on the leaves: W[leaf][kk][r] = sum_{k in leaf} B[k][r] u_kk((g_k - c)/r)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fmm_p2m(FmmDev F, const double* __restrict__ g, const int* status) {
+  __shared__ double op[32 * kP];   // [source in leaf][kk], at most 32 sources
+  __shared__ ChebTab T;
+  if (*status & kStFatal) return;
+  const int id = box_id(F.nlev, blockIdx.x);
+  const int a0 = F.s0[id], a1 = F.s1[id];
+  if (a1 <= a0) return;
+  double c, rad;
+  box_cr(F, id, &c, &rad);
+  const int ns = a1 - a0;
+  cheb_fill(&T, F.p);
+  __syncthreads();
+  for (int e = threadIdx.x; e < ns * F.p; e += blockDim.x) {
+    const int j = e / F.p, kk = e - j * F.p;
+    op[j * kP + kk] = lagrange(T, kk, F.p, (g[a0 + j] - c) / rad);
+  }
+  __syncthreads();
+  const int r = blockIdx.y * blockDim.x + threadIdx.x;
+  if (r >= F.R) return;
+  double acc[kP];
+#pragma unroll
+  for (int kk = 0; kk < kP; ++kk) acc[kk] = 0.0;
+  for (int j = 0; j < ns; ++j) {
+    const double b = F.B[(size_t)(a0 + j) * F.R + r];
+#pragma unroll
+    for (int kk = 0; kk < kP; ++kk)
+      if (kk < F.p) acc[kk] += b * op[j * kP + kk];
+  }
+  double* w = F.W + (size_t)id * kP * F.R + r;
+#pragma unroll
+  for (int kk = 0; kk < kP; ++kk)
+    if (kk < F.p) w[(size_t)kk * F.R] = acc[kk];
+}
+
+// ---------------------------------------------------------------------------
+// M2M for one level: parent W from its (non-empty) children
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fmm_m2m(FmmDev F, int level, const int* status) {
+  __shared__ double op[2][kP * kP];   // [child][kk_parent][kk_child]
+  __shared__ int has[2];
+  __shared__ ChebTab T;
+  if (*status & kStFatal) return;
+  const int id = box_id(level, blockIdx.x);
+  if (F.s1[id] <= F.s0[id]) return;
+  double cp, rp;
+  box_cr(F, id, &cp, &rp);
+  const int ch[2] = {box_id(level + 1, 2 * blockIdx.x), box_id(level + 1, 2 * blockIdx.x + 1)};
+  if (threadIdx.x < 2) has[threadIdx.x] = F.s1[ch[threadIdx.x]] > F.s0[ch[threadIdx.x]];
+  cheb_fill(&T, F.p);
+  __syncthreads();
+  for (int e = threadIdx.x; e < 2 * F.p * F.p; e += blockDim.x) {
+    const int q = e / (F.p * F.p), rem = e - q * F.p * F.p, kp = rem / F.p, kc = rem - kp * F.p;
+    double cc, rc;
+    box_cr(F, ch[q], &cc, &rc);
+    const double xc = cc + rc * T.t[kc];
+    op[q][kp * kP + kc] = lagrange(T, kp, F.p, (xc - cp) / rp);
+  }
+  __syncthreads();
+  const int r = blockIdx.y * blockDim.x + threadIdx.x;
+  if (r >= F.R) return;
+  double acc[kP];
+#pragma unroll
+  for (int kk = 0; kk < kP; ++kk) acc[kk] = 0.0;
+  for (int q = 0; q < 2; ++q) {
+    if (!has[q]) continue;
+    const double* w = F.W + (size_t)ch[q] * kP * F.R + r;
+    for (int kc = 0; kc < F.p; ++kc) {
+      const double v = w[(size_t)kc * F.R];
+#pragma unroll
+      for (int kp = 0; kp < kP; ++kp)
+        if (kp < F.p) acc[kp] += op[q][kp * kP + kc] * v;
+    }
+  }
+  double* o = F.W + (size_t)id * kP * F.R + r;
+#pragma unroll
+  for (int kk = 0; kk < kP; ++kk)
+    if (kk < F.p) o[(size_t)kk * F.R] = acc[kk];
+}
+
+// ---------------------------------------------------------------------------
+// Downward pass for one level: L[T] = L2L(L[parent]) + sum_S M2L(W[S])
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fmm_down(FmmDev F, int level, const int* status) {
+  __shared__ double op[kP * kP];
+  __shared__ ChebTab T;
+  if (*status & kStFatal) return;
+  const int id = box_id(level, blockIdx.x);
+  if (F.s1[id] <= F.s0[id]) return;
+  const int r = blockIdx.y * blockDim.x + threadIdx.x;
+  double ct, rt;
+  box_cr(F, id, &ct, &rt);
+  cheb_fill(&T, F.p);
+  __syncthreads();
+  double acc[kP];
+#pragma unroll
+  for (int kk = 0; kk < kP; ++kk) acc[kk] = 0.0;
+  if (level > 0) {
+    const int par = box_id(level - 1, blockIdx.x >> 1);
+    double cp, rp;
+    box_cr(F, par, &cp, &rp);
+    for (int e = threadIdx.x; e < F.p * F.p; e += blockDim.x) {
+      const int kc = e / F.p, kp = e - kc * F.p;
+      const double y = ct + rt * T.t[kc];
+      op[kc * kP + kp] = lagrange(T, kp, F.p, (y - cp) / rp);
+    }
+    __syncthreads();
+    if (r < F.R) {
+      const double* lp = F.L + (size_t)par * kP * F.R + r;
+      for (int kp = 0; kp < F.p; ++kp) {
+        const double v = lp[(size_t)kp * F.R];
+#pragma unroll
+        for (int kc = 0; kc < kP; ++kc)
+          if (kc < F.p) acc[kc] += op[kc * kP + kp] * v;
+      }
+    }
+    __syncthreads();
+  }
+  for (int q = F.m2l_ptr[id]; q < F.m2l_ptr[id + 1]; ++q) {
+    const int src = F.m2l_src[q];
+    double cs, rs;
+    box_cr(F, src, &cs, &rs);
+    for (int e = threadIdx.x; e < F.p * F.p; e += blockDim.x) {
+      const int kt = e / F.p, ks = e - kt * F.p;
+      const double y = ct + rt * T.t[kt];
+      const double x = cs + rs * T.t[ks];
+      op[kt * kP + ks] = 1.0 / (x - y);
+    }
+    __syncthreads();
+    if (r < F.R) {
+      const double* w = F.W + (size_t)src * kP * F.R + r;
+      for (int ks = 0; ks < F.p; ++ks) {
+        const double v = w[(size_t)ks * F.R];
+#pragma unroll
+        for (int kt = 0; kt < kP; ++kt)
+          if (kt < F.p) acc[kt] += op[kt * kP + ks] * v;
+      }
+    }
+    __syncthreads();
+  }
+  if (r < F.R) {
+    double* o = F.L + (size_t)id * kP * F.R + r;
+#pragma unroll
+    for (int kk = 0; kk < kP; ++kk)
+      if (kk < F.p) o[(size_t)kk * F.R] = acc[kk];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Leaves: L2P + P2P, scaled by the column scale, written to the output
+// positions of the roots. A leaf holds at most kS = 32 poles and roots.
+// ---------------------------------------------------------------------------
+constexpr int kS = 32;
+
+__global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* __restrict__ Xo, int ldo,
+                                                      const double* __restrict__ colscale) {
+  __shared__ double ul[kS * kP];     // L2P weights [target][kk]
+  __shared__ double inv[kS * kS];    // 1/delta [near source][target]
+  __shared__ double out[64 * (kS + 1)];   // results of 64 rows, staged for row-wise stores
+  __shared__ int pos[kS];
+  __shared__ double scl[kS];
+  __shared__ ChebTab T;
+  if (*s.status & kStFatal) return;
+  const int id = box_id(F.nlev, blockIdx.x);
+  const int a0 = F.s0[id], a1 = F.s1[id];
+  if (a1 <= a0) return;
+  const int nt = a1 - a0;
+  const int r = blockIdx.y * blockDim.x + threadIdx.x;
+  double ct, rt;
+  box_cr(F, id, &ct, &rt);
+  cheb_fill(&T, F.p);
+  __syncthreads();
+  for (int e = threadIdx.x; e < nt * F.p; e += blockDim.x) {
+    const int t = e / F.p, kk = e - t * F.p;
+    ul[t * kP + kk] = lagrange(T, kk, F.p, (s.mu[a0 + t] - ct) / rt);
+  }
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+    const int P = s.rootpos[a0 + t];
+    pos[t] = P;
+    scl[t] = (colscale ? colscale[P] : 1.0) * s.cs[a0 + t];
+  }
+  __syncthreads();
+  double acc[kS];
+#pragma unroll
+  for (int t = 0; t < kS; ++t) acc[t] = 0.0;
+  if (r < F.R) {
+    const double* l = F.L + (size_t)id * kP * F.R + r;
+    for (int kk = 0; kk < F.p; ++kk) {
+      const double v = l[(size_t)kk * F.R];
+#pragma unroll
+      for (int t = 0; t < kS; ++t)
+        if (t < nt) acc[t] += ul[t * kP + kk] * v;
+    }
+  }
+  for (int q = F.near_ptr[id]; q < F.near_ptr[id + 1]; ++q) {
+    const int nbx = F.near_src[q];
+    const int b0 = F.s0[nbx], ns = F.s1[nbx] - b0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < ns * nt; e += blockDim.x) {
+      const int j = e / nt, t = e - j * nt;
+      const int k = b0 + j, i = a0 + t;
+      inv[j * kS + t] = 1.0 / ((s.g[k] - s.g[s.org[i]]) - s.tau[i]);
+    }
+    __syncthreads();
+    if (r < F.R) {
+      for (int j = 0; j < ns; ++j) {
+        const double bv = F.B[(size_t)(b0 + j) * F.R + r];
+#pragma unroll
+        for (int t = 0; t < kS; ++t)
+          if (t < nt) acc[t] += bv * inv[j * kS + t];
+      }
+    }
+  }
+  // stores: 64 rows at a time through LDS so that each row's nt outputs are
+  // written by consecutive lanes
+  const int rb0 = blockIdx.y * blockDim.x;
+  for (int g0 = 0; g0 < (int)blockDim.x; g0 += 64) {
+    __syncthreads();
+    if ((int)threadIdx.x >= g0 && (int)threadIdx.x < g0 + 64) {
+#pragma unroll
+      for (int t = 0; t < kS; ++t)
+        if (t < nt) out[(threadIdx.x - g0) * (kS + 1) + t] = scl[t] * acc[t];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * nt; e += blockDim.x) {
+      const int rr = e / nt, t = e - rr * nt;
+      const int row = rb0 + g0 + rr;
+      if (row < F.R) Xo[(size_t)row * ldo + pos[t]] = out[rr * (kS + 1) + t];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Deflated output columns: Xo[r, c] = X[r, mem] - 2 h_c sum_{j in group} rh_j X[r, j]
+// ---------------------------------------------------------------------------
+__global__ void fmm_group_dots(int R, const double* __restrict__ X, int ldx, Stage s, double* __restrict__ hX) {
+  if (*s.status & kStFatal) return;
+  const int c = blockIdx.x;
+  const int K = s.counts[0];
+  if (c >= K || s.csize[c] < 2) return;
+  const int r = blockIdx.y * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int f = s.cfirst[c], sz = s.csize[c];
+  double a = 0.0;
+  for (int q = f; q < f + sz; ++q) {
+    const int j = s.col_of[s.Llist[q]];
+    a += s.rh[j] * X[(size_t)r * ldx + j];
+  }
+  hX[(size_t)c * R + r] = a;
+}
+
+__global__ void fmm_deflated_cols(int R, const double* __restrict__ X, int ldx, Stage s,
+                                  const double* __restrict__ hX, double* __restrict__ Xo, int ldo,
+                                  const double* __restrict__ colscale) {
+  if (*s.status & kStFatal) return;
+  const int Kd = s.counts[1], K = s.counts[0];
+  const int r = blockIdx.y * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  for (int kd = blockIdx.x; kd < Kd; kd += gridDim.x) {
+    const int P = s.dpos[kd];
+    const int mem = s.cmem[P], cl = s.ccl[P];
+    const double h = s.ch[P];
+    double v = X[(size_t)r * ldx + mem];
+    if (h != 0.0 && cl >= 0 && cl < K) v -= 2.0 * h * hX[(size_t)cl * R + r];
+    Xo[(size_t)r * ldo + P] = (colscale ? colscale[P] : 1.0) * v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side: plan building, upload and launch
+// ---------------------------------------------------------------------------
+static size_t tree_boxes(int N) {
+  const int s = 16;  // smallest leaf (p = 8)
+  const int nleaf = (N + s - 1) / s;
+  int nlev = 0;
+  while ((1 << nlev) < nleaf) ++nlev;
+  return (size_t(1) << (nlev + 1)) - 1;
+}
+
+size_t fmm_workspace_elems(int R, int N) {
+  // charges B (N R) + W and L (nbox kP R each) + group dot products (N R, by group id)
+  return (size_t)N * R + 2 * tree_boxes(N) * kP * (size_t)R + (size_t)N * R;
+}
+
+size_t fmm_plan_bytes(int N) {
+  const size_t nbox = tree_boxes(N);
+  // intervals, ranges, CSR pointers, and list space (<= 64 entries per box)
+  return sizeof(double) * 2 * nbox + sizeof(int) * (4 * nbox + 2 + 2 * 64 * nbox) + 16 * 256;
+}
+
+// Builds the plan of one product from host copies of the stage's poles g (K)
+// and roots mu (K) and appends its arrays to `blob` (256-byte aligned pieces).
+void fmm_prepare(int K, const double* g_host, const double* mu_host, double eps, std::vector<char>* blob,
+                 FmmPrepared* out) {
+  const int p = fmm_order(eps);
+  if (K > 0) build_plan(K, g_host, mu_host, p, &out->P);
+  out->P.p = p;
+  out->P.K = K;
+  const FmmHostPlan& P = out->P;
+  auto add = [&](const void* src, size_t bytes) {
+    size_t o = (blob->size() + 255) & ~size_t(255);
+    blob->resize(o + bytes);
+    if (bytes) std::memcpy(blob->data() + o, src, bytes);
+    return o;
+  };
+  const size_t nb = P.nbox;
+  out->off[0] = add(P.lo.data(), nb * sizeof(double));
+  out->off[1] = add(P.hi.data(), nb * sizeof(double));
+  out->off[2] = add(P.s0.data(), nb * sizeof(int));
+  out->off[3] = add(P.s1.data(), nb * sizeof(int));
+  out->off[4] = add(P.m2l_ptr.data(), P.m2l_ptr.size() * sizeof(int));
+  out->off[5] = add(P.m2l_src.data(), P.m2l_src.size() * sizeof(int));
+  out->off[6] = add(P.near_ptr.data(), P.near_ptr.size() * sizeof(int));
+  out->off[7] = add(P.near_src.data(), P.near_src.size() * sizeof(int));
+}
+
+// Enqueues the FMM product X_out = X C~ for stage `s` with a prepared plan
+// whose arrays sit at `plan_dev` (the uploaded blob). Returns 0 or -2 when the
+// workspace is too small.
+int fmm_launch(int R, const double* X, int ldx, const Stage& s, const FmmPrepared& pp, const char* plan_dev,
+               double* Xo, int ldo, const double* colscale, double* work, size_t work_elems, hipStream_t st) {
+  const FmmHostPlan& P = pp.P;
+  const int N = s.N, K = P.K;
+  if (R <= 0 || N <= 0) return 0;
+  const size_t nb = P.nbox;
+  FmmDev F{};
+  F.p = P.p;
+  F.s = P.s;
+  F.K = K;
+  F.nlev = P.nlev;
+  F.nbox = P.nbox;
+  F.R = R;
+  F.lo = reinterpret_cast<const double*>(plan_dev + pp.off[0]);
+  F.hi = reinterpret_cast<const double*>(plan_dev + pp.off[1]);
+  F.s0 = reinterpret_cast<const int*>(plan_dev + pp.off[2]);
+  F.s1 = reinterpret_cast<const int*>(plan_dev + pp.off[3]);
+  F.m2l_ptr = reinterpret_cast<const int*>(plan_dev + pp.off[4]);
+  F.m2l_src = reinterpret_cast<const int*>(plan_dev + pp.off[5]);
+  F.near_ptr = reinterpret_cast<const int*>(plan_dev + pp.off[6]);
+  F.near_src = reinterpret_cast<const int*>(plan_dev + pp.off[7]);
+  const size_t hx_elems = (size_t)N * R;   // indexed by group id < K <= N
+  if ((size_t)K * R + 2 * nb * kP * (size_t)R + hx_elems > work_elems) return -2;
+  F.B = work;
+  F.W = work + (size_t)K * R;
+  F.L = F.W + nb * kP * (size_t)R;
+  double* hX = work + (work_elems - hx_elems);
+  const int rb = (R + 255) / 256;
+  if (K > 0) {
+    hipLaunchKernelGGL(fmm_charges, dim3((K + 31) / 32, (R + 31) / 32), dim3(256), 0, st, R, X, ldx, s, F.B);
+    hipLaunchKernelGGL(fmm_p2m, dim3(1 << P.nlev, rb), dim3(256), 0, st, F, s.g, s.status);
+    for (int l = P.nlev - 1; l >= 0; --l)
+      hipLaunchKernelGGL(fmm_m2m, dim3(1 << l, rb), dim3(256), 0, st, F, l, s.status);
+    for (int l = 0; l <= P.nlev; ++l)
+      hipLaunchKernelGGL(fmm_down, dim3(1 << l, rb), dim3(256), 0, st, F, l, s.status);
+    hipLaunchKernelGGL(fmm_leaf_eval, dim3(1 << P.nlev, rb), dim3(256), 0, st, F, s, Xo, ldo, colscale);
+  }
+  if (K < N) {
+    hipLaunchKernelGGL(fmm_group_dots, dim3(std::max(K, 1), rb), dim3(256), 0, st, R, X, ldx, s, hX);
+    hipLaunchKernelGGL(fmm_deflated_cols, dim3(std::min(N - K, 4096), rb), dim3(256), 0, st, R, X, ldx, s, hX,
+                       Xo, ldo, colscale);
+  }
+  return 0;
+}
+
+}  // namespace svdu

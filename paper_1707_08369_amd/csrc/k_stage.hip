@@ -437,6 +437,7 @@ __global__ void merge_kernel(Stage s) {
     const double v = s.mu[idx];
     const int pos = idx + count_less(s.dval, Kd, v);
     const int P = s.descending ? N - 1 - pos : pos;
+    s.rootpos[idx] = P;
     s.lam_out[P] = v;
     s.ctype[P] = 0;
     s.co[P] = s.g[s.org[idx]];
@@ -452,6 +453,7 @@ __global__ void merge_kernel(Stage s) {
     const int P = s.descending ? N - 1 - pos : pos;
     const int t = s.dlist[kd];
     const int j = s.col_of[t];
+    s.dpos[kd] = P;
     s.lam_out[P] = v;
     s.ctype[P] = 1;
     s.co[P] = 0.0;

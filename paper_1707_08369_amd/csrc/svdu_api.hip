@@ -21,9 +21,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "../../include/svdu.h"
 #include "device_util.h"
+#include "fmm_plan.h"
 #include "svdu_internal.h"
 
 namespace svdu {
@@ -109,6 +111,8 @@ void carve_stage(Carver& c, Stage& s, int cap) {
   s.lam_out = c.take<double>(n);
   s.hx = c.take<double>(3 * n);
   s.col_of = c.take<int>(n);
+  s.rootpos = c.take<int>(n);
+  s.dpos = c.take<int>(n);
 }
 
 // Everything svdu_rank1_update keeps in the workspace.
@@ -124,10 +128,14 @@ struct Layout {
   double* renorm_scratch;
   double* T;  // n x n intermediate basis
   Stage st[4];
+  double* fmm_work;     // FMM path only
+  size_t fmm_elems;
+  char* fmm_plan;
+  size_t fmm_plan_bytes;
   size_t bytes;
 };
 
-Layout carve_update(void* base, int m, int n) {
+Layout carve_update(void* base, int m, int n, int path) {
   Layout L;
   Carver c(base);
   L.status = c.take<int>(16);
@@ -162,6 +170,10 @@ Layout carve_update(void* base, int m, int n) {
   L.renorm_scratch = c.take<double>(std::max(renorm_scratch_elems(m, m), renorm_scratch_elems(n, n)));
   for (int k = 0; k < 4; ++k) carve_stage(c, L.st[k], k < 2 ? m : n);
   L.T = c.take<double>((size_t)n * n);
+  L.fmm_elems = (path == SVDU_PATH_FMM) ? fmm_workspace_elems(n, n) : 0;
+  L.fmm_work = c.take<double>(L.fmm_elems);
+  L.fmm_plan_bytes = (path == SVDU_PATH_FMM) ? 4 * fmm_plan_bytes(n) : 0;
+  L.fmm_plan = c.take<char>(L.fmm_plan_bytes);
   L.bytes = c.off + 256;
   return L;
 }
@@ -318,6 +330,86 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
 
 int hip_ok() { return hipGetLastError() == hipSuccess ? SVDU_OK : SVDU_EHIP; }
 
+// Host copies of one stage's roots, for the FMM plans.
+struct HostRoots {
+  int counts[4];
+  std::vector<double> g, tau;
+  std::vector<int> org;
+};
+
+void enqueue_root_copies(const Stage& s, HostRoots* h, hipStream_t st) {
+  h->g.resize(s.N);
+  h->tau.resize(s.N);
+  h->org.resize(s.N);
+  (void)hipMemcpyAsync(h->counts, s.counts, sizeof(h->counts), hipMemcpyDeviceToHost, st);
+  (void)hipMemcpyAsync(h->g.data(), s.g, s.N * sizeof(double), hipMemcpyDeviceToHost, st);
+  (void)hipMemcpyAsync(h->tau.data(), s.tau, s.N * sizeof(double), hipMemcpyDeviceToHost, st);
+  (void)hipMemcpyAsync(h->org.data(), s.org, s.N * sizeof(int), hipMemcpyDeviceToHost, st);
+}
+
+// The four products through the FMM. One host round trip: the roots of all
+// four eigen-updates come to the host, the tree plans are built and uploaded
+// in one copy, then the kernels are enqueued.
+int fmm_products_impl(int nst, Stage* stages, const int* Rs, const double* const* Xs, const int* ldxs,
+                      double* const* Xos, const int* ldos, const double* const* scales, const int* status_dev,
+                      double* work, size_t work_elems, char* plan_dev, size_t plan_bytes, double eps,
+                      std::vector<int> marks, int tcall, hipStream_t st) {
+  std::vector<HostRoots> h(nst);
+  int status = 0;
+  (void)hipMemcpyAsync(&status, status_dev, sizeof(int), hipMemcpyDeviceToHost, st);
+  for (int k = 0; k < nst; ++k) enqueue_root_copies(stages[k], &h[k], st);
+  if (hipStreamSynchronize(st) != hipSuccess) return SVDU_EHIP;
+  if (status & kStFatal) return SVDU_OK;   // reported by svdu_get_status
+  std::vector<char> blob;
+  std::vector<FmmPrepared> prep(nst);
+  for (int k = 0; k < nst; ++k) {
+    const int K = h[k].counts[0];
+    std::vector<double> mu(K);
+    for (int i = 0; i < K; ++i) mu[i] = h[k].g[h[k].org[i]] + h[k].tau[i];
+    fmm_prepare(K, h[k].g.data(), mu.data(), eps, &blob, &prep[k]);
+  }
+  if (blob.size() > plan_bytes) return SVDU_ENOMEM;
+  if (!blob.empty()) {
+    if (hipMemcpyAsync(plan_dev, blob.data(), blob.size(), hipMemcpyHostToDevice, st) != hipSuccess) return SVDU_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return SVDU_EHIP;   // blob is a host temporary
+  }
+  for (int k = 0; k < nst; ++k) {
+    if (fmm_launch(Rs[k], Xs[k], ldxs[k], stages[k], prep[k], plan_dev, Xos[k], ldos[k], scales[k], work,
+                   work_elems, st) != 0)
+      return SVDU_ENOMEM;
+    if (k < (int)marks.size()) ring_mark(tcall, marks[k], st);
+  }
+  return SVDU_OK;
+}
+
+int fmm_products(Layout& L, int m, int n, const double* U, int ldu, const double* V, int ldv, double* U_out,
+                 int ldu_out, double* V_out, int ldv_out, double eps, int tcall, hipStream_t st) {
+  // the two sides share the intermediate T, so they run one after the other
+  {
+    Stage st2[2] = {L.st[0], L.st[1]};
+    const int Rs[2] = {m, m};
+    const double* Xs[2] = {U, L.T};
+    const int ldx[2] = {ldu, m};
+    double* Xo[2] = {L.T, U_out};
+    const int ldo[2] = {m, ldu_out};
+    const double* sc[2] = {nullptr, nullptr};
+    const int rc = fmm_products_impl(2, st2, Rs, Xs, ldx, Xo, ldo, sc, L.status, L.fmm_work, L.fmm_elems,
+                                     L.fmm_plan, L.fmm_plan_bytes, eps, {3, 4}, tcall, st);
+    if (rc != SVDU_OK) return rc;
+  }
+  {
+    Stage st2[2] = {L.st[2], L.st[3]};
+    const int Rs[2] = {n, n};
+    const double* Xs[2] = {V, L.T};
+    const int ldx[2] = {ldv, n};
+    double* Xo[2] = {L.T, V_out};
+    const int ldo[2] = {n, ldv_out};
+    const double* sc[2] = {nullptr, L.signs};
+    return fmm_products_impl(2, st2, Rs, Xs, ldx, Xo, ldo, sc, L.status, L.fmm_work, L.fmm_elems, L.fmm_plan,
+                             L.fmm_plan_bytes, eps, {5, 6}, tcall, st);
+  }
+}
+
 }  // namespace
 }  // namespace svdu
 
@@ -329,7 +421,7 @@ size_t svdu_workspace_bytes(int m, int n, int path, int precision) {
   (void)path;
   (void)precision;
   if (m < 1 || n < m) return 0;
-  return carve_update(nullptr, m, n).bytes;
+  return carve_update(nullptr, m, n, path).bytes;
 }
 
 int svdu_rank1_update(int m, int n, const double* U, int ldu, const double* sigma, const double* V, int ldv,
@@ -342,13 +434,13 @@ int svdu_rank1_update(int m, int n, const double* U, int ldu, const double* sigm
   if (path != SVDU_PATH_DIRECT && path != SVDU_PATH_FMM) return SVDU_EINVAL;
   if (precision != SVDU_PREC_FP64 && precision != SVDU_PREC_SPLIT32) return SVDU_EINVAL;
   if (path == SVDU_PATH_FMM && !(eps > 0.0 && eps < 1.0)) return SVDU_EINVAL;
-  if (path != SVDU_PATH_DIRECT) return SVDU_ENOTSUP;
+  if (path == SVDU_PATH_FMM && precision != SVDU_PREC_FP64) return SVDU_ENOTSUP;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return SVDU_EINVAL;
   const size_t ub = ((size_t)(m - 1) * ldu + m) * 8, vb = ((size_t)(n - 1) * ldv + n) * 8;
   const size_t uob = ((size_t)(m - 1) * ldu_out + m) * 8, vob = ((size_t)(n - 1) * ldv_out + n) * 8;
   if (overlaps(U, ub, U_out, uob) || overlaps(V, vb, V_out, vob) || overlaps(U_out, uob, V_out, vob))
     return SVDU_EINVAL;
-  Layout L = carve_update(workspace, m, n);
+  Layout L = carve_update(workspace, m, n, path);
   if (workspace_bytes < L.bytes) return SVDU_ENOMEM;
   if (overlaps(workspace, L.bytes, U_out, uob) || overlaps(workspace, L.bytes, V_out, vob)) return SVDU_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -407,24 +499,29 @@ int svdu_rank1_update(int m, int n, const double* U, int ldu, const double* sigm
   hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, st, m, n, sLm.lam_out, L.fL1, L.fL2,
                      L.fR1, L.fR2, sigma_out, L.signs);
   ring_mark(tcall, 2, st);
-  // 6. products (FP64 MFMA, or the split-FP32 precision form plus an FP64
-  //    column renormalisation of the final factors)
-  auto product = [&](int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo) {
-    if (precision == SVDU_PREC_SPLIT32)
-      launch_gemm_cauchy_split32(R, X, ldx, d, Xo, ldo, st);
-    else
-      launch_gemm_cauchy_f64(R, X, ldx, d, Xo, ldo, st);
-  };
-  product(m, U, ldu, desc_of(sLp), L.T, m);
-  ring_mark(tcall, 3, st);
-  product(m, L.T, m, desc_of(sLm), U_out, ldu_out);
-  ring_mark(tcall, 4, st);
-  product(n, V, ldv, desc_of(sRp), L.T, n);
-  ring_mark(tcall, 5, st);
-  product(n, L.T, n, desc_of(sRm, L.signs), V_out, ldv_out);
-  if (precision == SVDU_PREC_SPLIT32) {
-    launch_column_renorm(m, m, U_out, ldu_out, L.renorm_scratch, L.status, st);
-    launch_column_renorm(n, n, V_out, ldv_out, L.renorm_scratch, L.status, st);
+  // 6. products: FP64 MFMA (direct), split-FP32 MFMA plus an FP64 column
+  //    renormalisation (precision form), or the row-batched FMM
+  if (path == SVDU_PATH_FMM) {
+    const int rc = fmm_products(L, m, n, U, ldu, V, ldv, U_out, ldu_out, V_out, ldv_out, eps, tcall, st);
+    if (rc != SVDU_OK) return rc;
+  } else {
+    auto product = [&](int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo) {
+      if (precision == SVDU_PREC_SPLIT32)
+        launch_gemm_cauchy_split32(R, X, ldx, d, Xo, ldo, st);
+      else
+        launch_gemm_cauchy_f64(R, X, ldx, d, Xo, ldo, st);
+    };
+    product(m, U, ldu, desc_of(sLp), L.T, m);
+    ring_mark(tcall, 3, st);
+    product(m, L.T, m, desc_of(sLm), U_out, ldu_out);
+    ring_mark(tcall, 4, st);
+    product(n, V, ldv, desc_of(sRp), L.T, n);
+    ring_mark(tcall, 5, st);
+    product(n, L.T, n, desc_of(sRm, L.signs), V_out, ldv_out);
+    if (precision == SVDU_PREC_SPLIT32) {
+      launch_column_renorm(m, m, U_out, ldu_out, L.renorm_scratch, L.status, st);
+      launch_column_renorm(n, n, V_out, ldv_out, L.renorm_scratch, L.status, st);
+    }
   }
   ring_mark(tcall, 6, st);
   if (defl) {
@@ -462,47 +559,70 @@ int svdu_get_status(const void* workspace, void* stream) {
   return SVDU_OK;
 }
 
-static Stage carve_eig(void* ws, int N, int** status, size_t* bytes) {
-  Carver c(ws);
-  int* s = c.take<int>(16);
+struct EigLayout {
   Stage st;
-  carve_stage(c, st, N);
-  st.N = N;
-  if (status) *status = s;
-  *bytes = c.off + 256;
-  return st;
+  int* status;
+  double* fmm_work;
+  size_t fmm_elems;
+  char* fmm_plan;
+  size_t fmm_plan_bytes;
+  size_t bytes;
+};
+
+static EigLayout carve_eig(void* ws, int R, int N, int path) {
+  Carver c(ws);
+  EigLayout E;
+  E.status = c.take<int>(16);
+  carve_stage(c, E.st, N);
+  E.st.N = N;
+  E.fmm_elems = (path == SVDU_PATH_FMM) ? fmm_workspace_elems(std::max(R, 1), N) : 0;
+  E.fmm_work = c.take<double>(E.fmm_elems);
+  E.fmm_plan_bytes = (path == SVDU_PATH_FMM) ? fmm_plan_bytes(N) : 0;
+  E.fmm_plan = c.take<char>(E.fmm_plan_bytes);
+  E.bytes = c.off + 256;
+  return E;
 }
 
-size_t svdu_eig_update_workspace_bytes(int R, int N) {
-  (void)R;
-  if (N < 1) return 0;
-  size_t b;
-  carve_eig(nullptr, N, nullptr, &b);
-  return b;
+size_t svdu_eig_update_workspace_bytes(int R, int N, int path) {
+  if (N < 1 || R < 0 || (path != SVDU_PATH_DIRECT && path != SVDU_PATH_FMM)) return 0;
+  return carve_eig(nullptr, R, N, path).bytes;
 }
 
-int svdu_eig_update(int R, int N, const double* X, int ldx, const double* lam, const double* z, double rho,
-                    double* X_out, int ldo, double* lam_out, int8_t* defl, void* workspace,
+int svdu_eig_update(int R, int N, const double* X, int ldx, const double* lam, const double* z, double rho, int path,
+                    double eps, double* X_out, int ldo, double* lam_out, int8_t* defl, void* workspace,
                     size_t workspace_bytes, void* stream) {
   if (R < 0 || N < 1 || ldx < N || ldo < N || !lam || !z || !workspace || !lam_out) return SVDU_EINVAL;
   if (R > 0 && (!X || !X_out)) return SVDU_EINVAL;
   if (!(rho != 0.0) || !isfinite(rho)) return SVDU_EINVAL;
+  if (path != SVDU_PATH_DIRECT && path != SVDU_PATH_FMM) return SVDU_EINVAL;
+  if (path == SVDU_PATH_FMM && !(eps > 0.0 && eps < 1.0)) return SVDU_EINVAL;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return SVDU_EINVAL;
   if (R > 0 && overlaps(X, ((size_t)(R - 1) * ldx + N) * 8, X_out, ((size_t)(R - 1) * ldo + N) * 8))
     return SVDU_EINVAL;
-  size_t need;
-  int* status;
-  Stage s = carve_eig(workspace, N, &status, &need);
-  if (workspace_bytes < need) return SVDU_ENOMEM;
+  EigLayout E = carve_eig(workspace, R, N, path);
+  if (workspace_bytes < E.bytes) return SVDU_ENOMEM;
+  Stage& s = E.st;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(set_scalar, dim3(1), dim3(64), 0, st, s.rho, rho, status);
+  hipLaunchKernelGGL(set_scalar, dim3(1), dim3(64), 0, st, s.rho, rho, E.status);
   hipLaunchKernelGGL(identity_map, dim3((N + 255) / 256), dim3(256), 0, st, N, s.col_of);
   s.lam_in = lam;
   s.z = const_cast<double*>(z);
   s.descending = false;
-  s.status = status;
+  s.status = E.status;
   launch_stage_small(s, g_maxit, st);
-  launch_gemm_cauchy_f64(R, X, ldx, desc_of(s), X_out, ldo, st);
+  if (path == SVDU_PATH_FMM) {
+    const int Rs[1] = {R};
+    const double* Xs[1] = {X};
+    const int ldxs[1] = {ldx};
+    double* Xos[1] = {X_out};
+    const int ldos[1] = {ldo};
+    const double* sc[1] = {nullptr};
+    const int rc = fmm_products_impl(1, &s, Rs, Xs, ldxs, Xos, ldos, sc, E.status, E.fmm_work, E.fmm_elems,
+                                     E.fmm_plan, E.fmm_plan_bytes, eps, {}, -1, st);
+    if (rc != SVDU_OK) return rc;
+  } else {
+    launch_gemm_cauchy_f64(R, X, ldx, desc_of(s), X_out, ldo, st);
+  }
   if (hipMemcpyAsync(lam_out, s.lam_out, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
     return SVDU_EHIP;
   if (defl) hipLaunchKernelGGL(copy_flags, dim3((N + 255) / 256), dim3(256), 0, st, N, N, s.flags, defl);

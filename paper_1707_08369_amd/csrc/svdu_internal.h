@@ -76,6 +76,8 @@ struct Stage {
   int* cmem = nullptr;
   double* ch = nullptr;
   double* lam_out = nullptr;  // eigenvalue per output column
+  int* rootpos = nullptr;     // output position of each root
+  int* dpos = nullptr;        // output position of each deflated item
   double* hx = nullptr;       // per cluster x 3: Householder dot products for C~^T x
 };
 
@@ -126,5 +128,13 @@ void launch_gemm_cauchy_split32(int R, const double* X, int ldx, const CauchyDes
 // Rescales every column of X (R x N) to unit FP64 norm; scratch >= renorm_scratch_elems(R, N) doubles.
 size_t renorm_scratch_elems(int R, int N);
 void launch_column_renorm(int R, int N, double* X, int ldx, double* scratch, const int* status, hipStream_t st);
+
+// FMM path of the product (k_fmm.hip). The plan of a product is built on the
+// host from host copies of the stage's K poles and roots, all plans of a call
+// are uploaded in one copy, then the kernels are enqueued.
+struct FmmPrepared;
+int fmm_order(double eps);
+size_t fmm_workspace_elems(int R, int N);
+size_t fmm_plan_bytes(int N);
 
 }  // namespace svdu

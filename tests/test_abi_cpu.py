@@ -44,6 +44,8 @@ def test_workspace_sizes(lib):
     assert big < 8192 * 8192 * 8 * 1.1
     assert 0 < small < big
     assert svdu.svdu_eig_update_workspace_bytes(10, 7) > 0
+    assert svdu.svdu_eig_update_workspace_bytes(10, 7, svdu.SVDU_PATH_FMM) > svdu.svdu_eig_update_workspace_bytes(10, 7)
+    assert svdu.svdu_workspace_bytes(64, 64, svdu.SVDU_PATH_FMM) > svdu.svdu_workspace_bytes(64, 64)
     assert svdu.svdu_secular_workspace_bytes(7) > 0
 
 
@@ -78,10 +80,12 @@ def test_host_argument_errors_return_before_enqueue(lib):
     assert call(workspace=_p(0x100010)) == svdu.SVDU_EINVAL  # misaligned
     assert call(workspace_bytes=16) == svdu.SVDU_ENOMEM
     assert call(path=1, eps=0.0) == svdu.SVDU_EINVAL
-    assert svdu.svdu_eig_update(3, 0, fake, 1, fake, fake, 1.0, _p(0x50000), 1, fake, None, ws, 1 << 20,
+    assert svdu.svdu_eig_update(3, 0, fake, 1, fake, fake, 1.0, 0, 0.0, _p(0x50000), 1, fake, None, ws, 1 << 20,
                                 None) == svdu.SVDU_EINVAL
-    assert svdu.svdu_eig_update(3, 4, fake, 4, fake, fake, 0.0, _p(0x50000), 4, fake, None, ws, 1 << 20,
+    assert svdu.svdu_eig_update(3, 4, fake, 4, fake, fake, 0.0, 0, 0.0, _p(0x50000), 4, fake, None, ws, 1 << 20,
                                 None) == svdu.SVDU_EINVAL
+    assert svdu.svdu_eig_update(3, 4, fake, 4, fake, fake, 1.0, 1, 0.0, _p(0x50000), 4, fake, None, ws, 1 << 20,
+                                None) == svdu.SVDU_EINVAL   # FMM needs 0 < eps < 1
     assert svdu.svdu_secular(0, fake, fake, 1.0, fake, fake, None, ws, 1 << 20, None) == svdu.SVDU_EINVAL
     assert svdu.svdu_secular(4, fake, fake, 1.0, fake, fake, None, ws, 8, None) == svdu.SVDU_ENOMEM
 

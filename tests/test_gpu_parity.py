@@ -308,3 +308,56 @@ def test_precision_form_keeps_roots_and_reports_its_error(lib, m, n, kind):
     assert recon <= 5e-6 and orth <= 5e-6, (recon, orth)
     assert np.max(np.abs(np.linalg.norm(Ug, axis=0) - 1)) <= 1e-14   # the FP64 renormalisation sweep
     print(f"split32 m={m} n={n} {kind}: recon {recon:.2e} orth {orth:.2e}")
+
+
+# ---------------------------------------------------------------------------
+# FMM path of the product: matches the direct sum (the definition, here the
+# oracle's dense X C~) to <= 1e-9 at eps = 1e-10
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("N,kind", [(33, "uniform"), (257, "uniform"), (1000, "geometric"), (1000, "uniform"),
+                                    (3000, "geometric")])
+@pytest.mark.parametrize("rho", [0.9, -0.6])
+@pytest.mark.parametrize("variant", ["plain", "repeat_zeros"])
+def test_fmm_product_matches_direct_sum(lib, N, kind, rho, variant):
+    rng = np.random.default_rng(N)
+    R = 200
+    lam = np.sort(rng.uniform(0, 3, N)) if kind == "uniform" else np.sort(10.0 ** (-12.0 * rng.uniform(0, 1, N)))
+    z = rng.standard_normal(N) / np.sqrt(N)
+    if variant == "repeat_zeros":
+        lam[5:9] = lam[5]
+        lam = np.sort(lam)
+        z[[2, N // 3]] = 0.0
+    X = rng.standard_normal((R, N))
+    Xf, lf, ff = lib.eig_update(dev(X), dev(lam), dev(z), rho, path=lib.SVDU_PATH_FMM, eps=1e-10)
+    Xd, ld, fd = lib.eig_update(dev(X), dev(lam), dev(z), rho)
+    assert torch.equal(lf, ld) and torch.equal(ff, fd)      # same roots and deflation as the direct path
+    st = O.rank_one_update_z(X, lam, z, rho)                  # oracle: dense C~ and matmul
+    scale = np.max(np.abs(st.X))
+    err_oracle = np.max(np.abs(_align_cols(st.X, host(Xf)) - st.X)[:, _separated(st.lam)], initial=0.0)
+    err_direct = np.max(np.abs(host(Xf) - host(Xd)))
+    assert err_direct <= 1e-9 * scale, err_direct
+    assert err_oracle <= 1e-9 * scale, err_oracle
+
+
+@pytest.mark.parametrize("m,n,kind,kw", [(300, 457, "uniform", {}), (512, 512, "clustered",
+                                                                      dict(zero_frac=0.05, zero_q=True)),
+                                         (4096, 4096, "geometric", {})])
+def test_fmm_update_matches_direct_update(lib, m, n, kind, kw):
+    """Direct vs FMM at eps = 1e-10 on the whole update (the geometric 4096 case
+    is the direct-vs-FMM workload)."""
+    if m >= 4096:
+        U = S.haar_torch(m, seed=21, device="cuda")
+        V = S.haar_torch(n, seed=22, device="cuda")
+        rng = np.random.default_rng(23)
+        sig = dev(S.sigma_geometric(m))
+        a, b = dev(rng.standard_normal(m) / np.sqrt(n)), dev(rng.standard_normal(n) / np.sqrt(n))
+    else:
+        P = S.make_problem(m, n, kind, seed=7, **kw)
+        U, sig, V, a, b = dev(P.U), dev(P.sigma), dev(P.V), dev(P.a), dev(P.b)
+    Ud, sd, Vd, fd = lib.rank1_update(U, sig, V, a, b)
+    Uf, sf, Vf, ff = lib.rank1_update(U, sig, V, a, b, path=lib.SVDU_PATH_FMM, eps=1e-10)
+    assert torch.equal(sd, sf) and torch.equal(fd, ff)
+    assert (Uf - Ud).abs().max().item() <= 1e-9
+    assert (Vf - Vd).abs().max().item() <= 1e-9
+    recon, orthU, orthV, fro_err, inter = _full_size_checks(m, n, Uf, sf, Vf, U, sig, V, a, b)
+    assert recon <= 1e-9 and orthU <= 1e-9 and orthV <= 1e-9, (recon, orthU, orthV)
