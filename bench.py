@@ -9,9 +9,12 @@ Cauchy weights, sign pairing, four products X C~), with its inputs resident in
 HBM; every step gets its own (a, b).
 
 Prints one JSON line. `roofline` describes the product kernel (the dominant
-one): algorithmic FP64 flops per launch (2 R N^2) over its mean launch time,
-measured with HIP events recorded on the launch stream by the library's timing
-ring. `cpu_baseline` times the CPU oracle on a bounded sample (see
+one): algorithmic FP64 flops per launch over its mean launch time, measured
+with HIP events recorded on the launch stream by the library's timing ring.
+One launch computes the products of one level, U C~_L+ and V C~_R+ (or
+U~ C~_L- and V~ C~_R-): 2 m^3 + 2 n^3 flops. `forms` adds the precision form,
+the FMM path and the batched form (512 uneven problems in one captured graph)
+measured on the same box. `cpu_baseline` times the CPU oracle on a bounded sample (see
 cpu_baseline()). `traffic` comes from the rocprofv3 counter summary under
 profiles/ when it was taken on the current product-kernel source, else null.
 """
@@ -152,6 +155,88 @@ def measure_forms(svdu, torch, U, sigma, V, A_vecs, B_vecs, Uo, so, Vo, ws, stre
     return res
 
 
+def batched_workload(torch, count=512, seed=4):
+    """512 independent problems: m log-uniform in [64, 1024], n = m + U{0..m},
+    sigma ~ U[0.01, 10] descending, Haar U and V, a, b ~ N(0, 1/n)."""
+    import numpy as np
+
+    import synth_inputs as S
+    ms, ns = S.batched_sizes(count, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    items = []
+    for i, (m, n) in enumerate(zip(ms.tolist(), ns.tolist())):
+        U = S.haar_torch(m, seed=10_000 + 2 * i, device="cuda")
+        V = S.haar_torch(n, seed=10_001 + 2 * i, device="cuda")
+        sig = torch.as_tensor(S.sigma_uniform(m, 0.01, 10.0, rng), device="cuda")
+        a = torch.as_tensor(rng.standard_normal(m) / np.sqrt(n), device="cuda")
+        b = torch.as_tensor(rng.standard_normal(n) / np.sqrt(n), device="cuda")
+        items.append((U, sig, V, a, b))
+    return items
+
+
+def measure_batched(svdu, torch, reps=5, check=True,
+                    modes=("fp64_graph", "fp64_graph_persistent", "fp64_eager", "split32_graph")):
+    """The batched form: the 512-problem workload as one batch, launched as one
+    captured graph (or eagerly), against the same problems updated one call at
+    a time through svdu_rank1_update. Tile shapes come from the autotuner."""
+    import numpy as np
+    items = batched_workload(torch)
+    count = len(items)
+    flops = float(sum(4.0 * (it[0].shape[0] ** 3 + it[2].shape[0] ** 3) for it in items))
+    res = {"workload": "512 problems, m log-uniform [64,1024], n = m + U{0..m}, sigma~U[0.01,10], haar U,V, "
+                       "a,b~N(0,1/n)", "count": count, "product_flops_per_batch": flops}
+    tuned = {}
+    for prec in (svdu.SVDU_PREC_FP64, svdu.SVDU_PREC_SPLIT32):
+        table, times = svdu.autotune(prec, max_n=2048)
+        tuned["fp64" if prec == 0 else "split32"] = {"table": table, "ms": [[round(t, 4) for t in row]
+                                                                           for row in times[:6]]}
+    res["autotune"] = tuned
+    for mode in modes:
+        prec = svdu.SVDU_PREC_SPLIT32 if mode.startswith("split32") else svdu.SVDU_PREC_FP64
+        b = svdu.Batch(items, precision=prec, persistent="persistent" in mode)
+        graph = "graph" in mode
+        b.launch(use_graph=graph)                 # warm-up (and capture)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = []
+        for _ in range(reps):
+            e0.record()
+            b.launch(use_graph=graph)
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        st = b.status()
+        ms = float(np.median(times))
+        rec = {"ms_per_batch": ms, "ms_min": float(min(times)), "updates_per_s": count / (ms * 1e-3),
+               "product_tflops_effective": flops / (ms * 1e-3) / 1e12, "status_ok": all(c == 0 for c in st)}
+        if check and prec == svdu.SVDU_PREC_FP64:
+            worst = 0.0
+            for it, o in zip(items[:64], b.outs[:64]):
+                U, sg, V, a, bb = it
+                mm = U.shape[0]
+                Ah = (U * sg[None, :]) @ V[:, :mm].T + torch.outer(a, bb)
+                worst = max(worst, ((o[0] * o[1][None, :]) @ o[2][:, :mm].T - Ah).norm().item() / Ah.norm().item())
+            rec["recon_max_first64"] = worst
+        res[mode] = rec
+        b.close()
+        del b
+    # the same problems one call at a time (eager single-problem path)
+    outs = [(torch.empty_like(it[0]), torch.empty_like(it[1]), torch.empty_like(it[2])) for it in items]
+    wss = [svdu.new_workspace(svdu.svdu_workspace_bytes(it[0].shape[0], it[2].shape[0]), "cuda") for it in items]
+    for it, o, w in zip(items, outs, wss):
+        svdu.rank1_update(*it, out=o, workspace=w, want_defl=False, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it, o, w in zip(items, outs, wss):
+        svdu.rank1_update(*it, out=o, workspace=w, want_defl=False, check=False)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0)
+    res["one_call_per_problem"] = {"ms_per_batch": ms, "updates_per_s": count / (ms * 1e-3)}
+    best = min(res[m]["ms_per_batch"] for m in modes if not m.startswith("split32"))
+    res["speedup_batched_vs_one_call_per_problem"] = ms / best
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +252,10 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the reconstruction spot check")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the short measurements of the other forms (precision form) on the same inputs")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
+    ap.add_argument("--batch-reps", type=int, default=5, help="timed launches of the batched workload")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="measure only the batched form (for profiling it)")
     ap.add_argument("--profile-copy", type=int, default=0,
                     help="run only N plain 1 GiB device copies (counter calibration) and exit")
     args = ap.parse_args()
@@ -195,6 +284,10 @@ def main():
             torch.mul(src, 1.0, out=dst)      # one elementwise kernel: 1 GiB read, 1 GiB written
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each": src.numel() * 8, "copies": args.profile_copy}))
+        return
+
+    if args.batched_only:
+        print(json.dumps(measure_batched(svdu, torch, reps=args.batch_reps, check=False, modes=("fp64_graph",))))
         return
 
     m, n, K, W = args.m, args.n, args.steps, args.warmup
@@ -245,11 +338,10 @@ def main():
         Ah = (U * sigma[None, :]) @ V[:, :m].T + torch.outer(A_vecs[k], B_vecs[k])
         recon = ((Uo * so[None, :]) @ Vo[:, :m].T - Ah).norm().item() / Ah.norm().item()
 
-    ph = np.asarray(phases)                       # K x 7 ms
+    ph = np.asarray(phases)                       # K x 5 ms
     per_update = ph.sum(axis=1)
-    gemm_ms = ph[:, 2:6]
-    gemm_flops = np.array([2.0 * m * m * m, 2.0 * m * m * m, 2.0 * n * n * n, 2.0 * n * n * n])
-    mean_flops = float(gemm_flops.mean())
+    gemm_ms = ph[:, 2:4]                          # the two product launches of each update
+    mean_flops = 2.0 * m ** 3 + 2.0 * n ** 3      # per launch
     mean_gemm_ms = float(gemm_ms.mean())
     achieved = mean_flops / (mean_gemm_ms * 1e-3) / 1e12
     traffic = load_traffic(m, n)
@@ -274,11 +366,11 @@ def main():
         "latency_ms": {"p50": float(np.percentile(per_update, 50)), "p99": float(np.percentile(per_update, 99)),
                        "mean": float(per_update.mean())},
         "phase_ms_mean": {"projections": float(ph[:, 0].mean()), "eigen_updates_small": float(ph[:, 1].mean()),
-                          "products": float(gemm_ms.sum(axis=1).mean()), "flags": float(ph[:, 6].mean())},
+                          "products": float(gemm_ms.sum(axis=1).mean()), "flags": float(ph[:, 4].mean())},
         "recon_last": recon,
         "roofline": {
             "bound": "mfma",
-            "kernel": "gemm_cauchy_f64_kernel",
+            "kernel": "gemm_cauchy_f64_kernel<2, 2> (128x128 tiles)",
             "achieved": achieved,
             "peak": FP64_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",
@@ -291,6 +383,11 @@ def main():
     if not args.no_forms:
         out["forms"] = measure_forms(svdu, torch, U, sigma, V, A_vecs, B_vecs, Uo, so, Vo, ws, stream,
                                      fp64_ms=1e3 * (t1 - t0) / K, check=not args.no_check)
+        del ws, Uo, Vo
+    if not args.no_batched:
+        print("[bench] batched form ...", file=sys.stderr, flush=True)
+        out.setdefault("forms", {})["batched_512"] = measure_batched(svdu, torch, reps=args.batch_reps,
+                                                                     check=not args.no_check)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -55,7 +55,17 @@ extern "C" {
 /* options for svdu_set_option */
 #define SVDU_OPT_SECULAR_MAXIT 1 /* iteration cap of the secular solver (default 200) */
 #define SVDU_OPT_TIMING 2        /* 1: record phase timings of svdu_rank1_update (resets the record) */
-#define SVDU_OPT_GEMM_VARIANT 3  /* product kernel: 2 (default, X in registers) or 1 (both operands via LDS) */
+#define SVDU_OPT_TILE_SHAPE 3    /* -1 (default): tile shape of the products from the tuning table;
+                                    0..3 force SVDU_TILE_* (results are bitwise the same for every shape) */
+#define SVDU_OPT_PERSISTENT 4    /* 1: products of svdu_rank1_update and svdu_rank1_update_batched use the
+                                    persistent schedule (see SVDU_BATCH_PERSISTENT); default 0 */
+
+/* tile shapes of the product kernels (rows x columns of one block tile) */
+#define SVDU_TILE_128x128 0
+#define SVDU_TILE_64x128 1
+#define SVDU_TILE_128x64 2
+#define SVDU_TILE_64x64 3
+#define SVDU_TILE_BUCKETS 8      /* tuning-table buckets by order N: (0,64], (64,128], ..., (4096, inf) */
 
 /* Bytes of device workspace svdu_rank1_update needs for (m, n, path, precision). */
 size_t svdu_workspace_bytes(int m, int n, int path, int precision);
@@ -132,14 +142,87 @@ int svdu_secular(int K, const double* d, const double* z, double rho, int* org, 
 int svdu_set_option(int option, int value);
 
 /* Phase timings recorded while SVDU_OPT_TIMING is on (at most 256 calls since
- * it was switched on). For call c, ms[7 c + k] (host array of 7 max_calls
- * doubles) receives the milliseconds of phase k, measured with HIP events on
- * the call's stream: 0 projections and checks, 1 the O(n^2) eigen-update work
- * of all four updates (deflation, secular roots, weights, signs), 2..5 the
- * products X C~ of the updates (left rho+, left rho-, right rho+, right rho-;
- * one kernel each), 6 the flag copies. Waits for those events. Returns the
- * number of calls filled, or SVDU_EHIP. */
+ * it was switched on; svdu_rank1_update and eager svdu_batch_launch calls
+ * are recorded). For call c, ms[5 c + k] (host array of 5 max_calls doubles)
+ * receives the milliseconds of phase k, measured with HIP events on the
+ * call's stream: 0 projections, 1 the O(n^2) eigen-update work of all four
+ * updates (deflation, secular roots, weights, signs, singular values), 2 and
+ * 3 the products X C~ (direct path: first level U C~_L+ and V C~_R+, then
+ * second level U~ C~_L- and V~ C~_R-, with the column rescaling of the
+ * precision form; FMM path: left side, then right side), 4 the flag copies.
+ * Waits for those events. Returns the number of calls filled, or SVDU_EHIP. */
 int svdu_timing_read(double* ms, int max_calls);
+
+/* ---- batched updates (many independent problems of uneven sizes) ----------
+ * Every step of the update is one launch over all problems of the batch (a
+ * product launch per tile shape in use); a problem's results are bitwise the
+ * same as from svdu_rank1_update with the same inputs, whatever else is in
+ * the batch. Direct path only (SVDU_PREC_FP64 or SVDU_PREC_SPLIT32). */
+typedef struct {
+  int m, n;                       /* 1 <= m <= n */
+  const double* U; int ldu;       /* as for svdu_rank1_update (device pointers) */
+  const double* sigma;
+  const double* V; int ldv;
+  const double* a;
+  const double* b;
+  double* U_out; int ldu_out;
+  double* sigma_out;
+  double* V_out; int ldv_out;
+  int8_t* defl;                   /* NULL or 4 x n flags */
+} svdu_problem;
+
+typedef struct svdu_batch svdu_batch;   /* opaque; owns host-side tables, a graph, an event */
+
+#define SVDU_BATCH_PERSISTENT 1  /* product kernels run as many blocks as fit on the device at once, each
+                                    taking tiles (largest problems first) from a counter */
+
+/* Workspace bytes for the batch `probs` (host array of `count`). */
+size_t svdu_batch_workspace_bytes(int count, const svdu_problem* probs, int precision);
+
+/* Validates every problem (as svdu_rank1_update does) and that no output
+ * overlaps another output, an input or the workspace; carves the workspace;
+ * builds the job tables (ordered largest first), and enqueues their upload on
+ * `stream`. The problem array may be freed on return; the buffers it names
+ * and the workspace must stay valid until svdu_batch_destroy. flags: 0 or
+ * SVDU_BATCH_PERSISTENT. Returns 0 or a negative SVDU_E* code (*out = NULL). */
+int svdu_batch_create(svdu_batch** out, int count, const svdu_problem* probs, int precision, int flags,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/* Enqueues one update of every problem on `stream` (it may differ from the
+ * creation stream; the table upload is waited for). use_graph = 0: the
+ * launches are enqueued one by one. use_graph = 1: the first call captures
+ * the whole sequence into a HIP graph (on a stream the batch owns) and every
+ * call launches that graph once. Inputs may change between launches; sizes,
+ * pointers and the workspace may not. One launch in flight per batch. */
+int svdu_batch_launch(svdu_batch* b, int use_graph, void* stream);
+
+/* Waits for `stream` and writes each problem's device status (SVDU_OK,
+ * SVDU_ENONFINITE, SVDU_EBADSIGMA or SVDU_ENOCONV) to status[0..count-1]
+ * (host). Returns the first nonzero one, SVDU_OK, or SVDU_EHIP. */
+int svdu_batch_status(svdu_batch* b, int* status, void* stream);
+
+/* Waits for the table upload and frees the batch (not the workspace). */
+void svdu_batch_destroy(svdu_batch* b);
+
+/* create + eager launch + wait for `stream` + destroy. */
+int svdu_rank1_update_batched(int count, const svdu_problem* probs, int precision, void* workspace,
+                              size_t workspace_bytes, void* stream);
+
+/* ---- tile-shape autotuner --------------------------------------------------
+ * For each size bucket up to max_n (<= 8192 recommended), times the product
+ * kernel of every tile shape on the same set of synthetic products of order
+ * N (the bucket's upper end, or max_n) that fills the device, and stores the
+ * fastest shape in the process-wide table used by every later call of that
+ * precision. times_ms (host, SVDU_TILE_BUCKETS x 4, may be NULL) receives the
+ * best of three timed launches per shape (-1 for buckets above max_n), table
+ * (host, SVDU_TILE_BUCKETS, may be NULL) the chosen shapes. Synchronises
+ * `stream`. */
+size_t svdu_autotune_workspace_bytes(int max_n);
+int svdu_autotune(int precision, int max_n, double* times_ms, int* table, void* workspace,
+                  size_t workspace_bytes, void* stream);
+/* Reads (set = 0) or writes (set = 1) the process-wide tuning table of a
+ * precision (host array of SVDU_TILE_BUCKETS shapes). */
+int svdu_tile_table(int precision, int* table, int set);
 
 /* Static description of a status code (host). */
 const char* svdu_status_string(int status);

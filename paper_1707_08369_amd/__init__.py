@@ -30,11 +30,34 @@ SVDU_PREC_FP64 = 0
 SVDU_PREC_SPLIT32 = 1
 SVDU_OPT_SECULAR_MAXIT = 1
 SVDU_OPT_TIMING = 2
-SVDU_OPT_GEMM_VARIANT = 3
+SVDU_OPT_TILE_SHAPE = 3
+SVDU_OPT_PERSISTENT = 4
+SVDU_TILE_128x128 = 0
+SVDU_TILE_64x128 = 1
+SVDU_TILE_128x64 = 2
+SVDU_TILE_64x64 = 3
+SVDU_TILE_BUCKETS = 8
+SVDU_BATCH_PERSISTENT = 1
+TIMING_PHASES = 5
 
 EXPORTS = ("svdu_workspace_bytes", "svdu_rank1_update", "svdu_get_status", "svdu_eig_update_workspace_bytes",
            "svdu_eig_update", "svdu_secular_workspace_bytes", "svdu_secular", "svdu_set_option",
-           "svdu_status_string", "svdu_timing_read")
+           "svdu_status_string", "svdu_timing_read", "svdu_batch_workspace_bytes", "svdu_batch_create",
+           "svdu_batch_launch", "svdu_batch_status", "svdu_batch_destroy", "svdu_rank1_update_batched",
+           "svdu_autotune_workspace_bytes", "svdu_autotune", "svdu_tile_table")
+
+
+class svdu_problem(ctypes.Structure):
+    """Mirror of the C struct svdu_problem (include/svdu.h)."""
+    _fields_ = [("m", ctypes.c_int), ("n", ctypes.c_int),
+                ("U", ctypes.c_void_p), ("ldu", ctypes.c_int),
+                ("sigma", ctypes.c_void_p),
+                ("V", ctypes.c_void_p), ("ldv", ctypes.c_int),
+                ("a", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("U_out", ctypes.c_void_p), ("ldu_out", ctypes.c_int),
+                ("sigma_out", ctypes.c_void_p),
+                ("V_out", ctypes.c_void_p), ("ldv_out", ctypes.c_int),
+                ("defl", ctypes.c_void_p)]
 
 _lib = None
 
@@ -76,6 +99,25 @@ def load():
     lib.svdu_timing_read.restype = c_int
     lib.svdu_status_string.argtypes = [c_int]
     lib.svdu_status_string.restype = ctypes.c_char_p
+    c_pp = ctypes.POINTER(svdu_problem)
+    lib.svdu_batch_workspace_bytes.argtypes = [c_int, c_pp, c_int]
+    lib.svdu_batch_workspace_bytes.restype = c_size
+    lib.svdu_batch_create.argtypes = [ctypes.POINTER(c_vp), c_int, c_pp, c_int, c_int, c_vp, c_size, c_vp]
+    lib.svdu_batch_create.restype = c_int
+    lib.svdu_batch_launch.argtypes = [c_vp, c_int, c_vp]
+    lib.svdu_batch_launch.restype = c_int
+    lib.svdu_batch_status.argtypes = [c_vp, c_vp, c_vp]
+    lib.svdu_batch_status.restype = c_int
+    lib.svdu_batch_destroy.argtypes = [c_vp]
+    lib.svdu_batch_destroy.restype = None
+    lib.svdu_rank1_update_batched.argtypes = [c_int, c_pp, c_int, c_vp, c_size, c_vp]
+    lib.svdu_rank1_update_batched.restype = c_int
+    lib.svdu_autotune_workspace_bytes.argtypes = [c_int]
+    lib.svdu_autotune_workspace_bytes.restype = c_size
+    lib.svdu_autotune.argtypes = [c_int, c_int, c_vp, c_vp, c_vp, c_size, c_vp]
+    lib.svdu_autotune.restype = c_int
+    lib.svdu_tile_table.argtypes = [c_int, c_vp, c_int]
+    lib.svdu_tile_table.restype = c_int
     _lib = lib
     return lib
 
@@ -124,12 +166,49 @@ def svdu_timing_read(ms, max_calls) -> int:
 
 
 def timing_read(max_calls=256):
-    """Phase timings (ms) of the calls recorded since SVDU_OPT_TIMING was set: list of 7-tuples."""
-    buf = (ctypes.c_double * (7 * max_calls))()
+    """Phase timings (ms) of the calls recorded since SVDU_OPT_TIMING was set: list of 5-tuples."""
+    P = TIMING_PHASES
+    buf = (ctypes.c_double * (P * max_calls))()
     n = svdu_timing_read(ctypes.cast(buf, ctypes.c_void_p), max_calls)
     if n < 0:
         raise SvduError(n, "svdu_timing_read")
-    return [tuple(buf[7 * c + k] for k in range(7)) for c in range(n)]
+    return [tuple(buf[P * c + k] for k in range(P)) for c in range(n)]
+
+
+def svdu_batch_workspace_bytes(count, probs, precision) -> int:
+    return int(load().svdu_batch_workspace_bytes(count, probs, precision))
+
+
+def svdu_batch_create(out, count, probs, precision, flags, workspace, workspace_bytes, stream) -> int:
+    return int(load().svdu_batch_create(out, count, probs, precision, flags, workspace, workspace_bytes, stream))
+
+
+def svdu_batch_launch(batch, use_graph, stream) -> int:
+    return int(load().svdu_batch_launch(batch, use_graph, stream))
+
+
+def svdu_batch_status(batch, status, stream) -> int:
+    return int(load().svdu_batch_status(batch, status, stream))
+
+
+def svdu_batch_destroy(batch) -> None:
+    load().svdu_batch_destroy(batch)
+
+
+def svdu_rank1_update_batched(count, probs, precision, workspace, workspace_bytes, stream) -> int:
+    return int(load().svdu_rank1_update_batched(count, probs, precision, workspace, workspace_bytes, stream))
+
+
+def svdu_autotune_workspace_bytes(max_n) -> int:
+    return int(load().svdu_autotune_workspace_bytes(max_n))
+
+
+def svdu_autotune(precision, max_n, times_ms, table, workspace, workspace_bytes, stream) -> int:
+    return int(load().svdu_autotune(precision, max_n, times_ms, table, workspace, workspace_bytes, stream))
+
+
+def svdu_tile_table(precision, table, set_) -> int:
+    return int(load().svdu_tile_table(precision, table, set_))
 
 
 def svdu_status_string(code) -> str:
@@ -265,3 +344,125 @@ def secular(d, z, rho, stream=None, check=True):
         if rc != SVDU_OK:
             raise SvduError(rc, "svdu_secular (device)")
     return org, tau, its
+
+
+# ---------------------------------------------------------------------------
+# batched updates
+# ---------------------------------------------------------------------------
+class Batch:
+    """A batch of independent rank-1 updates (svdu_batch_* in include/svdu.h).
+
+    ``items`` is a list of (U, sigma, V, a, b) device tensors. Outputs are
+    allocated unless ``outs`` gives (U_out, sigma_out, V_out) per item. The batch
+    keeps references to every tensor it names, and its workspace.
+    """
+
+    def __init__(self, items, precision=SVDU_PREC_FP64, persistent=False, outs=None, want_defl=False,
+                 stream=None):
+        torch = _torch()
+        self._lib = load()
+        self.precision = precision
+        self.items = list(items)
+        self.count = len(self.items)
+        if self.count < 1:
+            raise ValueError("empty batch")
+        self.outs = []
+        self.defl = []
+        arr = (svdu_problem * self.count)()
+        for i, (U, sigma, V, a, b) in enumerate(self.items):
+            m, n = U.shape[0], V.shape[0]
+            ldu = _check_mat(U, m, m, "U")
+            ldv = _check_mat(V, n, n, "V")
+            _check_vec(sigma, m, "sigma")
+            _check_vec(a, m, "a")
+            _check_vec(b, n, "b")
+            if outs is None:
+                Uo = torch.empty((m, m), dtype=torch.float64, device=U.device)
+                so = torch.empty(m, dtype=torch.float64, device=U.device)
+                Vo = torch.empty((n, n), dtype=torch.float64, device=U.device)
+            else:
+                Uo, so, Vo = outs[i]
+            lduo = _check_mat(Uo, m, m, "U_out")
+            ldvo = _check_mat(Vo, n, n, "V_out")
+            _check_vec(so, m, "sigma_out")
+            d = torch.empty((4, n), dtype=torch.int8, device=U.device) if want_defl else None
+            self.outs.append((Uo, so, Vo))
+            self.defl.append(d)
+            arr[i] = svdu_problem(m, n, U.data_ptr(), ldu, sigma.data_ptr(), V.data_ptr(), ldv, a.data_ptr(),
+                                  b.data_ptr(), Uo.data_ptr(), lduo, so.data_ptr(), Vo.data_ptr(), ldvo,
+                                  None if d is None else d.data_ptr())
+        self._arr = arr
+        need = svdu_batch_workspace_bytes(self.count, arr, precision)
+        if need == 0:
+            raise ValueError("invalid batch")
+        self.workspace = new_workspace(need, self.items[0][0].device)
+        wp, wb = _aligned(self.workspace)
+        h = ctypes.c_void_p()
+        rc = svdu_batch_create(ctypes.byref(h), self.count, arr, precision,
+                               SVDU_BATCH_PERSISTENT if persistent else 0, wp, wb, _stream_handle(stream))
+        if rc != SVDU_OK:
+            raise SvduError(rc, "svdu_batch_create")
+        self._h = h
+
+    def launch(self, use_graph=False, stream=None):
+        rc = svdu_batch_launch(self._h, 1 if use_graph else 0, _stream_handle(stream))
+        if rc != SVDU_OK:
+            raise SvduError(rc, "svdu_batch_launch")
+
+    def status(self, stream=None):
+        """Per-problem device status codes (waits for the stream)."""
+        st = (ctypes.c_int * self.count)()
+        rc = svdu_batch_status(self._h, ctypes.cast(st, ctypes.c_void_p), _stream_handle(stream))
+        if rc == SVDU_EHIP:
+            raise SvduError(rc, "svdu_batch_status")
+        return list(st)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            svdu_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rank1_update_batched(items, precision=SVDU_PREC_FP64, use_graph=False, persistent=False, stream=None,
+                         check=True):
+    """Updates every (U, sigma, V, a, b) of ``items`` in one batch; returns [(U^, sigma^, V^), ...]."""
+    b = Batch(items, precision=precision, persistent=persistent, stream=stream)
+    b.launch(use_graph=use_graph, stream=stream)
+    if check:
+        st = b.status(stream)
+        bad = [(i, c) for i, c in enumerate(st) if c != SVDU_OK]
+        if bad:
+            raise SvduError(bad[0][1], f"batched update, problem {bad[0][0]}")
+    outs = b.outs
+    b.close()
+    return outs
+
+
+def autotune(precision=SVDU_PREC_FP64, max_n=4096, stream=None):
+    """Runs the tile-shape autotuner; returns (table, times_ms[bucket][shape])."""
+    torch = _torch()
+    need = svdu_autotune_workspace_bytes(max_n)
+    ws = new_workspace(need, torch.device("cuda"))
+    wp, wb = _aligned(ws)
+    times = (ctypes.c_double * (SVDU_TILE_BUCKETS * 4))()
+    table = (ctypes.c_int * SVDU_TILE_BUCKETS)()
+    rc = svdu_autotune(precision, max_n, ctypes.cast(times, ctypes.c_void_p), ctypes.cast(table, ctypes.c_void_p),
+                       wp, wb, _stream_handle(stream))
+    if rc != SVDU_OK:
+        raise SvduError(rc, "svdu_autotune")
+    return list(table), [[times[b * 4 + s] for s in range(4)] for b in range(SVDU_TILE_BUCKETS)]
+
+
+def tile_table(precision=SVDU_PREC_FP64, table=None):
+    """Reads the tuning table, or sets it when ``table`` is given."""
+    buf = (ctypes.c_int * SVDU_TILE_BUCKETS)(*(table or [0] * SVDU_TILE_BUCKETS))
+    rc = svdu_tile_table(precision, ctypes.cast(buf, ctypes.c_void_p), 1 if table is not None else 0)
+    if rc != SVDU_OK:
+        raise SvduError(rc, "svdu_tile_table")
+    return list(buf)

@@ -8,9 +8,8 @@ namespace svdu {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Block tile of the product kernels: 128 x 128 outputs, K step 16.
-constexpr int kBM = 128, kBN = 128, kBK = 16;
-constexpr int kLDA = kBK + 1;  // padded LDS row of the LDS-staged X tile
+// K step of the product kernels.
+constexpr int kBK = 16;
 
 // Entry C~[j, c] from the descriptors (see svdu_internal.h).
 struct ColDesc {
@@ -61,10 +60,12 @@ __device__ __forceinline__ double live_entry(double z, double g, const ColDesc& 
   return (z == 0.0) ? 0.0 : v;
 }
 
+// For a live column this is the value live_entry computes (the same refined
+// reciprocal), so an entry does not depend on which path generated it.
 __device__ __forceinline__ double general_entry(int j, const RowVals& rv, const ColDesc& c) {
   if (c.type == 0) {
     if (rv.z == 0.0) return 0.0;
-    return (rv.z * c.s) / ((rv.g - c.o) - c.t);
+    return (rv.z * c.s) * recip((rv.g - c.o) - c.t);
   }
   if (c.type < 0 || rv.cl != c.cl) return 0.0;
   return ((j == c.mem) ? 1.0 : 0.0) - 2.0 * rv.h * c.h;
@@ -88,17 +89,21 @@ __device__ __forceinline__ double gen_entry(const CauchyDesc& d, int j, int N, c
 }
 
 
-// XCD-aware order of the 2-D tile grid: blocks are dealt to the 8 XCDs in
-// turn, so consecutive tiles of one block row (sharing an X panel) land on
-// the same XCD and its L2.
-__device__ __forceinline__ void tile_origin(int N, int* m0, int* n0) {
-  const int tiles_n = (N + kBN - 1) / kBN;
-  const int G = gridDim.x;
-  const int bid = blockIdx.x;
-  const int full = (G / 8) * 8;
-  const int lid = (bid < full) ? (bid % 8) * (G / 8) + bid / 8 : bid;
-  *m0 = (lid / tiles_n) * kBM;
-  *n0 = (lid % tiles_n) * kBN;
+// Tile shapes of the product kernels: 4 waves stacked along M, each wave
+// 16 MB rows (MB = 1 or 2 MFMA blocks of 16) by 64 NC columns (NC = 1 or 2).
+enum TileShape : int { kT128x128 = 0, kT64x128 = 1, kT128x64 = 2, kT64x64 = 3, kNumShapes = 4 };
+__host__ __device__ constexpr int shape_bm(int s) { return (s == kT64x128 || s == kT64x64) ? 64 : 128; }
+__host__ __device__ constexpr int shape_bn(int s) { return (s == kT128x64 || s == kT64x64) ? 64 : 128; }
+
+// XCD-aware order of a job's 2-D tile grid. Consecutive blocks of a launch
+// are dealt to the 8 XCDs in turn, so local tiles t with equal t % 8 share an
+// XCD whatever the job's first block is; they are given consecutive tiles of
+// one block row (sharing an X panel, and that XCD's L2).
+__device__ __forceinline__ void tile_origin(int t, int tiles, int tiles_n, int bm, int bn, int* m0, int* n0) {
+  const int full = (tiles / 8) * 8;
+  const int lid = (t < full) ? (t % 8) * (tiles / 8) + t / 8 : t;
+  *m0 = (lid / tiles_n) * bm;
+  *n0 = (lid % tiles_n) * bn;
 }
 
 }  // namespace svdu

@@ -1,0 +1,179 @@
+// The launch sequence of rank-1 SVD updates (Section 6.1 of the paper) over
+// job tables: one update (svdu_rank1_update) or many (the batched entry
+// points) run the same kernels in the same order, one launch per step for
+// all of them.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string.h>
+
+#include <vector>
+
+#include "cauchy_tile.h"
+#include "jobs.h"
+
+namespace svdu {
+
+// ---- workspace carving ------------------------------------------------------
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+void carve_stage(Carver& c, Stage& s, int cap);
+
+// Everything one update keeps in its workspace.
+struct Layout {
+  int* status;
+  double* scal;  // [0] beta [1] alpha [2] b.w1 [3] b.w2
+  double *p, *q, *t1, *t2, *w1, *w2;
+  double *zLp, *yLm, *pL1, *pL2, *zLm, *pL1b, *pL2b, *fL1, *fL2;
+  double *zRp, *yRm, *zRm, *pR1b, *pR2b, *fR1, *fR2;
+  double *lamLp, *lamRp, *signs;
+  double *gemv_pu, *gemv_pv;      // partial sums of the projections through U and V
+  double *renorm_u, *renorm_v;    // precision form: column sums of squares
+  double *TL, *TR;                // intermediate bases U~ (m x m) and V~ (n x n)
+  Stage st[4];                    // L+, L-, R+, R-
+  double* fmm_work;               // FMM path only
+  size_t fmm_elems;
+  char* fmm_plan;
+  size_t fmm_plan_bytes;
+  size_t bytes;
+};
+Layout carve_update(void* base, int m, int n, int path, int precision);
+
+// One rank-1 update: the caller's device buffers and its workspace layout.
+struct Update {
+  int m = 0, n = 0;
+  const double *U = nullptr, *sigma = nullptr, *V = nullptr, *a = nullptr, *b = nullptr;
+  int ldu = 0, ldv = 0;
+  double *U_out = nullptr, *sigma_out = nullptr, *V_out = nullptr;
+  int ldu_out = 0, ldv_out = 0;
+  int8_t* defl = nullptr;
+  Layout L;
+};
+
+// ---- per-update jobs (projections set-up, singular values, flags) -------------
+struct SetupArgs {
+  int m, n;
+  const double *sigma, *a, *b, *p, *q, *t1, *t2, *w1, *w2;
+  double* scal;
+  int* status;
+  double *rho1, *rho2, *rho3, *rho4;
+  double *zLp, *yLm, *pL1, *pL2, *lamLp;
+  double *zRp, *yRm, *lamRp;
+  int *colLp, *colLm, *colRp, *colRm;
+};
+
+struct ProbJob {
+  int m, n;
+  int* status;
+  double *w1, *w2;
+  SetupArgs setup;
+  const double *lamL, *fL1, *fL2, *fR1, *fR2;
+  double *sigma_out, *signs;
+  int8_t* defl;
+  const int8_t* flags[4];
+  int fN[4];
+};
+
+struct ProbList {
+  int n = 0;
+  int blocks_n = 0;             // ceil(n / 256) blocks per update
+  const int* boff_n = nullptr;
+  const ProbJob* job = nullptr;
+  int* counters = nullptr;      // persistent-schedule tile counters, zeroed by the first kernel
+  int ncounters = 0;
+};
+
+// Device views of the tables of one launch sequence.
+struct Plan {
+  int precision = 0;
+  bool any_defl = false;
+  ProbList prob;
+  GemvList gemv;
+  StageLevel lev[2];
+  GemmList gemm[2][kNumShapes];
+  RenormList renorm;
+  std::vector<Stage> host_stages;   // per update: L+, L-, R+, R- (host copies, for the FMM path)
+};
+
+// Appends arrays to a host blob that will be copied to dev_base; put()
+// returns the device address of the array (dev_base may be nullptr when only
+// sizing the blob).
+struct BlobWriter {
+  std::vector<char>* b;
+  char* base;
+  template <class T>
+  const T* put(const std::vector<T>& v) {
+    const size_t off = (b->size() + 15) & ~size_t(15);
+    b->resize(off + v.size() * sizeof(T));
+    if (!v.empty()) memcpy(b->data() + off, v.data(), v.size() * sizeof(T));
+    return reinterpret_cast<const T*>(reinterpret_cast<uintptr_t>(base) + off);
+  }
+};
+
+// A level of eigen-updates (largest first) with its block offsets.
+StageLevel build_level(const std::vector<Stage>& st, const std::vector<TmvJob>& tmv, BlobWriter& B);
+// A product job in the tile shape the chooser gives for (R, N, precision).
+GemmJob make_gemm_job(int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo, int precision);
+// A list of products of one tile shape, largest first.
+GemmList build_gemm_list(std::vector<GemmJob> jobs, int* counter, BlobWriter& B);
+
+// Tables of `ups` appended to `blob`, with device views relative to
+// dev_base (the device address the blob will be copied to; nullptr to size
+// the blob only). `counters` points at 2 * kNumShapes ints of device memory.
+void build_plan(const std::vector<Update>& ups, int precision, char* dev_base, int* counters,
+                std::vector<char>* blob, Plan* plan);
+
+// Bytes reserved in a single update's workspace for its tables.
+constexpr size_t kSingleTableBytes = 16384;
+
+// Copies a host blob to device memory with kernels whose arguments carry the
+// bytes (stream-ordered, safe to capture in a graph; no host buffer needs to
+// outlive the call).
+void write_blob(const std::vector<char>& blob, char* dst, hipStream_t st);
+
+// Step groups of the launch sequence.
+enum : int { kStepAll = 0, kStepUpToRoots = 1, kStepProductsOnward = 2 };
+struct Sched {
+  int maxit = 200;
+  bool persistent = false;
+  int grid_cap[2][kNumShapes] = {};   // [precision][shape]
+};
+// Enqueues the sequence (or a part of it: the FMM path runs the products
+// itself between the two parts).
+void enqueue_plan(const Plan& P, const Sched& S, int tcall, int part, hipStream_t st);
+
+// Gathers the status words of the plan's updates into out[0..n-1] (device).
+void enqueue_status_gather(const Plan& P, int* out, hipStream_t st);
+
+// ---- tile-shape choice ---------------------------------------------------------
+constexpr int kShapeBuckets = 8;   // N in (0,64], (64,128], ..., (4096, inf)
+int shape_bucket(int N);
+int choose_shape(int R, int N, int precision);
+int shape_table_get(int precision, int bucket);
+void shape_table_set(int precision, int bucket, int shape);
+int set_forced_shape(int shape);   // -1: use the table
+int gemm_grid_cap(int shape, int precision);   // blocks resident at once (persistent schedule)
+
+// ---- timing ring ---------------------------------------------------------------
+constexpr int kRingCalls = 256, kRingEvents = 6;
+int ring_begin();
+void ring_mark(int call, int k, hipStream_t st);
+int ring_set(bool on);
+int ring_read(double* ms, int max_calls);
+
+int status_code(int bits);
+
+}  // namespace svdu

@@ -1,0 +1,120 @@
+// Job tables. Every launch of libsvdu serves a list of independent jobs: the
+// eigen-updates, products or projections of one rank-1 update, or of many
+// updates batched together. Job i of a list owns blocks [boff[i], boff[i+1])
+// of the launch and a block finds its job by a binary search over boff (a
+// uniform loop over scalar loads). A job's arithmetic does not depend on the
+// other jobs of its list, so a result is the same alone and batched.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "svdu_internal.h"
+
+namespace svdu {
+
+// Largest i < n with boff[i] <= b (jobs with no blocks are skipped).
+__device__ __forceinline__ int find_job(const int* __restrict__ boff, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (boff[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Vectors carried through C~^T after an eigen-update: y_k = C~^T x_k, k < nv
+// (nv = 0: none).
+struct TmvJob {
+  int nv;
+  const double* x[3];
+  double* y[3];
+};
+
+// The eigen-updates of one level (the first or the second update of each
+// side of every rank-1 update in the launch), with the block offsets of the
+// three launch shapes used by the stage kernels: one block per job
+// (deflation), one wave per root or pole (4 per block), one thread per index
+// (256 per block).
+struct StageLevel {
+  int n = 0;
+  const Stage* st = nullptr;
+  const TmvJob* tmv = nullptr;   // n entries, or nullptr
+  const int* boff_w = nullptr;   // ceil(N / 4) blocks per job
+  const int* boff_t = nullptr;   // ceil(N / 256) blocks per job
+  int blocks_w = 0, blocks_t = 0;
+};
+
+// One product X_out = X C~ in the tile grid of the list's tile shape.
+struct GemmJob {
+  int R, ldx, ldo, vec_a;
+  int shape, tiles_n, tiles;
+  const double* X;
+  double* Xo;
+  CauchyDesc d;
+};
+
+struct GemmList {
+  int n = 0;
+  int blocks = 0;               // total tiles
+  const int* boff = nullptr;
+  const GemmJob* job = nullptr;
+  int* counter = nullptr;       // persistent schedule: next tile (zeroed before the launch)
+};
+
+// X^T [v0 v1 v2] for X row-major R x N, in column blocks x row chunks.
+struct GemvJob {
+  int R, N, ldx, nv, cblocks, chunks;
+  const double* X;
+  const double* v[3];
+  double* out[3];
+  double* part;
+};
+
+struct GemvList {
+  int n = 0;
+  int blocks_p = 0, blocks_r = 0;
+  const int* boff_p = nullptr;  // partial sums: cblocks * chunks blocks per job
+  const int* boff_r = nullptr;  // reduction: ceil(nv N / 256) blocks per job
+  const GemvJob* job = nullptr;
+};
+
+// Column renormalisation of one factor (precision form).
+struct RenormJob {
+  int R, N, ld, cblocks, chunks;
+  double* X;
+  double* part;
+  const int* status;
+};
+
+struct RenormList {
+  int n = 0;
+  int blocks = 0;
+  const int* boff = nullptr;    // cblocks * chunks per job
+  const RenormJob* job = nullptr;
+};
+
+// ---- launchers (each enqueues on `st`, no host synchronisation) ----------------
+// Projections of every GemvJob: partial sums per row chunk, then a
+// fixed-order reduction.
+void launch_gemv_list(const GemvList& L, hipStream_t st);
+int gemv_cblocks(int N);
+int gemv_chunks(int R);
+size_t gemv_t_scratch_elems(int R, int N, int nv);
+// Deflation, secular roots, Loewner weights, column norms, descriptors of
+// every eigen-update of a level.
+void launch_stage_level(const StageLevel& L, int maxit, hipStream_t st);
+// The secular solve alone (svdu_secular).
+void launch_secular_level(const StageLevel& L, int maxit, hipStream_t st);
+// y = C~^T x for the TmvJobs of a level.
+void launch_cauchy_tmatvec_level(const StageLevel& L, hipStream_t st);
+// X_out = X C~ for every job of the list, in tile shape `shape` (TileShape),
+// one block per tile (grid) or at most grid_cap blocks taking tiles from
+// L.counter (persistent).
+void launch_gemm_f64(const GemmList& L, int shape, bool persistent, int grid_cap, hipStream_t st);
+void launch_gemm_split32(const GemmList& L, int shape, bool persistent, int grid_cap, hipStream_t st);
+// Column renormalisation of every RenormJob; scratch per job >=
+// renorm_scratch_elems(R, N) doubles.
+void launch_column_renorm(const RenormList& L, hipStream_t st);
+size_t renorm_scratch_elems(int R, int N);
+
+}  // namespace svdu

@@ -4,15 +4,16 @@
 // C~^T of the first applied to U^T b1, since U~^T b1 = C~^T U^T b1) and maps
 // the sign probes.
 #include "cauchy_tile.h"
+#include "jobs.h"
 
 namespace svdu {
 
 // ---------------------------------------------------------------------------
 // y = C~^T x
 // ---------------------------------------------------------------------------
-__global__ void householder_dots(Stage s, int nv, const double* x0, const double* x1, const double* x2) {
+__device__ void householder_dots_body(const Stage& s, int nv, const double* x0, const double* x1,
+                                      const double* x2, int c) {
   if (*s.status & kStFatal) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int K = s.counts[0];
   if (c >= K) return;
   const int sz = s.csize[c];
@@ -31,13 +32,10 @@ __global__ void householder_dots(Stage s, int nv, const double* x0, const double
   s.hx[3 * c + 2] = a2;
 }
 
-__global__ __launch_bounds__(256) void cauchy_tmatvec_kernel(CauchyDesc d, const double* __restrict__ hx, int nv,
-                                                             const double* __restrict__ x0,
-                                                             const double* __restrict__ x1,
-                                                             const double* __restrict__ x2, double* y0,
-                                                             double* y1, double* y2) {
+__device__ void cauchy_tmatvec_body(const CauchyDesc& d, const double* __restrict__ hx, int nv,
+                                    const double* __restrict__ x0, const double* __restrict__ x1,
+                                    const double* __restrict__ x2, double* y0, double* y1, double* y2, int c) {
   if (*d.status & kStFatal) return;
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= d.N) return;
   const ColDesc cd = load_col(d, c);
@@ -67,16 +65,32 @@ __global__ __launch_bounds__(256) void cauchy_tmatvec_kernel(CauchyDesc d, const
   }
 }
 
-void launch_cauchy_tmatvec(const Stage& s, int nv, const double* const* x, double* const* y, hipStream_t st) {
-  const int N = s.N;
-  if (N <= 0) return;
-  const double* x1 = nv > 1 ? x[1] : x[0];
-  const double* x2 = nv > 2 ? x[2] : x[0];
-  double* y1 = nv > 1 ? y[1] : nullptr;
-  double* y2 = nv > 2 ? y[2] : nullptr;
-  hipLaunchKernelGGL(householder_dots, dim3((N + 255) / 256), dim3(256), 0, st, s, nv, x[0], x1, x2);
-  hipLaunchKernelGGL(cauchy_tmatvec_kernel, dim3((N + 3) / 4), dim3(256), 0, st, desc_of(s), s.hx, nv, x[0], x1,
-                     x2, y[0], y1, y2);
+// Level kernels over the jobs of a StageLevel (jobs with nv = 0 do nothing).
+__global__ void householder_dots(StageLevel L) {
+  const int j = find_job(L.boff_t, L.n, blockIdx.x);
+  const TmvJob t = L.tmv[j];
+  if (t.nv <= 0) return;
+  const Stage s = L.st[j];
+  const double* x1 = t.nv > 1 ? t.x[1] : t.x[0];
+  const double* x2 = t.nv > 2 ? t.x[2] : t.x[0];
+  householder_dots_body(s, t.nv, t.x[0], x1, x2, (blockIdx.x - L.boff_t[j]) * 256 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void cauchy_tmatvec_kernel(StageLevel L) {
+  const int j = find_job(L.boff_w, L.n, blockIdx.x);
+  const TmvJob t = L.tmv[j];
+  if (t.nv <= 0) return;
+  const Stage s = L.st[j];
+  const double* x1 = t.nv > 1 ? t.x[1] : t.x[0];
+  const double* x2 = t.nv > 2 ? t.x[2] : t.x[0];
+  cauchy_tmatvec_body(desc_of(s), s.hx, t.nv, t.x[0], x1, x2, t.y[0], t.y[1], t.y[2],
+                      (blockIdx.x - L.boff_w[j]) * 4 + (threadIdx.x >> 6));
+}
+
+void launch_cauchy_tmatvec_level(const StageLevel& L, hipStream_t st) {
+  if (L.n <= 0 || !L.tmv || L.blocks_w <= 0) return;
+  hipLaunchKernelGGL(householder_dots, dim3(L.blocks_t), dim3(256), 0, st, L);
+  hipLaunchKernelGGL(cauchy_tmatvec_kernel, dim3(L.blocks_w), dim3(256), 0, st, L);
 }
 
 }  // namespace svdu

@@ -1,151 +1,64 @@
 // X_out = X C~ in FP64 on the matrix cores (RankOneUpdate Steps 4-7,
 // equation UCTildeProduct): the dense product of the direct path, with the
 // C~ tiles regenerated from O(N) descriptors and never stored in HBM.
-#include <stdint.h>
-
-#include "cauchy_tile.h"
-
-namespace svdu {
-
-// ---------------------------------------------------------------------------
-// X_out = X C~, FP64 MFMA (v_mfma_f64_16x16x4f64): first variant, kept for
-// comparison (SVDU_OPT_GEMM_VARIANT 1). Both operands are staged in LDS.
 //
-// Block tile 128 x 128, 4 waves in a 2 x 2 grid, each wave 64 x 64 = 4 x 4
-// MFMA blocks. K advances 16 at a time: the X tile (128 x 16) is loaded from
-// HBM into registers one step ahead, the C~ tile (16 x 128) is generated by
-// the VALU from O(N) descriptors (it never exists in HBM), both are staged in
-// LDS, then 64 MFMAs per wave consume them.
-//
-// MFMA operand layout (lane l): A[l % 16][l / 16], B[l / 16][l % 16];
-// result register v holds D[l / 16 + 4 v][l % 16].
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(256, 2) void gemm_cauchy_f64_lds_kernel(int R, const double* __restrict__ X, int ldx,
-                                                                 CauchyDesc d, double* __restrict__ Xo,
-                                                                 int ldo) {
-  __shared__ double As[kBM * kLDA];
-  __shared__ double Bs[kBK * kBN];
-  if (*d.status & kStFatal) return;
-  const int N = d.N;
-  int m0, n0;
-  tile_origin(N, &m0, &n0);
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int ar = tid >> 1, ak = (tid & 1) * 8;      // X tile: row, k offset
-  const int bn = tid & 127, bk = (tid >> 7) * 8;    // C~ tile: column, k offset
-  const ColDesc cd = load_col(d, n0 + bn);
-
-  d4 acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-
-  double ra[8], rb[8];
-  const int arow = m0 + ar;
-  const double* xrow = X + (size_t)(arow < R ? arow : 0) * ldx;
-  auto loadA = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int k = k0 + ak + q;
-      ra[q] = (arow < R && k < N) ? xrow[k] : 0.0;
-    }
-  };
-  auto genB = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) rb[q] = cauchy_entry(d, k0 + bk + q, cd);
-  };
-
-  const int nk = (N + kBK - 1) / kBK;
-  loadA(0);
-  genB(0);
-  for (int kc = 0; kc < nk; ++kc) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      As[ar * kLDA + ak + q] = ra[q];
-      Bs[(bk + q) * kBN + bn] = rb[q];
-    }
-    __syncthreads();
-    if (kc + 1 < nk) loadA((kc + 1) * kBK);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      double af[4], bf[4];
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) af[mb] = As[(wm * 64 + mb * 16 + (lane & 15)) * kLDA + s * 4 + (lane >> 4)];
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) bf[nb] = Bs[(s * 4 + (lane >> 4)) * kBN + wn * 64 + nb * 16 + (lane & 15)];
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb)
-          acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mb], bf[nb], acc[mb][nb], 0, 0, 0);
-    }
-    if (kc + 1 < nk) genB((kc + 1) * kBK);
-  }
-
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-    const int col = n0 + wn * 64 + nb * 16 + (lane & 15);
-    if (col >= N) continue;
-    const double sc = d.colscale ? d.colscale[col] : 1.0;
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm * 64 + mb * 16 + (lane >> 4) + 4 * v;
-        if (row < R) Xo[(size_t)row * ldo + col] = sc * acc[mb][nb][v];
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// The product kernel (default).
-//
-// 128 x 128 block tile, four waves stacked along M: wave w owns rows
-// 32 w .. 32 w + 31 and all 128 columns (2 x 8 MFMA blocks), so no wave loads
-// the X rows of another. K advances 16 per step. X fragments come straight
-// from HBM into registers one step ahead, in a K-permuted layout: in MFMA
-// step s, lane l supplies X[row][k0 + 4 (l/16) + s] (four consecutive doubles
-// of one row per lane) and the matching C~ entry C~[k0 + 4 (l/16) + s][col];
-// the contraction covers all 16 k either way. Two register sets are used
-// alternately (the K loop is unrolled by two). C~
+// One launch serves a list of products (GemmList). Four waves are stacked
+// along M: wave w owns 16 MB rows of the block tile and all of its 64 NC
+// columns, so no wave loads the X rows of another. K advances 16 per step.
+// X fragments come straight from HBM into registers one step ahead, in a
+// K-permuted layout: in MFMA step s, lane l supplies X[row][k0 + 4 (l/16) + s]
+// (four consecutive doubles of one row per lane) and the matching entry
+// C~[k0 + 4 (l/16) + s][col]; the contraction covers all 16 k either way.
+// Two register sets are used alternately (the K loop is unrolled by two). C~
 // tiles are double-buffered in LDS, one barrier per step. Wave w generates C~
 // rows 4 w .. 4 w + 3 of the next step; the generation of row s sits right
 // after the MFMAs of step s so that the VALU work overlaps the matrix core.
-// A block whose 128 columns are all secular roots (the usual case) runs the
-// Cauchy formula without any branch; other blocks use the general entry.
-// ---------------------------------------------------------------------------
-template <bool LIVE>
-__device__ __forceinline__ void gemm_v3_body(int R, const double* __restrict__ X, int ldx, const CauchyDesc& d,
-                                             double* __restrict__ Xo, int ldo, int vec_a, int m0, int n0,
-                                             const ColDesc& c0, const ColDesc& c1, double* Bs0, double* Bs1) {
-  const int N = d.N;
+// A block whose columns are all secular roots (the usual case) runs the
+// Cauchy formula without any branch; other blocks use the general entry,
+// which gives the same values.
+//
+// Every output element is accumulated by the same sequence of MFMAs (the
+// K order and permutation do not depend on the tile shape or on the other
+// jobs), so the result is bitwise the same for every tile shape, schedule and
+// batch composition.
+//
+// MFMA v_mfma_f64_16x16x4f64 operand layout (lane l): A[l % 16][l / 16],
+// B[l / 16][l % 16]; result register v holds D[l / 16 + 4 v][l % 16].
+#include <stdint.h>
+
+#include "cauchy_tile.h"
+#include "jobs.h"
+
+namespace svdu {
+
+template <int MB, int NC, bool LIVE>
+__device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, const ColDesc (&cc)[NC],
+                                              double* Bs0, double* Bs1) {
+  constexpr int BN = 64 * NC, NB = 4 * NC;
+  const CauchyDesc& d = J.d;
+  const int N = d.N, R = J.R;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kq = 4 * (lane >> 4);
-  const double* xr[2];
-  bool rok[2];
+  const double* xr[MB];
+  bool rok[MB];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb) {
-    const int r = m0 + wave * 32 + mb * 16 + (lane & 15);
+  for (int mb = 0; mb < MB; ++mb) {
+    const int r = m0 + wave * 16 * MB + mb * 16 + (lane & 15);
     rok[mb] = r < R;
-    xr[mb] = X + (size_t)(rok[mb] ? r : 0) * ldx;
+    xr[mb] = J.X + (size_t)(rok[mb] ? r : 0) * J.ldx;
   }
-  d4 acc[2][8];
+  d4 acc[MB][NB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MB; ++a)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  double aA[2][4], aB[2][4], bg[4][2];
-  auto loadA = [&](int k0, double (&a)[2][4]) {
+  double aA[MB][4], aB[MB][4], bg[4][NC];
+  auto loadA = [&](int k0, double (&a)[MB][4]) {
     const int kb = k0 + kq;
-    if (vec_a && k0 + kBK <= N) {   // block-uniform: the whole step is in range
+    if (J.vec_a && k0 + kBK <= N) {   // block-uniform: the whole step is in range
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb) {
+      for (int mb = 0; mb < MB; ++mb) {
         const double2 v0 = *reinterpret_cast<const double2*>(xr[mb] + kb);
         const double2 v1 = *reinterpret_cast<const double2*>(xr[mb] + kb + 2);
         a[mb][0] = rok[mb] ? v0.x : 0.0;
@@ -155,7 +68,7 @@ __device__ __forceinline__ void gemm_v3_body(int R, const double* __restrict__ X
       }
     } else {
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+      for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int k = kb + s;
@@ -164,38 +77,42 @@ __device__ __forceinline__ void gemm_v3_body(int R, const double* __restrict__ X
         }
     }
   };
-  // one K step: MFMAs on (a, Bs[buf]) interleaved with generating step kn
-  auto step = [&](const double (&a)[2][4], const double* Bcur, double* Bnext, int kn) {
+  // entries of C~ rows jb .. jb + 3 for this lane's NC columns
+  auto fix_tiny = [&](int jb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = jb + r;
+      const int jj = j < N ? j : N - 1;
+      RowVals rv{(j < N) ? d.rzeta[jj] : 0.0, d.rg[jj], 0.0, -2};
+#pragma unroll
+      for (int c = 0; c < NC; ++c) bg[r][c] = general_entry(j, rv, cc[c]);
+    }
+  };
+  auto store_b = [&](double* Bn) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) Bn[(4 * wave + r) * BN + 64 * c + lane] = bg[r][c];
+  };
+  // one K step: MFMAs on (a, Bcur) interleaved with generating step kn
+  auto step = [&](const double (&a)[MB][4], const double* Bcur, double* Bnext, int kn) {
     double mind = 1.0;
     const int jb = kn + 4 * wave;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      double bf[8];
+      double bf[NB];
 #pragma unroll
-      for (int nb = 0; nb < 8; ++nb) bf[nb] = Bcur[(kq + s) * kBN + nb * 16 + (lane & 15)];
+      for (int nb = 0; nb < NB; ++nb) bf[nb] = Bcur[(kq + s) * BN + nb * 16 + (lane & 15)];
 #pragma unroll
-      for (int nb = 0; nb < 8; ++nb)
+      for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
+        for (int mb = 0; mb < MB; ++mb)
           acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb][s], bf[nb], acc[mb][nb], 0, 0, 0);
-      bg[s][0] = gen_entry<LIVE>(d, jb + s, N, c0, &mind);
-      bg[s][1] = gen_entry<LIVE>(d, jb + s, N, c1, &mind);
-    }
-    if (LIVE && __any(mind < 0x1p-1000)) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = jb + r;
-        const int jj = j < N ? j : N - 1;
-        RowVals rv{(j < N) ? d.rzeta[jj] : 0.0, d.rg[jj], 0.0, -2};
-        bg[r][0] = general_entry(j, rv, c0);
-        bg[r][1] = general_entry(j, rv, c1);
-      }
+      for (int c = 0; c < NC; ++c) bg[s][c] = gen_entry<LIVE>(d, jb + s, N, cc[c], &mind);
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      Bnext[(4 * wave + r) * kBN + lane] = bg[r][0];
-      Bnext[(4 * wave + r) * kBN + 64 + lane] = bg[r][1];
-    }
+    if (LIVE && __any(mind < 0x1p-1000)) fix_tiny(jb);
+    store_b(Bnext);
     __syncthreads();
   };
 
@@ -204,25 +121,11 @@ __device__ __forceinline__ void gemm_v3_body(int R, const double* __restrict__ X
   {
     double mind = 1.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      bg[r][0] = gen_entry<LIVE>(d, 4 * wave + r, N, c0, &mind);
-      bg[r][1] = gen_entry<LIVE>(d, 4 * wave + r, N, c1, &mind);
-    }
-    if (LIVE && __any(mind < 0x1p-1000)) {
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = 4 * wave + r;
-        const int jj = j < N ? j : N - 1;
-        RowVals rv{(j < N) ? d.rzeta[jj] : 0.0, d.rg[jj], 0.0, -2};
-        bg[r][0] = general_entry(j, rv, c0);
-        bg[r][1] = general_entry(j, rv, c1);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      Bs0[(4 * wave + r) * kBN + lane] = bg[r][0];
-      Bs0[(4 * wave + r) * kBN + 64 + lane] = bg[r][1];
-    }
+      for (int c = 0; c < NC; ++c) bg[r][c] = gen_entry<LIVE>(d, 4 * wave + r, N, cc[c], &mind);
+    if (LIVE && __any(mind < 0x1p-1000)) fix_tiny(4 * wave);
+    store_b(Bs0);
   }
   loadA(0, aA);
   __syncthreads();
@@ -237,57 +140,111 @@ __device__ __forceinline__ void gemm_v3_body(int R, const double* __restrict__ X
   if (kc < nk) step(aA, Bs0, Bs1, kc * kBK);
 
 #pragma unroll
-  for (int nb = 0; nb < 8; ++nb) {
+  for (int nb = 0; nb < NB; ++nb) {
     const int col = n0 + nb * 16 + (lane & 15);
     if (col >= N) continue;
     const double sc = d.colscale ? d.colscale[col] : 1.0;
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
+    for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wave * 32 + mb * 16 + (lane >> 4) + 4 * v;
-        if (row < R) Xo[(size_t)row * ldo + col] = sc * acc[mb][nb][v];
+        const int row = m0 + wave * 16 * MB + mb * 16 + (lane >> 4) + 4 * v;
+        if (row < R) J.Xo[(size_t)row * J.ldo + col] = sc * acc[mb][nb][v];
       }
     }
   }
 }
 
-__global__ __launch_bounds__(256, 2) void gemm_cauchy_f64_kernel(int R, const double* __restrict__ X, int ldx,
-                                                                    CauchyDesc d, double* __restrict__ Xo, int ldo,
-                                                                    int vec_a) {
-  __shared__ double Bs[2][kBK * kBN];
-  if (*d.status & kStFatal) return;
-  const int N = d.N;
+// One tile (work item) of a GemmList.
+template <int MB, int NC>
+__device__ __forceinline__ void gemm_f64_tile(const GemmList& L, int item, double* Bs0, double* Bs1) {
+  constexpr int BM = 64 * MB, BN = 64 * NC;
+  const int j = find_job(L.boff, L.n, item);
+  const GemmJob J = L.job[j];
+  if (*J.d.status & kStFatal) return;
   int m0, n0;
-  tile_origin(N, &m0, &n0);
+  tile_origin(item - L.boff[j], J.tiles, J.tiles_n, BM, BN, &m0, &n0);
   const int lane = threadIdx.x & 63;
-  const ColDesc c0 = load_col(d, n0 + lane);
-  const ColDesc c1 = load_col(d, n0 + 64 + lane);
-  const bool live = __syncthreads_and((c0.type == 0) && (c1.type == 0));
-  if (live)
-    gemm_v3_body<true>(R, X, ldx, d, Xo, ldo, vec_a, m0, n0, c0, c1, Bs[0], Bs[1]);
+  ColDesc cc[NC];
+  bool live = true;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    cc[c] = load_col(J.d, n0 + 64 * c + lane);
+    live = live && cc[c].type == 0;
+  }
+  if (__syncthreads_and(live))
+    gemm_f64_body<MB, NC, true>(J, m0, n0, cc, Bs0, Bs1);
   else
-    gemm_v3_body<false>(R, X, ldx, d, Xo, ldo, vec_a, m0, n0, c0, c1, Bs[0], Bs[1]);
+    gemm_f64_body<MB, NC, false>(J, m0, n0, cc, Bs0, Bs1);
 }
 
-int g_gemm_variant = 2;
+// Grid schedule: one block per tile, in list order.
+template <int MB, int NC>
+__global__ __launch_bounds__(256, 2) void gemm_cauchy_f64_kernel(GemmList L) {
+  __shared__ double Bs[2][kBK * 64 * NC];
+  gemm_f64_tile<MB, NC>(L, blockIdx.x, Bs[0], Bs[1]);
+}
 
-void launch_gemm_cauchy_f64(int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo,
-                            hipStream_t st) {
-  if (R <= 0 || d.N <= 0) return;
-  const int tm = (R + kBM - 1) / kBM, tn = (d.N + kBN - 1) / kBN;
-  if (g_gemm_variant == 1) {
-    hipLaunchKernelGGL(gemm_cauchy_f64_lds_kernel, dim3(tm * tn), dim3(256), 0, st, R, X, ldx, d, Xo, ldo);
-  } else {
-    const int vec_a = ((ldx % 2) == 0 && (reinterpret_cast<uintptr_t>(X) % 16) == 0) ? 1 : 0;
-    hipLaunchKernelGGL(gemm_cauchy_f64_kernel, dim3(tm * tn), dim3(256), 0, st, R, X, ldx, d, Xo, ldo, vec_a);
+// Persistent schedule: as many blocks as fit on the device at once; each
+// takes tiles in list order from a counter until the list is exhausted.
+template <int MB, int NC>
+__global__ __launch_bounds__(256, 2) void gemm_cauchy_f64_persistent(GemmList L) {
+  __shared__ double Bs[2][kBK * 64 * NC];
+  __shared__ int next;
+  if (threadIdx.x == 0) next = atomicAdd(L.counter, 1);
+  __syncthreads();
+  int item = next;
+  while (item < L.blocks) {
+    gemm_f64_tile<MB, NC>(L, item, Bs[0], Bs[1]);
+    __syncthreads();   // every thread has read `next` and finished with Bs
+    if (threadIdx.x == 0) next = atomicAdd(L.counter, 1);
+    __syncthreads();
+    item = next;
   }
 }
 
-int set_gemm_variant(int v) {
-  const int old = g_gemm_variant;
-  g_gemm_variant = v;
-  return old;
+namespace {
+template <int MB, int NC>
+void launch_shape(const GemmList& L, bool persistent, int grid_cap, hipStream_t st) {
+  if (persistent) {
+    const int g = L.blocks < grid_cap ? L.blocks : grid_cap;
+    hipLaunchKernelGGL((gemm_cauchy_f64_persistent<MB, NC>), dim3(g), dim3(256), 0, st, L);
+  } else {
+    hipLaunchKernelGGL((gemm_cauchy_f64_kernel<MB, NC>), dim3(L.blocks), dim3(256), 0, st, L);
+  }
+}
+}  // namespace
+
+void launch_gemm_f64(const GemmList& L, int shape, bool persistent, int grid_cap, hipStream_t st) {
+  if (L.n <= 0 || L.blocks <= 0) return;
+  switch (shape) {
+    case kT64x128: launch_shape<1, 2>(L, persistent, grid_cap, st); break;
+    case kT128x64: launch_shape<2, 1>(L, persistent, grid_cap, st); break;
+    case kT64x64: launch_shape<1, 1>(L, persistent, grid_cap, st); break;
+    default: launch_shape<2, 2>(L, persistent, grid_cap, st); break;
+  }
+}
+
+namespace {
+template <int MB, int NC>
+int resident_blocks_gemm_f64_grid_cap() {
+  int dev = 0, cus = 0, nb = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_cauchy_f64_persistent<MB, NC>, 256, 0) != hipSuccess) return 0;
+  return nb * cus;
+}
+}  // namespace
+
+// Blocks of the persistent kernel of `shape` that fit on the current device
+// at once (0 if the runtime cannot tell).
+int gemm_f64_grid_cap(int shape) {
+  switch (shape) {
+    case kT64x128: return resident_blocks_gemm_f64_grid_cap<1, 2>();
+    case kT128x64: return resident_blocks_gemm_f64_grid_cap<2, 1>();
+    case kT64x64: return resident_blocks_gemm_f64_grid_cap<1, 1>();
+    default: return resident_blocks_gemm_f64_grid_cap<2, 2>();
+  }
 }
 
 }  // namespace svdu

@@ -3,6 +3,7 @@
 #include <stdint.h>
 
 #include "cauchy_tile.h"
+#include "jobs.h"
 
 namespace svdu {
 
@@ -19,34 +20,34 @@ namespace svdu {
 // ---------------------------------------------------------------------------
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-template <bool LIVE>
-__device__ __forceinline__ void gemm_split32_body(int R, const double* __restrict__ X, int ldx,
-                                                  const CauchyDesc& d, double* __restrict__ Xo, int ldo,
-                                                  int vec_a, int m0, int n0, const ColDesc& c0,
-                                                  const ColDesc& c1, float2* Bs0, float2* Bs1) {
-  const int N = d.N;
+template <int MB, int NC, bool LIVE>
+__device__ __forceinline__ void gemm_split32_body(const GemmJob& J, int m0, int n0, const ColDesc (&cc)[NC],
+                                                  float2* Bs0, float2* Bs1) {
+  constexpr int BN = 64 * NC, NB = 4 * NC;
+  const CauchyDesc& d = J.d;
+  const int N = d.N, R = J.R;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kq = 4 * (lane >> 4);
-  const double* xr[2];
-  bool rok[2];
+  const double* xr[MB];
+  bool rok[MB];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb) {
-    const int r = m0 + wave * 32 + mb * 16 + (lane & 15);
+  for (int mb = 0; mb < MB; ++mb) {
+    const int r = m0 + wave * 16 * MB + mb * 16 + (lane & 15);
     rok[mb] = r < R;
-    xr[mb] = X + (size_t)(rok[mb] ? r : 0) * ldx;
+    xr[mb] = J.X + (size_t)(rok[mb] ? r : 0) * J.ldx;
   }
-  d4 acc[2][8];
+  d4 acc[MB][NB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MB; ++a)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  double aX[2][4], bg[4][2];
+  double aX[MB][4], bg[4][NC];
   auto loadA = [&](int k0) {
     const int kb = k0 + kq;
-    if (vec_a && k0 + kBK <= N) {
+    if (J.vec_a && k0 + kBK <= N) {
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb) {
+      for (int mb = 0; mb < MB; ++mb) {
         const double2 v0 = *reinterpret_cast<const double2*>(xr[mb] + kb);
         const double2 v1 = *reinterpret_cast<const double2*>(xr[mb] + kb + 2);
         aX[mb][0] = rok[mb] ? v0.x : 0.0;
@@ -56,7 +57,7 @@ __device__ __forceinline__ void gemm_split32_body(int R, const double* __restric
       }
     } else {
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+      for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int k = kb + s;
@@ -73,25 +74,23 @@ __device__ __forceinline__ void gemm_split32_body(int R, const double* __restric
     double mind = 1.0;
     const int jb = kn + 4 * wave;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      bg[r][0] = gen_entry<LIVE>(d, jb + r, N, c0, &mind);
-      bg[r][1] = gen_entry<LIVE>(d, jb + r, N, c1, &mind);
-    }
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) bg[r][c] = gen_entry<LIVE>(d, jb + r, N, cc[c], &mind);
     if (LIVE && __any(mind < 0x1p-1000)) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int j = jb + r;
         const int jj = j < N ? j : N - 1;
         RowVals rv{(j < N) ? d.rzeta[jj] : 0.0, d.rg[jj], 0.0, -2};
-        bg[r][0] = general_entry(j, rv, c0);
-        bg[r][1] = general_entry(j, rv, c1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) bg[r][c] = general_entry(j, rv, cc[c]);
       }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      Bn[(4 * wave + r) * kBN + lane] = split(bg[r][0]);
-      Bn[(4 * wave + r) * kBN + 64 + lane] = split(bg[r][1]);
-    }
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) Bn[(4 * wave + r) * BN + 64 * c + lane] = split(bg[r][c]);
   };
 
   const int nk = (N + kBK - 1) / kBK;
@@ -101,9 +100,9 @@ __device__ __forceinline__ void gemm_split32_body(int R, const double* __restric
   for (int kc = 0; kc < nk; ++kc) {
     const float2* Bc = (kc & 1) ? Bs1 : Bs0;
     float2* Bn = (kc & 1) ? Bs0 : Bs1;
-    float ah[2][4], al[2][4];
+    float ah[MB][4], al[MB][4];
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const float2 t = split(aX[mb][s]);
@@ -112,29 +111,29 @@ __device__ __forceinline__ void gemm_split32_body(int R, const double* __restric
       }
     const int kn = (kc + 1 < nk) ? (kc + 1) * kBK : kc * kBK;
     loadA(kn);
-    f4 a32[2][8];
+    f4 a32[MB][NB];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < MB; ++a)
 #pragma unroll
-      for (int b = 0; b < 8; ++b) a32[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int b = 0; b < NB; ++b) a32[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      float2 bf[8];
+      float2 bf[NB];
 #pragma unroll
-      for (int nb = 0; nb < 8; ++nb) bf[nb] = Bc[(kq + s) * kBN + nb * 16 + (lane & 15)];
+      for (int nb = 0; nb < NB; ++nb) bf[nb] = Bc[(kq + s) * BN + nb * 16 + (lane & 15)];
 #pragma unroll
-      for (int nb = 0; nb < 8; ++nb)
+      for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
+        for (int mb = 0; mb < MB; ++mb) {
           a32[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(al[mb][s], bf[nb].x, a32[mb][nb], 0, 0, 0);
           a32[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[mb][s], bf[nb].y, a32[mb][nb], 0, 0, 0);
           a32[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[mb][s], bf[nb].x, a32[mb][nb], 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < MB; ++a)
 #pragma unroll
-      for (int b = 0; b < 8; ++b)
+      for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[a][b][v] += (double)a32[a][b][v];
     gen_store(kn, Bn);
@@ -142,45 +141,85 @@ __device__ __forceinline__ void gemm_split32_body(int R, const double* __restric
   }
 
 #pragma unroll
-  for (int nb = 0; nb < 8; ++nb) {
+  for (int nb = 0; nb < NB; ++nb) {
     const int col = n0 + nb * 16 + (lane & 15);
     if (col >= N) continue;
     const double sc = d.colscale ? d.colscale[col] : 1.0;
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
+    for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wave * 32 + mb * 16 + 4 * (lane >> 4) + v;
-        if (row < R) Xo[(size_t)row * ldo + col] = sc * acc[mb][nb][v];
+        const int row = m0 + wave * 16 * MB + mb * 16 + 4 * (lane >> 4) + v;
+        if (row < R) J.Xo[(size_t)row * J.ldo + col] = sc * acc[mb][nb][v];
       }
     }
   }
 }
 
-__global__ __launch_bounds__(256, 1) void gemm_cauchy_split32_kernel(int R, const double* __restrict__ X, int ldx,
-                                                                     CauchyDesc d, double* __restrict__ Xo,
-                                                                     int ldo, int vec_a) {
-  __shared__ float2 Bs[2][kBK * kBN];
-  if (*d.status & kStFatal) return;
-  const int N = d.N;
+template <int MB, int NC>
+__device__ __forceinline__ void gemm_split32_tile(const GemmList& L, int item, float2* Bs0, float2* Bs1) {
+  constexpr int BM = 64 * MB, BN = 64 * NC;
+  const int j = find_job(L.boff, L.n, item);
+  const GemmJob J = L.job[j];
+  if (*J.d.status & kStFatal) return;
   int m0, n0;
-  tile_origin(N, &m0, &n0);
+  tile_origin(item - L.boff[j], J.tiles, J.tiles_n, BM, BN, &m0, &n0);
   const int lane = threadIdx.x & 63;
-  const ColDesc c0 = load_col(d, n0 + lane);
-  const ColDesc c1 = load_col(d, n0 + 64 + lane);
-  const bool live = __syncthreads_and((c0.type == 0) && (c1.type == 0));
-  if (live)
-    gemm_split32_body<true>(R, X, ldx, d, Xo, ldo, vec_a, m0, n0, c0, c1, Bs[0], Bs[1]);
+  ColDesc cc[NC];
+  bool live = true;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    cc[c] = load_col(J.d, n0 + 64 * c + lane);
+    live = live && cc[c].type == 0;
+  }
+  if (__syncthreads_and(live))
+    gemm_split32_body<MB, NC, true>(J, m0, n0, cc, Bs0, Bs1);
   else
-    gemm_split32_body<false>(R, X, ldx, d, Xo, ldo, vec_a, m0, n0, c0, c1, Bs[0], Bs[1]);
+    gemm_split32_body<MB, NC, false>(J, m0, n0, cc, Bs0, Bs1);
 }
 
-void launch_gemm_cauchy_split32(int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo,
-                                hipStream_t st) {
-  if (R <= 0 || d.N <= 0) return;
-  const int tm = (R + kBM - 1) / kBM, tn = (d.N + kBN - 1) / kBN;
-  const int vec_a = ((ldx % 2) == 0 && (reinterpret_cast<uintptr_t>(X) % 16) == 0) ? 1 : 0;
-  hipLaunchKernelGGL(gemm_cauchy_split32_kernel, dim3(tm * tn), dim3(256), 0, st, R, X, ldx, d, Xo, ldo, vec_a);
+template <int MB, int NC>
+__global__ __launch_bounds__(256, 1) void gemm_cauchy_split32_kernel(GemmList L) {
+  __shared__ float2 Bs[2][kBK * 64 * NC];
+  gemm_split32_tile<MB, NC>(L, blockIdx.x, Bs[0], Bs[1]);
+}
+
+template <int MB, int NC>
+__global__ __launch_bounds__(256, 1) void gemm_cauchy_split32_persistent(GemmList L) {
+  __shared__ float2 Bs[2][kBK * 64 * NC];
+  __shared__ int next;
+  if (threadIdx.x == 0) next = atomicAdd(L.counter, 1);
+  __syncthreads();
+  int item = next;
+  while (item < L.blocks) {
+    gemm_split32_tile<MB, NC>(L, item, Bs[0], Bs[1]);
+    __syncthreads();
+    if (threadIdx.x == 0) next = atomicAdd(L.counter, 1);
+    __syncthreads();
+    item = next;
+  }
+}
+
+namespace {
+template <int MB, int NC>
+void launch_shape32(const GemmList& L, bool persistent, int grid_cap, hipStream_t st) {
+  if (persistent) {
+    const int g = L.blocks < grid_cap ? L.blocks : grid_cap;
+    hipLaunchKernelGGL((gemm_cauchy_split32_persistent<MB, NC>), dim3(g), dim3(256), 0, st, L);
+  } else {
+    hipLaunchKernelGGL((gemm_cauchy_split32_kernel<MB, NC>), dim3(L.blocks), dim3(256), 0, st, L);
+  }
+}
+}  // namespace
+
+void launch_gemm_split32(const GemmList& L, int shape, bool persistent, int grid_cap, hipStream_t st) {
+  if (L.n <= 0 || L.blocks <= 0) return;
+  switch (shape) {
+    case kT64x128: launch_shape32<1, 2>(L, persistent, grid_cap, st); break;
+    case kT128x64: launch_shape32<2, 1>(L, persistent, grid_cap, st); break;
+    case kT64x64: launch_shape32<1, 1>(L, persistent, grid_cap, st); break;
+    default: launch_shape32<2, 2>(L, persistent, grid_cap, st); break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -188,38 +227,71 @@ void launch_gemm_cauchy_split32(int R, const double* X, int ldx, const CauchyDes
 // rescaled to unit FP64 norm (column sums of squares in per-chunk partials,
 // reduced in fixed order).
 // ---------------------------------------------------------------------------
-__global__ void colsumsq_partial(int R, int N, const double* __restrict__ X, int ldx, double* __restrict__ part) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r0 = blockIdx.y * 128, r1 = min(R, r0 + 128);
-  if (j >= N) return;
+__device__ void colsumsq_body(const RenormJob& J, int cb, int chunk) {
+  const int j = cb * 256 + threadIdx.x;
+  const int r0 = chunk * 128, r1 = min(J.R, r0 + 128);
+  if (j >= J.N) return;
   double s = 0.0;
   for (int r = r0; r < r1; ++r) {
-    const double x = X[(size_t)r * ldx + j];
+    const double x = J.X[(size_t)r * J.ld + j];
     s += x * x;
   }
-  part[(size_t)blockIdx.y * N + j] = s;
+  J.part[(size_t)chunk * J.N + j] = s;
 }
 
-__global__ void colscale_apply(int R, int N, double* __restrict__ X, int ldx, const double* __restrict__ part,
-                               int chunks, const int* status) {
-  if (*status & kStFatal) return;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
+__device__ void colscale_body(const RenormJob& J, int cb, int chunk) {
+  if (*J.status & kStFatal) return;
+  const int j = cb * 256 + threadIdx.x;
+  if (j >= J.N) return;
   double s = 0.0;
-  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * N + j];
+  for (int c = 0; c < J.chunks; ++c) s += J.part[(size_t)c * J.N + j];
   const double f = (s > 0.0) ? 1.0 / sqrt(s) : 1.0;
-  const int r0 = blockIdx.y * 128, r1 = min(R, r0 + 128);
-  for (int r = r0; r < r1; ++r) X[(size_t)r * ldx + j] *= f;
+  const int r0 = chunk * 128, r1 = min(J.R, r0 + 128);
+  for (int r = r0; r < r1; ++r) J.X[(size_t)r * J.ld + j] *= f;
+}
+
+__global__ __launch_bounds__(256) void colsumsq_partial(RenormList L) {
+  const int j = find_job(L.boff, L.n, blockIdx.x);
+  const RenormJob J = L.job[j];
+  const int b = blockIdx.x - L.boff[j];
+  colsumsq_body(J, b % J.cblocks, b / J.cblocks);
+}
+
+__global__ __launch_bounds__(256) void colscale_apply(RenormList L) {
+  const int j = find_job(L.boff, L.n, blockIdx.x);
+  const RenormJob J = L.job[j];
+  const int b = blockIdx.x - L.boff[j];
+  colscale_body(J, b % J.cblocks, b / J.cblocks);
 }
 
 size_t renorm_scratch_elems(int R, int N) { return (size_t)((R + 127) / 128) * (N > 0 ? N : 1); }
 
-void launch_column_renorm(int R, int N, double* X, int ldx, double* scratch, const int* status, hipStream_t st) {
-  if (R <= 0 || N <= 0) return;
-  const int chunks = (R + 127) / 128;
-  dim3 grid((N + 255) / 256, chunks);
-  hipLaunchKernelGGL(colsumsq_partial, grid, dim3(256), 0, st, R, N, X, ldx, scratch);
-  hipLaunchKernelGGL(colscale_apply, grid, dim3(256), 0, st, R, N, X, ldx, scratch, chunks, status);
+void launch_column_renorm(const RenormList& L, hipStream_t st) {
+  if (L.n <= 0 || L.blocks <= 0) return;
+  hipLaunchKernelGGL(colsumsq_partial, dim3(L.blocks), dim3(256), 0, st, L);
+  hipLaunchKernelGGL(colscale_apply, dim3(L.blocks), dim3(256), 0, st, L);
+}
+
+namespace {
+template <int MB, int NC>
+int resident_blocks_gemm_split32_grid_cap() {
+  int dev = 0, cus = 0, nb = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_cauchy_split32_persistent<MB, NC>, 256, 0) != hipSuccess) return 0;
+  return nb * cus;
+}
+}  // namespace
+
+// Blocks of the persistent kernel of `shape` that fit on the current device
+// at once (0 if the runtime cannot tell).
+int gemm_split32_grid_cap(int shape) {
+  switch (shape) {
+    case kT64x128: return resident_blocks_gemm_split32_grid_cap<1, 2>();
+    case kT128x64: return resident_blocks_gemm_split32_grid_cap<2, 1>();
+    case kT64x64: return resident_blocks_gemm_split32_grid_cap<1, 1>();
+    default: return resident_blocks_gemm_split32_grid_cap<2, 2>();
+  }
 }
 
 }  // namespace svdu

@@ -4,21 +4,19 @@
 // own columns (coalesced 2 KiB rows per block) and a block owns a chunk of
 // rows; per-chunk partial sums are reduced in a second, fixed-order pass so
 // that results are bitwise reproducible. HBM-bound: 8 R N bytes per pass.
-#include "svdu_internal.h"
 #include "device_util.h"
+#include "jobs.h"
+#include "svdu_internal.h"
 
 namespace svdu {
 
 constexpr int kGemvCols = 256;
 constexpr int kGemvRows = 128;
 
-__global__ __launch_bounds__(kGemvCols) void gemv_t_partial(int R, int N, const double* __restrict__ X, int ldx,
-                                                            int nv, const double* __restrict__ v0,
-                                                            const double* __restrict__ v1,
-                                                            const double* __restrict__ v2,
-                                                            double* __restrict__ part) {
-  const int j = blockIdx.x * kGemvCols + threadIdx.x;
-  const int chunk = blockIdx.y;
+__device__ void gemv_t_partial_body(int R, int N, const double* __restrict__ X, int ldx, int nv,
+                                    const double* __restrict__ v0, const double* __restrict__ v1,
+                                    const double* __restrict__ v2, double* __restrict__ part, int cb, int chunk) {
+  const int j = cb * kGemvCols + threadIdx.x;
   const int r0 = chunk * kGemvRows;
   const int r1 = min(R, r0 + kGemvRows);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -59,9 +57,8 @@ __global__ __launch_bounds__(kGemvCols) void gemv_t_partial(int R, int N, const 
   }
 }
 
-__global__ void gemv_t_reduce(int N, int nv, int chunks, const double* __restrict__ part, double* out0,
-                              double* out1, double* out2) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void gemv_t_reduce_body(int N, int nv, int chunks, const double* __restrict__ part, double* out0,
+                                   double* out1, double* out2, int idx) {
   if (idx >= nv * N) return;
   const int k = idx / N, j = idx - k * N;
   double s = 0.0;
@@ -70,23 +67,34 @@ __global__ void gemv_t_reduce(int N, int nv, int chunks, const double* __restric
   o[j] = s;
 }
 
+__global__ __launch_bounds__(kGemvCols) void gemv_t_partial(GemvList L) {
+  const int j = find_job(L.boff_p, L.n, blockIdx.x);
+  const GemvJob J = L.job[j];
+  const int b = blockIdx.x - L.boff_p[j];
+  const double* v1 = J.nv > 1 ? J.v[1] : J.v[0];
+  const double* v2 = J.nv > 2 ? J.v[2] : J.v[0];
+  gemv_t_partial_body(J.R, J.N, J.X, J.ldx, J.nv, J.v[0], v1, v2, J.part, b % J.cblocks, b / J.cblocks);
+}
+
+__global__ __launch_bounds__(256) void gemv_t_reduce(GemvList L) {
+  const int j = find_job(L.boff_r, L.n, blockIdx.x);
+  const GemvJob J = L.job[j];
+  gemv_t_reduce_body(J.N, J.nv, J.chunks, J.part, J.out[0], J.out[1], J.out[2],
+                     (blockIdx.x - L.boff_r[j]) * 256 + threadIdx.x);
+}
+
+int gemv_cblocks(int N) { return (N + kGemvCols - 1) / kGemvCols; }
+int gemv_chunks(int R) { return (R + kGemvRows - 1) / kGemvRows; }
+
 size_t gemv_t_scratch_elems(int R, int N, int nv) {
   const int chunks = (R + kGemvRows - 1) / kGemvRows;
   return (size_t)(chunks > 0 ? chunks : 1) * nv * N;
 }
 
-void launch_gemv_t(int R, int N, const double* X, int ldx, int nv, const double* v0, const double* v1,
-                   const double* v2, double* out0, double* out1, double* out2, double* scratch,
-                   size_t scratch_elems, hipStream_t st) {
-  if (N <= 0) return;
-  const int chunks = (R + kGemvRows - 1) / kGemvRows;
-  if (chunks == 0) return;
-  (void)scratch_elems;
-  dim3 grid((N + kGemvCols - 1) / kGemvCols, chunks);
-  hipLaunchKernelGGL(gemv_t_partial, grid, dim3(kGemvCols), 0, st, R, N, X, ldx, nv, v0, v1, v2, scratch);
-  const int tot = nv * N;
-  hipLaunchKernelGGL(gemv_t_reduce, dim3((tot + 255) / 256), dim3(256), 0, st, N, nv, chunks, scratch, out0,
-                     out1, out2);
+void launch_gemv_list(const GemvList& L, hipStream_t st) {
+  if (L.n <= 0 || L.blocks_p <= 0) return;
+  hipLaunchKernelGGL(gemv_t_partial, dim3(L.blocks_p), dim3(kGemvCols), 0, st, L);
+  hipLaunchKernelGGL(gemv_t_reduce, dim3(L.blocks_r), dim3(256), 0, st, L);
 }
 
 }  // namespace svdu

@@ -16,6 +16,7 @@
 #include <math.h>
 
 #include "device_util.h"
+#include "jobs.h"
 #include "svdu_internal.h"
 
 namespace svdu {
@@ -25,7 +26,7 @@ namespace svdu {
 // ---------------------------------------------------------------------------
 constexpr int kDeflThreads = 1024;
 
-__global__ __launch_bounds__(kDeflThreads) void deflate_kernel(Stage s) {
+__device__ void deflate_body(const Stage& s) {
   __shared__ int shi[64];
   __shared__ double shd[64];
   if (*s.status & kStFatal) return;
@@ -231,14 +232,12 @@ __device__ inline bool quad_root_in(double c, double a, double b, double lo, dou
   return false;
 }
 
-__global__ __launch_bounds__(256) void secular_kernel(const int* __restrict__ Kdev, const double* __restrict__ g,
-                                                      const double* __restrict__ W2,
-                                                      const double* __restrict__ rhop, int* __restrict__ org,
-                                                      double* __restrict__ tau_out, int* __restrict__ iters,
-                                                      int* status, int maxit) {
+__device__ void secular_body(const int* __restrict__ Kdev, const double* __restrict__ g,
+                             const double* __restrict__ W2, const double* __restrict__ rhop,
+                             int* __restrict__ org, double* __restrict__ tau_out, int* __restrict__ iters,
+                             int* status, int maxit, int wave) {
   if (*status & kStFatal) return;
   const int K = *Kdev;
-  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (wave >= K) return;
   const double rho0 = *rhop;
@@ -333,13 +332,12 @@ __global__ __launch_bounds__(256) void secular_kernel(const int* __restrict__ Kd
 // |w_j|^2 = prod_i (mu_i - d_j) / (rho prod_{k != j} (d_k - d_j)), as K ratios
 // in (0, 1] pairing root i with pole i (i < j) or i+1 (i >= j), last with rho.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void loewner_kernel(const int* __restrict__ Kdev, const double* __restrict__ g,
-                                                      const double* __restrict__ rhop,
-                                                      const int* __restrict__ org, const double* __restrict__ tau,
-                                                      double* __restrict__ what, const int* status) {
+__device__ void loewner_body(const int* __restrict__ Kdev, const double* __restrict__ g,
+                             const double* __restrict__ rhop, const int* __restrict__ org,
+                             const double* __restrict__ tau, double* __restrict__ what, const int* status,
+                             int wave) {
   if (*status & kStFatal) return;
   const int K = *Kdev;
-  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (wave >= K) return;
   const double rho0 = *rhop;
@@ -371,14 +369,12 @@ __global__ __launch_bounds__(256) void loewner_kernel(const int* __restrict__ Kd
 // Column scales 1/|c_i| with |c_i|^2 = sum_k what_k^2 / delta_ki^2, and mu.
 // One root per wave, two passes (max, then scaled sum of squares).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void colnorm_kernel(const int* __restrict__ Kdev, const double* __restrict__ g,
-                                                      const double* __restrict__ what,
-                                                      const int* __restrict__ org,
-                                                      const double* __restrict__ tau, double* __restrict__ cs,
-                                                      double* __restrict__ mu, const int* status) {
+__device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restrict__ g,
+                             const double* __restrict__ what, const int* __restrict__ org,
+                             const double* __restrict__ tau, double* __restrict__ cs, double* __restrict__ mu,
+                             const int* status, int i) {
   if (*status & kStFatal) return;
   const int K = *Kdev;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= K) return;
   const double go = g[org[i]];
@@ -421,9 +417,8 @@ __device__ inline int count_leq(const double* a, int n, double v) {
   return lo;
 }
 
-__global__ void merge_kernel(Stage s) {
+__device__ void merge_body(const Stage& s, int idx) {
   if (*s.status & kStFatal) return;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int N = s.N;
   const int K = s.counts[0], Kd = s.counts[1];
   if (idx < N) {
@@ -465,23 +460,53 @@ __global__ void merge_kernel(Stage s) {
   }
 }
 
-void launch_secular(int K_max, const int* Kdev, const double* g, const double* W2, const double* rho, int* org,
-                    double* tau, int* iters, int* status, int maxit, hipStream_t st) {
-  if (K_max <= 0) return;
-  hipLaunchKernelGGL(secular_kernel, dim3((K_max + 3) / 4), dim3(256), 0, st, Kdev, g, W2, rho, org, tau, iters,
-                     status, maxit);
+// ---------------------------------------------------------------------------
+// Level kernels: each serves every eigen-update of a level.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kDeflThreads) void deflate_kernel(StageLevel L) {
+  const Stage s = L.st[blockIdx.x];
+  if (s.N > 0) deflate_body(s);
 }
 
-void launch_stage_small(Stage& s, int maxit, hipStream_t st) {
-  const int N = s.N;
-  if (N <= 0) return;
-  hipLaunchKernelGGL(deflate_kernel, dim3(1), dim3(kDeflThreads), 0, st, s);
-  launch_secular(N, s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, st);
-  hipLaunchKernelGGL(loewner_kernel, dim3((N + 3) / 4), dim3(256), 0, st, s.counts, s.g, s.rho, s.org, s.tau,
-                     s.what, s.status);
-  hipLaunchKernelGGL(colnorm_kernel, dim3((N + 3) / 4), dim3(256), 0, st, s.counts, s.g, s.what, s.org, s.tau,
-                     s.cs, s.mu, s.status);
-  hipLaunchKernelGGL(merge_kernel, dim3((N + 255) / 256), dim3(256), 0, st, s);
+__global__ __launch_bounds__(256) void secular_kernel(StageLevel L, int maxit) {
+  const int j = find_job(L.boff_w, L.n, blockIdx.x);
+  const Stage s = L.st[j];
+  const int wave = (blockIdx.x - L.boff_w[j]) * 4 + (threadIdx.x >> 6);
+  secular_body(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, wave);
+}
+
+__global__ __launch_bounds__(256) void loewner_kernel(StageLevel L) {
+  const int j = find_job(L.boff_w, L.n, blockIdx.x);
+  const Stage s = L.st[j];
+  const int wave = (blockIdx.x - L.boff_w[j]) * 4 + (threadIdx.x >> 6);
+  loewner_body(s.counts, s.g, s.rho, s.org, s.tau, s.what, s.status, wave);
+}
+
+__global__ __launch_bounds__(256) void colnorm_kernel(StageLevel L) {
+  const int j = find_job(L.boff_w, L.n, blockIdx.x);
+  const Stage s = L.st[j];
+  const int wave = (blockIdx.x - L.boff_w[j]) * 4 + (threadIdx.x >> 6);
+  colnorm_body(s.counts, s.g, s.what, s.org, s.tau, s.cs, s.mu, s.status, wave);
+}
+
+__global__ __launch_bounds__(256) void merge_kernel(StageLevel L) {
+  const int j = find_job(L.boff_t, L.n, blockIdx.x);
+  const Stage s = L.st[j];
+  merge_body(s, (blockIdx.x - L.boff_t[j]) * 256 + threadIdx.x);
+}
+
+void launch_secular_level(const StageLevel& L, int maxit, hipStream_t st) {
+  if (L.blocks_w <= 0) return;
+  hipLaunchKernelGGL(secular_kernel, dim3(L.blocks_w), dim3(256), 0, st, L, maxit);
+}
+
+void launch_stage_level(const StageLevel& L, int maxit, hipStream_t st) {
+  if (L.n <= 0 || L.blocks_w <= 0) return;
+  hipLaunchKernelGGL(deflate_kernel, dim3(L.n), dim3(kDeflThreads), 0, st, L);
+  launch_secular_level(L, maxit, st);
+  hipLaunchKernelGGL(loewner_kernel, dim3(L.blocks_w), dim3(256), 0, st, L);
+  hipLaunchKernelGGL(colnorm_kernel, dim3(L.blocks_w), dim3(256), 0, st, L);
+  hipLaunchKernelGGL(merge_kernel, dim3(L.blocks_t), dim3(256), 0, st, L);
 }
 
 }  // namespace svdu

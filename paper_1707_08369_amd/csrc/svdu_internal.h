@@ -99,35 +99,12 @@ struct CauchyDesc {
   const int* status;       // device status word; fatal bits make the kernels return
 };
 
-inline CauchyDesc desc_of(const Stage& s, const double* colscale = nullptr) {
+__host__ __device__ inline CauchyDesc desc_of(const Stage& s, const double* colscale = nullptr) {
   return CauchyDesc{s.N, s.rg, s.rzeta, s.rh, s.rcl, s.ctype, s.co, s.ctau, s.ccs, s.ccl, s.cmem, s.ch,
                     colscale, s.status};
 }
 
-// ---- launchers (each enqueues on `st`, no host synchronisation) ----------------
-// Projections: part/out = X^T [v0 v1 v2] (nv of them), X row-major R x N.
-void launch_gemv_t(int R, int N, const double* X, int ldx, int nv, const double* v0, const double* v1,
-                   const double* v2, double* out0, double* out1, double* out2, double* scratch,
-                   size_t scratch_elems, hipStream_t st);
-size_t gemv_t_scratch_elems(int R, int N, int nv);
-
-// Deflation, secular roots, Loewner weights, column norms, descriptors.
-void launch_stage_small(Stage& s, int maxit, hipStream_t st);
-// The secular solve alone, for distinct ascending poles g with weights W2 (K of them).
-void launch_secular(int K_max, const int* Kdev, const double* g, const double* W2, const double* rho,
-                    int* org, double* tau, int* iters, int* status, int maxit, hipStream_t st);
-// y_k = C~^T x_k for up to 3 vectors (storage order in, output positions out).
-void launch_cauchy_tmatvec(const Stage& s, int nv, const double* const* x, double* const* y, hipStream_t st);
-// X_out = X * C~ (R x N times N x N), FP64 MFMA with C~ tiles generated in LDS.
-void launch_gemm_cauchy_f64(int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo,
-                            hipStream_t st);
-int set_gemm_variant(int v);  // 1: LDS for both operands, 2: X in registers (default)
-// Precision form: X_out = X * C~ as split-FP32 products with FP32 accumulation drained to FP64.
-void launch_gemm_cauchy_split32(int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo,
-                                hipStream_t st);
-// Rescales every column of X (R x N) to unit FP64 norm; scratch >= renorm_scratch_elems(R, N) doubles.
-size_t renorm_scratch_elems(int R, int N);
-void launch_column_renorm(int R, int N, double* X, int ldx, double* scratch, const int* status, hipStream_t st);
+// Launchers over job lists are declared in jobs.h.
 
 // FMM path of the product (k_fmm.hip). The plan of a product is built on the
 // host from host copies of the stage's K poles and roots, all plans of a call

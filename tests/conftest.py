@@ -30,13 +30,13 @@ def lib():
 
 
 @pytest.fixture(autouse=True)
-def _gemm_variant_from_env(request):
-    """SVDU_TEST_GEMM_VARIANT=k runs the GPU tests with product-kernel variant k."""
-    v = os.environ.get("SVDU_TEST_GEMM_VARIANT")
+def _tile_shape_from_env(request):
+    """SVDU_TEST_TILE_SHAPE=k runs the GPU tests with the product kernels forced to tile shape k."""
+    v = os.environ.get("SVDU_TEST_TILE_SHAPE")
     if not v or request.node.get_closest_marker("gpu") is None:
         yield
         return
     import paper_1707_08369_amd as svdu
-    old = svdu.svdu_set_option(svdu.SVDU_OPT_GEMM_VARIANT, int(v))
+    old = svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, int(v))
     yield
-    svdu.svdu_set_option(svdu.SVDU_OPT_GEMM_VARIANT, old)
+    svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, old)

@@ -39,9 +39,11 @@ def test_workspace_sizes(lib):
     assert svdu.svdu_workspace_bytes(6, 5) == 0
     small = svdu.svdu_workspace_bytes(256, 256)
     big = svdu.svdu_workspace_bytes(8192, 8192)
-    # the n x n intermediate basis dominates
-    assert big >= 8192 * 8192 * 8
-    assert big < 8192 * 8192 * 8 * 1.1
+    # the intermediate bases U~ (m x m) and V~ (n x n) dominate; the FMM
+    # path runs the two sides in turn through one of them
+    assert big >= 2 * 8192 * 8192 * 8
+    assert big < 2 * 8192 * 8192 * 8 * 1.1
+    assert svdu.svdu_workspace_bytes(4096, 8192) < 8192 * 8192 * 8 * 1.35
     assert 0 < small < big
     assert svdu.svdu_eig_update_workspace_bytes(10, 7) > 0
     assert svdu.svdu_eig_update_workspace_bytes(10, 7, svdu.SVDU_PATH_FMM) > svdu.svdu_eig_update_workspace_bytes(10, 7)
@@ -94,3 +96,97 @@ def test_options(lib):
     old = svdu.svdu_set_option(svdu.SVDU_OPT_SECULAR_MAXIT, 17)
     assert svdu.svdu_set_option(svdu.SVDU_OPT_SECULAR_MAXIT, old) == 17
     assert svdu.svdu_set_option(999, 1) == svdu.SVDU_EINVAL
+    old = svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, svdu.SVDU_TILE_64x64)
+    assert old == -1
+    assert svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, -1) == svdu.SVDU_TILE_64x64
+    assert svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, 4) == svdu.SVDU_EINVAL
+    assert svdu.svdu_set_option(svdu.SVDU_OPT_PERSISTENT, 1) == 0
+    assert svdu.svdu_set_option(svdu.SVDU_OPT_PERSISTENT, 0) == 1
+
+
+def test_tile_table_roundtrip(lib):
+    t = svdu.tile_table(svdu.SVDU_PREC_FP64)
+    assert len(t) == svdu.SVDU_TILE_BUCKETS and all(0 <= x < 4 for x in t)
+    new = [(x + 1) % 4 for x in t]
+    assert svdu.tile_table(svdu.SVDU_PREC_FP64, new) == new
+    assert svdu.tile_table(svdu.SVDU_PREC_FP64) == new
+    svdu.tile_table(svdu.SVDU_PREC_FP64, t)
+    bad = (ctypes.c_int * svdu.SVDU_TILE_BUCKETS)(*([0] * 7 + [9]))
+    assert svdu.svdu_tile_table(svdu.SVDU_PREC_FP64, ctypes.cast(bad, ctypes.c_void_p), 1) == svdu.SVDU_EINVAL
+    assert svdu.tile_table(svdu.SVDU_PREC_FP64) == t
+
+
+def _prob(m, n, base, ld_extra=0, defl=False):
+    """A problem whose buffers are fake, disjoint device addresses starting at base."""
+    P = svdu.svdu_problem()
+    P.m, P.n = m, n
+    off = [base]
+
+    def take(nbytes):
+        p = off[0]
+        off[0] += (nbytes + 255) // 256 * 256
+        return p
+
+    P.ldu, P.ldv, P.ldu_out, P.ldv_out = m + ld_extra, n + ld_extra, m, n
+    P.U = take(8 * m * P.ldu)
+    P.sigma = take(8 * m)
+    P.V = take(8 * n * P.ldv)
+    P.a = take(8 * m)
+    P.b = take(8 * n)
+    P.U_out = take(8 * m * m)
+    P.sigma_out = take(8 * m)
+    P.V_out = take(8 * n * n)
+    P.defl = take(4 * n) if defl else None
+    return P, off[0]
+
+
+def test_batch_workspace_and_argument_errors(lib):
+    """Host-side checks of the batched entry points (nothing reaches the device)."""
+    arr = (svdu.svdu_problem * 3)()
+    base = 0x10000000
+    for i, (m, n) in enumerate([(64, 100), (17, 17), (300, 555)]):
+        arr[i], base = _prob(m, n, base, defl=i == 1)
+    wsb = svdu.svdu_batch_workspace_bytes(3, arr, svdu.SVDU_PREC_FP64)
+    single = sum(svdu.svdu_workspace_bytes(arr[i].m, arr[i].n) for i in range(3))
+    assert wsb > 0 and wsb >= single - 3 * 32768
+    assert svdu.svdu_batch_workspace_bytes(3, arr, svdu.SVDU_PREC_SPLIT32) > wsb
+    assert svdu.svdu_batch_workspace_bytes(0, arr, 0) == 0
+    ws = base + 0x100000
+    h = ctypes.c_void_p()
+
+    def create(a, count=3, prec=svdu.SVDU_PREC_FP64, flags=0, w=ws, wb=None):
+        return svdu.svdu_batch_create(ctypes.byref(h), count, a, prec, flags, _p(w), wsb if wb is None else wb,
+                                      None)
+
+    assert create(arr, wb=wsb - 1) == svdu.SVDU_ENOMEM
+    assert create(arr, w=ws + 8) == svdu.SVDU_EINVAL        # alignment
+    assert create(arr, prec=7) == svdu.SVDU_EINVAL
+    assert create(arr, flags=4) == svdu.SVDU_EINVAL
+    assert create(arr, count=0) == svdu.SVDU_EINVAL
+    assert h.value is None
+    # an output overlapping another problem's input
+    bad = (svdu.svdu_problem * 3)(*arr)
+    bad[2].U_out = arr[0].V
+    assert create(bad) == svdu.SVDU_EINVAL
+    # two outputs overlapping
+    bad = (svdu.svdu_problem * 3)(*arr)
+    bad[1].sigma_out = arr[0].sigma_out
+    assert create(bad) == svdu.SVDU_EINVAL
+    # an input inside the workspace
+    bad = (svdu.svdu_problem * 3)(*arr)
+    bad[0].a = ws + 4096
+    assert create(bad) == svdu.SVDU_EINVAL
+    # m > n, small leading dimension
+    bad = (svdu.svdu_problem * 3)(*arr)
+    bad[1].m = 18
+    assert create(bad) == svdu.SVDU_EINVAL
+    bad = (svdu.svdu_problem * 3)(*arr)
+    bad[2].ldv_out = 554
+    assert create(bad) == svdu.SVDU_EINVAL
+    assert svdu.svdu_batch_launch(None, 0, None) == svdu.SVDU_EINVAL
+    assert svdu.svdu_batch_status(None, None, None) == svdu.SVDU_EINVAL
+    svdu.svdu_batch_destroy(None)
+    assert svdu.svdu_autotune_workspace_bytes(0) == 0
+    assert svdu.svdu_autotune_workspace_bytes(256) > 8 * 256 * 256
+    assert svdu.svdu_autotune(5, 256, None, None, _p(ws), 1 << 30, None) == svdu.SVDU_EINVAL
+    assert svdu.svdu_autotune(0, 256, None, None, _p(ws), 16, None) == svdu.SVDU_ENOMEM
