@@ -126,8 +126,7 @@ def measure_forms(svdu, torch, U, sigma, V, A_vecs, B_vecs, Uo, so, Vo, ws, stre
         ref = svdu.rank1_update(U, sigma, V, A_vecs[k], B_vecs[k], workspace=ws, want_defl=False, stream=stream)
     for name, prec, path in (("split32", svdu.SVDU_PREC_SPLIT32, svdu.SVDU_PATH_DIRECT),
                              ("fmm_eps1e-10", svdu.SVDU_PREC_FP64, svdu.SVDU_PATH_FMM)):
-        wsf = ws if path == svdu.SVDU_PATH_DIRECT else svdu.new_workspace(svdu.svdu_workspace_bytes(m, n, path),
-                                                                          U.device)
+        wsf = svdu.new_workspace(svdu.svdu_workspace_bytes(m, n, path, prec), U.device)
 
         def run(k):
             svdu.rank1_update(U, sigma, V, A_vecs[k], B_vecs[k], eps=1e-10, path=path, precision=prec,

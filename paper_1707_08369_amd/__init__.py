@@ -32,6 +32,7 @@ SVDU_OPT_SECULAR_MAXIT = 1
 SVDU_OPT_TIMING = 2
 SVDU_OPT_TILE_SHAPE = 3
 SVDU_OPT_PERSISTENT = 4
+SVDU_OPT_REFINE = 5
 SVDU_TILE_128x128 = 0
 SVDU_TILE_64x128 = 1
 SVDU_TILE_128x64 = 2

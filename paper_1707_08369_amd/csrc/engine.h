@@ -43,6 +43,9 @@ struct Layout {
   double *gemv_pu, *gemv_pv;      // partial sums of the projections through U and V
   double *renorm_u, *renorm_v;    // precision form: column sums of squares
   double *TL, *TR;                // intermediate bases U~ (m x m) and V~ (n x n)
+  int kmax, cmax;                 // cluster refinement: gathered columns, cluster records
+  int *rf_info, *rf_start, *rf_size, *rf_off, *rf_idx;
+  double *rf_Yu, *rf_Yv, *rf_T, *rf_W, *rf_beta;
   Stage st[4];                    // L+, L-, R+, R-
   double* fmm_work;               // FMM path only
   size_t fmm_elems;
@@ -105,6 +108,7 @@ struct Plan {
   StageLevel lev[2];
   GemmList gemm[2][kNumShapes];
   RenormList renorm;
+  RefineList refine;
   std::vector<Stage> host_stages;   // per update: L+, L-, R+, R- (host copies, for the FMM path)
 };
 
@@ -149,6 +153,7 @@ enum : int { kStepAll = 0, kStepUpToRoots = 1, kStepProductsOnward = 2 };
 struct Sched {
   int maxit = 200;
   bool persistent = false;
+  bool refine = true;
   int grid_cap[2][kNumShapes] = {};   // [precision][shape]
 };
 // Enqueues the sequence (or a part of it: the FMM path runs the products

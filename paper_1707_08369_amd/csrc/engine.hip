@@ -112,6 +112,20 @@ Layout carve_update(void* base, int m, int n, int path, int precision) {
   const bool fmm = path == SVDU_PATH_FMM;
   L.TL = fmm ? nullptr : c.take<double>((size_t)m * m);   // the FMM path runs the sides in turn through TR
   L.TR = c.take<double>((size_t)n * n);
+  L.kmax = std::min(m, 128);
+  L.cmax = std::max(1, L.kmax / 2);
+  const bool rf = precision == SVDU_PREC_FP64;
+  const size_t km = rf ? (size_t)L.kmax : 0;
+  L.rf_info = c.take<int>(4);
+  L.rf_start = c.take<int>(rf ? L.cmax : 0);
+  L.rf_size = c.take<int>(rf ? L.cmax : 0);
+  L.rf_off = c.take<int>(rf ? L.cmax : 0);
+  L.rf_idx = c.take<int>(km);
+  L.rf_Yu = c.take<double>(km * m);
+  L.rf_Yv = c.take<double>(km * n);
+  L.rf_T = c.take<double>(km * m);
+  L.rf_W = c.take<double>(km * m);
+  L.rf_beta = c.take<double>(km);
   L.fmm_elems = fmm ? fmm_workspace_elems(n, n) : 0;
   L.fmm_work = c.take<double>(L.fmm_elems);
   L.fmm_plan_bytes = fmm ? 4 * fmm_plan_bytes(n) : 0;
@@ -472,6 +486,61 @@ void build_plan(const std::vector<Update>& ups_in, int precision, char* dev_base
     P.renorm.boff = B.put(o);
     P.renorm.job = B.put(jobs);
   }
+  // refinement of close clusters (FP64 only)
+  {
+    std::vector<RefineJob> jobs;
+    std::vector<int> bn, bc, bw, bcl;
+    if (precision == SVDU_PREC_FP64) {
+      for (const Update& u : ups) {
+        const Layout& L = u.L;
+        RefineJob R{};
+        R.m = u.m;
+        R.n = u.n;
+        R.kmax = L.kmax;
+        R.cmax = L.cmax;
+        R.U = u.U;
+        R.V = u.V;
+        R.a = u.a;
+        R.b = u.b;
+        R.sigma = u.sigma;
+        R.ldu = u.ldu;
+        R.ldv = u.ldv;
+        R.Uo = u.U_out;
+        R.so = u.sigma_out;
+        R.Vo = u.V_out;
+        R.lduo = u.ldu_out;
+        R.ldvo = u.ldv_out;
+        R.status = L.status;
+        R.info = L.rf_info;
+        R.cl_start = L.rf_start;
+        R.cl_size = L.rf_size;
+        R.cl_off = L.rf_off;
+        R.col_idx = L.rf_idx;
+        R.Yu = L.rf_Yu;
+        R.Yv = L.rf_Yv;
+        R.T = L.rf_T;
+        R.W = L.rf_W;
+        R.beta = L.rf_beta;
+        jobs.push_back(R);
+        bn.push_back(cdiv(u.n, 256));
+        bc.push_back(cdiv(u.m + 1, 64));
+        bw.push_back(cdiv(u.m, 4));
+        bcl.push_back(std::min(32, L.cmax));
+      }
+    }
+    const std::vector<int> on = prefix(bn), oc = prefix(bc), ow = prefix(bw), ocl = prefix(bcl);
+    RefineList& F = P.refine;
+    F.n = (int)jobs.size();
+    F.blocks_n = on.back();
+    F.blocks_c = oc.back();
+    F.blocks_w = ow.back();
+    F.blocks_cl = ocl.back();
+    F.boff_n = B.put(on);
+    F.boff_c = B.put(oc);
+    F.boff_w = B.put(ow);
+    F.boff_cl = B.put(ocl);
+    F.job = B.put(jobs);
+  }
   blob->resize((blob->size() + 15) & ~size_t(15));
 }
 
@@ -534,6 +603,7 @@ void enqueue_plan(const Plan& P, const Sched& S, int tcall, int part, hipStream_
       ring_mark(tcall, 3 + lev, st);
     }
   }
+  if (S.refine) launch_refine(P.refine, st);
   if (P.any_defl && P.prob.blocks_n > 0)
     hipLaunchKernelGGL(prob_flags_kernel, dim3(P.prob.blocks_n), dim3(256), 0, st, P.prob);
   ring_mark(tcall, 5, st);

@@ -93,6 +93,29 @@ struct RenormList {
   const RenormJob* job = nullptr;
 };
 
+// Refinement of close singular-value clusters of one update (k_refine.hip).
+struct RefineJob {
+  int m, n, kmax, cmax;            // cmax: cluster records, kmax: gathered columns
+  const double *U, *V, *a, *b, *sigma;
+  int ldu, ldv;
+  double *Uo, *so, *Vo;            // the update's outputs, refined in place
+  int lduo, ldvo;
+  const int* status;
+  int* info;                       // [0] gathered columns k, [1] clusters
+  int *cl_start, *cl_size, *cl_off, *col_idx;
+  double *Yu, *Yv, *T, *W, *beta;  // kmax x m, kmax x n, kmax x m, kmax x m, kmax
+};
+
+struct RefineList {
+  int n = 0;
+  int blocks_n = 0, blocks_c = 0, blocks_w = 0, blocks_cl = 0;
+  const int* boff_n = nullptr;     // ceil(n / 256) per update (gather)
+  const int* boff_c = nullptr;     // ceil((m + 1) / 64) per update (V^T products)
+  const int* boff_w = nullptr;     // ceil(m / 4) per update (U products)
+  const int* boff_cl = nullptr;    // blocks sharing the clusters of an update
+  const RefineJob* job = nullptr;
+};
+
 // ---- launchers (each enqueues on `st`, no host synchronisation) ----------------
 // Projections of every GemvJob: partial sums per row chunk, then a
 // fixed-order reduction.
@@ -115,6 +138,8 @@ void launch_gemm_split32(const GemmList& L, int shape, bool persistent, int grid
 // Column renormalisation of every RenormJob; scratch per job >=
 // renorm_scratch_elems(R, N) doubles.
 void launch_column_renorm(const RenormList& L, hipStream_t st);
+// Cluster refinement of every update of the list.
+void launch_refine(const RefineList& L, hipStream_t st);
 size_t renorm_scratch_elems(int R, int N);
 
 }  // namespace svdu

@@ -21,6 +21,7 @@ namespace svdu {
 
 int g_maxit = 200;
 bool g_persistent = false;
+bool g_refine = true;
 
 // Schedule of a launch sequence: iteration cap, GEMM schedule, and the
 // device's capacity for persistent blocks (queried once per process).
@@ -30,6 +31,7 @@ Sched current_sched(bool persistent) {
   Sched S;
   S.maxit = g_maxit;
   S.persistent = persistent;
+  S.refine = g_refine;
   if (persistent && !have) {
     for (int p = 0; p < 2; ++p)
       for (int s = 0; s < kNumShapes; ++s) caps[p][s] = gemm_grid_cap(s, p);
@@ -401,6 +403,11 @@ int svdu_set_option(int option, int value) {
   if (option == SVDU_OPT_PERSISTENT) {
     const int old = g_persistent ? 1 : 0;
     g_persistent = value != 0;
+    return old;
+  }
+  if (option == SVDU_OPT_REFINE) {
+    const int old = g_refine ? 1 : 0;
+    g_refine = value != 0;
     return old;
   }
   if (option == SVDU_OPT_TIMING) return ring_set(value != 0);

@@ -233,3 +233,66 @@ def test_autotune_table_and_results_unchanged(lib):
         lib.tile_table(0, saved)
     for x, y in zip(before, after):
         assert torch.equal(x, y)
+
+
+# ---------------------------------------------------------------------------
+# close-cluster refinement
+# ---------------------------------------------------------------------------
+def _planted_close_output(m, n, seed, gaps=(1e-9, 1e-11, 1e-13), triple=True):
+    """Inputs whose updated matrix A^ has planted close singular values: A^ is
+    built first (Haar factors, sigma^ with pairs at the given relative gaps),
+    then A = A^ - a b^T is decomposed on the host (LAPACK, a library routine
+    used only to make inputs)."""
+    rng = np.random.default_rng(seed)
+    Uh = S.haar(m, rng)
+    Vh = S.haar(n, rng)
+    sh = np.sort(rng.uniform(0.5, 10.0, m))[::-1].copy()
+    pos = 1
+    for g in gaps:
+        sh[pos + 1] = sh[pos] * (1.0 - g)
+        pos += 7
+    if triple:
+        sh[pos + 1] = sh[pos] * (1 - 3e-12)
+        sh[pos + 2] = sh[pos] * (1 - 7e-12)
+    sh = np.sort(sh)[::-1].copy()
+    Ah = (Uh * sh[None, :]) @ Vh[:, :m].T
+    a = rng.standard_normal(m) / np.sqrt(n)
+    b = rng.standard_normal(n) / np.sqrt(n)
+    A = Ah - np.outer(a, b)
+    Ua, sa, Vta = np.linalg.svd(A, full_matrices=True)
+    return Ua, sa, Vta.T.copy(), a, b, Ah
+
+
+def _recon_np(Ah, U, s, V):
+    m = U.shape[0]
+    return np.linalg.norm((U * s[None, :]) @ V[:, :m].T - Ah) / np.linalg.norm(Ah)
+
+
+@pytest.mark.parametrize("m,n", [(200, 200), (150, 260)])
+def test_refinement_of_close_clusters(lib, m, n):
+    U, s, V, a, b, Ah = _planted_close_output(m, n, seed=m + n)
+    args = (dev(U), dev(s), dev(V), dev(a), dev(b))
+    on = [host(t) for t in lib.rank1_update(*args)[:3]]
+    old = lib.svdu_set_option(lib.SVDU_OPT_REFINE, 0)
+    try:
+        off = [host(t) for t in lib.rank1_update(*args)[:3]]
+    finally:
+        lib.svdu_set_option(lib.SVDU_OPT_REFINE, old)
+    r_on, r_off = _recon_np(Ah, *on), _recon_np(Ah, *off)
+    assert r_on <= 1e-13, (r_on, r_off)
+    assert r_on <= r_off * 1.01
+    assert O.orth_error(on[0]) <= 1e-13 and O.orth_error(on[2]) <= 1e-13
+    # columns outside the close clusters are untouched
+    sg = off[1]
+    close = np.zeros(m, dtype=bool)
+    d = (sg[:-1] - sg[1:]) * (sg[:-1] + sg[1:]) <= 1e-7 * sg[0] ** 2
+    close[:-1] |= d
+    close[1:] |= d
+    assert np.any(close)
+    assert np.array_equal(on[0][:, ~close], off[0][:, ~close])
+    assert np.array_equal(on[1][~close], off[1][~close])
+    assert np.array_equal(on[2][:, np.r_[~close, np.ones(n - m, bool)]],
+                          off[2][:, np.r_[~close, np.ones(n - m, bool)]])
+    # singular values against the oracle
+    r = O.svd_rank1_update(U, s, V, a, b)
+    assert np.max(np.abs(on[1] - r.sigma)) <= 1e-13 * r.sigma[0]
