@@ -174,7 +174,8 @@ def batched_workload(torch, count=512, seed=4):
 
 
 def measure_batched(svdu, torch, reps=5, check=True,
-                    modes=("fp64_graph", "fp64_graph_persistent", "fp64_eager", "split32_graph")):
+                    modes=("fp64_graph", "fp64_graph_persistent", "fp64_eager", "split32_graph"),
+                    table=None, one_by_one=True):
     """The batched form: the 512-problem workload as one batch, launched as one
     captured graph (or eagerly), against the same problems updated one call at
     a time through svdu_rank1_update. Tile shapes come from the autotuner."""
@@ -185,10 +186,14 @@ def measure_batched(svdu, torch, reps=5, check=True,
     res = {"workload": "512 problems, m log-uniform [64,1024], n = m + U{0..m}, sigma~U[0.01,10], haar U,V, "
                        "a,b~N(0,1/n)", "count": count, "product_flops_per_batch": flops}
     tuned = {}
-    for prec in (svdu.SVDU_PREC_FP64, svdu.SVDU_PREC_SPLIT32):
-        table, times = svdu.autotune(prec, max_n=2048)
-        tuned["fp64" if prec == 0 else "split32"] = {"table": table, "ms": [[round(t, 4) for t in row]
-                                                                           for row in times[:6]]}
+    if table is not None:   # a given FP64 table instead of tuning (profiling runs)
+        svdu.tile_table(svdu.SVDU_PREC_FP64, table)
+        tuned["fp64"] = {"table": table, "ms": None}
+    else:
+        for prec in (svdu.SVDU_PREC_FP64, svdu.SVDU_PREC_SPLIT32):
+            tab, times = svdu.autotune(prec, max_n=2048)
+            tuned["fp64" if prec == 0 else "split32"] = {"table": tab, "ms": [[round(t, 4) for t in row]
+                                                                             for row in times[:6]]}
     res["autotune"] = tuned
     for mode in modes:
         prec = svdu.SVDU_PREC_SPLIT32 if mode.startswith("split32") else svdu.SVDU_PREC_FP64
@@ -219,6 +224,8 @@ def measure_batched(svdu, torch, reps=5, check=True,
         res[mode] = rec
         b.close()
         del b
+    if not one_by_one:
+        return res
     # the same problems one call at a time (eager single-problem path)
     outs = [(torch.empty_like(it[0]), torch.empty_like(it[1]), torch.empty_like(it[2])) for it in items]
     wss = [svdu.new_workspace(svdu.svdu_workspace_bytes(it[0].shape[0], it[2].shape[0]), "cuda") for it in items]
@@ -231,7 +238,7 @@ def measure_batched(svdu, torch, reps=5, check=True,
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0)
     res["one_call_per_problem"] = {"ms_per_batch": ms, "updates_per_s": count / (ms * 1e-3)}
-    best = min(res[m]["ms_per_batch"] for m in modes if not m.startswith("split32"))
+    best = min(res[mo]["ms_per_batch"] for mo in modes if not mo.startswith("split32"))
     res["speedup_batched_vs_one_call_per_problem"] = ms / best
     return res
 
@@ -255,6 +262,8 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=5, help="timed launches of the batched workload")
     ap.add_argument("--batched-only", action="store_true",
                     help="measure only the batched form (for profiling it)")
+    ap.add_argument("--tile-table", default="",
+                    help="with --batched-only: FP64 tile shapes per size bucket (comma list) instead of tuning")
     ap.add_argument("--profile-copy", type=int, default=0,
                     help="run only N plain 1 GiB device copies (counter calibration) and exit")
     args = ap.parse_args()
@@ -286,7 +295,9 @@ def main():
         return
 
     if args.batched_only:
-        print(json.dumps(measure_batched(svdu, torch, reps=args.batch_reps, check=False, modes=("fp64_graph",))))
+        table = [int(x) for x in args.tile_table.split(",")] if args.tile_table else None
+        print(json.dumps(measure_batched(svdu, torch, reps=args.batch_reps, check=False, modes=("fp64_graph",),
+                                         table=table, one_by_one=False)))
         return
 
     m, n, K, W = args.m, args.n, args.steps, args.warmup

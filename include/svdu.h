@@ -60,11 +60,11 @@ extern "C" {
 #define SVDU_OPT_PERSISTENT 4    /* 1: products of svdu_rank1_update and svdu_rank1_update_batched use the
                                     persistent schedule (see SVDU_BATCH_PERSISTENT); default 0 */
 #define SVDU_OPT_REFINE 5        /* 1 (default): FP64 results get the close-cluster refinement (not in the
-                                    paper): for consecutive sigma^ with squared gaps <= 1e-7 sigma^_0^2,
-                                    clusters of up to 8 and up to min(m, 128) columns in all, the block
+                                    paper): for consecutive sigma^ with relative gaps <= 1e-6, in clusters
+                                    of up to 8 and up to min(m, 128) columns in all, the block
                                     U^_c^T A^ V^_c is formed from the inputs and its SVD rotates U^_c and
-                                    V^_c and replaces sigma^_c. 0: off. Read when a call is enqueued (a
-                                    batch graph keeps the value it was captured with). */
+                                    V^_c (sigma^ is kept). 0: off. Read when a call is enqueued (a batch
+                                    graph keeps the value it was captured with). */
 
 /* tile shapes of the product kernels (rows x columns of one block tile) */
 #define SVDU_TILE_128x128 0

@@ -1,17 +1,19 @@
 // Refinement of close singular-value clusters (not in the paper).
 //
 // The method computes the left vectors from A^ A^T and the right vectors from
-// A^T A^ independently. For a pair of singular values whose squares differ by
-// delta, each side's eigenvectors carry an error of order u lambda_max / delta
-// inside the pair's plane, and the two sides' errors do not match, so
-// U^ S^ V^^T misses A^ by about sigma u lambda_max / delta in that block. For
-// every cluster of consecutive sigma^ whose squared gaps are at most
-// tau sigma^_0^2 (and that are not negligible against sigma^_0), this pass
-// forms the small block B = U^_c^T A^ V^_c from the inputs,
+// A^T A^ independently. Inside a group of relatively close singular values
+// each side's eigenvectors are accurate to about u / relgap within the group's
+// span, and the two sides' errors do not match, so U^ S^ V^^T misses A^ by
+// about sigma u / relgap in that block. For every cluster of consecutive
+// sigma^ with relative gaps (sigma_i - sigma_{i+1}) / sigma_i <= tau (and sigma^
+// not negligible against sigma^_0), this pass forms the small block
+// B = U^_c^T A^ V^_c from the inputs,
 //   A^ V^_c = U (S (V^T V^_c)) + a (b^T V^_c),
-// takes its SVD B = P diag(s) Q^T (one-sided Jacobi), and replaces U^_c, V^_c
-// and sigma^_c by U^_c P, V^_c Q and s. Work: two passes over U and V with at
-// most kmax gathered columns, and O(m) per cluster entry.
+// takes its SVD B = P diag(s) Q^T (one-sided Jacobi, s descending), and
+// replaces U^_c and V^_c by U^_c P and V^_c Q. sigma^ itself is kept (it is
+// the secular solution; s differs from it by O(u |A^|)), so singular values
+// and deflation are not touched. Work: one pass over V and one over U per
+// kRefineChunk gathered columns (at most kmax), and O(m) per block entry.
 #include <math.h>
 
 #include "device_util.h"
@@ -20,7 +22,7 @@
 
 namespace svdu {
 
-constexpr double kRefineTau = 1e-7;   // relative squared gap below which neighbours are refined together
+constexpr double kRefineTau = 1e-6;   // relative gap below which neighbours are refined together
 constexpr int kRefineSmax = 8;        // largest cluster refined as one block
 constexpr int kRefineChunk = 8;       // gathered columns per pass of the skinny products
 
@@ -30,11 +32,11 @@ constexpr int kRefineChunk = 8;       // gathered columns per pass of the skinny
 // kRefineSmax; block scans give every cluster its record and column offset.
 // Columns beyond kmax are not refined (sigma^ descending: the largest first).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool refine_link(const double* so, int m, double tiny, double lim, int i) {
+__device__ __forceinline__ bool refine_link(const double* so, int m, double tiny, double tau, int i) {
   if (i < 0 || i >= m - 1) return false;
   const double a = so[i], b = so[i + 1];
   if (!(a > tiny)) return false;
-  return (a - b) * (a + b) <= lim;
+  return a - b <= tau * a;
 }
 
 __global__ __launch_bounds__(256) void refine_detect_kernel(RefineList L) {
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(256) void refine_detect_kernel(RefineList L) {
   }
   const int m = J.m;
   const double s0 = J.so[0];
-  const double tiny = 64.0 * kU * s0, lim = kRefineTau * s0 * s0;
+  const double tiny = 64.0 * kU * s0, lim = kRefineTau;
   if (tid == 0) first_skip = 1 << 30;
   __syncthreads();
   int carry_c = 0, carry_cols = 0;
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(256) void refine_u_kernel(RefineList L) {
 
 // ---------------------------------------------------------------------------
 // Per cluster: B = Yu^T W (s x s), its SVD by one-sided Jacobi (thread 0),
-// then U^_c <- Yu P, V^_c <- Yv Q, sigma^_c <- s (descending).
+// then U^_c <- Yu P, V^_c <- Yv Q (singular values descending).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void refine_apply_kernel(RefineList L) {
   constexpr int S = kRefineSmax;
@@ -300,7 +302,6 @@ __global__ __launch_bounds__(256) void refine_apply_kernel(RefineList L) {
         if (r < J.m) J.Uo[(size_t)r * J.lduo + col] = nu;
       }
     }
-    if (tid < s) J.so[J.col_idx[off + tid]] = sv[tid];
     __syncthreads();
   }
 }
