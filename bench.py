@@ -243,6 +243,85 @@ def measure_batched(svdu, torch, reps=5, check=True,
     return res
 
 
+def measure_serving(svdu, torch, arrival_s=4.0, rate=2000.0, workers=2, sustain_s=6.0, seed=5):
+    """The serving form: 64 resident matrices (m = n drawn from {256, 1024,
+    2048, 4096, 8192}), Poisson arrivals targeting matrices uniformly, memory
+    admission and continuous batching in the library's server. First at the
+    stated rate for `arrival_s` seconds (the offered load far exceeds the
+    device, so the backlog grows; requests still queued when arrivals end are
+    dropped), then at 70 % of the throughput measured there, drained, so that
+    latency is interpretable. Factors: one Haar pair per size, copied into every
+    matrix of that size; sigma ~ U[0.1, 10] descending; a, b ~ N(0, 1/n) from a
+    pool of 16 pairs per size."""
+    import numpy as np
+
+    import synth_inputs as S
+    sizes = S.serving_sizes(64, seed=seed).tolist()
+    rng = np.random.default_rng(seed + 1)
+    haar = {n: (S.haar_torch(n, seed=20_000 + n, device="cuda"), S.haar_torch(n, seed=30_000 + n, device="cuda"))
+            for n in sorted(set(sizes))}
+    pool = {n: [(torch.as_tensor(rng.standard_normal(n) / np.sqrt(n), device="cuda"),
+                 torch.as_tensor(rng.standard_normal(n) / np.sqrt(n), device="cuda")) for _ in range(16)]
+            for n in haar}
+    factors = []
+    for n in sizes:
+        sig = torch.as_tensor(np.sort(rng.uniform(0.1, 10.0, n))[::-1].copy(), device="cuda")
+        factors.append((haar[n][0].clone(), sig, haar[n][1].clone()))
+    resident = sum(2 * (2 * n * n + n) * 8 for n in sizes)
+
+    def run(rate_, span, drain, fmm_min_n=0):
+        srv = svdu.Server(arena_bytes=24 << 30, workers=workers, max_batch=64, fmm_min_n=fmm_min_n,
+                          min_batch_cost=2e10)
+        for U, sg, V in factors:
+            srv.add_matrix(U, sg, V)
+        r = np.random.default_rng(seed + 7)
+        t, reqs = 0.0, []
+        while True:
+            t += r.exponential(1.0 / rate_)
+            if t > span:
+                break
+            reqs.append((int(r.integers(0, 64)), t))
+        srv.start()
+        for k, (i, tr) in enumerate(reqs):
+            a, b = pool[sizes[i]][k % 16]
+            srv.submit(i, a, b, tr)
+        done = []
+        while srv.now() < span:
+            time.sleep(0.05)
+            done += srv.poll()
+        backlog = srv.stats()["queued"]
+        if drain:
+            srv.drain(600.0)
+        done += srv.poll()
+        st = srv.stats()
+        srv.close()
+        ok = [c for c in done if c["status"] == 0]
+        in_window = [c for c in ok if c["t_done"] <= span]
+        lat = np.array([c["t_done"] - c["t_release"] for c in (ok if drain else in_window)]) * 1e3
+        by_n = {}
+        for c in ok:
+            by_n.setdefault(sizes[c["matrix"]], []).append(1e3 * (c["t_done"] - c["t_release"]))
+        return {"offered_per_s": rate_, "arrivals": len(reqs), "window_s": span,
+                "completed": len(ok), "completed_in_window": len(in_window),
+                "updates_per_s": (len(ok) / max(c["t_done"] for c in ok)) if drain and ok
+                else len(in_window) / span,
+                "latency_ms": {"p50": float(np.percentile(lat, 50)) if lat.size else None,
+                               "p99": float(np.percentile(lat, 99)) if lat.size else None},
+                "latency_p50_ms_by_n": {str(n): float(np.percentile(v, 50)) for n, v in sorted(by_n.items())},
+                "backlog_at_end_of_arrivals": int(backlog),
+                "mean_batch": (st["updates"] / st["batches"]) if st["batches"] else None,
+                "errors": len(done) - len(ok)}
+
+    res = {"workload": "64 resident matrices, m=n from {256,1024,2048,4096,8192}, Poisson arrivals, "
+                       "uniform targets, a,b~N(0,1/n)", "sizes_count": {str(n): sizes.count(n) for n in haar},
+           "resident_bytes": resident, "workers": workers}
+    res["stated_rate"] = run(rate, arrival_s, drain=False)
+    sus = 0.7 * res["stated_rate"]["updates_per_s"]
+    res["sustainable_rate"] = run(sus, sustain_s, drain=True)
+    res["stated_rate_fmm_n_ge_4096"] = run(rate, arrival_s, drain=False, fmm_min_n=4096)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +338,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the short measurements of the other forms (precision form) on the same inputs")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving form")
+    ap.add_argument("--serving-only", action="store_true", help="measure only the serving form")
     ap.add_argument("--batch-reps", type=int, default=5, help="timed launches of the batched workload")
     ap.add_argument("--batched-only", action="store_true",
                     help="measure only the batched form (for profiling it)")
@@ -294,6 +375,9 @@ def main():
         print(json.dumps({"copy_bytes_each": src.numel() * 8, "copies": args.profile_copy}))
         return
 
+    if args.serving_only:
+        print(json.dumps(measure_serving(svdu, torch)))
+        return
     if args.batched_only:
         table = [int(x) for x in args.tile_table.split(",")] if args.tile_table else None
         print(json.dumps(measure_batched(svdu, torch, reps=args.batch_reps, check=False, modes=("fp64_graph",),
@@ -394,6 +478,9 @@ def main():
         out["forms"] = measure_forms(svdu, torch, U, sigma, V, A_vecs, B_vecs, Uo, so, Vo, ws, stream,
                                      fp64_ms=1e3 * (t1 - t0) / K, check=not args.no_check)
         del ws, Uo, Vo
+    if not args.no_serving:
+        print("[bench] serving form ...", file=sys.stderr, flush=True)
+        out.setdefault("forms", {})["serving"] = measure_serving(svdu, torch)
     if not args.no_batched:
         print("[bench] batched form ...", file=sys.stderr, flush=True)
         out.setdefault("forms", {})["batched_512"] = measure_batched(svdu, torch, reps=args.batch_reps,

@@ -217,7 +217,8 @@ int svdu_rank1_update_batched(int count, const svdu_problem* probs, int precisio
 /* ---- tile-shape autotuner --------------------------------------------------
  * For each size bucket up to max_n (<= 8192 recommended), times the product
  * kernel of every tile shape on the same set of synthetic products of order
- * N (the bucket's upper end, or max_n) that fills the device, and stores the
+ * N (the bucket's upper end, or max_n), as many as make 4096 tiles of
+ * 128 x 128 (16 per compute unit, so every shape runs on a full device), and stores the
  * fastest shape in the process-wide table used by every later call of that
  * precision. times_ms (host, SVDU_TILE_BUCKETS x 4, may be NULL) receives the
  * best of three timed launches per shape (-1 for buckets above max_n), table
@@ -229,6 +230,73 @@ int svdu_autotune(int precision, int max_n, double* times_ms, int* table, void* 
 /* Reads (set = 0) or writes (set = 1) the process-wide tuning table of a
  * precision (host array of SVDU_TILE_BUCKETS shapes). */
 int svdu_tile_table(int precision, int* table, int set);
+
+/* ---- serving runtime (resident matrices, memory admission, continuous batching)
+ * The server holds matrices registered with two buffer sets each (U m x m,
+ * sigma m, V n x n, row-major with ld = m and n; device memory owned by the
+ * caller): an update reads the current set and writes the other, which then
+ * becomes current. Requests name a matrix, device vectors a (m) and b (n),
+ * which must stay valid until the request completes, and a release time on
+ * the server clock (svdu_server_now; a request is not started before it).
+ * `workers` threads, each with its own stream, form batches continuously:
+ * the oldest released request whose matrix is idle, plus further released
+ * requests, oldest first, at most one per matrix, none costlier than the
+ * first, while the batch's product flops stay within
+ * max(batch_cost_factor x the first's, min_batch_cost) and its workspace fits
+ * in the largest free block of the caller's arena (memory admission; a
+ * request that cannot fit even in an empty arena completes with
+ * SVDU_ENOMEM). Updates of one matrix run in release order; each result
+ * is bitwise the one svdu_rank1_update gives for the same inputs on the same
+ * path. Requests for matrices of order >= fmm_min_n (if > 0, FP64 only) run
+ * alone through the FMM path with tolerance fmm_eps. */
+typedef struct {
+  int workers;                 /* 1..8 batches in flight */
+  int max_batch;               /* updates per batch at most */
+  int precision;               /* SVDU_PREC_FP64 or SVDU_PREC_SPLIT32 */
+  int fmm_min_n;
+  double fmm_eps;
+  double batch_cost_factor;    /* >= 1 */
+  double min_batch_cost;       /* flops, >= 0 */
+} svdu_server_config;
+
+typedef struct {
+  long long id;                /* as returned by svdu_server_submit */
+  int matrix;
+  int status;                  /* SVDU_OK or an SVDU_E* code of the update */
+  int batch;                   /* updates in the batch it ran in */
+  double t_release, t_start, t_done;   /* server clock, seconds */
+} svdu_completion;
+
+typedef struct svdu_server svdu_server;
+
+/* arena: device memory of arena_bytes (>= 1 MiB, 256-byte aligned) that the
+ * server carves its workspaces from; it allocates no device memory itself. */
+int svdu_server_create(svdu_server** out, const svdu_server_config* cfg, void* arena, size_t arena_bytes);
+/* Registers a matrix (before svdu_server_start); *id receives its index. */
+int svdu_server_add_matrix(svdu_server* s, int m, int n, double* U0, double* sigma0, double* V0, double* U1,
+                           double* sigma1, double* V1, int* id);
+/* Starts the worker threads and resets the server clock to 0. */
+int svdu_server_start(svdu_server* s);
+/* Seconds since svdu_server_start (or create). */
+double svdu_server_now(svdu_server* s);
+/* Queues an update of `matrix` released at t_release; *req_id (may be NULL)
+ * receives its id. */
+int svdu_server_submit(svdu_server* s, int matrix, const double* a, const double* b, double t_release,
+                       long long* req_id);
+/* Moves up to max_out completions (host array) out of the server; returns
+ * their number. */
+int svdu_server_poll(svdu_server* s, svdu_completion* out, int max_out);
+/* stats (host, 6): queued requests, batches running, batches run, updates
+ * run, largest free arena block (bytes), first runtime error (0 if none). */
+int svdu_server_stats(svdu_server* s, long long* stats);
+/* Waits until nothing is queued or running, or timeout_s passes
+ * (SVDU_ENOCONV); returns the first runtime error or SVDU_OK. */
+int svdu_server_drain(svdu_server* s, double timeout_s);
+/* Current factors of an idle matrix (SVDU_EINVAL while it is being updated). */
+int svdu_server_current(svdu_server* s, int matrix, double** U, double** sigma, double** V);
+/* Stops the workers after the batches they are running (queued requests are
+ * dropped) and frees the server (not the arena or the matrices). */
+void svdu_server_destroy(svdu_server* s);
 
 /* Static description of a status code (host). */
 const char* svdu_status_string(int status);

@@ -45,7 +45,10 @@ EXPORTS = ("svdu_workspace_bytes", "svdu_rank1_update", "svdu_get_status", "svdu
            "svdu_eig_update", "svdu_secular_workspace_bytes", "svdu_secular", "svdu_set_option",
            "svdu_status_string", "svdu_timing_read", "svdu_batch_workspace_bytes", "svdu_batch_create",
            "svdu_batch_launch", "svdu_batch_status", "svdu_batch_destroy", "svdu_rank1_update_batched",
-           "svdu_autotune_workspace_bytes", "svdu_autotune", "svdu_tile_table")
+           "svdu_autotune_workspace_bytes", "svdu_autotune", "svdu_tile_table", "svdu_server_create",
+           "svdu_server_add_matrix", "svdu_server_start", "svdu_server_now", "svdu_server_submit",
+           "svdu_server_poll", "svdu_server_stats", "svdu_server_drain", "svdu_server_current",
+           "svdu_server_destroy")
 
 
 class svdu_problem(ctypes.Structure):
@@ -59,6 +62,22 @@ class svdu_problem(ctypes.Structure):
                 ("sigma_out", ctypes.c_void_p),
                 ("V_out", ctypes.c_void_p), ("ldv_out", ctypes.c_int),
                 ("defl", ctypes.c_void_p)]
+
+
+
+class svdu_server_config(ctypes.Structure):
+    """Mirror of the C struct svdu_server_config (include/svdu.h)."""
+    _fields_ = [("workers", ctypes.c_int), ("max_batch", ctypes.c_int), ("precision", ctypes.c_int),
+                ("fmm_min_n", ctypes.c_int), ("fmm_eps", ctypes.c_double),
+                ("batch_cost_factor", ctypes.c_double), ("min_batch_cost", ctypes.c_double)]
+
+
+class svdu_completion(ctypes.Structure):
+    """Mirror of the C struct svdu_completion (include/svdu.h)."""
+    _fields_ = [("id", ctypes.c_longlong), ("matrix", ctypes.c_int), ("status", ctypes.c_int),
+                ("batch", ctypes.c_int), ("t_release", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
 
 _lib = None
 
@@ -119,6 +138,28 @@ def load():
     lib.svdu_autotune.restype = c_int
     lib.svdu_tile_table.argtypes = [c_int, c_vp, c_int]
     lib.svdu_tile_table.restype = c_int
+    lib.svdu_server_create.argtypes = [ctypes.POINTER(c_vp), ctypes.POINTER(svdu_server_config), c_vp, c_size]
+    lib.svdu_server_create.restype = c_int
+    lib.svdu_server_add_matrix.argtypes = [c_vp, c_int, c_int, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                           ctypes.POINTER(c_int)]
+    lib.svdu_server_add_matrix.restype = c_int
+    lib.svdu_server_start.argtypes = [c_vp]
+    lib.svdu_server_start.restype = c_int
+    lib.svdu_server_now.argtypes = [c_vp]
+    lib.svdu_server_now.restype = c_dbl
+    lib.svdu_server_submit.argtypes = [c_vp, c_int, c_vp, c_vp, c_dbl, ctypes.POINTER(ctypes.c_longlong)]
+    lib.svdu_server_submit.restype = c_int
+    lib.svdu_server_poll.argtypes = [c_vp, ctypes.POINTER(svdu_completion), c_int]
+    lib.svdu_server_poll.restype = c_int
+    lib.svdu_server_stats.argtypes = [c_vp, ctypes.POINTER(ctypes.c_longlong)]
+    lib.svdu_server_stats.restype = c_int
+    lib.svdu_server_drain.argtypes = [c_vp, c_dbl]
+    lib.svdu_server_drain.restype = c_int
+    lib.svdu_server_current.argtypes = [c_vp, c_int, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp),
+                                        ctypes.POINTER(c_vp)]
+    lib.svdu_server_current.restype = c_int
+    lib.svdu_server_destroy.argtypes = [c_vp]
+    lib.svdu_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -467,3 +508,145 @@ def tile_table(precision=SVDU_PREC_FP64, table=None):
     if rc != SVDU_OK:
         raise SvduError(rc, "svdu_tile_table")
     return list(buf)
+
+
+# ---------------------------------------------------------------------------
+# serving runtime
+# ---------------------------------------------------------------------------
+def svdu_server_create(out, cfg, arena, arena_bytes) -> int:
+    return int(load().svdu_server_create(out, cfg, arena, arena_bytes))
+
+
+def svdu_server_add_matrix(server, m, n, U0, s0, V0, U1, s1, V1, id_out) -> int:
+    return int(load().svdu_server_add_matrix(server, m, n, U0, s0, V0, U1, s1, V1, id_out))
+
+
+def svdu_server_start(server) -> int:
+    return int(load().svdu_server_start(server))
+
+
+def svdu_server_now(server) -> float:
+    return float(load().svdu_server_now(server))
+
+
+def svdu_server_submit(server, matrix, a, b, t_release, req_id) -> int:
+    return int(load().svdu_server_submit(server, matrix, a, b, t_release, req_id))
+
+
+def svdu_server_poll(server, out, max_out) -> int:
+    return int(load().svdu_server_poll(server, out, max_out))
+
+
+def svdu_server_stats(server, stats) -> int:
+    return int(load().svdu_server_stats(server, stats))
+
+
+def svdu_server_drain(server, timeout_s) -> int:
+    return int(load().svdu_server_drain(server, timeout_s))
+
+
+def svdu_server_current(server, matrix, U, s, V) -> int:
+    return int(load().svdu_server_current(server, matrix, U, s, V))
+
+
+def svdu_server_destroy(server) -> None:
+    load().svdu_server_destroy(server)
+
+
+class Server:
+    """Serving runtime (svdu_server_* in include/svdu.h).
+
+    Matrices are registered with their current factors (the tensors become the
+    first buffer set; a second set is allocated here). Request vectors are kept
+    referenced until their completion has been polled.
+    """
+
+    def __init__(self, arena_bytes, workers=2, max_batch=64, precision=SVDU_PREC_FP64, fmm_min_n=0,
+                 fmm_eps=1e-10, batch_cost_factor=2.0, min_batch_cost=4e9):
+        torch = _torch()
+        self._arena = new_workspace(int(arena_bytes), torch.device("cuda"))
+        ap, ab = _aligned(self._arena)
+        cfg = svdu_server_config(workers, max_batch, precision, fmm_min_n, fmm_eps, batch_cost_factor,
+                                 min_batch_cost)
+        h = ctypes.c_void_p()
+        rc = svdu_server_create(ctypes.byref(h), ctypes.byref(cfg), ap, ab)
+        if rc != SVDU_OK:
+            raise SvduError(rc, "svdu_server_create")
+        self._h = h
+        self._sets = []
+        self._live = {}
+
+    def add_matrix(self, U, sigma, V):
+        torch = _torch()
+        m, n = U.shape[0], V.shape[0]
+        _check_mat(U, m, m, "U")
+        _check_mat(V, n, n, "V")
+        _check_vec(sigma, m, "sigma")
+        if U.stride(0) != m or V.stride(0) != n:
+            raise ValueError("resident factors must be contiguous")
+        s1 = (torch.empty_like(U), torch.empty_like(sigma), torch.empty_like(V))
+        mid = ctypes.c_int()
+        rc = svdu_server_add_matrix(self._h, m, n, _ptr(U), _ptr(sigma), _ptr(V), _ptr(s1[0]), _ptr(s1[1]),
+                                    _ptr(s1[2]), ctypes.byref(mid))
+        if rc != SVDU_OK:
+            raise SvduError(rc, "svdu_server_add_matrix")
+        self._sets.append(((U, sigma, V), s1))
+        return mid.value
+
+    def start(self):
+        rc = svdu_server_start(self._h)
+        if rc != SVDU_OK:
+            raise SvduError(rc, "svdu_server_start")
+
+    def now(self):
+        return svdu_server_now(self._h)
+
+    def submit(self, matrix, a, b, t_release=0.0):
+        rid = ctypes.c_longlong()
+        rc = svdu_server_submit(self._h, matrix, _ptr(a), _ptr(b), float(t_release), ctypes.byref(rid))
+        if rc != SVDU_OK:
+            raise SvduError(rc, "svdu_server_submit")
+        self._live[rid.value] = (a, b)
+        return rid.value
+
+    def poll(self, max_out=4096):
+        buf = (svdu_completion * max_out)()
+        n = svdu_server_poll(self._h, buf, max_out)
+        out = []
+        for i in range(n):
+            c = buf[i]
+            self._live.pop(c.id, None)
+            out.append(dict(id=c.id, matrix=c.matrix, status=c.status, batch=c.batch, t_release=c.t_release,
+                            t_start=c.t_start, t_done=c.t_done))
+        return out
+
+    def stats(self):
+        st = (ctypes.c_longlong * 6)()
+        svdu_server_stats(self._h, st)
+        return dict(queued=st[0], running=st[1], batches=st[2], updates=st[3], largest_free=st[4],
+                    error=st[5])
+
+    def drain(self, timeout_s=600.0):
+        return svdu_server_drain(self._h, float(timeout_s))
+
+    def current(self, matrix):
+        """The tensors that hold the matrix's factors now (matrix idle)."""
+        U, s, V = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        rc = svdu_server_current(self._h, matrix, ctypes.byref(U), ctypes.byref(s), ctypes.byref(V))
+        if rc != SVDU_OK:
+            raise SvduError(rc, "svdu_server_current")
+        for st in self._sets[matrix]:
+            if st[0].data_ptr() == U.value:
+                return st
+        raise RuntimeError("unknown buffer set")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            svdu_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

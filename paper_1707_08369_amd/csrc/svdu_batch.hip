@@ -43,6 +43,9 @@ namespace {
 
 int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+constexpr int kTuneTiles = 4096;                       // tuning workload per bucket, in 128 x 128 tiles
+constexpr size_t kTuneOutElems = (size_t)1 << 26;      // 512 MiB of outputs: 4096 tiles of any N <= 8192
+
 // Batch workspace: status words, tile counters, tables, then one update layout per problem.
 struct BatchWs {
   int* status;
@@ -342,7 +345,7 @@ size_t svdu_autotune_workspace_bytes(int max_n) {
   c.take<int>(3 * n);              // rcl ccl cmem
   c.take<int8_t>(n);               // ctype
   c.take<double>(n * n);           // X
-  c.take<double>(std::max<size_t>(n * n, (size_t)1 << 22));   // outputs
+  c.take<double>(std::max<size_t>(n * n, kTuneOutElems));   // outputs
   c.take<char>(1 << 20);           // tables
   return c.off + 256;
 }
@@ -361,7 +364,7 @@ int svdu_autotune(int precision, int max_n, double* times_ms, int* table, void* 
   int* ii = c.take<int>(3 * n);
   int8_t* ctype = c.take<int8_t>(n);
   double* X = c.take<double>(n * n);
-  const size_t out_elems = std::max<size_t>(n * n, (size_t)1 << 22);
+  const size_t out_elems = std::max<size_t>(n * n, kTuneOutElems);
   double* Xo = c.take<double>(out_elems);
   char* tables = c.take<char>(1 << 20);
   CauchyDesc d{};
@@ -382,9 +385,10 @@ int svdu_autotune(int precision, int max_n, double* times_ms, int* table, void* 
       if (table) table[bk] = shape_table_get(precision, bk);
       continue;
     }
-    // the same set of products for every shape: enough to fill the device
+    // the same set of products for every shape: 4096 tiles of 128 x 128 (16 per
+    // compute unit), so that every shape sees the device full
     const int tiles128 = cdiv(N, 128) * cdiv(N, 128);
-    int count = std::max(1, cdiv(1024, tiles128));
+    int count = std::max(1, cdiv(kTuneTiles, tiles128));
     count = (int)std::min<size_t>((size_t)count, out_elems / ((size_t)N * N));
     d = CauchyDesc{N, rg, rzeta, rh, rcl, ctype, co, ctau, ccs, ccl, cmem, ch, nullptr, status};
     double best = 1e30;

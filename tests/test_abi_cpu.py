@@ -190,3 +190,35 @@ def test_batch_workspace_and_argument_errors(lib):
     assert svdu.svdu_autotune_workspace_bytes(256) > 8 * 256 * 256
     assert svdu.svdu_autotune(5, 256, None, None, _p(ws), 1 << 30, None) == svdu.SVDU_EINVAL
     assert svdu.svdu_autotune(0, 256, None, None, _p(ws), 16, None) == svdu.SVDU_ENOMEM
+
+
+def test_server_argument_errors(lib):
+    """Server configuration checks happen on the host before any device call."""
+    h = ctypes.c_void_p()
+    arena = _p(0x7000000000)
+
+    def create(**kw):
+        c = dict(workers=2, max_batch=8, precision=0, fmm_min_n=0, fmm_eps=1e-10, batch_cost_factor=2.0,
+                 min_batch_cost=0.0)
+        c.update(kw)
+        cfg = svdu.svdu_server_config(c["workers"], c["max_batch"], c["precision"], c["fmm_min_n"], c["fmm_eps"],
+                                      c["batch_cost_factor"], c["min_batch_cost"])
+        return svdu.svdu_server_create(ctypes.byref(h), ctypes.byref(cfg), kw.get("arena", arena),
+                                       kw.get("bytes", 1 << 30))
+
+    assert create(workers=0) == svdu.SVDU_EINVAL
+    assert create(workers=9) == svdu.SVDU_EINVAL
+    assert create(max_batch=0) == svdu.SVDU_EINVAL
+    assert create(precision=3) == svdu.SVDU_EINVAL
+    assert create(fmm_min_n=100, fmm_eps=0.0) == svdu.SVDU_EINVAL
+    assert create(batch_cost_factor=0.5) == svdu.SVDU_EINVAL
+    assert create(min_batch_cost=-1.0) == svdu.SVDU_EINVAL
+    assert create(arena=_p(0x7000000008)) == svdu.SVDU_EINVAL
+    assert create(bytes=1000) == svdu.SVDU_EINVAL
+    assert svdu.svdu_server_create(ctypes.byref(h), None, arena, 1 << 30) == svdu.SVDU_EINVAL
+    assert h.value is None
+    assert svdu.svdu_server_start(None) == svdu.SVDU_EINVAL
+    assert svdu.svdu_server_submit(None, 0, _p(8), _p(8), 0.0, None) == svdu.SVDU_EINVAL
+    assert svdu.svdu_server_poll(None, None, 0) == svdu.SVDU_EINVAL
+    assert svdu.svdu_server_drain(None, 1.0) == svdu.SVDU_EINVAL
+    svdu.svdu_server_destroy(None)
