@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
 CSRC = os.path.join(ROOT, "paper_1707_08369_amd", "csrc")
-GEMM_SRCS = [os.path.join(CSRC, f) for f in ("k_gemm_f64.hip", "cauchy_tile.h", "device_util.h")]
+GEMM_SRCS = [os.path.join(CSRC, f) for f in ("k_gemm_f64.hip", "cauchy_tile.h", "device_util.h", "jobs.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_cauchy_f64_traffic.json")
 
 
