@@ -243,7 +243,7 @@ def measure_batched(svdu, torch, reps=5, check=True,
     return res
 
 
-def measure_serving(svdu, torch, arrival_s=4.0, rate=2000.0, workers=2, sustain_s=6.0, seed=5):
+def measure_serving(svdu, torch, arrival_s=4.0, rate=2000.0, workers=3, sustain_s=6.0, seed=5):
     """The serving form: 64 resident matrices (m = n drawn from {256, 1024,
     2048, 4096, 8192}), Poisson arrivals targeting matrices uniformly, memory
     admission and continuous batching in the library's server. First at the
@@ -298,9 +298,10 @@ def measure_serving(svdu, torch, arrival_s=4.0, rate=2000.0, workers=2, sustain_
         ok = [c for c in done if c["status"] == 0]
         in_window = [c for c in ok if c["t_done"] <= span]
         lat = np.array([c["t_done"] - c["t_release"] for c in (ok if drain else in_window)]) * 1e3
-        by_n = {}
+        by_n, svc_n = {}, {}
         for c in ok:
             by_n.setdefault(sizes[c["matrix"]], []).append(1e3 * (c["t_done"] - c["t_release"]))
+            svc_n.setdefault(sizes[c["matrix"]], []).append(1e3 * (c["t_done"] - c["t_start"]))
         return {"offered_per_s": rate_, "arrivals": len(reqs), "window_s": span,
                 "completed": len(ok), "completed_in_window": len(in_window),
                 "updates_per_s": (len(ok) / max(c["t_done"] for c in ok)) if drain and ok
@@ -308,6 +309,8 @@ def measure_serving(svdu, torch, arrival_s=4.0, rate=2000.0, workers=2, sustain_
                 "latency_ms": {"p50": float(np.percentile(lat, 50)) if lat.size else None,
                                "p99": float(np.percentile(lat, 99)) if lat.size else None},
                 "latency_p50_ms_by_n": {str(n): float(np.percentile(v, 50)) for n, v in sorted(by_n.items())},
+                "completed_by_n": {str(n): len(v) for n, v in sorted(by_n.items())},
+                "service_ms_mean_by_n": {str(n): float(np.mean(v)) for n, v in sorted(svc_n.items())},
                 "backlog_at_end_of_arrivals": int(backlog),
                 "mean_batch": (st["updates"] / st["batches"]) if st["batches"] else None,
                 "errors": len(done) - len(ok)}

@@ -240,8 +240,9 @@ int svdu_tile_table(int precision, int* table, int set);
  * the server clock (svdu_server_now; a request is not started before it).
  * `workers` threads, each with its own stream, form batches continuously:
  * the oldest released request whose matrix is idle, plus further released
- * requests, oldest first, at most one per matrix, none costlier than the
- * first, while the batch's product flops stay within
+ * requests, oldest first, at most one per matrix, each costing between
+ * min_cost_ratio times the first's and the first's, while the batch's
+ * product flops stay within
  * max(batch_cost_factor x the first's, min_batch_cost) and its workspace fits
  * in the largest free block of the caller's arena (memory admission; a
  * request that cannot fit even in an empty arena completes with
@@ -257,6 +258,7 @@ typedef struct {
   double fmm_eps;
   double batch_cost_factor;    /* >= 1 */
   double min_batch_cost;       /* flops, >= 0 */
+  double min_cost_ratio;       /* 0..1: smaller requests do not join a batch (they go to another worker) */
 } svdu_server_config;
 
 typedef struct {

@@ -69,7 +69,8 @@ class svdu_server_config(ctypes.Structure):
     """Mirror of the C struct svdu_server_config (include/svdu.h)."""
     _fields_ = [("workers", ctypes.c_int), ("max_batch", ctypes.c_int), ("precision", ctypes.c_int),
                 ("fmm_min_n", ctypes.c_int), ("fmm_eps", ctypes.c_double),
-                ("batch_cost_factor", ctypes.c_double), ("min_batch_cost", ctypes.c_double)]
+                ("batch_cost_factor", ctypes.c_double), ("min_batch_cost", ctypes.c_double),
+                ("min_cost_ratio", ctypes.c_double)]
 
 
 class svdu_completion(ctypes.Structure):
@@ -562,12 +563,12 @@ class Server:
     """
 
     def __init__(self, arena_bytes, workers=2, max_batch=64, precision=SVDU_PREC_FP64, fmm_min_n=0,
-                 fmm_eps=1e-10, batch_cost_factor=2.0, min_batch_cost=4e9):
+                 fmm_eps=1e-10, batch_cost_factor=2.0, min_batch_cost=4e9, min_cost_ratio=0.25):
         torch = _torch()
         self._arena = new_workspace(int(arena_bytes), torch.device("cuda"))
         ap, ab = _aligned(self._arena)
         cfg = svdu_server_config(workers, max_batch, precision, fmm_min_n, fmm_eps, batch_cost_factor,
-                                 min_batch_cost)
+                                 min_batch_cost, min_cost_ratio)
         h = ctypes.c_void_p()
         rc = svdu_server_create(ctypes.byref(h), ctypes.byref(cfg), ap, ab)
         if rc != SVDU_OK:

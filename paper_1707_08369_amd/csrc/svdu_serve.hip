@@ -6,9 +6,11 @@
 // becomes current. Requests carry a release time on the server clock. S
 // worker threads, each with its own stream, repeatedly take the oldest
 // released request whose matrix is idle and add further released requests
-// (oldest first, at most one per matrix, none larger than the first, total
-// cost bounded) whose workspace fits in the server's device arena (memory
-// admission); the batch then runs through the same launch sequence as
+// of a similar size (oldest first, at most one per matrix, cost between
+// min_cost_ratio times the first's and the first's, total cost bounded) whose
+// workspace fits in the server's device arena (memory admission), so that
+// small requests are not held up inside a batch of large ones but go to
+// another worker; the batch then runs through the same launch sequence as
 // svdu_batch_launch while the other workers keep forming and running
 // batches, so work admitted later overlaps work already on the device.
 // Updates of one matrix are applied in release order.
@@ -205,7 +207,7 @@ bool form_batch(svdu_server* S, double now, Picked* out) {
       if (M.busy || fmm_of(M)) continue;
       if (std::find(in_batch.begin(), in_batch.end(), r.matrix) != in_batch.end()) continue;
       const double rc = cost_of(M.m, M.n);
-      if (rc > hc || tot + rc > cap) continue;
+      if (rc > hc || rc < c.min_cost_ratio * hc || tot + rc > cap) continue;
       const size_t rws = update_ws_bytes(M.m, M.n, SVDU_PATH_DIRECT, c.precision);
       if (ws + rws > avail) continue;
       take.push_back(i);
@@ -391,6 +393,7 @@ int svdu_server_create(svdu_server** out, const svdu_server_config* cfg, void* a
   if (cfg->precision != SVDU_PREC_FP64 && cfg->precision != SVDU_PREC_SPLIT32) return SVDU_EINVAL;
   if (cfg->fmm_min_n > 0 && !(cfg->fmm_eps > 0.0 && cfg->fmm_eps < 1.0)) return SVDU_EINVAL;
   if (!(cfg->batch_cost_factor >= 1.0) || cfg->min_batch_cost < 0.0) return SVDU_EINVAL;
+  if (!(cfg->min_cost_ratio >= 0.0 && cfg->min_cost_ratio <= 1.0)) return SVDU_EINVAL;
   if ((reinterpret_cast<uintptr_t>(arena) & 255) != 0 || arena_bytes < (1u << 20)) return SVDU_EINVAL;
   svdu_server* S = new svdu_server;
   S->cfg = *cfg;

@@ -199,10 +199,10 @@ def test_server_argument_errors(lib):
 
     def create(**kw):
         c = dict(workers=2, max_batch=8, precision=0, fmm_min_n=0, fmm_eps=1e-10, batch_cost_factor=2.0,
-                 min_batch_cost=0.0)
+                 min_batch_cost=0.0, min_cost_ratio=0.25)
         c.update(kw)
         cfg = svdu.svdu_server_config(c["workers"], c["max_batch"], c["precision"], c["fmm_min_n"], c["fmm_eps"],
-                                      c["batch_cost_factor"], c["min_batch_cost"])
+                                      c["batch_cost_factor"], c["min_batch_cost"], c["min_cost_ratio"])
         return svdu.svdu_server_create(ctypes.byref(h), ctypes.byref(cfg), kw.get("arena", arena),
                                        kw.get("bytes", 1 << 30))
 
@@ -213,6 +213,7 @@ def test_server_argument_errors(lib):
     assert create(fmm_min_n=100, fmm_eps=0.0) == svdu.SVDU_EINVAL
     assert create(batch_cost_factor=0.5) == svdu.SVDU_EINVAL
     assert create(min_batch_cost=-1.0) == svdu.SVDU_EINVAL
+    assert create(min_cost_ratio=1.5) == svdu.SVDU_EINVAL
     assert create(arena=_p(0x7000000008)) == svdu.SVDU_EINVAL
     assert create(bytes=1000) == svdu.SVDU_EINVAL
     assert svdu.svdu_server_create(ctypes.byref(h), None, arena, 1 << 30) == svdu.SVDU_EINVAL
