@@ -223,10 +223,65 @@ __global__ __launch_bounds__(256) void fmm_charges(int R, const double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// P2M on the leaves: W[leaf][kk][r] = sum_{k in leaf} B[k][r] u_kk((g_k - c)/r)
+// Row-batched operator products on the matrix cores. Every translation of
+// the expansion applies a small operator (at most 32 x 32, built in LDS from
+// the box geometry) to the same coefficients of all R rows:
+//   out[i][r] = sum_k Op[i][k] src[k][r],
+// one v_mfma_f64_16x16x4f64 per 16 operator rows, 4 k and 16 rows, with the
+// operator as the A operand (lane l: Op[l % 16][k0 + l / 16]) and 16
+// consecutive rows of the coefficients as B (lane l: src[k0 + l / 16][r0 +
+// l % 16]); result register v of lane l holds out[l / 16 + 4 v][r0 + l % 16].
+// A block has 4 waves; a wave owns kNT tiles of 16 rows.
+// ---------------------------------------------------------------------------
+typedef double fd4 __attribute__((ext_vector_type(4)));
+constexpr int kNT = 4;                     // row tiles of 16 per wave
+constexpr int kRowsPerBlock = 4 * 16 * kNT;
+constexpr int kOpLd = kP + 1;              // LDS row stride of a p x p operator (odd: no bank conflicts)
+
+// acc[t] += Op[mrow0 .. mrow0 + 15][0 .. 4 ksteps) x src[k][rows of tile t], src[k] = 0 for k >= kvalid.
+__device__ __forceinline__ void mfma_apply(const double* op, int ld, int ksteps, int kvalid, const double* src,
+                                           int R, int r0, fd4 (&acc)[kNT]) {
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4;
+  for (int ks = 0; ks < ksteps; ++ks) {
+    const int k = 4 * ks + kq;
+    const double a = op[i * ld + k];
+    const bool kok = k < kvalid;
+    const double* row = src + (size_t)(kok ? k : 0) * R;
+#pragma unroll
+    for (int t = 0; t < kNT; ++t) {
+      const int r = r0 + 16 * t + i;
+      const double v = row[r < R ? r : R - 1];
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (kok && r < R) ? v : 0.0, acc[t], 0, 0, 0);
+    }
+  }
+}
+
+// dst[m][r] = acc for operator rows m < mvalid (dst row stride R).
+__device__ __forceinline__ void store_rows(const fd4 (&acc)[kNT], double* dst, int mvalid, int R, int r0) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < kNT; ++t) {
+    const int r = r0 + 16 * t + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int mi = (lane >> 4) + 4 * v;
+      if (mi < mvalid && r < R) dst[(size_t)mi * R + r] = acc[t][v];
+    }
+  }
+}
+
+__device__ __forceinline__ void zero_acc(fd4 (&acc)[kNT]) {
+#pragma unroll
+  for (int t = 0; t < kNT; ++t) acc[t] = fd4{0.0, 0.0, 0.0, 0.0};
+}
+
+// ---------------------------------------------------------------------------
+// P2M on the leaves: W[leaf][kk][r] = sum_{j in leaf} u_kk((g_j - c)/rad) B[j][r]
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void fmm_p2m(FmmDev F, const double* __restrict__ g, const int* status) {
-  __shared__ double op[32 * kP];   // [source in leaf][kk], at most 32 sources
+  constexpr int ld = 33;
+  __shared__ double op[16 * ld];   // [kk][source in leaf], at most 32 sources
   __shared__ ChebTab T;
   if (*status & kStFatal) return;
   const int id = box_id(F.nlev, blockIdx.x);
@@ -237,33 +292,23 @@ __global__ __launch_bounds__(256) void fmm_p2m(FmmDev F, const double* __restric
   const int ns = a1 - a0;
   cheb_fill(&T, F.p);
   __syncthreads();
-  for (int e = threadIdx.x; e < ns * F.p; e += blockDim.x) {
-    const int j = e / F.p, kk = e - j * F.p;
-    op[j * kP + kk] = lagrange(T, kk, F.p, (g[a0 + j] - c) / rad);
+  for (int e = threadIdx.x; e < 16 * 32; e += blockDim.x) {
+    const int kk = e >> 5, j = e & 31;
+    op[kk * ld + j] = (kk < F.p && j < ns) ? lagrange(T, kk, F.p, (g[a0 + j] - c) / rad) : 0.0;
   }
   __syncthreads();
-  const int r = blockIdx.y * blockDim.x + threadIdx.x;
-  if (r >= F.R) return;
-  double acc[kP];
-#pragma unroll
-  for (int kk = 0; kk < kP; ++kk) acc[kk] = 0.0;
-  for (int j = 0; j < ns; ++j) {
-    const double b = F.B[(size_t)(a0 + j) * F.R + r];
-#pragma unroll
-    for (int kk = 0; kk < kP; ++kk)
-      if (kk < F.p) acc[kk] += b * op[j * kP + kk];
-  }
-  double* w = F.W + (size_t)id * kP * F.R + r;
-#pragma unroll
-  for (int kk = 0; kk < kP; ++kk)
-    if (kk < F.p) w[(size_t)kk * F.R] = acc[kk];
+  const int r0 = blockIdx.y * kRowsPerBlock + (threadIdx.x >> 6) * 16 * kNT;
+  fd4 acc[kNT];
+  zero_acc(acc);
+  mfma_apply(op, ld, (ns + 3) / 4, ns, F.B + (size_t)a0 * F.R, F.R, r0, acc);
+  store_rows(acc, F.W + (size_t)id * kP * F.R, F.p, F.R, r0);
 }
 
 // ---------------------------------------------------------------------------
-// M2M for one level: parent W from its (non-empty) children
+// M2M for one level: W[parent][kp][r] = sum_children sum_kc M[kp][kc] W[child][kc][r]
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void fmm_m2m(FmmDev F, int level, const int* status) {
-  __shared__ double op[2][kP * kP];   // [child][kk_parent][kk_child]
+  __shared__ double op[2][16 * kOpLd];   // [child][kp][kc]
   __shared__ int has[2];
   __shared__ ChebTab T;
   if (*status & kStFatal) return;
@@ -275,114 +320,83 @@ __global__ __launch_bounds__(256) void fmm_m2m(FmmDev F, int level, const int* s
   if (threadIdx.x < 2) has[threadIdx.x] = F.s1[ch[threadIdx.x]] > F.s0[ch[threadIdx.x]];
   cheb_fill(&T, F.p);
   __syncthreads();
-  for (int e = threadIdx.x; e < 2 * F.p * F.p; e += blockDim.x) {
-    const int q = e / (F.p * F.p), rem = e - q * F.p * F.p, kp = rem / F.p, kc = rem - kp * F.p;
-    double cc, rc;
-    box_cr(F, ch[q], &cc, &rc);
-    const double xc = cc + rc * T.t[kc];
-    op[q][kp * kP + kc] = lagrange(T, kp, F.p, (xc - cp) / rp);
+  for (int e = threadIdx.x; e < 2 * 16 * 16; e += blockDim.x) {
+    const int q = e >> 8, rem = e & 255, kp = rem >> 4, kc = rem & 15;
+    double v = 0.0;
+    if (kp < F.p && kc < F.p && has[q]) {
+      double cc, rc;
+      box_cr(F, ch[q], &cc, &rc);
+      v = lagrange(T, kp, F.p, (cc + rc * T.t[kc] - cp) / rp);
+    }
+    op[q][kp * kOpLd + kc] = v;
   }
   __syncthreads();
-  const int r = blockIdx.y * blockDim.x + threadIdx.x;
-  if (r >= F.R) return;
-  double acc[kP];
-#pragma unroll
-  for (int kk = 0; kk < kP; ++kk) acc[kk] = 0.0;
-  for (int q = 0; q < 2; ++q) {
-    if (!has[q]) continue;
-    const double* w = F.W + (size_t)ch[q] * kP * F.R + r;
-    for (int kc = 0; kc < F.p; ++kc) {
-      const double v = w[(size_t)kc * F.R];
-#pragma unroll
-      for (int kp = 0; kp < kP; ++kp)
-        if (kp < F.p) acc[kp] += op[q][kp * kP + kc] * v;
-    }
-  }
-  double* o = F.W + (size_t)id * kP * F.R + r;
-#pragma unroll
-  for (int kk = 0; kk < kP; ++kk)
-    if (kk < F.p) o[(size_t)kk * F.R] = acc[kk];
+  const int r0 = blockIdx.y * kRowsPerBlock + (threadIdx.x >> 6) * 16 * kNT;
+  fd4 acc[kNT];
+  zero_acc(acc);
+  for (int q = 0; q < 2; ++q)
+    if (has[q]) mfma_apply(op[q], kOpLd, (F.p + 3) / 4, F.p, F.W + (size_t)ch[q] * kP * F.R, F.R, r0, acc);
+  store_rows(acc, F.W + (size_t)id * kP * F.R, F.p, F.R, r0);
 }
 
 // ---------------------------------------------------------------------------
 // Downward pass for one level: L[T] = L2L(L[parent]) + sum_S M2L(W[S])
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void fmm_down(FmmDev F, int level, const int* status) {
-  __shared__ double op[kP * kP];
+  __shared__ double op[16 * kOpLd];
   __shared__ ChebTab T;
   if (*status & kStFatal) return;
   const int id = box_id(level, blockIdx.x);
   if (F.s1[id] <= F.s0[id]) return;
-  const int r = blockIdx.y * blockDim.x + threadIdx.x;
   double ct, rt;
   box_cr(F, id, &ct, &rt);
   cheb_fill(&T, F.p);
   __syncthreads();
-  double acc[kP];
-#pragma unroll
-  for (int kk = 0; kk < kP; ++kk) acc[kk] = 0.0;
+  const int r0 = blockIdx.y * kRowsPerBlock + (threadIdx.x >> 6) * 16 * kNT;
+  const int ksteps = (F.p + 3) / 4;
+  fd4 acc[kNT];
+  zero_acc(acc);
   if (level > 0) {
     const int par = box_id(level - 1, blockIdx.x >> 1);
     double cp, rp;
     box_cr(F, par, &cp, &rp);
-    for (int e = threadIdx.x; e < F.p * F.p; e += blockDim.x) {
-      const int kc = e / F.p, kp = e - kc * F.p;
-      const double y = ct + rt * T.t[kc];
-      op[kc * kP + kp] = lagrange(T, kp, F.p, (y - cp) / rp);
+    for (int e = threadIdx.x; e < 16 * 16; e += blockDim.x) {
+      const int kc = e >> 4, kp = e & 15;
+      op[kc * kOpLd + kp] =
+          (kc < F.p && kp < F.p) ? lagrange(T, kp, F.p, (ct + rt * T.t[kc] - cp) / rp) : 0.0;
     }
     __syncthreads();
-    if (r < F.R) {
-      const double* lp = F.L + (size_t)par * kP * F.R + r;
-      for (int kp = 0; kp < F.p; ++kp) {
-        const double v = lp[(size_t)kp * F.R];
-#pragma unroll
-        for (int kc = 0; kc < kP; ++kc)
-          if (kc < F.p) acc[kc] += op[kc * kP + kp] * v;
-      }
-    }
+    mfma_apply(op, kOpLd, ksteps, F.p, F.L + (size_t)par * kP * F.R, F.R, r0, acc);
     __syncthreads();
   }
   for (int q = F.m2l_ptr[id]; q < F.m2l_ptr[id + 1]; ++q) {
     const int src = F.m2l_src[q];
     double cs, rs;
     box_cr(F, src, &cs, &rs);
-    for (int e = threadIdx.x; e < F.p * F.p; e += blockDim.x) {
-      const int kt = e / F.p, ks = e - kt * F.p;
-      const double y = ct + rt * T.t[kt];
-      const double x = cs + rs * T.t[ks];
-      op[kt * kP + ks] = 1.0 / (x - y);
+    for (int e = threadIdx.x; e < 16 * 16; e += blockDim.x) {
+      const int kt = e >> 4, ks = e & 15;
+      op[kt * kOpLd + ks] = (kt < F.p && ks < F.p) ? 1.0 / ((cs + rs * T.t[ks]) - (ct + rt * T.t[kt])) : 0.0;
     }
     __syncthreads();
-    if (r < F.R) {
-      const double* w = F.W + (size_t)src * kP * F.R + r;
-      for (int ks = 0; ks < F.p; ++ks) {
-        const double v = w[(size_t)ks * F.R];
-#pragma unroll
-        for (int kt = 0; kt < kP; ++kt)
-          if (kt < F.p) acc[kt] += op[kt * kP + ks] * v;
-      }
-    }
+    mfma_apply(op, kOpLd, ksteps, F.p, F.W + (size_t)src * kP * F.R, F.R, r0, acc);
     __syncthreads();
   }
-  if (r < F.R) {
-    double* o = F.L + (size_t)id * kP * F.R + r;
-#pragma unroll
-    for (int kk = 0; kk < kP; ++kk)
-      if (kk < F.p) o[(size_t)kk * F.R] = acc[kk];
-  }
+  store_rows(acc, F.L + (size_t)id * kP * F.R, F.p, F.R, r0);
 }
 
 // ---------------------------------------------------------------------------
 // Leaves: L2P + P2P, scaled by the column scale, written to the output
-// positions of the roots. A leaf holds at most kS = 32 poles and roots.
+// positions of the roots. A leaf holds at most kS = 32 poles and roots; the
+// targets are two 16-row operator blocks.
 // ---------------------------------------------------------------------------
 constexpr int kS = 32;
 
 __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* __restrict__ Xo, int ldo,
                                                       const double* __restrict__ colscale) {
-  __shared__ double ul[kS * kP];     // L2P weights [target][kk]
-  __shared__ double inv[kS * kS];    // 1/delta [near source][target]
-  __shared__ double out[64 * (kS + 1)];   // results of 64 rows, staged for row-wise stores
+  constexpr int ldu = kOpLd, ldi = kS + 1;
+  __shared__ double ul[kS * ldu];        // L2P weights [target][kk]
+  __shared__ double inv[kS * ldi];       // 1/delta [target][near source]
+  __shared__ double out[64 * (kS + 1)];  // one wave's 64 rows, staged for row-wise stores
   __shared__ int pos[kS];
   __shared__ double scl[kS];
   __shared__ ChebTab T;
@@ -391,14 +405,13 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
   const int a0 = F.s0[id], a1 = F.s1[id];
   if (a1 <= a0) return;
   const int nt = a1 - a0;
-  const int r = blockIdx.y * blockDim.x + threadIdx.x;
   double ct, rt;
   box_cr(F, id, &ct, &rt);
   cheb_fill(&T, F.p);
   __syncthreads();
-  for (int e = threadIdx.x; e < nt * F.p; e += blockDim.x) {
-    const int t = e / F.p, kk = e - t * F.p;
-    ul[t * kP + kk] = lagrange(T, kk, F.p, (s.mu[a0 + t] - ct) / rt);
+  for (int e = threadIdx.x; e < kS * 16; e += blockDim.x) {
+    const int t = e >> 4, kk = e & 15;
+    ul[t * ldu + kk] = (t < nt && kk < F.p) ? lagrange(T, kk, F.p, (s.mu[a0 + t] - ct) / rt) : 0.0;
   }
   for (int t = threadIdx.x; t < nt; t += blockDim.x) {
     const int P = s.rootpos[a0 + t];
@@ -406,51 +419,54 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
     scl[t] = (colscale ? colscale[P] : 1.0) * s.cs[a0 + t];
   }
   __syncthreads();
-  double acc[kS];
-#pragma unroll
-  for (int t = 0; t < kS; ++t) acc[t] = 0.0;
-  if (r < F.R) {
-    const double* l = F.L + (size_t)id * kP * F.R + r;
-    for (int kk = 0; kk < F.p; ++kk) {
-      const double v = l[(size_t)kk * F.R];
-#pragma unroll
-      for (int t = 0; t < kS; ++t)
-        if (t < nt) acc[t] += ul[t * kP + kk] * v;
-    }
-  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r0 = blockIdx.y * kRowsPerBlock + wave * 16 * kNT;
+  fd4 acc[2][kNT];
+  zero_acc(acc[0]);
+  zero_acc(acc[1]);
+  const int ksl = (F.p + 3) / 4;
+  const double* Lsrc = F.L + (size_t)id * kP * F.R;
+  mfma_apply(ul, ldu, ksl, F.p, Lsrc, F.R, r0, acc[0]);
+  if (nt > 16) mfma_apply(ul + 16 * ldu, ldu, ksl, F.p, Lsrc, F.R, r0, acc[1]);
   for (int q = F.near_ptr[id]; q < F.near_ptr[id + 1]; ++q) {
     const int nbx = F.near_src[q];
     const int b0 = F.s0[nbx], ns = F.s1[nbx] - b0;
     __syncthreads();
-    for (int e = threadIdx.x; e < ns * nt; e += blockDim.x) {
-      const int j = e / nt, t = e - j * nt;
-      const int k = b0 + j, i = a0 + t;
-      inv[j * kS + t] = 1.0 / ((s.g[k] - s.g[s.org[i]]) - s.tau[i]);
-    }
-    __syncthreads();
-    if (r < F.R) {
-      for (int j = 0; j < ns; ++j) {
-        const double bv = F.B[(size_t)(b0 + j) * F.R + r];
-#pragma unroll
-        for (int t = 0; t < kS; ++t)
-          if (t < nt) acc[t] += bv * inv[j * kS + t];
+    for (int e = threadIdx.x; e < kS * kS; e += blockDim.x) {
+      const int t = e >> 5, j = e & 31;
+      double v = 0.0;
+      if (t < nt && j < ns) {
+        const int k = b0 + j, i = a0 + t;
+        v = 1.0 / ((s.g[k] - s.g[s.org[i]]) - s.tau[i]);
       }
+      inv[t * ldi + j] = v;
     }
+    __syncthreads();
+    const int ksn = (ns + 3) / 4;
+    const double* Bsrc = F.B + (size_t)b0 * F.R;
+    mfma_apply(inv, ldi, ksn, ns, Bsrc, F.R, r0, acc[0]);
+    if (nt > 16) mfma_apply(inv + 16 * ldi, ldi, ksn, ns, Bsrc, F.R, r0, acc[1]);
   }
-  // stores: 64 rows at a time through LDS so that each row's nt outputs are
-  // written by consecutive lanes
-  const int rb0 = blockIdx.y * blockDim.x;
-  for (int g0 = 0; g0 < (int)blockDim.x; g0 += 64) {
+  // stores: one wave's 64 rows at a time through LDS, then each row's nt
+  // outputs by consecutive lanes
+  for (int w = 0; w < 4; ++w) {
     __syncthreads();
-    if ((int)threadIdx.x >= g0 && (int)threadIdx.x < g0 + 64) {
+    if (wave == w) {
 #pragma unroll
-      for (int t = 0; t < kS; ++t)
-        if (t < nt) out[(threadIdx.x - g0) * (kS + 1) + t] = scl[t] * acc[t];
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int t = 0; t < kNT; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int tg = mb * 16 + (lane >> 4) + 4 * v;
+            if (tg < nt) out[(16 * t + (lane & 15)) * (kS + 1) + tg] = scl[tg] * acc[mb][t][v];
+          }
     }
     __syncthreads();
+    const int rw = blockIdx.y * kRowsPerBlock + w * 16 * kNT;
     for (int e = threadIdx.x; e < 64 * nt; e += blockDim.x) {
       const int rr = e / nt, t = e - rr * nt;
-      const int row = rb0 + g0 + rr;
+      const int row = rw + rr;
       if (row < F.R) Xo[(size_t)row * ldo + pos[t]] = out[rr * (kS + 1) + t];
     }
   }
@@ -570,7 +586,7 @@ int fmm_launch(int R, const double* X, int ldx, const Stage& s, const FmmPrepare
   F.W = work + (size_t)K * R;
   F.L = F.W + nb * kP * (size_t)R;
   double* hX = work + (work_elems - hx_elems);
-  const int rb = (R + 255) / 256;
+  const int rb = (R + kRowsPerBlock - 1) / kRowsPerBlock;
   if (K > 0) {
     hipLaunchKernelGGL(fmm_charges, dim3((K + 31) / 32, (R + 31) / 32), dim3(256), 0, st, R, X, ldx, s, F.B);
     hipLaunchKernelGGL(fmm_p2m, dim3(1 << P.nlev, rb), dim3(256), 0, st, F, s.g, s.status);

@@ -98,7 +98,7 @@ void enqueue_root_copies(const Stage& s, HostRoots* h, hipStream_t st) {
 int fmm_products_impl(int nst, Stage* stages, const int* Rs, const double* const* Xs, const int* ldxs,
                       double* const* Xos, const int* ldos, const double* const* scales, const int* status_dev,
                       double* work, size_t work_elems, char* plan_dev, size_t plan_bytes, double eps,
-                      int mark_after, int tcall, hipStream_t st) {
+                      const int* marks, int tcall, hipStream_t st) {
   std::vector<HostRoots> h(nst);
   int status = 0;
   (void)hipMemcpyAsync(&status, status_dev, sizeof(int), hipMemcpyDeviceToHost, st);
@@ -122,37 +122,25 @@ int fmm_products_impl(int nst, Stage* stages, const int* Rs, const double* const
     if (fmm_launch(Rs[k], Xs[k], ldxs[k], stages[k], prep[k], plan_dev, Xos[k], ldos[k], scales[k], work,
                    work_elems, st) != 0)
       return SVDU_ENOMEM;
-    if (k == nst - 1 && mark_after >= 0) ring_mark(tcall, mark_after, st);
+    if (marks && marks[k] >= 0) ring_mark(tcall, marks[k], st);
   }
   return SVDU_OK;
 }
 
 int fmm_products(const Update& u, const Plan& P, double eps, int tcall, hipStream_t st) {
   const Layout& L = u.L;
-  // the two sides share the intermediate TR, so they run one after the other
-  {
-    Stage st2[2] = {P.host_stages[0], P.host_stages[1]};
-    const int Rs[2] = {u.m, u.m};
-    const double* Xs[2] = {u.U, L.TR};
-    const int ldx[2] = {u.ldu, u.m};
-    double* Xo[2] = {L.TR, u.U_out};
-    const int ldo[2] = {u.m, u.ldu_out};
-    const double* sc[2] = {nullptr, nullptr};
-    const int rc = fmm_products_impl(2, st2, Rs, Xs, ldx, Xo, ldo, sc, L.status, L.fmm_work, L.fmm_elems,
-                                     L.fmm_plan, L.fmm_plan_bytes, eps, 3, tcall, st);
-    if (rc != SVDU_OK) return rc;
-  }
-  {
-    Stage st2[2] = {P.host_stages[2], P.host_stages[3]};
-    const int Rs[2] = {u.n, u.n};
-    const double* Xs[2] = {u.V, L.TR};
-    const int ldx[2] = {u.ldv, u.n};
-    double* Xo[2] = {L.TR, u.V_out};
-    const int ldo[2] = {u.n, u.ldv_out};
-    const double* sc[2] = {nullptr, L.signs};
-    return fmm_products_impl(2, st2, Rs, Xs, ldx, Xo, ldo, sc, L.status, L.fmm_work, L.fmm_elems, L.fmm_plan,
-                             L.fmm_plan_bytes, eps, 4, tcall, st);
-  }
+  // all four products in one host round trip; the two sides use TR in turn,
+  // which stream order makes safe
+  Stage st4[4] = {P.host_stages[0], P.host_stages[1], P.host_stages[2], P.host_stages[3]};
+  const int Rs[4] = {u.m, u.m, u.n, u.n};
+  const double* Xs[4] = {u.U, L.TR, u.V, L.TR};
+  const int ldx[4] = {u.ldu, u.m, u.ldv, u.n};
+  double* Xo[4] = {L.TR, u.U_out, L.TR, u.V_out};
+  const int ldo[4] = {u.m, u.ldu_out, u.n, u.ldv_out};
+  const double* sc[4] = {nullptr, nullptr, nullptr, L.signs};
+  const int marks[4] = {-1, 3, -1, 4};
+  return fmm_products_impl(4, st4, Rs, Xs, ldx, Xo, ldo, sc, L.status, L.fmm_work, L.fmm_elems, L.fmm_plan,
+                           L.fmm_plan_bytes, eps, marks, tcall, st);
 }
 
 // Single-update workspace: the update's layout, then 2 kNumShapes tile
@@ -333,7 +321,7 @@ int svdu_eig_update(int R, int N, const double* X, int ldx, const double* lam, c
     const int ldos[1] = {ldo};
     const double* sc[1] = {nullptr};
     const int rc = fmm_products_impl(1, &s, Rs, Xs, ldxs, Xos, ldos, sc, E.status, E.fmm_work, E.fmm_elems,
-                                     E.fmm_plan, E.fmm_plan_bytes, eps, -1, -1, st);
+                                     E.fmm_plan, E.fmm_plan_bytes, eps, nullptr, -1, st);
     if (rc != SVDU_OK) return rc;
   } else {
     launch_gemm_f64(G, shape, false, 0, st);
