@@ -340,6 +340,8 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the reconstruction spot check")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the short measurements of the other forms (precision form) on the same inputs")
+    ap.add_argument("--path", choices=("direct", "fmm"), default="direct",
+                    help="product path of the timed steps (the metric is the direct path; fmm is for profiling)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving form")
     ap.add_argument("--serving-only", action="store_true", help="measure only the serving form")
@@ -401,12 +403,13 @@ def main():
     Uo = torch.empty((m, m), dtype=torch.float64, device=dev)
     so = torch.empty(m, dtype=torch.float64, device=dev)
     Vo = torch.empty((n, n), dtype=torch.float64, device=dev)
-    ws = svdu.new_workspace(svdu.svdu_workspace_bytes(m, n), dev)
+    path = svdu.SVDU_PATH_FMM if args.path == "fmm" else svdu.SVDU_PATH_DIRECT
+    ws = svdu.new_workspace(svdu.svdu_workspace_bytes(m, n, path), dev)
     stream = torch.cuda.current_stream()
 
     def step(k, check=False):
-        svdu.rank1_update(U, sigma, V, A_vecs[k], B_vecs[k], out=(Uo, so, Vo), workspace=ws, want_defl=False,
-                          stream=stream, check=check)
+        svdu.rank1_update(U, sigma, V, A_vecs[k], B_vecs[k], eps=1e-10, path=path, out=(Uo, so, Vo), workspace=ws,
+                          want_defl=False, stream=stream, check=check)
 
     for k in range(W):
         step(k, check=(k == 0))
@@ -458,7 +461,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"rank1_svd_update m={m} n={n} sigma~U[1e-3,1] haar U,V a,b~N(0,1/n) "
-                               "fp64 direct product", "m": m, "n": n, "path": "direct", "precision": "fp64",
+                               f"fp64 {args.path} product", "m": m, "n": n, "path": args.path, "precision": "fp64",
                    "seed": args.seed},
         "latency_ms": {"p50": float(np.percentile(per_update, 50)), "p99": float(np.percentile(per_update, 99)),
                        "mean": float(per_update.mean())},

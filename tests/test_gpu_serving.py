@@ -58,8 +58,14 @@ def test_served_results_equal_one_at_a_time(lib, workers, fmm_min_n):
                      min_batch_cost=2e9)
     init = _setup(lib, srv, SIZES)
     reqs = _requests(SIZES, 60, span=0.05, seed=workers + fmm_min_n)
+    # the first 20 are queued before the workers start (released at 0, so they
+    # batch); the rest arrive while those run
+    for k, (i, a, b, t) in enumerate(reqs):
+        if k < 20:
+            reqs[k] = (i, a, b, 0.0)
+            srv.submit(i, a, b, 0.0)
     srv.start()
-    for i, a, b, t in reqs:
+    for i, a, b, t in reqs[20:]:
         srv.submit(i, a, b, t)
     assert srv.drain(300.0) == lib.SVDU_OK
     done = sorted(srv.poll(), key=lambda c: c["id"])
