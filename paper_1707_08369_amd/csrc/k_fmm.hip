@@ -224,35 +224,62 @@ __global__ __launch_bounds__(256) void fmm_charges(int R, const double* __restri
 
 // ---------------------------------------------------------------------------
 // Row-batched operator products on the matrix cores. Every translation of
-// the expansion applies a small operator (at most 32 x 32, built in LDS from
+// the expansion applies small operators (at most 32 x 32, built in LDS from
 // the box geometry) to the same coefficients of all R rows:
 //   out[i][r] = sum_k Op[i][k] src[k][r],
 // one v_mfma_f64_16x16x4f64 per 16 operator rows, 4 k and 16 rows, with the
 // operator as the A operand (lane l: Op[l % 16][k0 + l / 16]) and 16
 // consecutive rows of the coefficients as B (lane l: src[k0 + l / 16][r0 +
 // l % 16]); result register v of lane l holds out[l / 16 + 4 v][r0 + l % 16].
-// A block has 4 waves; a wave owns kNT tiles of 16 rows.
+// A block builds the operators of its box once and then walks a chunk of
+// rows, 256 at a time (4 waves x kNT tiles of 16 rows); all loads of an
+// operator's coefficients are issued before its MFMAs.
 // ---------------------------------------------------------------------------
 typedef double fd4 __attribute__((ext_vector_type(4)));
 constexpr int kNT = 4;                     // row tiles of 16 per wave
 constexpr int kRowsPerBlock = 4 * 16 * kNT;
 constexpr int kOpLd = kP + 1;              // LDS row stride of a p x p operator (odd: no bank conflicts)
+constexpr int kOpsMax = 8;                 // p x p operators held in LDS at once (down pass)
+constexpr int kS = 32;                     // largest leaf
+constexpr int kNearMax = 5;                // near-field operators held in LDS at once (leaves)
 
-// acc[t] += Op[mrow0 .. mrow0 + 15][0 .. 4 ksteps) x src[k][rows of tile t], src[k] = 0 for k >= kvalid.
-__device__ __forceinline__ void mfma_apply(const double* op, int ld, int ksteps, int kvalid, const double* src,
-                                           int R, int r0, fd4 (&acc)[kNT]) {
-  const int lane = threadIdx.x & 63;
-  const int i = lane & 15, kq = lane >> 4;
-  for (int ks = 0; ks < ksteps; ++ks) {
-    const int k = 4 * ks + kq;
-    const double a = op[i * ld + k];
-    const bool kok = k < kvalid;
-    const double* row = src + (size_t)(kok ? k : 0) * R;
+__device__ __forceinline__ void zero_acc(fd4 (&acc)[kNT]) {
 #pragma unroll
-    for (int t = 0; t < kNT; ++t) {
-      const int r = r0 + 16 * t + i;
-      const double v = row[r < R ? r : R - 1];
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (kok && r < R) ? v : 0.0, acc[t], 0, 0, 0);
+  for (int t = 0; t < kNT; ++t) acc[t] = fd4{0.0, 0.0, 0.0, 0.0};
+}
+
+// Coefficients src[k][rows of the wave's tiles] for k < 4 KS, zero for k >= kvalid or r >= R.
+template <int KS>
+__device__ __forceinline__ void load_b(double (&b)[KS][kNT], int ksteps, int kvalid, const double* src, int R,
+                                       int r0) {
+  const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    if (ks < ksteps) {
+      const int k = 4 * ks + kq;
+      const bool kok = k < kvalid;
+      const double* row = src + (size_t)(kok ? k : 0) * R;
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) {
+        const int r = r0 + 16 * t + i;
+        const double v = row[r < R ? r : R - 1];
+        b[ks][t] = (kok && r < R) ? v : 0.0;
+      }
+    }
+  }
+}
+
+// acc[t] += Op[16 rows][0 .. 4 ksteps) x b[.][t]
+template <int KS>
+__device__ __forceinline__ void mfma_b(const double* op, int ld, int ksteps, const double (&b)[KS][kNT],
+                                       fd4 (&acc)[kNT]) {
+  const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    if (ks < ksteps) {
+      const double a = op[i * ld + 4 * ks + kq];
+#pragma unroll
+      for (int t = 0; t < kNT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ks][t], acc[t], 0, 0, 0);
     }
   }
 }
@@ -271,17 +298,20 @@ __device__ __forceinline__ void store_rows(const fd4 (&acc)[kNT], double* dst, i
   }
 }
 
-__device__ __forceinline__ void zero_acc(fd4 (&acc)[kNT]) {
-#pragma unroll
-  for (int t = 0; t < kNT; ++t) acc[t] = fd4{0.0, 0.0, 0.0, 0.0};
+// Row range of this block: chunks of whole 256-row groups.
+__device__ __forceinline__ void row_chunk(int R, int* rbeg, int* rend) {
+  const int groups = (R + kRowsPerBlock - 1) / kRowsPerBlock;
+  const int per = (groups + gridDim.y - 1) / gridDim.y;
+  *rbeg = blockIdx.y * per * kRowsPerBlock;
+  *rend = min(R, *rbeg + per * kRowsPerBlock);
 }
 
 // ---------------------------------------------------------------------------
 // P2M on the leaves: W[leaf][kk][r] = sum_{j in leaf} u_kk((g_j - c)/rad) B[j][r]
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void fmm_p2m(FmmDev F, const double* __restrict__ g, const int* status) {
-  constexpr int ld = 33;
-  __shared__ double op[16 * ld];   // [kk][source in leaf], at most 32 sources
+  constexpr int ld = kS + 1;
+  __shared__ double op[16 * ld];   // [kk][source in leaf]
   __shared__ ChebTab T;
   if (*status & kStFatal) return;
   const int id = box_id(F.nlev, blockIdx.x);
@@ -292,16 +322,23 @@ __global__ __launch_bounds__(256) void fmm_p2m(FmmDev F, const double* __restric
   const int ns = a1 - a0;
   cheb_fill(&T, F.p);
   __syncthreads();
-  for (int e = threadIdx.x; e < 16 * 32; e += blockDim.x) {
-    const int kk = e >> 5, j = e & 31;
+  for (int e = threadIdx.x; e < 16 * kS; e += blockDim.x) {
+    const int kk = e / kS, j = e % kS;
     op[kk * ld + j] = (kk < F.p && j < ns) ? lagrange(T, kk, F.p, (g[a0 + j] - c) / rad) : 0.0;
   }
   __syncthreads();
-  const int r0 = blockIdx.y * kRowsPerBlock + (threadIdx.x >> 6) * 16 * kNT;
-  fd4 acc[kNT];
-  zero_acc(acc);
-  mfma_apply(op, ld, (ns + 3) / 4, ns, F.B + (size_t)a0 * F.R, F.R, r0, acc);
-  store_rows(acc, F.W + (size_t)id * kP * F.R, F.p, F.R, r0);
+  int rbeg, rend;
+  row_chunk(F.R, &rbeg, &rend);
+  const int ksteps = (ns + 3) / 4;
+  for (int rt = rbeg; rt < rend; rt += kRowsPerBlock) {
+    const int r0 = rt + (threadIdx.x >> 6) * 16 * kNT;
+    double b[kS / 4][kNT];
+    load_b(b, ksteps, ns, F.B + (size_t)a0 * F.R, F.R, r0);
+    fd4 acc[kNT];
+    zero_acc(acc);
+    mfma_b(op, ld, ksteps, b, acc);
+    store_rows(acc, F.W + (size_t)id * kP * F.R, F.p, F.R, r0);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -331,19 +368,30 @@ __global__ __launch_bounds__(256) void fmm_m2m(FmmDev F, int level, const int* s
     op[q][kp * kOpLd + kc] = v;
   }
   __syncthreads();
-  const int r0 = blockIdx.y * kRowsPerBlock + (threadIdx.x >> 6) * 16 * kNT;
-  fd4 acc[kNT];
-  zero_acc(acc);
-  for (int q = 0; q < 2; ++q)
-    if (has[q]) mfma_apply(op[q], kOpLd, (F.p + 3) / 4, F.p, F.W + (size_t)ch[q] * kP * F.R, F.R, r0, acc);
-  store_rows(acc, F.W + (size_t)id * kP * F.R, F.p, F.R, r0);
+  int rbeg, rend;
+  row_chunk(F.R, &rbeg, &rend);
+  const int ksteps = (F.p + 3) / 4;
+  for (int rt = rbeg; rt < rend; rt += kRowsPerBlock) {
+    const int r0 = rt + (threadIdx.x >> 6) * 16 * kNT;
+    fd4 acc[kNT];
+    zero_acc(acc);
+    for (int q = 0; q < 2; ++q) {
+      if (!has[q]) continue;
+      double b[kP / 4][kNT];
+      load_b(b, ksteps, F.p, F.W + (size_t)ch[q] * kP * F.R, F.R, r0);
+      mfma_b(op[q], kOpLd, ksteps, b, acc);
+    }
+    store_rows(acc, F.W + (size_t)id * kP * F.R, F.p, F.R, r0);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Downward pass for one level: L[T] = L2L(L[parent]) + sum_S M2L(W[S])
+// Downward pass for one level: L[T] = L2L(L[parent]) + sum_S M2L(W[S]).
+// Operators in groups of kOpsMax (L2L first); one group in LDS at a time.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void fmm_down(FmmDev F, int level, const int* status) {
-  __shared__ double op[16 * kOpLd];
+  __shared__ double op[kOpsMax][16 * kOpLd];
+  __shared__ const double* srcp[kOpsMax];
   __shared__ ChebTab T;
   if (*status & kStFatal) return;
   const int id = box_id(level, blockIdx.x);
@@ -351,52 +399,78 @@ __global__ __launch_bounds__(256) void fmm_down(FmmDev F, int level, const int* 
   double ct, rt;
   box_cr(F, id, &ct, &rt);
   cheb_fill(&T, F.p);
+  const int q0 = F.m2l_ptr[id], nm2l = F.m2l_ptr[id + 1] - q0;
+  const int nops = (level > 0 ? 1 : 0) + nm2l;
+  const int ngroups = (nops + kOpsMax - 1) / kOpsMax;
   __syncthreads();
-  const int r0 = blockIdx.y * kRowsPerBlock + (threadIdx.x >> 6) * 16 * kNT;
+  // operator o of the box: o = 0 is L2L when level > 0, the rest M2L
+  auto build_group = [&](int gidx) {
+    const int o0 = gidx * kOpsMax, cnt = min(kOpsMax, nops - o0);
+    for (int e = threadIdx.x; e < cnt * 256; e += blockDim.x) {
+      const int qi = e >> 8, rem = e & 255, i = rem >> 4, k = rem & 15;
+      const int o = o0 + qi;
+      double v = 0.0;
+      if (i < F.p && k < F.p) {
+        if (level > 0 && o == 0) {
+          const int par = box_id(level - 1, blockIdx.x >> 1);
+          double cp, rp;
+          box_cr(F, par, &cp, &rp);
+          v = lagrange(T, k, F.p, (ct + rt * T.t[i] - cp) / rp);
+        } else {
+          const int src = F.m2l_src[q0 + o - (level > 0 ? 1 : 0)];
+          double cs, rs;
+          box_cr(F, src, &cs, &rs);
+          v = 1.0 / ((cs + rs * T.t[k]) - (ct + rt * T.t[i]));
+        }
+      }
+      op[qi][i * kOpLd + k] = v;
+    }
+    for (int qi = threadIdx.x; qi < cnt; qi += blockDim.x) {
+      const int o = o0 + qi;
+      if (level > 0 && o == 0)
+        srcp[qi] = F.L + (size_t)box_id(level - 1, blockIdx.x >> 1) * kP * F.R;
+      else
+        srcp[qi] = F.W + (size_t)F.m2l_src[q0 + o - (level > 0 ? 1 : 0)] * kP * F.R;
+    }
+  };
+  if (ngroups == 1) build_group(0);
+  __syncthreads();
+  int rbeg, rend;
+  row_chunk(F.R, &rbeg, &rend);
   const int ksteps = (F.p + 3) / 4;
-  fd4 acc[kNT];
-  zero_acc(acc);
-  if (level > 0) {
-    const int par = box_id(level - 1, blockIdx.x >> 1);
-    double cp, rp;
-    box_cr(F, par, &cp, &rp);
-    for (int e = threadIdx.x; e < 16 * 16; e += blockDim.x) {
-      const int kc = e >> 4, kp = e & 15;
-      op[kc * kOpLd + kp] =
-          (kc < F.p && kp < F.p) ? lagrange(T, kp, F.p, (ct + rt * T.t[kc] - cp) / rp) : 0.0;
+  for (int rt0 = rbeg; rt0 < rend; rt0 += kRowsPerBlock) {
+    const int r0 = rt0 + (threadIdx.x >> 6) * 16 * kNT;
+    fd4 acc[kNT];
+    zero_acc(acc);
+    for (int gi = 0; gi < ngroups; ++gi) {
+      if (ngroups > 1) {
+        __syncthreads();
+        build_group(gi);
+        __syncthreads();
+      }
+      const int cnt = min(kOpsMax, nops - gi * kOpsMax);
+      for (int qi = 0; qi < cnt; ++qi) {
+        double b[kP / 4][kNT];
+        load_b(b, ksteps, F.p, srcp[qi], F.R, r0);
+        mfma_b(op[qi], kOpLd, ksteps, b, acc);
+      }
     }
-    __syncthreads();
-    mfma_apply(op, kOpLd, ksteps, F.p, F.L + (size_t)par * kP * F.R, F.R, r0, acc);
-    __syncthreads();
+    store_rows(acc, F.L + (size_t)id * kP * F.R, F.p, F.R, r0);
   }
-  for (int q = F.m2l_ptr[id]; q < F.m2l_ptr[id + 1]; ++q) {
-    const int src = F.m2l_src[q];
-    double cs, rs;
-    box_cr(F, src, &cs, &rs);
-    for (int e = threadIdx.x; e < 16 * 16; e += blockDim.x) {
-      const int kt = e >> 4, ks = e & 15;
-      op[kt * kOpLd + ks] = (kt < F.p && ks < F.p) ? 1.0 / ((cs + rs * T.t[ks]) - (ct + rt * T.t[kt])) : 0.0;
-    }
-    __syncthreads();
-    mfma_apply(op, kOpLd, ksteps, F.p, F.W + (size_t)src * kP * F.R, F.R, r0, acc);
-    __syncthreads();
-  }
-  store_rows(acc, F.L + (size_t)id * kP * F.R, F.p, F.R, r0);
 }
 
 // ---------------------------------------------------------------------------
 // Leaves: L2P + P2P, scaled by the column scale, written to the output
 // positions of the roots. A leaf holds at most kS = 32 poles and roots; the
-// targets are two 16-row operator blocks.
+// targets are two 16-row operator blocks that share every loaded coefficient.
 // ---------------------------------------------------------------------------
-constexpr int kS = 32;
-
 __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* __restrict__ Xo, int ldo,
                                                       const double* __restrict__ colscale) {
   constexpr int ldu = kOpLd, ldi = kS + 1;
-  __shared__ double ul[kS * ldu];        // L2P weights [target][kk]
-  __shared__ double inv[kS * ldi];       // 1/delta [target][near source]
-  __shared__ double out[64 * (kS + 1)];  // one wave's 64 rows, staged for row-wise stores
+  __shared__ double ul[kS * ldu];               // L2P weights [target][kk]
+  __shared__ double inv[kNearMax][kS * ldi];    // 1/delta [near box][target][source]
+  __shared__ double out[64 * (kS + 1)];         // one wave's 64 rows, staged for row-wise stores
+  __shared__ int nb0[kNearMax], nns[kNearMax];
   __shared__ int pos[kS];
   __shared__ double scl[kS];
   __shared__ ChebTab T;
@@ -408,6 +482,8 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
   double ct, rt;
   box_cr(F, id, &ct, &rt);
   cheb_fill(&T, F.p);
+  const int q0 = F.near_ptr[id], nnear = F.near_ptr[id + 1] - q0;
+  const int ngroups = (nnear + kNearMax - 1) / kNearMax;
   __syncthreads();
   for (int e = threadIdx.x; e < kS * 16; e += blockDim.x) {
     const int t = e >> 4, kk = e & 15;
@@ -418,57 +494,83 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
     pos[t] = P;
     scl[t] = (colscale ? colscale[P] : 1.0) * s.cs[a0 + t];
   }
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = blockIdx.y * kRowsPerBlock + wave * 16 * kNT;
-  fd4 acc[2][kNT];
-  zero_acc(acc[0]);
-  zero_acc(acc[1]);
-  const int ksl = (F.p + 3) / 4;
-  const double* Lsrc = F.L + (size_t)id * kP * F.R;
-  mfma_apply(ul, ldu, ksl, F.p, Lsrc, F.R, r0, acc[0]);
-  if (nt > 16) mfma_apply(ul + 16 * ldu, ldu, ksl, F.p, Lsrc, F.R, r0, acc[1]);
-  for (int q = F.near_ptr[id]; q < F.near_ptr[id + 1]; ++q) {
-    const int nbx = F.near_src[q];
-    const int b0 = F.s0[nbx], ns = F.s1[nbx] - b0;
-    __syncthreads();
-    for (int e = threadIdx.x; e < kS * kS; e += blockDim.x) {
-      const int t = e >> 5, j = e & 31;
+  auto build_group = [&](int gidx) {
+    const int o0 = gidx * kNearMax, cnt = min(kNearMax, nnear - o0);
+    for (int e = threadIdx.x; e < cnt * kS * kS; e += blockDim.x) {
+      const int qi = e / (kS * kS), rem = e % (kS * kS), t = rem / kS, j = rem % kS;
+      const int nbx = F.near_src[q0 + o0 + qi];
+      const int b0 = F.s0[nbx], ns = F.s1[nbx] - b0;
       double v = 0.0;
       if (t < nt && j < ns) {
         const int k = b0 + j, i = a0 + t;
         v = 1.0 / ((s.g[k] - s.g[s.org[i]]) - s.tau[i]);
       }
-      inv[t * ldi + j] = v;
+      inv[qi][t * ldi + j] = v;
     }
-    __syncthreads();
-    const int ksn = (ns + 3) / 4;
-    const double* Bsrc = F.B + (size_t)b0 * F.R;
-    mfma_apply(inv, ldi, ksn, ns, Bsrc, F.R, r0, acc[0]);
-    if (nt > 16) mfma_apply(inv + 16 * ldi, ldi, ksn, ns, Bsrc, F.R, r0, acc[1]);
-  }
-  // stores: one wave's 64 rows at a time through LDS, then each row's nt
-  // outputs by consecutive lanes
-  for (int w = 0; w < 4; ++w) {
-    __syncthreads();
-    if (wave == w) {
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+    for (int qi = threadIdx.x; qi < cnt; qi += blockDim.x) {
+      const int nbx = F.near_src[q0 + o0 + qi];
+      nb0[qi] = F.s0[nbx];
+      nns[qi] = F.s1[nbx] - F.s0[nbx];
+    }
+  };
+  if (ngroups == 1) build_group(0);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ksl = (F.p + 3) / 4;
+  const bool two = nt > 16;
+  const double* Lsrc = F.L + (size_t)id * kP * F.R;
+  int rbeg, rend;
+  row_chunk(F.R, &rbeg, &rend);
+  for (int rt0 = rbeg; rt0 < rend; rt0 += kRowsPerBlock) {
+    const int r0 = rt0 + wave * 16 * kNT;
+    fd4 acc0[kNT], acc1[kNT];
+    zero_acc(acc0);
+    zero_acc(acc1);
+    {
+      double b[kP / 4][kNT];
+      load_b(b, ksl, F.p, Lsrc, F.R, r0);
+      mfma_b(ul, ldu, ksl, b, acc0);
+      if (two) mfma_b(ul + 16 * ldu, ldu, ksl, b, acc1);
+    }
+    for (int gi = 0; gi < ngroups; ++gi) {
+      if (ngroups > 1) {
+        __syncthreads();
+        build_group(gi);
+        __syncthreads();
+      }
+      const int cnt = min(kNearMax, nnear - gi * kNearMax);
+      for (int qi = 0; qi < cnt; ++qi) {
+        const int ns = nns[qi], ksn = (ns + 3) / 4;
+        double b[kS / 4][kNT];
+        load_b(b, ksn, ns, F.B + (size_t)nb0[qi] * F.R, F.R, r0);
+        mfma_b(inv[qi], ldi, ksn, b, acc0);
+        if (two) mfma_b(inv[qi] + 16 * ldi, ldi, ksn, b, acc1);
+      }
+    }
+    // stores: one wave's 64 rows at a time through LDS, then each row's nt
+    // outputs by consecutive lanes
+    for (int w = 0; w < 4; ++w) {
+      __syncthreads();
+      if (wave == w) {
 #pragma unroll
         for (int t = 0; t < kNT; ++t)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int tg = mb * 16 + (lane >> 4) + 4 * v;
-            if (tg < nt) out[(16 * t + (lane & 15)) * (kS + 1) + tg] = scl[tg] * acc[mb][t][v];
+            const int tg = (lane >> 4) + 4 * v;
+            double* o = out + (16 * t + (lane & 15)) * (kS + 1);
+            if (tg < nt) o[tg] = scl[tg] * acc0[t][v];
+            if (tg + 16 < nt) o[tg + 16] = scl[tg + 16] * acc1[t][v];
           }
+      }
+      __syncthreads();
+      const int rw = rt0 + w * 16 * kNT;
+      for (int e = threadIdx.x; e < 64 * nt; e += blockDim.x) {
+        const int rr = e / nt, t = e - rr * nt;
+        const int row = rw + rr;
+        if (row < F.R) Xo[(size_t)row * ldo + pos[t]] = out[rr * (kS + 1) + t];
+      }
     }
-    __syncthreads();
-    const int rw = blockIdx.y * kRowsPerBlock + w * 16 * kNT;
-    for (int e = threadIdx.x; e < 64 * nt; e += blockDim.x) {
-      const int rr = e / nt, t = e - rr * nt;
-      const int row = rw + rr;
-      if (row < F.R) Xo[(size_t)row * ldo + pos[t]] = out[rr * (kS + 1) + t];
-    }
+    __syncthreads();   // `out` and the near-field groups are reused by the next row group
   }
 }
 
@@ -587,14 +689,17 @@ int fmm_launch(int R, const double* X, int ldx, const Stage& s, const FmmPrepare
   F.L = F.W + nb * kP * (size_t)R;
   double* hX = work + (work_elems - hx_elems);
   const int rb = (R + kRowsPerBlock - 1) / kRowsPerBlock;
+  // row chunks per box: about 1024 blocks per launch, whole 256-row groups
+  auto chunks = [&](int boxes) { return std::max(1, std::min(rb, (1024 + boxes - 1) / boxes)); };
   if (K > 0) {
     hipLaunchKernelGGL(fmm_charges, dim3((K + 31) / 32, (R + 31) / 32), dim3(256), 0, st, R, X, ldx, s, F.B);
-    hipLaunchKernelGGL(fmm_p2m, dim3(1 << P.nlev, rb), dim3(256), 0, st, F, s.g, s.status);
+    hipLaunchKernelGGL(fmm_p2m, dim3(1 << P.nlev, chunks(1 << P.nlev)), dim3(256), 0, st, F, s.g, s.status);
     for (int l = P.nlev - 1; l >= 0; --l)
-      hipLaunchKernelGGL(fmm_m2m, dim3(1 << l, rb), dim3(256), 0, st, F, l, s.status);
+      hipLaunchKernelGGL(fmm_m2m, dim3(1 << l, chunks(1 << l)), dim3(256), 0, st, F, l, s.status);
     for (int l = 0; l <= P.nlev; ++l)
-      hipLaunchKernelGGL(fmm_down, dim3(1 << l, rb), dim3(256), 0, st, F, l, s.status);
-    hipLaunchKernelGGL(fmm_leaf_eval, dim3(1 << P.nlev, rb), dim3(256), 0, st, F, s, Xo, ldo, colscale);
+      hipLaunchKernelGGL(fmm_down, dim3(1 << l, chunks(1 << l)), dim3(256), 0, st, F, l, s.status);
+    hipLaunchKernelGGL(fmm_leaf_eval, dim3(1 << P.nlev, chunks(1 << P.nlev)), dim3(256), 0, st, F, s, Xo, ldo,
+                       colscale);
   }
   if (K < N) {
     hipLaunchKernelGGL(fmm_group_dots, dim3(std::max(K, 1), rb), dim3(256), 0, st, R, X, ldx, s, hX);
