@@ -21,13 +21,13 @@ struct ColDesc {
 __device__ __forceinline__ ColDesc load_col(const CauchyDesc& d, int c) {
   ColDesc r{-1, 0.0, 0.0, 0.0, 0.0, -1, -1};
   if (c < d.N) {
-    r.type = d.ctype[c];
-    r.o = d.co[c];
-    r.t = d.ctau[c];
-    r.s = d.ccs[c];
-    r.h = d.ch[c];
-    r.cl = d.ccl[c];
-    r.mem = d.cmem[c];
+    r.type = gld(d.ctype + c);
+    r.o = gld(d.co + c);
+    r.t = gld(d.ctau + c);
+    r.s = gld(d.ccs + c);
+    r.h = gld(d.ch + c);
+    r.cl = gld(d.ccl + c);
+    r.mem = gld(d.cmem + c);
   }
   return r;
 }
@@ -74,16 +74,16 @@ __device__ __forceinline__ double general_entry(int j, const RowVals& rv, const 
 template <bool LIVE>
 __device__ __forceinline__ double gen_entry(const CauchyDesc& d, int j, int N, const ColDesc& c, double* mind) {
   const int jj = j < N ? j : N - 1;
-  const double zl = d.rzeta[jj];   // unconditional load (index clamped), then select
+  const double zl = gld(d.rzeta + jj);   // unconditional load (index clamped), then select
   const double z = (j < N) ? zl : 0.0;
-  const double g = d.rg[jj];
+  const double g = gld(d.rg + jj);
   if (LIVE) {
     double ad;
     const double v = live_entry(z, g, c, &ad);
     *mind = __builtin_fmin(*mind, ad);
     return v;
   } else {
-    RowVals rv{z, g, d.rh[jj], (j < N) ? d.rcl[jj] : -2};
+    RowVals rv{z, g, gld(d.rh + jj), (j < N) ? gld(d.rcl + jj) : -2};
     return general_entry(j, rv, c);
   }
 }

@@ -19,6 +19,25 @@ __device__ __forceinline__ double recip(double x) {
   return __builtin_fma(r, e, r);
 }
 
+// Global-memory access through a generic pointer. Pointers read from job
+// tables are generic to the compiler; casting them to the global address space
+// gives global (not flat) loads and stores, which the memory counters track
+// apart from LDS traffic.
+template <class T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *((const __attribute__((address_space(1))) T*)p);
+}
+template <class T>
+__device__ __forceinline__ void gst(T* p, T v) {
+  *((__attribute__((address_space(1))) T*)p) = v;
+}
+// 16-byte load of two consecutive doubles (p 16-byte aligned).
+__device__ __forceinline__ double2 gld2(const double* p) {
+  typedef double dv2 __attribute__((ext_vector_type(2)));
+  const dv2 v = *((const __attribute__((address_space(1))) dv2*)p);
+  return double2{v.x, v.y};
+}
+
 // Butterfly reductions over a full wave of 64 lanes. IEEE addition and
 // multiplication commute, so every lane ends with the same bits.
 __device__ __forceinline__ double wave_sum(double v) {

@@ -59,8 +59,8 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
     if (J.vec_a && k0 + kBK <= N) {   // block-uniform: the whole step is in range
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
-        const double2 v0 = *reinterpret_cast<const double2*>(xr[mb] + kb);
-        const double2 v1 = *reinterpret_cast<const double2*>(xr[mb] + kb + 2);
+        const double2 v0 = gld2(xr[mb] + kb);
+        const double2 v1 = gld2(xr[mb] + kb + 2);
         a[mb][0] = rok[mb] ? v0.x : 0.0;
         a[mb][1] = rok[mb] ? v0.y : 0.0;
         a[mb][2] = rok[mb] ? v1.x : 0.0;
@@ -72,7 +72,7 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int k = kb + s;
-          const double v = xr[mb][k < N ? k : (N - 1)];
+          const double v = gld(xr[mb] + (k < N ? k : (N - 1)));
           a[mb][s] = (rok[mb] && k < N) ? v : 0.0;
         }
     }
@@ -83,7 +83,7 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
     for (int r = 0; r < 4; ++r) {
       const int j = jb + r;
       const int jj = j < N ? j : N - 1;
-      RowVals rv{(j < N) ? d.rzeta[jj] : 0.0, d.rg[jj], 0.0, -2};
+      RowVals rv{(j < N) ? gld(d.rzeta + jj) : 0.0, gld(d.rg + jj), 0.0, -2};
 #pragma unroll
       for (int c = 0; c < NC; ++c) bg[r][c] = general_entry(j, rv, cc[c]);
     }
@@ -143,13 +143,13 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
   for (int nb = 0; nb < NB; ++nb) {
     const int col = n0 + nb * 16 + (lane & 15);
     if (col >= N) continue;
-    const double sc = d.colscale ? d.colscale[col] : 1.0;
+    const double sc = d.colscale ? gld(d.colscale + col) : 1.0;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = m0 + wave * 16 * MB + mb * 16 + (lane >> 4) + 4 * v;
-        if (row < R) J.Xo[(size_t)row * J.ldo + col] = sc * acc[mb][nb][v];
+        if (row < R) gst(J.Xo + (size_t)row * J.ldo + col, sc * acc[mb][nb][v]);
       }
     }
   }
