@@ -10,6 +10,7 @@ namespace svdu {
 
 struct FmmHostPlan {
   int p = 0, s = 0, K = 0, nlev = 0, nbox = 0;
+  int outlier = -1;                 // root outside [g_0, g_K-1], evaluated directly
   std::vector<double> lo, hi;       // box intervals
   std::vector<int> s0, s1;          // source / target index range of each box
   std::vector<int> m2l_ptr, m2l_src;

@@ -54,11 +54,19 @@ int fmm_order(double eps) {
 static void build_plan(int K, const double* g, const double* mu, int p, FmmHostPlan* P) {
   P->p = p;
   P->K = K;
-  P->s = 2 * p;
-  const int s = P->s;
-  const int nleaf = (K + s - 1) / s;
+  // a full binary tree whose leaves hold at most 32 poles each
   int nlev = 0;
-  while ((1 << nlev) < nleaf) ++nlev;
+  while ((K + (1 << nlev) - 1) >> nlev > 32) ++nlev;
+  P->s = (K + (1 << nlev) - 1) >> nlev;
+  const int s = P->s;
+  // The extreme root (beyond the last pole for rho > 0, before the first for
+  // rho < 0) can lie far outside the spectrum; it is evaluated directly
+  // against all poles and kept out of the box intervals, which would
+  // otherwise make its leaf, and every box above it, inadmissible to all.
+  P->outlier = -1;
+  for (int i = 0; i < K; ++i)
+    if (mu[i] > g[K - 1] || mu[i] < g[0]) P->outlier = i;
+  auto in_box = [&](int i) { return i != P->outlier; };
   P->nlev = nlev;
   P->nbox = (1 << (nlev + 1)) - 1;
   P->lo.assign(P->nbox, 0.0);
@@ -75,8 +83,12 @@ static void build_plan(int K, const double* g, const double* mu, int p, FmmHostP
     if (a0 < a1) {
       double lo = g[a0], hi = g[a0];
       for (int i = a0; i < a1; ++i) {
-        lo = std::min(lo, std::min(g[i], mu[i]));
-        hi = std::max(hi, std::max(g[i], mu[i]));
+        lo = std::min(lo, g[i]);
+        hi = std::max(hi, g[i]);
+        if (in_box(i)) {
+          lo = std::min(lo, mu[i]);
+          hi = std::max(hi, mu[i]);
+        }
       }
       P->lo[id] = lo;
       P->hi[id] = hi;
@@ -149,6 +161,7 @@ static void build_plan(int K, const double* g, const double* mu, int p, FmmHostP
 // ---------------------------------------------------------------------------
 struct FmmDev {
   int p, s, K, nlev, nbox, R;
+  int outlier;  // root evaluated directly (-1: none)
   const double* lo;
   const double* hi;
   const int* s0;
@@ -241,7 +254,7 @@ constexpr int kRowsPerBlock = 4 * 16 * kNT;
 constexpr int kOpLd = kP + 1;              // LDS row stride of a p x p operator (odd: no bank conflicts)
 constexpr int kOpsMax = 8;                 // p x p operators held in LDS at once (down pass)
 constexpr int kS = 32;                     // largest leaf
-constexpr int kNearMax = 5;                // near-field operators held in LDS at once (leaves)
+constexpr int kNearMax = 6;                // near-field operators held in LDS at once (leaves)
 
 __device__ __forceinline__ void zero_acc(fd4 (&acc)[kNT]) {
 #pragma unroll
@@ -262,7 +275,7 @@ __device__ __forceinline__ void load_b(double (&b)[KS][kNT], int ksteps, int kva
 #pragma unroll
       for (int t = 0; t < kNT; ++t) {
         const int r = r0 + 16 * t + i;
-        const double v = row[r < R ? r : R - 1];
+        const double v = gld(row + (r < R ? r : R - 1));
         b[ks][t] = (kok && r < R) ? v : 0.0;
       }
     }
@@ -293,7 +306,7 @@ __device__ __forceinline__ void store_rows(const fd4 (&acc)[kNT], double* dst, i
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int mi = (lane >> 4) + 4 * v;
-      if (mi < mvalid && r < R) dst[(size_t)mi * R + r] = acc[t][v];
+      if (mi < mvalid && r < R) gst(dst + (size_t)mi * R + r, acc[t][v]);
     }
   }
 }
@@ -392,6 +405,7 @@ __global__ __launch_bounds__(256) void fmm_m2m(FmmDev F, int level, const int* s
 __global__ __launch_bounds__(256) void fmm_down(FmmDev F, int level, const int* status) {
   __shared__ double op[kOpsMax][16 * kOpLd];
   __shared__ const double* srcp[kOpsMax];
+  __shared__ double oc[kOpsMax], orad[kOpsMax];
   __shared__ ChebTab T;
   if (*status & kStFatal) return;
   const int id = box_id(level, blockIdx.x);
@@ -403,34 +417,32 @@ __global__ __launch_bounds__(256) void fmm_down(FmmDev F, int level, const int* 
   const int nops = (level > 0 ? 1 : 0) + nm2l;
   const int ngroups = (nops + kOpsMax - 1) / kOpsMax;
   __syncthreads();
-  // operator o of the box: o = 0 is L2L when level > 0, the rest M2L
+  // operator o of the box: o = 0 is L2L when level > 0, the rest M2L. The
+  // centre and radius of each operator's other box are staged first.
   auto build_group = [&](int gidx) {
     const int o0 = gidx * kOpsMax, cnt = min(kOpsMax, nops - o0);
+    for (int qi = threadIdx.x; qi < cnt; qi += blockDim.x) {
+      const int o = o0 + qi;
+      const int other = (level > 0 && o == 0) ? box_id(level - 1, blockIdx.x >> 1)
+                                              : F.m2l_src[q0 + o - (level > 0 ? 1 : 0)];
+      double c, r;
+      box_cr(F, other, &c, &r);
+      oc[qi] = c;
+      orad[qi] = r;
+      srcp[qi] = ((level > 0 && o == 0) ? F.L : F.W) + (size_t)other * kP * F.R;
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < cnt * 256; e += blockDim.x) {
       const int qi = e >> 8, rem = e & 255, i = rem >> 4, k = rem & 15;
       const int o = o0 + qi;
       double v = 0.0;
       if (i < F.p && k < F.p) {
-        if (level > 0 && o == 0) {
-          const int par = box_id(level - 1, blockIdx.x >> 1);
-          double cp, rp;
-          box_cr(F, par, &cp, &rp);
-          v = lagrange(T, k, F.p, (ct + rt * T.t[i] - cp) / rp);
-        } else {
-          const int src = F.m2l_src[q0 + o - (level > 0 ? 1 : 0)];
-          double cs, rs;
-          box_cr(F, src, &cs, &rs);
-          v = 1.0 / ((cs + rs * T.t[k]) - (ct + rt * T.t[i]));
-        }
+        if (level > 0 && o == 0)
+          v = lagrange(T, k, F.p, (ct + rt * T.t[i] - oc[qi]) / orad[qi]);
+        else
+          v = 1.0 / ((oc[qi] + orad[qi] * T.t[k]) - (ct + rt * T.t[i]));
       }
       op[qi][i * kOpLd + k] = v;
-    }
-    for (int qi = threadIdx.x; qi < cnt; qi += blockDim.x) {
-      const int o = o0 + qi;
-      if (level > 0 && o == 0)
-        srcp[qi] = F.L + (size_t)box_id(level - 1, blockIdx.x >> 1) * kP * F.R;
-      else
-        srcp[qi] = F.W + (size_t)F.m2l_src[q0 + o - (level > 0 ? 1 : 0)] * kP * F.R;
     }
   };
   if (ngroups == 1) build_group(0);
@@ -472,7 +484,7 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
   __shared__ double out[64 * (kS + 1)];         // one wave's 64 rows, staged for row-wise stores
   __shared__ int nb0[kNearMax], nns[kNearMax];
   __shared__ int pos[kS];
-  __shared__ double scl[kS];
+  __shared__ double scl[kS], tgo[kS], tgt[kS], srcg[kNearMax][kS];
   __shared__ ChebTab T;
   if (*s.status & kStFatal) return;
   const int id = box_id(F.nlev, blockIdx.x);
@@ -484,33 +496,39 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
   cheb_fill(&T, F.p);
   const int q0 = F.near_ptr[id], nnear = F.near_ptr[id + 1] - q0;
   const int ngroups = (nnear + kNearMax - 1) / kNearMax;
+  // per target: origin pole, offset, column position and scale (one load each)
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+    const int i = a0 + t;
+    const int P = gld(s.rootpos + i);
+    pos[t] = P;
+    scl[t] = (colscale ? gld(colscale + P) : 1.0) * gld(s.cs + i);
+    tgo[t] = gld(s.g + gld(s.org + i));
+    tgt[t] = gld(s.tau + i);
+    if (i == F.outlier) pos[t] = -1;   // evaluated by fmm_outlier_partial / fmm_outlier_reduce
+  }
   __syncthreads();
   for (int e = threadIdx.x; e < kS * 16; e += blockDim.x) {
     const int t = e >> 4, kk = e & 15;
-    ul[t * ldu + kk] = (t < nt && kk < F.p) ? lagrange(T, kk, F.p, (s.mu[a0 + t] - ct) / rt) : 0.0;
-  }
-  for (int t = threadIdx.x; t < nt; t += blockDim.x) {
-    const int P = s.rootpos[a0 + t];
-    pos[t] = P;
-    scl[t] = (colscale ? colscale[P] : 1.0) * s.cs[a0 + t];
+    ul[t * ldu + kk] =
+        (t < nt && kk < F.p && pos[t] >= 0) ? lagrange(T, kk, F.p, ((tgo[t] + tgt[t]) - ct) / rt) : 0.0;
   }
   auto build_group = [&](int gidx) {
     const int o0 = gidx * kNearMax, cnt = min(kNearMax, nnear - o0);
-    for (int e = threadIdx.x; e < cnt * kS * kS; e += blockDim.x) {
-      const int qi = e / (kS * kS), rem = e % (kS * kS), t = rem / kS, j = rem % kS;
+    for (int e = threadIdx.x; e < cnt * kS; e += blockDim.x) {
+      const int qi = e / kS, j = e % kS;
       const int nbx = F.near_src[q0 + o0 + qi];
       const int b0 = F.s0[nbx], ns = F.s1[nbx] - b0;
-      double v = 0.0;
-      if (t < nt && j < ns) {
-        const int k = b0 + j, i = a0 + t;
-        v = 1.0 / ((s.g[k] - s.g[s.org[i]]) - s.tau[i]);
+      srcg[qi][j] = (j < ns) ? gld(s.g + b0 + j) : 0.0;
+      if (j == 0) {
+        nb0[qi] = b0;
+        nns[qi] = ns;
       }
-      inv[qi][t * ldi + j] = v;
     }
-    for (int qi = threadIdx.x; qi < cnt; qi += blockDim.x) {
-      const int nbx = F.near_src[q0 + o0 + qi];
-      nb0[qi] = F.s0[nbx];
-      nns[qi] = F.s1[nbx] - F.s0[nbx];
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt * kS * kS; e += blockDim.x) {
+      const int qi = e / (kS * kS), rem = e % (kS * kS), t = rem / kS, j = rem % kS;
+      inv[qi][t * ldi + j] =
+          (t < nt && j < nns[qi] && pos[t] >= 0) ? 1.0 / ((srcg[qi][j] - tgo[t]) - tgt[t]) : 0.0;
     }
   };
   if (ngroups == 1) build_group(0);
@@ -567,11 +585,53 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
       for (int e = threadIdx.x; e < 64 * nt; e += blockDim.x) {
         const int rr = e / nt, t = e - rr * nt;
         const int row = rw + rr;
-        if (row < F.R) Xo[(size_t)row * ldo + pos[t]] = out[rr * (kS + 1) + t];
+        if (row < F.R && pos[t] >= 0) gst(Xo + (size_t)row * ldo + pos[t], out[rr * (kS + 1) + t]);
       }
     }
     __syncthreads();   // `out` and the near-field groups are reused by the next row group
   }
+}
+
+// ---------------------------------------------------------------------------
+// The outlier root, directly: Xo[r, P] = s_c sum_k B[k][r] / ((g_k - d_org) - tau),
+// as partial sums over kOutChunks ranges of poles (into `part`, chunk-major),
+// then a fixed-order reduction.
+// ---------------------------------------------------------------------------
+constexpr int kOutChunks = 32;
+
+__global__ __launch_bounds__(256) void fmm_outlier_partial(FmmDev F, Stage s, double* __restrict__ part) {
+  __shared__ double w[256];
+  if (*s.status & kStFatal) return;
+  const int i = F.outlier;
+  const double go = gld(s.g + gld(s.org + i)), ti = gld(s.tau + i);
+  const int per = (F.K + kOutChunks - 1) / kOutChunks;
+  const int kb = blockIdx.y * per, ke = min(F.K, kb + per);
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  for (int k0 = kb; k0 < ke; k0 += 256) {
+    __syncthreads();
+    const int k = k0 + threadIdx.x;
+    if (k < ke) w[threadIdx.x] = 1.0 / ((gld(s.g + k) - go) - ti);
+    __syncthreads();
+    const int kn = min(256, ke - k0);
+    if (r < F.R)
+      for (int q = 0; q < kn; ++q) acc += gld(F.B + (size_t)(k0 + q) * F.R + r) * w[q];
+  }
+  if (r < F.R) gst(part + (size_t)blockIdx.y * F.R + r, acc);
+}
+
+__global__ __launch_bounds__(256) void fmm_outlier_reduce(FmmDev F, Stage s, const double* __restrict__ part,
+                                                           double* __restrict__ Xo, int ldo,
+                                                           const double* __restrict__ colscale) {
+  if (*s.status & kStFatal) return;
+  const int i = F.outlier;
+  const int P = gld(s.rootpos + i);
+  const double sc = (colscale ? gld(colscale + P) : 1.0) * gld(s.cs + i);
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= F.R) return;
+  double acc = 0.0;
+  for (int c = 0; c < kOutChunks; ++c) acc += gld(part + (size_t)c * F.R + r);
+  gst(Xo + (size_t)r * ldo + P, sc * acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -614,10 +674,8 @@ __global__ void fmm_deflated_cols(int R, const double* __restrict__ X, int ldx, 
 // host side: plan building, upload and launch
 // ---------------------------------------------------------------------------
 static size_t tree_boxes(int N) {
-  const int s = 16;  // smallest leaf (p = 8)
-  const int nleaf = (N + s - 1) / s;
-  int nlev = 0;
-  while ((1 << nlev) < nleaf) ++nlev;
+  int nlev = 0;   // as in build_plan: leaves of at most 32 poles
+  while ((N + (1 << nlev) - 1) >> nlev > 32) ++nlev;
   return (size_t(1) << (nlev + 1)) - 1;
 }
 
@@ -674,6 +732,7 @@ int fmm_launch(int R, const double* X, int ldx, const Stage& s, const FmmPrepare
   F.nlev = P.nlev;
   F.nbox = P.nbox;
   F.R = R;
+  F.outlier = P.outlier;
   F.lo = reinterpret_cast<const double*>(plan_dev + pp.off[0]);
   F.hi = reinterpret_cast<const double*>(plan_dev + pp.off[1]);
   F.s0 = reinterpret_cast<const int*>(plan_dev + pp.off[2]);
@@ -689,8 +748,13 @@ int fmm_launch(int R, const double* X, int ldx, const Stage& s, const FmmPrepare
   F.L = F.W + nb * kP * (size_t)R;
   double* hX = work + (work_elems - hx_elems);
   const int rb = (R + kRowsPerBlock - 1) / kRowsPerBlock;
-  // row chunks per box: about 1024 blocks per launch, whole 256-row groups
-  auto chunks = [&](int boxes) { return std::max(1, std::min(rb, (1024 + boxes - 1) / boxes)); };
+  // one block per (box, 256-row group): the kernels are bound by memory
+  // latency, so they need every block they can get (building a box's
+  // operators once per block is cheap next to that)
+  auto chunks = [&](int boxes) {
+    (void)boxes;
+    return rb;
+  };
   if (K > 0) {
     hipLaunchKernelGGL(fmm_charges, dim3((K + 31) / 32, (R + 31) / 32), dim3(256), 0, st, R, X, ldx, s, F.B);
     hipLaunchKernelGGL(fmm_p2m, dim3(1 << P.nlev, chunks(1 << P.nlev)), dim3(256), 0, st, F, s.g, s.status);
@@ -700,6 +764,14 @@ int fmm_launch(int R, const double* X, int ldx, const Stage& s, const FmmPrepare
       hipLaunchKernelGGL(fmm_down, dim3(1 << l, chunks(1 << l)), dim3(256), 0, st, F, l, s.status);
     hipLaunchKernelGGL(fmm_leaf_eval, dim3(1 << P.nlev, chunks(1 << P.nlev)), dim3(256), 0, st, F, s, Xo, ldo,
                        colscale);
+    if (P.outlier >= 0) {
+      // W and L (contiguous, 2 nbox kP R >= 32 R doubles) are no longer needed:
+      // their space holds the partial sums
+      static_assert(2 * kP >= kOutChunks, "partial sums must fit in W and L of a one-box tree");
+      hipLaunchKernelGGL(fmm_outlier_partial, dim3((R + 255) / 256, kOutChunks), dim3(256), 0, st, F, s, F.W);
+      hipLaunchKernelGGL(fmm_outlier_reduce, dim3((R + 255) / 256), dim3(256), 0, st, F, s, F.W, Xo, ldo,
+                         colscale);
+    }
   }
   if (K < N) {
     hipLaunchKernelGGL(fmm_group_dots, dim3(std::max(K, 1), rb), dim3(256), 0, st, R, X, ldx, s, hX);
