@@ -255,15 +255,18 @@ constexpr int kOpLd = kP + 1;              // LDS row stride of a p x p operator
 constexpr int kOpsMax = 8;                 // p x p operators held in LDS at once (down pass)
 constexpr int kS = 32;                     // largest leaf
 constexpr int kNearMax = 6;                // near-field operators held in LDS at once (leaves)
+constexpr int kLNT = 4;                    // row tiles of 16 per wave in the leaf kernel
+constexpr int kLeafRows = 4 * 16 * kLNT;
 
-__device__ __forceinline__ void zero_acc(fd4 (&acc)[kNT]) {
+template <int NT>
+__device__ __forceinline__ void zero_acc(fd4 (&acc)[NT]) {
 #pragma unroll
-  for (int t = 0; t < kNT; ++t) acc[t] = fd4{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < NT; ++t) acc[t] = fd4{0.0, 0.0, 0.0, 0.0};
 }
 
 // Coefficients src[k][rows of the wave's tiles] for k < 4 KS, zero for k >= kvalid or r >= R.
-template <int KS>
-__device__ __forceinline__ void load_b(double (&b)[KS][kNT], int ksteps, int kvalid, const double* src, int R,
+template <int KS, int NT>
+__device__ __forceinline__ void load_b(double (&b)[KS][NT], int ksteps, int kvalid, const double* src, int R,
                                        int r0) {
   const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
 #pragma unroll
@@ -273,7 +276,7 @@ __device__ __forceinline__ void load_b(double (&b)[KS][kNT], int ksteps, int kva
       const bool kok = k < kvalid;
       const double* row = src + (size_t)(kok ? k : 0) * R;
 #pragma unroll
-      for (int t = 0; t < kNT; ++t) {
+      for (int t = 0; t < NT; ++t) {
         const int r = r0 + 16 * t + i;
         const double v = gld(row + (r < R ? r : R - 1));
         b[ks][t] = (kok && r < R) ? v : 0.0;
@@ -283,25 +286,26 @@ __device__ __forceinline__ void load_b(double (&b)[KS][kNT], int ksteps, int kva
 }
 
 // acc[t] += Op[16 rows][0 .. 4 ksteps) x b[.][t]
-template <int KS>
-__device__ __forceinline__ void mfma_b(const double* op, int ld, int ksteps, const double (&b)[KS][kNT],
-                                       fd4 (&acc)[kNT]) {
+template <int KS, int NT>
+__device__ __forceinline__ void mfma_b(const double* op, int ld, int ksteps, const double (&b)[KS][NT],
+                                       fd4 (&acc)[NT]) {
   const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
     if (ks < ksteps) {
       const double a = op[i * ld + 4 * ks + kq];
 #pragma unroll
-      for (int t = 0; t < kNT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ks][t], acc[t], 0, 0, 0);
+      for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ks][t], acc[t], 0, 0, 0);
     }
   }
 }
 
 // dst[m][r] = acc for operator rows m < mvalid (dst row stride R).
-__device__ __forceinline__ void store_rows(const fd4 (&acc)[kNT], double* dst, int mvalid, int R, int r0) {
+template <int NT>
+__device__ __forceinline__ void store_rows(const fd4 (&acc)[NT], double* dst, int mvalid, int R, int r0) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int t = 0; t < kNT; ++t) {
+  for (int t = 0; t < NT; ++t) {
     const int r = r0 + 16 * t + (lane & 15);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -311,12 +315,12 @@ __device__ __forceinline__ void store_rows(const fd4 (&acc)[kNT], double* dst, i
   }
 }
 
-// Row range of this block: chunks of whole 256-row groups.
-__device__ __forceinline__ void row_chunk(int R, int* rbeg, int* rend) {
-  const int groups = (R + kRowsPerBlock - 1) / kRowsPerBlock;
+// Row range of this block: chunks of whole groups of `rows` rows.
+__device__ __forceinline__ void row_chunk(int R, int rows, int* rbeg, int* rend) {
+  const int groups = (R + rows - 1) / rows;
   const int per = (groups + gridDim.y - 1) / gridDim.y;
-  *rbeg = blockIdx.y * per * kRowsPerBlock;
-  *rend = min(R, *rbeg + per * kRowsPerBlock);
+  *rbeg = blockIdx.y * per * rows;
+  *rend = min(R, *rbeg + per * rows);
 }
 
 // ---------------------------------------------------------------------------
@@ -341,7 +345,7 @@ __global__ __launch_bounds__(256) void fmm_p2m(FmmDev F, const double* __restric
   }
   __syncthreads();
   int rbeg, rend;
-  row_chunk(F.R, &rbeg, &rend);
+  row_chunk(F.R, kRowsPerBlock, &rbeg, &rend);
   const int ksteps = (ns + 3) / 4;
   for (int rt = rbeg; rt < rend; rt += kRowsPerBlock) {
     const int r0 = rt + (threadIdx.x >> 6) * 16 * kNT;
@@ -382,7 +386,7 @@ __global__ __launch_bounds__(256) void fmm_m2m(FmmDev F, int level, const int* s
   }
   __syncthreads();
   int rbeg, rend;
-  row_chunk(F.R, &rbeg, &rend);
+  row_chunk(F.R, kRowsPerBlock, &rbeg, &rend);
   const int ksteps = (F.p + 3) / 4;
   for (int rt = rbeg; rt < rend; rt += kRowsPerBlock) {
     const int r0 = rt + (threadIdx.x >> 6) * 16 * kNT;
@@ -448,7 +452,7 @@ __global__ __launch_bounds__(256) void fmm_down(FmmDev F, int level, const int* 
   if (ngroups == 1) build_group(0);
   __syncthreads();
   int rbeg, rend;
-  row_chunk(F.R, &rbeg, &rend);
+  row_chunk(F.R, kRowsPerBlock, &rbeg, &rend);
   const int ksteps = (F.p + 3) / 4;
   for (int rt0 = rbeg; rt0 < rend; rt0 += kRowsPerBlock) {
     const int r0 = rt0 + (threadIdx.x >> 6) * 16 * kNT;
@@ -481,7 +485,7 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
   constexpr int ldu = kOpLd, ldi = kS + 1;
   __shared__ double ul[kS * ldu];               // L2P weights [target][kk]
   __shared__ double inv[kNearMax][kS * ldi];    // 1/delta [near box][target][source]
-  __shared__ double out[64 * (kS + 1)];         // one wave's 64 rows, staged for row-wise stores
+  __shared__ double out[64 * (kS + 1)];         // 64 rows of results, staged for row-wise stores
   __shared__ int nb0[kNearMax], nns[kNearMax];
   __shared__ int pos[kS];
   __shared__ double scl[kS], tgo[kS], tgt[kS], srcg[kNearMax][kS];
@@ -538,14 +542,14 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
   const bool two = nt > 16;
   const double* Lsrc = F.L + (size_t)id * kP * F.R;
   int rbeg, rend;
-  row_chunk(F.R, &rbeg, &rend);
-  for (int rt0 = rbeg; rt0 < rend; rt0 += kRowsPerBlock) {
-    const int r0 = rt0 + wave * 16 * kNT;
-    fd4 acc0[kNT], acc1[kNT];
+  row_chunk(F.R, kLeafRows, &rbeg, &rend);
+  for (int rt0 = rbeg; rt0 < rend; rt0 += kLeafRows) {
+    const int r0 = rt0 + wave * 16 * kLNT;
+    fd4 acc0[kLNT], acc1[kLNT];
     zero_acc(acc0);
     zero_acc(acc1);
     {
-      double b[kP / 4][kNT];
+      double b[kP / 4][kLNT];
       load_b(b, ksl, F.p, Lsrc, F.R, r0);
       mfma_b(ul, ldu, ksl, b, acc0);
       if (two) mfma_b(ul + 16 * ldu, ldu, ksl, b, acc1);
@@ -559,29 +563,31 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
       const int cnt = min(kNearMax, nnear - gi * kNearMax);
       for (int qi = 0; qi < cnt; ++qi) {
         const int ns = nns[qi], ksn = (ns + 3) / 4;
-        double b[kS / 4][kNT];
+        double b[kS / 4][kLNT];
         load_b(b, ksn, ns, F.B + (size_t)nb0[qi] * F.R, F.R, r0);
         mfma_b(inv[qi], ldi, ksn, b, acc0);
         if (two) mfma_b(inv[qi] + 16 * ldi, ldi, ksn, b, acc1);
       }
     }
-    // stores: one wave's 64 rows at a time through LDS, then each row's nt
-    // outputs by consecutive lanes
-    for (int w = 0; w < 4; ++w) {
+    // stores: 64 rows (the rows of kWavesPerStage waves) at a time through
+    // LDS, then each row's nt outputs by consecutive lanes
+    constexpr int kWavesPerStage = 64 / (16 * kLNT);
+    for (int h = 0; h < 4 / kWavesPerStage; ++h) {
       __syncthreads();
-      if (wave == w) {
+      if (wave / kWavesPerStage == h) {
+        const int rbase = (wave % kWavesPerStage) * 16 * kLNT;
 #pragma unroll
-        for (int t = 0; t < kNT; ++t)
+        for (int t = 0; t < kLNT; ++t)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int tg = (lane >> 4) + 4 * v;
-            double* o = out + (16 * t + (lane & 15)) * (kS + 1);
+            double* o = out + (rbase + 16 * t + (lane & 15)) * (kS + 1);
             if (tg < nt) o[tg] = scl[tg] * acc0[t][v];
             if (tg + 16 < nt) o[tg + 16] = scl[tg + 16] * acc1[t][v];
           }
       }
       __syncthreads();
-      const int rw = rt0 + w * 16 * kNT;
+      const int rw = rt0 + h * 64;
       for (int e = threadIdx.x; e < 64 * nt; e += blockDim.x) {
         const int rr = e / nt, t = e - rr * nt;
         const int row = rw + rr;
@@ -762,8 +768,8 @@ int fmm_launch(int R, const double* X, int ldx, const Stage& s, const FmmPrepare
       hipLaunchKernelGGL(fmm_m2m, dim3(1 << l, chunks(1 << l)), dim3(256), 0, st, F, l, s.status);
     for (int l = 0; l <= P.nlev; ++l)
       hipLaunchKernelGGL(fmm_down, dim3(1 << l, chunks(1 << l)), dim3(256), 0, st, F, l, s.status);
-    hipLaunchKernelGGL(fmm_leaf_eval, dim3(1 << P.nlev, chunks(1 << P.nlev)), dim3(256), 0, st, F, s, Xo, ldo,
-                       colscale);
+    hipLaunchKernelGGL(fmm_leaf_eval, dim3(1 << P.nlev, (R + kLeafRows - 1) / kLeafRows), dim3(256), 0, st, F, s,
+                       Xo, ldo, colscale);
     if (P.outlier >= 0) {
       // W and L (contiguous, 2 nbox kP R >= 32 R doubles) are no longer needed:
       // their space holds the partial sums
