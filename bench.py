@@ -348,6 +348,8 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=5, help="timed launches of the batched workload")
     ap.add_argument("--batched-only", action="store_true",
                     help="measure only the batched form (for profiling it)")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="force the product tile shape of the timed steps (SVDU_TILE_*; -1: tuning table)")
     ap.add_argument("--tile-table", default="",
                     help="with --batched-only: FP64 tile shapes per size bucket (comma list) instead of tuning")
     ap.add_argument("--profile-copy", type=int, default=0,
@@ -404,6 +406,8 @@ def main():
     so = torch.empty(m, dtype=torch.float64, device=dev)
     Vo = torch.empty((n, n), dtype=torch.float64, device=dev)
     path = svdu.SVDU_PATH_FMM if args.path == "fmm" else svdu.SVDU_PATH_DIRECT
+    if args.tile >= 0:
+        svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, args.tile)
     ws = svdu.new_workspace(svdu.svdu_workspace_bytes(m, n, path), dev)
     stream = torch.cuda.current_stream()
 

@@ -37,6 +37,8 @@ SVDU_TILE_128x128 = 0
 SVDU_TILE_64x128 = 1
 SVDU_TILE_128x64 = 2
 SVDU_TILE_64x64 = 3
+SVDU_TILE_128x128_K32 = 4
+SVDU_TILE_SHAPES = 5
 SVDU_TILE_BUCKETS = 8
 SVDU_BATCH_PERSISTENT = 1
 TIMING_PHASES = 5
@@ -493,13 +495,14 @@ def autotune(precision=SVDU_PREC_FP64, max_n=4096, stream=None):
     need = svdu_autotune_workspace_bytes(max_n)
     ws = new_workspace(need, torch.device("cuda"))
     wp, wb = _aligned(ws)
-    times = (ctypes.c_double * (SVDU_TILE_BUCKETS * 4))()
+    times = (ctypes.c_double * (SVDU_TILE_BUCKETS * SVDU_TILE_SHAPES))()
     table = (ctypes.c_int * SVDU_TILE_BUCKETS)()
     rc = svdu_autotune(precision, max_n, ctypes.cast(times, ctypes.c_void_p), ctypes.cast(table, ctypes.c_void_p),
                        wp, wb, _stream_handle(stream))
     if rc != SVDU_OK:
         raise SvduError(rc, "svdu_autotune")
-    return list(table), [[times[b * 4 + s] for s in range(4)] for b in range(SVDU_TILE_BUCKETS)]
+    return list(table), [[times[b * SVDU_TILE_SHAPES + s] for s in range(SVDU_TILE_SHAPES)]
+                         for b in range(SVDU_TILE_BUCKETS)]
 
 
 def tile_table(precision=SVDU_PREC_FP64, table=None):

@@ -91,7 +91,8 @@ __device__ __forceinline__ double gen_entry(const CauchyDesc& d, int j, int N, c
 
 // Tile shapes of the product kernels: 4 waves stacked along M, each wave
 // 16 MB rows (MB = 1 or 2 MFMA blocks of 16) by 64 NC columns (NC = 1 or 2).
-enum TileShape : int { kT128x128 = 0, kT64x128 = 1, kT128x64 = 2, kT64x64 = 3, kNumShapes = 4 };
+// kT128x128k32: 128 x 128 with LDS tiles of 32 k rows, one barrier per 32 k.
+enum TileShape : int { kT128x128 = 0, kT64x128 = 1, kT128x64 = 2, kT64x64 = 3, kT128x128k32 = 4, kNumShapes = 5 };
 __host__ __device__ constexpr int shape_bm(int s) { return (s == kT64x128 || s == kT64x64) ? 64 : 128; }
 __host__ __device__ constexpr int shape_bn(int s) { return (s == kT128x64 || s == kT64x64) ? 64 : 128; }
 

@@ -31,7 +31,7 @@
 
 namespace svdu {
 
-template <int MB, int NC, bool LIVE>
+template <int MB, int NC, int KH, bool LIVE>
 __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, const ColDesc (&cc)[NC],
                                               double* Bs0, double* Bs1) {
   constexpr int BN = 64 * NC, NB = 4 * NC;
@@ -94,8 +94,15 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
 #pragma unroll
       for (int c = 0; c < NC; ++c) Bn[(4 * wave + r) * BN + 64 * c + lane] = bg[r][c];
   };
-  // one K step: MFMAs on (a, Bcur) interleaved with generating step kn
-  auto step = [&](const double (&a)[MB][4], const double* Bcur, double* Bnext, int kn) {
+  // Half-step hs covers k in [16 hs, 16 hs + 16). The LDS buffers hold KH
+  // half-steps each; half-step hs is row block hs % KH of buffer (hs / KH) % 2.
+  auto bufof = [&](int hs) { return (((hs / KH) & 1) ? Bs1 : Bs0) + (hs % KH) * kBK * BN; };
+  // one half-step: MFMAs on (a, C~ of hs) interleaved with generating
+  // half-step hs + KH; one barrier per KH half-steps
+  auto step = [&](const double (&a)[MB][4], int hs) {
+    const double* Bcur = bufof(hs);
+    double* Bnext = bufof(hs + KH);
+    const int kn = (hs + KH) * kBK;
     double mind = 1.0;
     const int jb = kn + 4 * wave;
 #pragma unroll
@@ -113,31 +120,32 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
     }
     if (LIVE && __any(mind < 0x1p-1000)) fix_tiny(jb);
     store_b(Bnext);
-    __syncthreads();
+    if (hs % KH == KH - 1) __syncthreads();
   };
 
   const int nk = (N + kBK - 1) / kBK;
-  // prologue: C~ step 0 into Bs0, X step 0 into aA
-  {
+  // prologue: C~ of half-steps 0 .. KH-1 into buffer 0, X of half-step 0 into aA
+#pragma unroll
+  for (int h = 0; h < KH; ++h) {
     double mind = 1.0;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) bg[r][c] = gen_entry<LIVE>(d, 4 * wave + r, N, cc[c], &mind);
-    if (LIVE && __any(mind < 0x1p-1000)) fix_tiny(4 * wave);
-    store_b(Bs0);
+      for (int c = 0; c < NC; ++c) bg[r][c] = gen_entry<LIVE>(d, h * kBK + 4 * wave + r, N, cc[c], &mind);
+    if (LIVE && __any(mind < 0x1p-1000)) fix_tiny(h * kBK + 4 * wave);
+    store_b(bufof(h));
   }
   loadA(0, aA);
   __syncthreads();
   int kc = 0;
   for (; kc + 2 <= nk; kc += 2) {
     loadA((kc + 1) * kBK, aB);
-    step(aA, Bs0, Bs1, (kc + 1) * kBK);
+    step(aA, kc);
     const int k2 = (kc + 2 < nk) ? (kc + 2) * kBK : (kc + 1) * kBK;
     loadA(k2, aA);
-    step(aB, Bs1, Bs0, k2);
+    step(aB, kc + 1);
   }
-  if (kc < nk) step(aA, Bs0, Bs1, kc * kBK);
+  if (kc < nk) step(aA, kc);
 
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
@@ -156,7 +164,7 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
 }
 
 // One tile (work item) of a GemmList.
-template <int MB, int NC>
+template <int MB, int NC, int KH>
 __device__ __forceinline__ void gemm_f64_tile(const GemmList& L, int item, double* Bs0, double* Bs1) {
   constexpr int BM = 64 * MB, BN = 64 * NC;
   const int j = find_job(L.boff, L.n, item);
@@ -173,29 +181,30 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmList& L, int item, doubl
     live = live && cc[c].type == 0;
   }
   if (__syncthreads_and(live))
-    gemm_f64_body<MB, NC, true>(J, m0, n0, cc, Bs0, Bs1);
+    gemm_f64_body<MB, NC, KH, true>(J, m0, n0, cc, Bs0, Bs1);
   else
-    gemm_f64_body<MB, NC, false>(J, m0, n0, cc, Bs0, Bs1);
+    gemm_f64_body<MB, NC, KH, false>(J, m0, n0, cc, Bs0, Bs1);
 }
 
-// Grid schedule: one block per tile, in list order.
-template <int MB, int NC>
+// Grid schedule: one block per tile, in list order. KH half-steps of 16 k
+// share one barrier (LDS buffers of 16 KH rows).
+template <int MB, int NC, int KH>
 __global__ __launch_bounds__(256, 2) void gemm_cauchy_f64_kernel(GemmList L) {
-  __shared__ double Bs[2][kBK * 64 * NC];
-  gemm_f64_tile<MB, NC>(L, blockIdx.x, Bs[0], Bs[1]);
+  __shared__ double Bs[2][KH * kBK * 64 * NC];
+  gemm_f64_tile<MB, NC, KH>(L, blockIdx.x, Bs[0], Bs[1]);
 }
 
 // Persistent schedule: as many blocks as fit on the device at once; each
 // takes tiles in list order from a counter until the list is exhausted.
-template <int MB, int NC>
+template <int MB, int NC, int KH>
 __global__ __launch_bounds__(256, 2) void gemm_cauchy_f64_persistent(GemmList L) {
-  __shared__ double Bs[2][kBK * 64 * NC];
+  __shared__ double Bs[2][KH * kBK * 64 * NC];
   __shared__ int next;
   if (threadIdx.x == 0) next = atomicAdd(L.counter, 1);
   __syncthreads();
   int item = next;
   while (item < L.blocks) {
-    gemm_f64_tile<MB, NC>(L, item, Bs[0], Bs[1]);
+    gemm_f64_tile<MB, NC, KH>(L, item, Bs[0], Bs[1]);
     __syncthreads();   // every thread has read `next` and finished with Bs
     if (threadIdx.x == 0) next = atomicAdd(L.counter, 1);
     __syncthreads();
@@ -204,13 +213,13 @@ __global__ __launch_bounds__(256, 2) void gemm_cauchy_f64_persistent(GemmList L)
 }
 
 namespace {
-template <int MB, int NC>
+template <int MB, int NC, int KH>
 void launch_shape(const GemmList& L, bool persistent, int grid_cap, hipStream_t st) {
   if (persistent) {
     const int g = L.blocks < grid_cap ? L.blocks : grid_cap;
-    hipLaunchKernelGGL((gemm_cauchy_f64_persistent<MB, NC>), dim3(g), dim3(256), 0, st, L);
+    hipLaunchKernelGGL((gemm_cauchy_f64_persistent<MB, NC, KH>), dim3(g), dim3(256), 0, st, L);
   } else {
-    hipLaunchKernelGGL((gemm_cauchy_f64_kernel<MB, NC>), dim3(L.blocks), dim3(256), 0, st, L);
+    hipLaunchKernelGGL((gemm_cauchy_f64_kernel<MB, NC, KH>), dim3(L.blocks), dim3(256), 0, st, L);
   }
 }
 }  // namespace
@@ -218,20 +227,23 @@ void launch_shape(const GemmList& L, bool persistent, int grid_cap, hipStream_t 
 void launch_gemm_f64(const GemmList& L, int shape, bool persistent, int grid_cap, hipStream_t st) {
   if (L.n <= 0 || L.blocks <= 0) return;
   switch (shape) {
-    case kT64x128: launch_shape<1, 2>(L, persistent, grid_cap, st); break;
-    case kT128x64: launch_shape<2, 1>(L, persistent, grid_cap, st); break;
-    case kT64x64: launch_shape<1, 1>(L, persistent, grid_cap, st); break;
-    default: launch_shape<2, 2>(L, persistent, grid_cap, st); break;
+    case kT64x128: launch_shape<1, 2, 1>(L, persistent, grid_cap, st); break;
+    case kT128x64: launch_shape<2, 1, 1>(L, persistent, grid_cap, st); break;
+    case kT64x64: launch_shape<1, 1, 1>(L, persistent, grid_cap, st); break;
+    case kT128x128k32: launch_shape<2, 2, 2>(L, persistent, grid_cap, st); break;
+    default: launch_shape<2, 2, 1>(L, persistent, grid_cap, st); break;
   }
 }
 
 namespace {
-template <int MB, int NC>
+template <int MB, int NC, int KH>
 int resident_blocks_gemm_f64_grid_cap() {
   int dev = 0, cus = 0, nb = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_cauchy_f64_persistent<MB, NC>, 256, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_cauchy_f64_persistent<MB, NC, KH>, 256, 0) !=
+      hipSuccess)
+    return 0;
   return nb * cus;
 }
 }  // namespace
@@ -240,10 +252,11 @@ int resident_blocks_gemm_f64_grid_cap() {
 // at once (0 if the runtime cannot tell).
 int gemm_f64_grid_cap(int shape) {
   switch (shape) {
-    case kT64x128: return resident_blocks_gemm_f64_grid_cap<1, 2>();
-    case kT128x64: return resident_blocks_gemm_f64_grid_cap<2, 1>();
-    case kT64x64: return resident_blocks_gemm_f64_grid_cap<1, 1>();
-    default: return resident_blocks_gemm_f64_grid_cap<2, 2>();
+    case kT64x128: return resident_blocks_gemm_f64_grid_cap<1, 2, 1>();
+    case kT128x64: return resident_blocks_gemm_f64_grid_cap<2, 1, 1>();
+    case kT64x64: return resident_blocks_gemm_f64_grid_cap<1, 1, 1>();
+    case kT128x128k32: return resident_blocks_gemm_f64_grid_cap<2, 2, 2>();
+    default: return resident_blocks_gemm_f64_grid_cap<2, 2, 1>();
   }
 }
 

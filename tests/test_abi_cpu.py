@@ -99,15 +99,15 @@ def test_options(lib):
     old = svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, svdu.SVDU_TILE_64x64)
     assert old == -1
     assert svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, -1) == svdu.SVDU_TILE_64x64
-    assert svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, 4) == svdu.SVDU_EINVAL
+    assert svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, svdu.SVDU_TILE_SHAPES) == svdu.SVDU_EINVAL
     assert svdu.svdu_set_option(svdu.SVDU_OPT_PERSISTENT, 1) == 0
     assert svdu.svdu_set_option(svdu.SVDU_OPT_PERSISTENT, 0) == 1
 
 
 def test_tile_table_roundtrip(lib):
     t = svdu.tile_table(svdu.SVDU_PREC_FP64)
-    assert len(t) == svdu.SVDU_TILE_BUCKETS and all(0 <= x < 4 for x in t)
-    new = [(x + 1) % 4 for x in t]
+    assert len(t) == svdu.SVDU_TILE_BUCKETS and all(0 <= x < svdu.SVDU_TILE_SHAPES for x in t)
+    new = [(x + 1) % svdu.SVDU_TILE_SHAPES for x in t]
     assert svdu.tile_table(svdu.SVDU_PREC_FP64, new) == new
     assert svdu.tile_table(svdu.SVDU_PREC_FP64) == new
     svdu.tile_table(svdu.SVDU_PREC_FP64, t)

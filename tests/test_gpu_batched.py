@@ -131,7 +131,7 @@ def test_batched_per_problem_status(lib):
     b.close()
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
 def test_tile_shapes_give_identical_results(lib, shape):
     P = S.make_problem(300, 457, "uniform", seed=7)
     args = (dev(P.U), dev(P.sigma), dev(P.V), dev(P.a), dev(P.b))
@@ -223,7 +223,7 @@ def test_autotune_table_and_results_unchanged(lib):
     saved = lib.tile_table(0)
     try:
         table, times = lib.autotune(0, max_n=512)
-        assert len(table) == lib.SVDU_TILE_BUCKETS and all(0 <= s < 4 for s in table)
+        assert len(table) == lib.SVDU_TILE_BUCKETS and all(0 <= s < lib.SVDU_TILE_SHAPES for s in table)
         for bk in range(4):   # buckets up to 512 were timed
             assert all(t > 0 for t in times[bk])
             assert times[bk][table[bk]] == min(times[bk])
