@@ -474,7 +474,7 @@ def main():
         "recon_last": recon,
         "roofline": {
             "bound": "mfma",
-            "kernel": "gemm_cauchy_f64_kernel<2, 2> (128x128 tiles)",
+            "kernel": "gemm_cauchy_f64_kernel<2, 2, 2> (128x128 tiles, 32-k LDS stages)",
             "achieved": achieved,
             "peak": FP64_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",

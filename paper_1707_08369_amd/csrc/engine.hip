@@ -616,13 +616,12 @@ void enqueue_status_gather(const Plan& P, int* out, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 // tile shapes: a table per precision and size bucket, filled by the autotuner
-// (svdu_autotune); the defaults favour the largest tile that still gives the
-// device a few tiles per compute unit.
+// (svdu_autotune); the defaults are what it measured on MI355X.
 // ---------------------------------------------------------------------------
 namespace {
 int g_shape_table[2][kShapeBuckets] = {
-    {kT64x64, kT64x64, kT64x128, kT64x128, kT128x128, kT128x128, kT128x128, kT128x128},
-    {kT64x64, kT64x64, kT64x128, kT64x128, kT128x128, kT128x128, kT128x128, kT128x128}};
+    {kT64x64, kT128x128, kT128x128, kT128x128, kT128x128, kT128x128k32, kT128x128k32, kT128x128k32},
+    {kT64x64, kT64x64, kT64x64, kT64x64, kT64x64, kT64x64, kT128x128, kT128x128}};
 int g_forced_shape = -1;
 }  // namespace
 
