@@ -474,7 +474,7 @@ def main():
         "recon_last": recon,
         "roofline": {
             "bound": "mfma",
-            "kernel": "gemm_cauchy_f64_kernel<2, 2, 2> (128x128 tiles, 32-k LDS stages)",
+            "kernel": "gemm_cauchy_f64_kernel<2, 2, 2, 8> (256x128 tiles on 8 waves, 32-k LDS stages)",
             "achieved": achieved,
             "peak": FP64_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",

@@ -56,8 +56,9 @@ extern "C" {
 #define SVDU_OPT_SECULAR_MAXIT 1 /* iteration cap of the secular solver (default 200) */
 #define SVDU_OPT_TIMING 2        /* 1: record phase timings of svdu_rank1_update (resets the record) */
 #define SVDU_OPT_TILE_SHAPE 3    /* -1 (default): tile shape of the products from the tuning table;
-                                    0..4 force SVDU_TILE_* (results are bitwise the same for every shape;
-                                    the precision form runs SVDU_TILE_128x128_K32 as 128 x 128) */
+                                    0..5 force SVDU_TILE_* (results are bitwise the same for every shape;
+                                    the precision form runs SVDU_TILE_128x128_K32 and
+                                    SVDU_TILE_256x128_K32 as 128 x 128) */
 #define SVDU_OPT_PERSISTENT 4    /* 1: products of svdu_rank1_update and svdu_rank1_update_batched use the
                                     persistent schedule (see SVDU_BATCH_PERSISTENT); default 0 */
 #define SVDU_OPT_REFINE 5        /* 1 (default): FP64 results get the close-cluster refinement (not in the
@@ -73,7 +74,8 @@ extern "C" {
 #define SVDU_TILE_128x64 2
 #define SVDU_TILE_64x64 3
 #define SVDU_TILE_128x128_K32 4  /* 128 x 128, C~ staged 32 k rows at a time (one barrier per 32 k) */
-#define SVDU_TILE_SHAPES 5
+#define SVDU_TILE_256x128_K32 5  /* 256 x 128 on 8 waves, 32-k stages: each generated C~ entry serves 256 rows */
+#define SVDU_TILE_SHAPES 6
 #define SVDU_TILE_BUCKETS 8      /* tuning-table buckets by order N: (0,64], (64,128], ..., (4096, inf) */
 
 /* Bytes of device workspace svdu_rank1_update needs for (m, n, path, precision). */

@@ -317,7 +317,7 @@ StageLevel build_level(const std::vector<Stage>& st_in, const std::vector<TmvJob
 }
 
 GemmJob make_gemm_job(int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo, int precision) {
-  const int sh = choose_shape(R, d.N, precision);
+  const int sh = run_shape(choose_shape(R, d.N, precision), precision == SVDU_PREC_SPLIT32);
   GemmJob J{};
   J.R = R;
   J.ldx = ldx;
@@ -620,7 +620,7 @@ void enqueue_status_gather(const Plan& P, int* out, hipStream_t st) {
 // ---------------------------------------------------------------------------
 namespace {
 int g_shape_table[2][kShapeBuckets] = {
-    {kT64x64, kT128x128, kT128x128, kT128x128, kT128x128, kT128x128k32, kT128x128k32, kT128x128k32},
+    {kT64x64, kT128x128, kT128x128, kT128x128, kT128x128, kT256x128k32, kT256x128k32, kT256x128k32},
     {kT64x64, kT64x64, kT64x64, kT64x64, kT64x64, kT64x64, kT128x128, kT128x128}};
 int g_forced_shape = -1;
 }  // namespace

@@ -2,20 +2,24 @@
 // equation UCTildeProduct): the dense product of the direct path, with the
 // C~ tiles regenerated from O(N) descriptors and never stored in HBM.
 //
-// One launch serves a list of products (GemmList). Four waves are stacked
-// along M: wave w owns 16 MB rows of the block tile and all of its 64 NC
-// columns, so no wave loads the X rows of another. K advances 16 per step.
+// One launch serves a list of products (GemmList). W waves (4 or 8) are
+// stacked along M: wave w owns 16 MB rows of the block tile and all of its
+// 64 NC columns, so no wave loads the X rows of another. K advances 16 per
+// half-step.
 // X fragments come straight from HBM into registers one step ahead, in a
 // K-permuted layout: in MFMA step s, lane l supplies X[row][k0 + 4 (l/16) + s]
 // (four consecutive doubles of one row per lane) and the matching entry
 // C~[k0 + 4 (l/16) + s][col]; the contraction covers all 16 k either way.
 // Two register sets are used alternately (the K loop is unrolled by two). C~
-// tiles are double-buffered in LDS, one barrier per step. Wave w generates C~
-// rows 4 w .. 4 w + 3 of the next step; the generation of row s sits right
-// after the MFMAs of step s so that the VALU work overlaps the matrix core.
+// tiles are double-buffered in LDS in stages of KH half-steps, one barrier
+// per stage. Each wave generates 16 / W rows of every half-step KH ahead,
+// interleaved with its MFMAs. The generation is VALU work that the matrix
+// core does not hide, so its share of the time falls with the rows of X each
+// generated entry serves: 8 waves (256 rows) halve it against 4 waves.
 // A block whose columns are all secular roots (the usual case) runs the
 // Cauchy formula without any branch; other blocks use the general entry,
-// which gives the same values.
+// which gives the same values. Out-of-range rows of X load row 0 instead of
+// zeros: their accumulators are never stored.
 //
 // Every output element is accumulated by the same sequence of MFMAs (the
 // K order and permutation do not depend on the tile shape or on the other
@@ -31,10 +35,36 @@
 
 namespace svdu {
 
-template <int MB, int NC, int KH, bool LIVE>
+// Live entry of the product kernels: the refined reciprocal of live_entry,
+// without its select for z = 0. A row with z = 0 either gives a signed zero
+// (0 times a finite reciprocal) or has |delta| below the tiny-delta bound,
+// which sends the whole row group through general_entry.
+__device__ __forceinline__ double prod_live_entry(double z, double g, const ColDesc& c, double* mind) {
+  const double del = (g - c.o) - c.t;
+  *mind = __builtin_fmin(*mind, __builtin_fabs(del));
+  double r = __builtin_amdgcn_rcp(del);
+  double e = __builtin_fma(-del, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-del, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  return (z * c.s) * r;
+}
+
+template <bool LIVE>
+__device__ __forceinline__ double prod_entry(const CauchyDesc& d, int j, int N, const ColDesc& c, double* mind) {
+  if (!LIVE) return gen_entry<false>(d, j, N, c, mind);
+  const int jj = j < N ? j : N - 1;
+  const double zl = gld(d.rzeta + jj);
+  const double z = (j < N) ? zl : 0.0;
+  return prod_live_entry(z, gld(d.rg + jj), c, mind);
+}
+
+template <int MB, int NC, int KH, int W, bool LIVE>
 __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, const ColDesc (&cc)[NC],
                                               double* Bs0, double* Bs1) {
-  constexpr int BN = 64 * NC, NB = 4 * NC;
+  // RPW: C~ rows each wave generates per half-step; SPR: MFMA groups per row
+  constexpr int BN = 64 * NC, NB = 4 * NC, RPW = 16 / W, SPR = 4 / RPW;
+  static_assert(W == 4 || W == 8, "4 or 8 waves");
   const CauchyDesc& d = J.d;
   const int N = d.N, R = J.R;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -45,7 +75,7 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
   for (int mb = 0; mb < MB; ++mb) {
     const int r = m0 + wave * 16 * MB + mb * 16 + (lane & 15);
     rok[mb] = r < R;
-    xr[mb] = J.X + (size_t)(rok[mb] ? r : 0) * J.ldx;
+    xr[mb] = J.X + (size_t)(rok[mb] ? r : 0) * J.ldx;   // rows past R read row 0; never stored
   }
   d4 acc[MB][NB];
 #pragma unroll
@@ -53,7 +83,7 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  double aA[MB][4], aB[MB][4], bg[4][NC];
+  double aA[MB][4], aB[MB][4], bg[RPW][NC];
   auto loadA = [&](int k0, double (&a)[MB][4]) {
     const int kb = k0 + kq;
     if (J.vec_a && k0 + kBK <= N) {   // block-uniform: the whole step is in range
@@ -61,10 +91,10 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
       for (int mb = 0; mb < MB; ++mb) {
         const double2 v0 = gld2(xr[mb] + kb);
         const double2 v1 = gld2(xr[mb] + kb + 2);
-        a[mb][0] = rok[mb] ? v0.x : 0.0;
-        a[mb][1] = rok[mb] ? v0.y : 0.0;
-        a[mb][2] = rok[mb] ? v1.x : 0.0;
-        a[mb][3] = rok[mb] ? v1.y : 0.0;
+        a[mb][0] = v0.x;
+        a[mb][1] = v0.y;
+        a[mb][2] = v1.x;
+        a[mb][3] = v1.y;
       }
     } else {
 #pragma unroll
@@ -77,10 +107,10 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
         }
     }
   };
-  // entries of C~ rows jb .. jb + 3 for this lane's NC columns
+  // entries of C~ rows jb .. jb + RPW - 1 for this lane's NC columns
   auto fix_tiny = [&](int jb) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < RPW; ++r) {
       const int j = jb + r;
       const int jj = j < N ? j : N - 1;
       RowVals rv{(j < N) ? gld(d.rzeta + jj) : 0.0, gld(d.rg + jj), 0.0, -2};
@@ -90,9 +120,9 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
   };
   auto store_b = [&](double* Bn) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < RPW; ++r)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) Bn[(4 * wave + r) * BN + 64 * c + lane] = bg[r][c];
+      for (int c = 0; c < NC; ++c) Bn[(RPW * wave + r) * BN + 64 * c + lane] = bg[r][c];
   };
   // Half-step hs covers k in [16 hs, 16 hs + 16). The LDS buffers hold KH
   // half-steps each; half-step hs is row block hs % KH of buffer (hs / KH) % 2.
@@ -104,7 +134,7 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
     double* Bnext = bufof(hs + KH);
     const int kn = (hs + KH) * kBK;
     double mind = 1.0;
-    const int jb = kn + 4 * wave;
+    const int jb = kn + RPW * wave;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       double bf[NB];
@@ -115,8 +145,10 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
           acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb][s], bf[nb], acc[mb][nb], 0, 0, 0);
+      if (s % SPR == SPR - 1) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) bg[s][c] = gen_entry<LIVE>(d, jb + s, N, cc[c], &mind);
+        for (int c = 0; c < NC; ++c) bg[s / SPR][c] = prod_entry<LIVE>(d, jb + s / SPR, N, cc[c], &mind);
+      }
     }
     if (LIVE && __any(mind < 0x1p-1000)) fix_tiny(jb);
     store_b(Bnext);
@@ -129,10 +161,10 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
   for (int h = 0; h < KH; ++h) {
     double mind = 1.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < RPW; ++r)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) bg[r][c] = gen_entry<LIVE>(d, h * kBK + 4 * wave + r, N, cc[c], &mind);
-    if (LIVE && __any(mind < 0x1p-1000)) fix_tiny(h * kBK + 4 * wave);
+      for (int c = 0; c < NC; ++c) bg[r][c] = prod_entry<LIVE>(d, h * kBK + RPW * wave + r, N, cc[c], &mind);
+    if (LIVE && __any(mind < 0x1p-1000)) fix_tiny(h * kBK + RPW * wave);
     store_b(bufof(h));
   }
   loadA(0, aA);
@@ -164,9 +196,9 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
 }
 
 // One tile (work item) of a GemmList.
-template <int MB, int NC, int KH>
+template <int MB, int NC, int KH, int W>
 __device__ __forceinline__ void gemm_f64_tile(const GemmList& L, int item, double* Bs0, double* Bs1) {
-  constexpr int BM = 64 * MB, BN = 64 * NC;
+  constexpr int BM = 16 * MB * W, BN = 64 * NC;
   const int j = find_job(L.boff, L.n, item);
   const GemmJob J = L.job[j];
   if (*J.d.status & kStFatal) return;
@@ -181,30 +213,31 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmList& L, int item, doubl
     live = live && cc[c].type == 0;
   }
   if (__syncthreads_and(live))
-    gemm_f64_body<MB, NC, KH, true>(J, m0, n0, cc, Bs0, Bs1);
+    gemm_f64_body<MB, NC, KH, W, true>(J, m0, n0, cc, Bs0, Bs1);
   else
-    gemm_f64_body<MB, NC, KH, false>(J, m0, n0, cc, Bs0, Bs1);
+    gemm_f64_body<MB, NC, KH, W, false>(J, m0, n0, cc, Bs0, Bs1);
 }
 
 // Grid schedule: one block per tile, in list order. KH half-steps of 16 k
-// share one barrier (LDS buffers of 16 KH rows).
-template <int MB, int NC, int KH>
-__global__ __launch_bounds__(256, 2) void gemm_cauchy_f64_kernel(GemmList L) {
+// share one barrier (LDS buffers of 16 KH rows). Two blocks of 4 waves or one
+// of 8 waves per CU: 2 waves per SIMD, 256 VGPRs each.
+template <int MB, int NC, int KH, int W>
+__global__ __launch_bounds__(64 * W, 8 / W) void gemm_cauchy_f64_kernel(GemmList L) {
   __shared__ double Bs[2][KH * kBK * 64 * NC];
-  gemm_f64_tile<MB, NC, KH>(L, blockIdx.x, Bs[0], Bs[1]);
+  gemm_f64_tile<MB, NC, KH, W>(L, blockIdx.x, Bs[0], Bs[1]);
 }
 
 // Persistent schedule: as many blocks as fit on the device at once; each
 // takes tiles in list order from a counter until the list is exhausted.
-template <int MB, int NC, int KH>
-__global__ __launch_bounds__(256, 2) void gemm_cauchy_f64_persistent(GemmList L) {
+template <int MB, int NC, int KH, int W>
+__global__ __launch_bounds__(64 * W, 8 / W) void gemm_cauchy_f64_persistent(GemmList L) {
   __shared__ double Bs[2][KH * kBK * 64 * NC];
   __shared__ int next;
   if (threadIdx.x == 0) next = atomicAdd(L.counter, 1);
   __syncthreads();
   int item = next;
   while (item < L.blocks) {
-    gemm_f64_tile<MB, NC, KH>(L, item, Bs[0], Bs[1]);
+    gemm_f64_tile<MB, NC, KH, W>(L, item, Bs[0], Bs[1]);
     __syncthreads();   // every thread has read `next` and finished with Bs
     if (threadIdx.x == 0) next = atomicAdd(L.counter, 1);
     __syncthreads();
@@ -213,13 +246,13 @@ __global__ __launch_bounds__(256, 2) void gemm_cauchy_f64_persistent(GemmList L)
 }
 
 namespace {
-template <int MB, int NC, int KH>
+template <int MB, int NC, int KH, int W>
 void launch_shape(const GemmList& L, bool persistent, int grid_cap, hipStream_t st) {
   if (persistent) {
     const int g = L.blocks < grid_cap ? L.blocks : grid_cap;
-    hipLaunchKernelGGL((gemm_cauchy_f64_persistent<MB, NC, KH>), dim3(g), dim3(256), 0, st, L);
+    hipLaunchKernelGGL((gemm_cauchy_f64_persistent<MB, NC, KH, W>), dim3(g), dim3(64 * W), 0, st, L);
   } else {
-    hipLaunchKernelGGL((gemm_cauchy_f64_kernel<MB, NC, KH>), dim3(L.blocks), dim3(256), 0, st, L);
+    hipLaunchKernelGGL((gemm_cauchy_f64_kernel<MB, NC, KH, W>), dim3(L.blocks), dim3(64 * W), 0, st, L);
   }
 }
 }  // namespace
@@ -227,21 +260,22 @@ void launch_shape(const GemmList& L, bool persistent, int grid_cap, hipStream_t 
 void launch_gemm_f64(const GemmList& L, int shape, bool persistent, int grid_cap, hipStream_t st) {
   if (L.n <= 0 || L.blocks <= 0) return;
   switch (shape) {
-    case kT64x128: launch_shape<1, 2, 1>(L, persistent, grid_cap, st); break;
-    case kT128x64: launch_shape<2, 1, 1>(L, persistent, grid_cap, st); break;
-    case kT64x64: launch_shape<1, 1, 1>(L, persistent, grid_cap, st); break;
-    case kT128x128k32: launch_shape<2, 2, 2>(L, persistent, grid_cap, st); break;
-    default: launch_shape<2, 2, 1>(L, persistent, grid_cap, st); break;
+    case kT64x128: launch_shape<1, 2, 1, 4>(L, persistent, grid_cap, st); break;
+    case kT128x64: launch_shape<2, 1, 1, 4>(L, persistent, grid_cap, st); break;
+    case kT64x64: launch_shape<1, 1, 1, 4>(L, persistent, grid_cap, st); break;
+    case kT128x128k32: launch_shape<2, 2, 2, 4>(L, persistent, grid_cap, st); break;
+    case kT256x128k32: launch_shape<2, 2, 2, 8>(L, persistent, grid_cap, st); break;
+    default: launch_shape<2, 2, 1, 4>(L, persistent, grid_cap, st); break;
   }
 }
 
 namespace {
-template <int MB, int NC, int KH>
+template <int MB, int NC, int KH, int W>
 int resident_blocks_gemm_f64_grid_cap() {
   int dev = 0, cus = 0, nb = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_cauchy_f64_persistent<MB, NC, KH>, 256, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_cauchy_f64_persistent<MB, NC, KH, W>, 64 * W, 0) !=
       hipSuccess)
     return 0;
   return nb * cus;
@@ -252,11 +286,12 @@ int resident_blocks_gemm_f64_grid_cap() {
 // at once (0 if the runtime cannot tell).
 int gemm_f64_grid_cap(int shape) {
   switch (shape) {
-    case kT64x128: return resident_blocks_gemm_f64_grid_cap<1, 2, 1>();
-    case kT128x64: return resident_blocks_gemm_f64_grid_cap<2, 1, 1>();
-    case kT64x64: return resident_blocks_gemm_f64_grid_cap<1, 1, 1>();
-    case kT128x128k32: return resident_blocks_gemm_f64_grid_cap<2, 2, 2>();
-    default: return resident_blocks_gemm_f64_grid_cap<2, 2, 1>();
+    case kT64x128: return resident_blocks_gemm_f64_grid_cap<1, 2, 1, 4>();
+    case kT128x64: return resident_blocks_gemm_f64_grid_cap<2, 1, 1, 4>();
+    case kT64x64: return resident_blocks_gemm_f64_grid_cap<1, 1, 1, 4>();
+    case kT128x128k32: return resident_blocks_gemm_f64_grid_cap<2, 2, 2, 4>();
+    case kT256x128k32: return resident_blocks_gemm_f64_grid_cap<2, 2, 2, 8>();
+    default: return resident_blocks_gemm_f64_grid_cap<2, 2, 1, 4>();
   }
 }
 

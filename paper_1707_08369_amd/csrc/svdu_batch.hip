@@ -401,9 +401,9 @@ int svdu_autotune(int precision, int max_n, double* times_ms, int* table, void* 
         J.ldx = N;
         J.ldo = N;
         J.vec_a = (N % 2) == 0 ? 1 : 0;
-        J.shape = s;
-        J.tiles_n = cdiv(N, shape_bn(s));
-        J.tiles = cdiv(N, shape_bm(s)) * J.tiles_n;
+        J.shape = run_shape(s, precision == SVDU_PREC_SPLIT32);
+        J.tiles_n = cdiv(N, shape_bn(J.shape));
+        J.tiles = cdiv(N, shape_bm(J.shape)) * J.tiles_n;
         J.X = X;
         J.Xo = Xo + (size_t)k * N * N;
         J.d = d;
@@ -422,7 +422,7 @@ int svdu_autotune(int precision, int max_n, double* times_ms, int* table, void* 
       for (int rep = 0; rep < 4; ++rep) {
         (void)hipEventRecord(e0, st);
         if (precision == SVDU_PREC_SPLIT32)
-          launch_gemm_split32(G, s, false, 0, st);
+          launch_gemm_split32(G, run_shape(s, true), false, 0, st);
         else
           launch_gemm_f64(G, s, false, 0, st);
         (void)hipEventRecord(e1, st);

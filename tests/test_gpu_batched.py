@@ -131,7 +131,7 @@ def test_batched_per_problem_status(lib):
     b.close()
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4, 5])
 def test_tile_shapes_give_identical_results(lib, shape):
     P = S.make_problem(300, 457, "uniform", seed=7)
     args = (dev(P.U), dev(P.sigma), dev(P.V), dev(P.a), dev(P.b))
@@ -155,15 +155,18 @@ def test_tile_shapes_give_identical_results(lib, shape):
     assert np.max(np.abs(host(got[1]) - r.sigma)) <= 1e-13 * r.sigma[0]
 
 
-def test_persistent_single_update(lib):
+@pytest.mark.parametrize("shape", [-1, 4, 5])
+def test_persistent_single_update(lib, shape):
     P = S.make_problem(513, 700, "uniform", seed=8)
     args = (dev(P.U), dev(P.sigma), dev(P.V), dev(P.a), dev(P.b))
     ref = lib.rank1_update(*args)
+    old_s = lib.svdu_set_option(lib.SVDU_OPT_TILE_SHAPE, shape)
     old = lib.svdu_set_option(lib.SVDU_OPT_PERSISTENT, 1)
     try:
         got = lib.rank1_update(*args)
     finally:
         lib.svdu_set_option(lib.SVDU_OPT_PERSISTENT, old)
+        lib.svdu_set_option(lib.SVDU_OPT_TILE_SHAPE, old_s)
     for x, y in zip(ref, got):
         assert torch.equal(x, y)
 
