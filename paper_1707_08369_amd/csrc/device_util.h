@@ -7,17 +7,18 @@ namespace svdu {
 
 constexpr double kU = 1.1102230246251565e-16;  // unit roundoff 2^-53
 
-// 1/x to within an ulp: hardware reciprocal (about 2^-24 relative) refined by
-// two Newton steps. Inputs too small for the hardware estimate use the IEEE
-// divide.
-__device__ __forceinline__ double recip(double x) {
-  if (__builtin_fabs(x) < 0x1p-1000) return 1.0 / x;
+// 1/x to within an ulp for |x| >= 2^-1000: hardware reciprocal (about 2^-24
+// relative) refined by two Newton steps.
+__device__ __forceinline__ double recip_fast(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = __builtin_fma(-x, r, 1.0);
   r = __builtin_fma(r, e, r);
   e = __builtin_fma(-x, r, 1.0);
   return __builtin_fma(r, e, r);
 }
+// recip_fast where it applies, the IEEE divide for smaller inputs.
+__device__ __forceinline__ bool recip_tiny(double x) { return __builtin_fabs(x) < 0x1p-1000; }
+__device__ __forceinline__ double recip(double x) { return recip_tiny(x) ? 1.0 / x : recip_fast(x); }
 
 // Global-memory access through a generic pointer. Pointers read from job
 // tables are generic to the compiler; casting them to the global address space

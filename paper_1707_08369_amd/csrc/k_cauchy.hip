@@ -40,14 +40,31 @@ __device__ void cauchy_tmatvec_body(const CauchyDesc& d, const double* __restric
   if (c >= d.N) return;
   const ColDesc cd = load_col(d, c);
   if (cd.type == 0) {
+    // branch-free pass (a zero weight adds a signed zero, which leaves the
+    // sum as it is); a wave with a |delta| below recip_fast's range repeats
+    // the pass with the exact reciprocal, in the same order of terms
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    bool tiny = false;
+    #pragma unroll 4
     for (int j = lane; j < d.N; j += 64) {
       const double z = d.rzeta[j];
-      if (z == 0.0) continue;
-      const double w = z * recip((d.rg[j] - cd.o) - cd.t);
+      const double del = (d.rg[j] - cd.o) - cd.t;
+      tiny = tiny || (z != 0.0 && recip_tiny(del));
+      const double w = (z == 0.0) ? 0.0 : z * recip_fast(del);
       a0 += w * x0[j];
       if (nv > 1) a1 += w * x1[j];
       if (nv > 2) a2 += w * x2[j];
+    }
+    if (__any(tiny)) {
+      a0 = a1 = a2 = 0.0;
+      for (int j = lane; j < d.N; j += 64) {
+        const double z = d.rzeta[j];
+        if (z == 0.0) continue;
+        const double w = z * recip((d.rg[j] - cd.o) - cd.t);
+        a0 += w * x0[j];
+        if (nv > 1) a1 += w * x1[j];
+        if (nv > 2) a2 += w * x2[j];
+      }
     }
     a0 = wave_sum(a0);
     if (nv > 1) a1 = wave_sum(a1);

@@ -181,30 +181,67 @@ struct Reflect {
   const double* W2;
   int K;
   bool refl;
-  __device__ __forceinline__ double pole(int k) const { return refl ? -g[K - 1 - k] : g[k]; }
-  __device__ __forceinline__ double wt(int k) const { return refl ? W2[K - 1 - k] : W2[k]; }
+  // branch-free (index and sign by select), so loops over k keep several loads in flight
+  __device__ __forceinline__ double pole(int k) const {
+    const double v = g[refl ? K - 1 - k : k];
+    return refl ? -v : v;
+  }
+  __device__ __forceinline__ double wt(int k) const { return W2[refl ? K - 1 - k : k]; }
 };
 
 struct SecSums {
   double psi, dpsi, phi, dphi;
 };
 
-// Sums over poles at x = P(o) + tau: psi/dpsi over poles k <= i, phi/dphi over k > i.
-__device__ inline SecSums secular_sums(const Reflect& R, int i, double po, double tau, int lane) {
-  double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
-  for (int k = lane; k < R.K; k += 64) {
-    const double del = (R.pole(k) - po) - tau;
-    const double r = recip(del);
-    const double t = R.wt(k) * r;
-    if (k <= i) {
-      psi += t;
-      dpsi += t * r;
+// Sums over poles at x = P(o) + tau: psi/dpsi over poles k <= i, phi/dphi over
+// k > i. Lane l takes k = l, l + 64, ... in increasing order; the poles k <= i
+// and k > i run as two loops, the reflection is a template parameter, so the
+// loops are branch-free and keep several loads in flight. A wave that meets a
+// |delta| below recip_fast's range repeats the sums with the exact
+// reciprocal; the terms and their order are the same in both versions.
+template <bool REFL, bool EXACT>
+__device__ inline void secular_range(const double* __restrict__ g, const double* __restrict__ W2, int K, int k0,
+                                     int k1, double po, double tau, double* s, double* ds, bool* tiny) {
+  double a = *s, da = *ds;
+  bool t = false;
+#pragma unroll 4
+  for (int k = k0; k < k1; k += 64) {
+    const int kk = REFL ? K - 1 - k : k;
+    const double p = REFL ? -g[kk] : g[kk];
+    const double del = (p - po) - tau;
+    double r;
+    if (EXACT) {
+      r = recip(del);
     } else {
-      phi += t;
-      dphi += t * r;
+      t = t || recip_tiny(del);
+      r = recip_fast(del);
     }
+    const double w = W2[kk] * r;
+    a += w;
+    da = __builtin_fma(w, r, da);
+  }
+  *s = a;
+  *ds = da;
+  *tiny = *tiny || t;
+}
+
+template <bool REFL>
+__device__ inline SecSums secular_sums_t(const Reflect& R, int i, double po, double tau, int lane) {
+  double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+  bool tiny = false;
+  const int kr = (i + 1) + ((lane - (i + 1)) & 63);   // first k > i with k = lane (mod 64)
+  secular_range<REFL, false>(R.g, R.W2, R.K, lane, i + 1, po, tau, &psi, &dpsi, &tiny);
+  secular_range<REFL, false>(R.g, R.W2, R.K, kr, R.K, po, tau, &phi, &dphi, &tiny);
+  if (__any(tiny)) {
+    psi = dpsi = phi = dphi = 0.0;
+    secular_range<REFL, true>(R.g, R.W2, R.K, lane, i + 1, po, tau, &psi, &dpsi, &tiny);
+    secular_range<REFL, true>(R.g, R.W2, R.K, kr, R.K, po, tau, &phi, &dphi, &tiny);
   }
   return SecSums{wave_sum(psi), wave_sum(dpsi), wave_sum(phi), wave_sum(dphi)};
+}
+
+__device__ inline SecSums secular_sums(const Reflect& R, int i, double po, double tau, int lane) {
+  return R.refl ? secular_sums_t<true>(R, i, po, tau, lane) : secular_sums_t<false>(R, i, po, tau, lane);
 }
 
 // Root of c x^2 - a x + b = 0 inside (lo, hi); returns false when none is.
@@ -347,19 +384,17 @@ __device__ void loewner_body(const int* __restrict__ Kdev, const double* __restr
   const int jr = refl ? K - 1 - wave : wave;  // pole index in the reflected problem
   const double pj = R.pole(jr);
   double prod = 1.0;
-  for (int ir = lane; ir < K; ir += 64) {
+  #pragma unroll 4
+  for (int ir = lane; ir < K; ir += 64) {   // branch-free body
     const int io = refl ? K - 1 - ir : ir;
-    const int orr = refl ? K - 1 - org[io] : org[io];
-    const double tr = refl ? -tau[io] : tau[io];
+    const int o = org[io];
+    const double tv = tau[io];
+    const int orr = refl ? K - 1 - o : o;
+    const double tr = refl ? -tv : tv;
     const double num = (R.pole(orr) - pj) + tr;
-    double ratio;
-    if (ir == K - 1) {
-      ratio = num / rho;
-    } else {
-      const int pr = (ir < jr) ? ir : ir + 1;
-      ratio = num / (R.pole(pr) - pj);
-    }
-    prod *= ratio;
+    const int pr = (ir < jr) ? ir : (ir + 1 < K ? ir + 1 : K - 1);
+    const double den = (ir == K - 1) ? rho : (R.pole(pr) - pj);
+    prod *= num / den;
   }
   prod = wave_prod(prod);
   if (lane == 0) what[wave] = sqrt(fabs(prod));
@@ -379,14 +414,35 @@ __device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restr
   if (i >= K) return;
   const double go = g[org[i]];
   const double ti = tau[i];
+  // branch-free passes; a wave with a |delta| below recip_fast's range
+  // repeats them with the exact reciprocal (same order of terms)
   double mx = 0.0;
-  for (int k = lane; k < K; k += 64) mx = fmax(mx, fabs(what[k] * recip((g[k] - go) - ti)));
+  bool tiny = false;
+  #pragma unroll 4
+  for (int k = lane; k < K; k += 64) {
+    const double del = (g[k] - go) - ti;
+    tiny = tiny || recip_tiny(del);
+    mx = fmax(mx, fabs(what[k] * recip_fast(del)));
+  }
+  const bool exact = __any(tiny);
+  if (exact) {
+    mx = 0.0;
+    for (int k = lane; k < K; k += 64) mx = fmax(mx, fabs(what[k] * recip((g[k] - go) - ti)));
+  }
   mx = wave_max(mx);
   const double inv = (mx > 0.0) ? 1.0 / mx : 1.0;
   double ss = 0.0;
-  for (int k = lane; k < K; k += 64) {
-    const double t = what[k] * recip((g[k] - go) - ti) * inv;
-    ss += t * t;
+  if (!exact) {
+    #pragma unroll 4
+    for (int k = lane; k < K; k += 64) {
+      const double t = what[k] * recip_fast((g[k] - go) - ti) * inv;
+      ss += t * t;
+    }
+  } else {
+    for (int k = lane; k < K; k += 64) {
+      const double t = what[k] * recip((g[k] - go) - ti) * inv;
+      ss += t * t;
+    }
   }
   ss = wave_sum(ss);
   if (lane == 0) {
