@@ -32,6 +32,46 @@ __device__ void householder_dots_body(const Stage& s, int nv, const double* x0, 
   s.hx[3 * c + 2] = a2;
 }
 
+// One pass of y = C~^T x over the rows of a live column, NV vectors. Lane l
+// takes rows l, l + 64, ... in order; a zero weight adds a signed zero, which
+// leaves the sum as it is. The fast pass records whether any nonzero weight
+// met a |delta| below recip_fast's range; the exact pass (recip) then repeats
+// it with the same terms in the same order.
+template <int NV, bool EXACT>
+__device__ inline void tmv_pass(const CauchyDesc& d, const ColDesc& cd, const double* x0, const double* x1,
+                                const double* x2, int lane, double (&acc)[3], bool* tiny) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  bool t = false;
+#pragma unroll 4
+  for (int j = lane; j < d.N; j += 64) {
+    const double z = gld(d.rzeta + j);
+    const double del = (gld(d.rg + j) - cd.o) - cd.t;
+    double r;
+    if (EXACT) {
+      r = (z == 0.0) ? 0.0 : recip(del);
+    } else {
+      t |= (z != 0.0) & recip_tiny(del);
+      r = recip_fast(del);
+    }
+    const double w = (z == 0.0) ? 0.0 : z * r;
+    a0 = __builtin_fma(w, gld(x0 + j), a0);
+    if (NV > 1) a1 = __builtin_fma(w, gld(x1 + j), a1);
+    if (NV > 2) a2 = __builtin_fma(w, gld(x2 + j), a2);
+  }
+  acc[0] = a0;
+  acc[1] = a1;
+  acc[2] = a2;
+  *tiny = t;
+}
+
+template <int NV>
+__device__ inline void tmv_live(const CauchyDesc& d, const ColDesc& cd, const double* x0, const double* x1,
+                                const double* x2, int lane, double (&acc)[3]) {
+  bool tiny = false;
+  tmv_pass<NV, false>(d, cd, x0, x1, x2, lane, acc, &tiny);
+  if (__any(tiny)) tmv_pass<NV, true>(d, cd, x0, x1, x2, lane, acc, &tiny);
+}
+
 __device__ void cauchy_tmatvec_body(const CauchyDesc& d, const double* __restrict__ hx, int nv,
                                     const double* __restrict__ x0, const double* __restrict__ x1,
                                     const double* __restrict__ x2, double* y0, double* y1, double* y2, int c) {
@@ -40,35 +80,16 @@ __device__ void cauchy_tmatvec_body(const CauchyDesc& d, const double* __restric
   if (c >= d.N) return;
   const ColDesc cd = load_col(d, c);
   if (cd.type == 0) {
-    // branch-free pass (a zero weight adds a signed zero, which leaves the
-    // sum as it is); a wave with a |delta| below recip_fast's range repeats
-    // the pass with the exact reciprocal, in the same order of terms
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    bool tiny = false;
-    #pragma unroll 4
-    for (int j = lane; j < d.N; j += 64) {
-      const double z = d.rzeta[j];
-      const double del = (d.rg[j] - cd.o) - cd.t;
-      tiny = tiny || (z != 0.0 && recip_tiny(del));
-      const double w = (z == 0.0) ? 0.0 : z * recip_fast(del);
-      a0 += w * x0[j];
-      if (nv > 1) a1 += w * x1[j];
-      if (nv > 2) a2 += w * x2[j];
-    }
-    if (__any(tiny)) {
-      a0 = a1 = a2 = 0.0;
-      for (int j = lane; j < d.N; j += 64) {
-        const double z = d.rzeta[j];
-        if (z == 0.0) continue;
-        const double w = z * recip((d.rg[j] - cd.o) - cd.t);
-        a0 += w * x0[j];
-        if (nv > 1) a1 += w * x1[j];
-        if (nv > 2) a2 += w * x2[j];
-      }
-    }
-    a0 = wave_sum(a0);
-    if (nv > 1) a1 = wave_sum(a1);
-    if (nv > 2) a2 = wave_sum(a2);
+    double acc[3];
+    if (nv > 2)
+      tmv_live<3>(d, cd, x0, x1, x2, lane, acc);
+    else if (nv > 1)
+      tmv_live<2>(d, cd, x0, x1, x2, lane, acc);
+    else
+      tmv_live<1>(d, cd, x0, x1, x2, lane, acc);
+    const double a0 = wave_sum(acc[0]);
+    const double a1 = nv > 1 ? wave_sum(acc[1]) : 0.0;
+    const double a2 = nv > 2 ? wave_sum(acc[2]) : 0.0;
     if (lane == 0) {
       y0[c] = cd.s * a0;
       if (nv > 1) y1[c] = cd.s * a1;

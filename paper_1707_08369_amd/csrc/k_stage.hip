@@ -183,10 +183,10 @@ struct Reflect {
   bool refl;
   // branch-free (index and sign by select), so loops over k keep several loads in flight
   __device__ __forceinline__ double pole(int k) const {
-    const double v = g[refl ? K - 1 - k : k];
+    const double v = gld(g + (refl ? K - 1 - k : k));
     return refl ? -v : v;
   }
-  __device__ __forceinline__ double wt(int k) const { return W2[refl ? K - 1 - k : k]; }
+  __device__ __forceinline__ double wt(int k) const { return gld(W2 + (refl ? K - 1 - k : k)); }
 };
 
 struct SecSums {
@@ -207,16 +207,16 @@ __device__ inline void secular_range(const double* __restrict__ g, const double*
 #pragma unroll 4
   for (int k = k0; k < k1; k += 64) {
     const int kk = REFL ? K - 1 - k : k;
-    const double p = REFL ? -g[kk] : g[kk];
+    const double p = REFL ? -gld(g + kk) : gld(g + kk);
     const double del = (p - po) - tau;
     double r;
     if (EXACT) {
       r = recip(del);
     } else {
-      t = t || recip_tiny(del);
+      t |= recip_tiny(del);
       r = recip_fast(del);
     }
-    const double w = W2[kk] * r;
+    const double w = gld(W2 + kk) * r;
     a += w;
     da = __builtin_fma(w, r, da);
   }
@@ -387,8 +387,8 @@ __device__ void loewner_body(const int* __restrict__ Kdev, const double* __restr
   #pragma unroll 4
   for (int ir = lane; ir < K; ir += 64) {   // branch-free body
     const int io = refl ? K - 1 - ir : ir;
-    const int o = org[io];
-    const double tv = tau[io];
+    const int o = gld(org + io);
+    const double tv = gld(tau + io);
     const int orr = refl ? K - 1 - o : o;
     const double tr = refl ? -tv : tv;
     const double num = (R.pole(orr) - pj) + tr;
@@ -414,33 +414,32 @@ __device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restr
   if (i >= K) return;
   const double go = g[org[i]];
   const double ti = tau[i];
-  // branch-free passes; a wave with a |delta| below recip_fast's range
-  // repeats them with the exact reciprocal (same order of terms)
-  double mx = 0.0;
+  // One branch-free pass for the largest term and the unscaled sum of
+  // squares. With the largest term in [2^-450, 2^450] no square overflows and
+  // any that underflows is negligible; otherwise, or if a |delta| is below
+  // recip_fast's range, the wave takes two exact passes, scaled by the largest
+  // term.
+  double mx = 0.0, ss = 0.0;
   bool tiny = false;
-  #pragma unroll 4
+#pragma unroll 4
   for (int k = lane; k < K; k += 64) {
-    const double del = (g[k] - go) - ti;
-    tiny = tiny || recip_tiny(del);
-    mx = fmax(mx, fabs(what[k] * recip_fast(del)));
-  }
-  const bool exact = __any(tiny);
-  if (exact) {
-    mx = 0.0;
-    for (int k = lane; k < K; k += 64) mx = fmax(mx, fabs(what[k] * recip((g[k] - go) - ti)));
+    const double del = (gld(g + k) - go) - ti;
+    tiny |= recip_tiny(del);
+    const double t = gld(what + k) * recip_fast(del);
+    mx = fmax(mx, fabs(t));
+    ss = __builtin_fma(t, t, ss);
   }
   mx = wave_max(mx);
-  const double inv = (mx > 0.0) ? 1.0 / mx : 1.0;
-  double ss = 0.0;
-  if (!exact) {
-    #pragma unroll 4
+  const bool scaled = __any(tiny) || !(mx >= 0x1p-450 && mx <= 0x1p450);
+  double inv = 1.0;
+  if (scaled) {
+    mx = 0.0;
+    for (int k = lane; k < K; k += 64) mx = fmax(mx, fabs(gld(what + k) * recip((gld(g + k) - go) - ti)));
+    mx = wave_max(mx);
+    inv = (mx > 0.0) ? 1.0 / mx : 1.0;
+    ss = 0.0;
     for (int k = lane; k < K; k += 64) {
-      const double t = what[k] * recip_fast((g[k] - go) - ti) * inv;
-      ss += t * t;
-    }
-  } else {
-    for (int k = lane; k < K; k += 64) {
-      const double t = what[k] * recip((g[k] - go) - ti) * inv;
+      const double t = gld(what + k) * recip((gld(g + k) - go) - ti) * inv;
       ss += t * t;
     }
   }
