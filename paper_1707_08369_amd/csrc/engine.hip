@@ -620,7 +620,7 @@ void enqueue_status_gather(const Plan& P, int* out, hipStream_t st) {
 // ---------------------------------------------------------------------------
 namespace {
 int g_shape_table[2][kShapeBuckets] = {
-    {kT64x64, kT128x128, kT128x128, kT128x128, kT128x128, kT256x128k32, kT256x128k32, kT256x128k32},
+    {kT64x64, kT128x64, kT256x128k32, kT256x128k32, kT256x128k32, kT256x128k32, kT256x128k32, kT256x128k32},
     {kT64x64, kT64x64, kT64x64, kT64x64, kT64x64, kT64x64, kT128x128, kT128x128}};
 int g_forced_shape = -1;
 }  // namespace
