@@ -297,22 +297,25 @@ StageLevel build_level(const std::vector<Stage>& st_in, const std::vector<TmvJob
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return st_in[x].N > st_in[y].N; });
   std::vector<Stage> st;
   std::vector<TmvJob> tv;
-  std::vector<int> bw, bt;
+  std::vector<int> bw, bt, bs;
   for (int i : order) {
     st.push_back(st_in[i]);
     tv.push_back(i < (int)tv_in.size() ? tv_in[i] : TmvJob{0, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}});
     bw.push_back(cdiv(st_in[i].N, 4));
     bt.push_back(cdiv(st_in[i].N, 256));
+    bs.push_back(st_in[i].N <= kSecLaneMaxN ? cdiv(st_in[i].N, 256) : cdiv(st_in[i].N, 4));
   }
-  const std::vector<int> ow = prefix(bw), ot = prefix(bt);
+  const std::vector<int> ow = prefix(bw), ot = prefix(bt), os = prefix(bs);
   StageLevel S;
   S.n = (int)st.size();
   S.st = B.put(st);
   S.tmv = B.put(tv);
   S.boff_w = B.put(ow);
   S.boff_t = B.put(ot);
+  S.boff_s = B.put(os);
   S.blocks_w = ow.back();
   S.blocks_t = ot.back();
+  S.blocks_s = os.back();
   return S;
 }
 

@@ -35,13 +35,18 @@ struct TmvJob {
 // three launch shapes used by the stage kernels: one block per job
 // (deflation), one wave per root or pole (4 per block), one thread per index
 // (256 per block).
+// Secular solves of eigenproblems up to this order run one root per lane
+// (many short sums per wave); larger ones one root per wave.
+constexpr int kSecLaneMaxN = 2048;
+
 struct StageLevel {
   int n = 0;
   const Stage* st = nullptr;
   const TmvJob* tmv = nullptr;   // n entries, or nullptr
   const int* boff_w = nullptr;   // ceil(N / 4) blocks per job
   const int* boff_t = nullptr;   // ceil(N / 256) blocks per job
-  int blocks_w = 0, blocks_t = 0;
+  const int* boff_s = nullptr;   // secular solve: ceil(N / 256) if N <= kSecLaneMaxN, else ceil(N / 4)
+  int blocks_w = 0, blocks_t = 0, blocks_s = 0;
 };
 
 // One product X_out = X C~ in the tile grid of the list's tile shape.

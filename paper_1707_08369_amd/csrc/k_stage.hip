@@ -244,6 +244,79 @@ __device__ inline SecSums secular_sums(const Reflect& R, int i, double po, doubl
   return R.refl ? secular_sums_t<true>(R, i, po, tau, lane) : secular_sums_t<false>(R, i, po, tau, lane);
 }
 
+// The same sums with one root per lane: the lane adds all K terms itself, in
+// increasing k, and the pole index is the same in every lane of the wave.
+// Poles up to the wave's lowest root index ilo are left of all its roots and
+// poles past the highest, ihi, right of all, so only (ilo, ihi] (fewer than 64
+// poles) needs the per-lane test. A lane that meets a |delta| below
+// recip_fast's range repeats its sums with the exact reciprocal.
+template <bool REFL, bool EXACT>
+__device__ inline void secular_lane_range(const double* __restrict__ g, const double* __restrict__ W2, int K,
+                                          int k0, int k1, double po, double tau, double* s, double* ds,
+                                          bool* tiny) {
+  double a = *s, da = *ds;
+  bool t = false;
+#pragma unroll 4
+  for (int k = k0; k < k1; ++k) {
+    const int kk = REFL ? K - 1 - k : k;
+    const double p = REFL ? -gld(g + kk) : gld(g + kk);
+    const double del = (p - po) - tau;
+    double r;
+    if (EXACT) {
+      r = recip(del);
+    } else {
+      t |= recip_tiny(del);
+      r = recip_fast(del);
+    }
+    const double w = gld(W2 + kk) * r;
+    a += w;
+    da = __builtin_fma(w, r, da);
+  }
+  *s = a;
+  *ds = da;
+  *tiny = *tiny || t;
+}
+
+template <bool REFL, bool EXACT>
+__device__ inline void secular_lane_all(const Reflect& R, int i, int ilo, int ihi, double po, double tau,
+                                        SecSums* S, bool* tiny) {
+  double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+  secular_lane_range<REFL, EXACT>(R.g, R.W2, R.K, 0, ilo + 1, po, tau, &psi, &dpsi, tiny);
+  bool t = false;
+  for (int k = ilo + 1; k <= ihi; ++k) {
+    const int kk = REFL ? R.K - 1 - k : k;
+    const double p = REFL ? -gld(R.g + kk) : gld(R.g + kk);
+    const double del = (p - po) - tau;
+    double r;
+    if (EXACT) {
+      r = recip(del);
+    } else {
+      t |= recip_tiny(del);
+      r = recip_fast(del);
+    }
+    const double w = gld(R.W2 + kk) * r;
+    if (k <= i) {
+      psi += w;
+      dpsi = __builtin_fma(w, r, dpsi);
+    } else {
+      phi += w;
+      dphi = __builtin_fma(w, r, dphi);
+    }
+  }
+  *tiny = *tiny || t;
+  secular_lane_range<REFL, EXACT>(R.g, R.W2, R.K, ihi + 1, R.K, po, tau, &phi, &dphi, tiny);
+  *S = SecSums{psi, dpsi, phi, dphi};
+}
+
+template <bool REFL>
+__device__ inline SecSums secular_lane_sums_t(const Reflect& R, int i, int ilo, int ihi, double po, double tau) {
+  SecSums S;
+  bool tiny = false;
+  secular_lane_all<REFL, false>(R, i, ilo, ihi, po, tau, &S, &tiny);
+  if (tiny) secular_lane_all<REFL, true>(R, i, ilo, ihi, po, tau, &S, &tiny);
+  return S;
+}
+
 // Root of c x^2 - a x + b = 0 inside (lo, hi); returns false when none is.
 __device__ inline bool quad_root_in(double c, double a, double b, double lo, double hi, double* x) {
   double r1, r2;
@@ -269,19 +342,33 @@ __device__ inline bool quad_root_in(double c, double a, double b, double lo, dou
   return false;
 }
 
+// One root: the midpoint two-pole start, then middle-way steps safeguarded
+// by bisection. LANE = false: root `idx` belongs to the whole wave, which
+// splits the sums over its lanes. LANE = true: root `idx` belongs to this lane
+// and r0 is the first root of the wave.
+template <bool LANE>
 __device__ void secular_body(const int* __restrict__ Kdev, const double* __restrict__ g,
                              const double* __restrict__ W2, const double* __restrict__ rhop,
                              int* __restrict__ org, double* __restrict__ tau_out, int* __restrict__ iters,
-                             int* status, int maxit, int wave) {
+                             int* status, int maxit, int idx, int r0) {
   if (*status & kStFatal) return;
   const int K = *Kdev;
   const int lane = threadIdx.x & 63;
-  if (wave >= K) return;
+  if (idx >= K) return;
   const double rho0 = *rhop;
   Reflect R{g, W2, K, rho0 < 0.0};
   const double rho = fabs(rho0);
   const double rinv = 1.0 / rho;
-  const int i = R.refl ? K - 1 - wave : wave;  // root index in the reflected problem
+  const int i = R.refl ? K - 1 - idx : idx;  // root index in the reflected problem
+  // LANE: the wave's roots r0 .. r1 are reflected indices ilo .. ihi
+  const int r1 = (r0 + 63 < K - 1) ? r0 + 63 : K - 1;
+  const int ilo = R.refl ? K - 1 - r1 : r0, ihi = R.refl ? K - 1 - r0 : r1;
+  auto sums = [&](double po, double tau) -> SecSums {
+    if (LANE)
+      return R.refl ? secular_lane_sums_t<true>(R, i, ilo, ihi, po, tau)
+                    : secular_lane_sums_t<false>(R, i, ilo, ihi, po, tau);
+    return secular_sums(R, i, po, tau, lane);
+  };
 
   int o;
   double lo, hi, tau;
@@ -289,7 +376,7 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
     const double pi = R.pole(i), pi1 = R.pole(i + 1);
     const double gap = pi1 - pi;
     const double half = 0.5 * gap;
-    const SecSums m = secular_sums(R, i, pi, half, lane);
+    const SecSums m = sums(pi, half);
     const double fmid = rinv + m.psi + m.phi;
     const double qi = R.wt(i), qi1 = R.wt(i + 1);
     // two-pole model at the midpoint: c + qi/(pi - x) + qi1/(pi1 - x)
@@ -313,8 +400,12 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
   } else {
     o = K - 1;
     double w = 0.0;
-    for (int k = lane; k < K; k += 64) w += R.wt(k);
-    w = wave_sum(w);
+    if (LANE) {
+      for (int k = 0; k < K; ++k) w += R.wt(k);
+    } else {
+      for (int k = lane; k < K; k += 64) w += R.wt(k);
+      w = wave_sum(w);
+    }
     lo = 0.0;
     hi = rho * w;
     tau = 0.5 * hi;
@@ -325,7 +416,7 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
   bool done = false;
   int it = 0;
   for (; it < maxit; ++it) {
-    const SecSums s = secular_sums(R, i, po, tau, lane);
+    const SecSums s = sums(po, tau);
     const double f = rinv + s.psi + s.phi;
     if (f < 0.0) lo = tau; else hi = tau;
     const double err = 8.0 * (s.phi - s.psi) + 2.0 * rinv + 3.0 * fabs(f) + fabs(tau) * (s.dpsi + s.dphi);
@@ -355,12 +446,12 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
     tau = 0.0;
     done = false;
   }
-  if (lane == 0) {
+  if (LANE || lane == 0) {
     if (!done) atomicOr(status, (int)kStNoConv);
     const int ow = R.refl ? K - 1 - o : o;
-    org[wave] = ow;
-    tau_out[wave] = R.refl ? -tau : tau;
-    if (iters) iters[wave] = it + 1;
+    org[idx] = ow;
+    tau_out[idx] = R.refl ? -tau : tau;
+    if (iters) iters[idx] = it + 1;
   }
 }
 
@@ -523,11 +614,20 @@ __global__ __launch_bounds__(kDeflThreads) void deflate_kernel(StageLevel L) {
   if (s.N > 0) deflate_body(s);
 }
 
+// Problems with N <= kSecLaneMaxN take one root per lane (256 per block),
+// larger ones one root per wave (4 per block); the host sizes boff_s to match.
 __global__ __launch_bounds__(256) void secular_kernel(StageLevel L, int maxit) {
-  const int j = find_job(L.boff_w, L.n, blockIdx.x);
+  const int j = find_job(L.boff_s, L.n, blockIdx.x);
   const Stage s = L.st[j];
-  const int wave = (blockIdx.x - L.boff_w[j]) * 4 + (threadIdx.x >> 6);
-  secular_body(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, wave);
+  const int b = blockIdx.x - L.boff_s[j];
+  if (s.N <= kSecLaneMaxN) {
+    const int r0 = b * 256 + (threadIdx.x & ~63);
+    secular_body<true>(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, r0 + (threadIdx.x & 63),
+                       r0);
+  } else {
+    const int wave = b * 4 + (threadIdx.x >> 6);
+    secular_body<false>(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, wave, wave);
+  }
 }
 
 __global__ __launch_bounds__(256) void loewner_kernel(StageLevel L) {
@@ -551,8 +651,8 @@ __global__ __launch_bounds__(256) void merge_kernel(StageLevel L) {
 }
 
 void launch_secular_level(const StageLevel& L, int maxit, hipStream_t st) {
-  if (L.blocks_w <= 0) return;
-  hipLaunchKernelGGL(secular_kernel, dim3(L.blocks_w), dim3(256), 0, st, L, maxit);
+  if (L.blocks_s <= 0) return;
+  hipLaunchKernelGGL(secular_kernel, dim3(L.blocks_s), dim3(256), 0, st, L, maxit);
 }
 
 void launch_stage_level(const StageLevel& L, int maxit, hipStream_t st) {
