@@ -37,7 +37,7 @@ __device__ __forceinline__ double cauchy_entry(const CauchyDesc& d, int j, const
   if (c.type == 0) {
     const double z = d.rzeta[j];
     if (z == 0.0) return 0.0;
-    return (z * c.s) * recip((d.rg[j] - c.o) - c.t);
+    return div_by(z * c.s, (d.rg[j] - c.o) - c.t);
   }
   if (d.rcl[j] != c.cl) return 0.0;
   return ((j == c.mem) ? 1.0 : 0.0) - 2.0 * d.rh[j] * c.h;
@@ -65,7 +65,7 @@ __device__ __forceinline__ double live_entry(double z, double g, const ColDesc& 
 __device__ __forceinline__ double general_entry(int j, const RowVals& rv, const ColDesc& c) {
   if (c.type == 0) {
     if (rv.z == 0.0) return 0.0;
-    return (rv.z * c.s) * recip((rv.g - c.o) - c.t);
+    return div_by(rv.z * c.s, (rv.g - c.o) - c.t);
   }
   if (c.type < 0 || rv.cl != c.cl) return 0.0;
   return ((j == c.mem) ? 1.0 : 0.0) - 2.0 * rv.h * c.h;

@@ -19,6 +19,11 @@ __device__ __forceinline__ double recip_fast(double x) {
 // recip_fast where it applies, the IEEE divide for smaller inputs.
 __device__ __forceinline__ bool recip_tiny(double x) { return __builtin_fabs(x) < 0x1p-1000; }
 __device__ __forceinline__ double recip(double x) { return recip_tiny(x) ? 1.0 / x : recip_fast(x); }
+// num / x: num times recip_fast(x) where that applies, a true division below
+// (where 1 / x alone can overflow although num / x does not).
+__device__ __forceinline__ double div_by(double num, double x) {
+  return recip_tiny(x) ? num / x : num * recip_fast(x);
+}
 
 // Global-memory access through a generic pointer. Pointers read from job
 // tables are generic to the compiler; casting them to the global address space

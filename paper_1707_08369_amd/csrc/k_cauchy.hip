@@ -35,7 +35,7 @@ __device__ void householder_dots_body(const Stage& s, int nv, const double* x0, 
 // One pass of y = C~^T x over the rows of a live column, NV vectors. Lane l
 // takes rows l, l + 64, ... in order; a zero weight adds a signed zero, which
 // leaves the sum as it is. The fast pass records whether any nonzero weight
-// met a |delta| below recip_fast's range; the exact pass (recip) then repeats
+// met a |delta| below recip_fast's range; the exact pass (div_by) then repeats
 // it with the same terms in the same order.
 template <int NV, bool EXACT>
 __device__ inline void tmv_pass(const CauchyDesc& d, const ColDesc& cd, const double* x0, const double* x1,
@@ -46,14 +46,14 @@ __device__ inline void tmv_pass(const CauchyDesc& d, const ColDesc& cd, const do
   for (int j = lane; j < d.N; j += 64) {
     const double z = gld(d.rzeta + j);
     const double del = (gld(d.rg + j) - cd.o) - cd.t;
-    double r;
+    double w;
     if (EXACT) {
-      r = (z == 0.0) ? 0.0 : recip(del);
+      w = (z == 0.0) ? 0.0 : div_by(z, del);
     } else {
       t |= (z != 0.0) & recip_tiny(del);
-      r = recip_fast(del);
+      const double r = recip_fast(del);
+      w = (z == 0.0) ? 0.0 : z * r;
     }
-    const double w = (z == 0.0) ? 0.0 : z * r;
     a0 = __builtin_fma(w, gld(x0 + j), a0);
     if (NV > 1) a1 = __builtin_fma(w, gld(x1 + j), a1);
     if (NV > 2) a2 = __builtin_fma(w, gld(x2 + j), a2);

@@ -193,55 +193,71 @@ struct SecSums {
   double psi, dpsi, phi, dphi;
 };
 
-// Sums over poles at x = P(o) + tau: psi/dpsi over poles k <= i, phi/dphi over
-// k > i. Lane l takes k = l, l + 64, ... in increasing order; the poles k <= i
-// and k > i run as two loops, the reflection is a template parameter, so the
-// loops are branch-free and keep several loads in flight. A wave that meets a
-// |delta| below recip_fast's range repeats the sums with the exact
-// reciprocal; the terms and their order are the same in both versions.
-template <bool REFL, bool EXACT>
-__device__ inline void secular_range(const double* __restrict__ g, const double* __restrict__ W2, int K, int k0,
-                                     int k1, double po, double tau, double* s, double* ds, bool* tiny) {
+// Pole k and its weight z_k^2 of the (reflected) problem, in units of 1 / sc
+// when SC (an exact power-of-two scaling).
+template <bool REFL, bool SC>
+__device__ __forceinline__ void sec_pole(const Reflect& R, int k, double sc, double* p, double* wt) {
+  const int kk = REFL ? R.K - 1 - k : k;
+  const double v = gld(R.g + kk), w = gld(R.W2 + kk);
+  *p = SC ? (REFL ? -v : v) * sc : (REFL ? -v : v);
+  *wt = SC ? w * sc : w;
+}
+
+// Adds one term w = wt / del to a and w / del to da: times recip_fast(del)
+// with an fma for the derivative, or, in the EXACT pass, by true divisions
+// where |del| is below recip_fast's range (where 1 / del alone may overflow).
+// The fast pass flags such terms in t.
+template <bool EXACT>
+__device__ __forceinline__ void sec_add(double wt, double del, double* a, double* da, bool* t) {
+  if (EXACT && recip_tiny(del)) {
+    const double w = wt / del;
+    *a += w;
+    *da += w / del;
+  } else {
+    if (!EXACT) *t |= recip_tiny(del);
+    const double r = recip_fast(del);
+    const double w = wt * r;
+    *a += w;
+    *da = __builtin_fma(w, r, *da);
+  }
+}
+
+// Terms k = k0, k0 + STEP, ... < k1 added in increasing k.
+template <bool REFL, bool SC, bool EXACT, int STEP>
+__device__ inline void secular_range(const Reflect& R, double sc, int k0, int k1, double po, double tau, double* s,
+                                     double* ds, bool* tiny) {
   double a = *s, da = *ds;
   bool t = false;
 #pragma unroll 4
-  for (int k = k0; k < k1; k += 64) {
-    const int kk = REFL ? K - 1 - k : k;
-    const double p = REFL ? -gld(g + kk) : gld(g + kk);
-    const double del = (p - po) - tau;
-    double r;
-    if (EXACT) {
-      r = recip(del);
-    } else {
-      t |= recip_tiny(del);
-      r = recip_fast(del);
-    }
-    const double w = gld(W2 + kk) * r;
-    a += w;
-    da = __builtin_fma(w, r, da);
+  for (int k = k0; k < k1; k += STEP) {
+    double p, wt;
+    sec_pole<REFL, SC>(R, k, sc, &p, &wt);
+    sec_add<EXACT>(wt, (p - po) - tau, &a, &da, &t);
   }
   *s = a;
   *ds = da;
   *tiny = *tiny || t;
 }
 
-template <bool REFL>
-__device__ inline SecSums secular_sums_t(const Reflect& R, int i, double po, double tau, int lane) {
+// Sums over poles at x = P(o) + tau: psi/dpsi over poles k <= i, phi/dphi over
+// k > i, with one root per wave. Lane l takes k = l, l + 64, ... in increasing
+// order; the poles k <= i and k > i run as two loops and the reflection is a
+// template parameter, so the loops are branch-free and keep several loads in
+// flight. A wave that meets a |delta| below recip_fast's range repeats the
+// sums in the exact form, with the same terms in the same order.
+template <bool REFL, bool SC>
+__device__ inline SecSums secular_sums_t(const Reflect& R, double sc, int i, double po, double tau, int lane) {
   double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
   bool tiny = false;
   const int kr = (i + 1) + ((lane - (i + 1)) & 63);   // first k > i with k = lane (mod 64)
-  secular_range<REFL, false>(R.g, R.W2, R.K, lane, i + 1, po, tau, &psi, &dpsi, &tiny);
-  secular_range<REFL, false>(R.g, R.W2, R.K, kr, R.K, po, tau, &phi, &dphi, &tiny);
+  secular_range<REFL, SC, false, 64>(R, sc, lane, i + 1, po, tau, &psi, &dpsi, &tiny);
+  secular_range<REFL, SC, false, 64>(R, sc, kr, R.K, po, tau, &phi, &dphi, &tiny);
   if (__any(tiny)) {
     psi = dpsi = phi = dphi = 0.0;
-    secular_range<REFL, true>(R.g, R.W2, R.K, lane, i + 1, po, tau, &psi, &dpsi, &tiny);
-    secular_range<REFL, true>(R.g, R.W2, R.K, kr, R.K, po, tau, &phi, &dphi, &tiny);
+    secular_range<REFL, SC, true, 64>(R, sc, lane, i + 1, po, tau, &psi, &dpsi, &tiny);
+    secular_range<REFL, SC, true, 64>(R, sc, kr, R.K, po, tau, &phi, &dphi, &tiny);
   }
   return SecSums{wave_sum(psi), wave_sum(dpsi), wave_sum(phi), wave_sum(dphi)};
-}
-
-__device__ inline SecSums secular_sums(const Reflect& R, int i, double po, double tau, int lane) {
-  return R.refl ? secular_sums_t<true>(R, i, po, tau, lane) : secular_sums_t<false>(R, i, po, tau, lane);
 }
 
 // The same sums with one root per lane: the lane adds all K terms itself, in
@@ -249,72 +265,44 @@ __device__ inline SecSums secular_sums(const Reflect& R, int i, double po, doubl
 // Poles up to the wave's lowest root index ilo are left of all its roots and
 // poles past the highest, ihi, right of all, so only (ilo, ihi] (fewer than 64
 // poles) needs the per-lane test. A lane that meets a |delta| below
-// recip_fast's range repeats its sums with the exact reciprocal.
-template <bool REFL, bool EXACT>
-__device__ inline void secular_lane_range(const double* __restrict__ g, const double* __restrict__ W2, int K,
-                                          int k0, int k1, double po, double tau, double* s, double* ds,
-                                          bool* tiny) {
-  double a = *s, da = *ds;
-  bool t = false;
-#pragma unroll 4
-  for (int k = k0; k < k1; ++k) {
-    const int kk = REFL ? K - 1 - k : k;
-    const double p = REFL ? -gld(g + kk) : gld(g + kk);
-    const double del = (p - po) - tau;
-    double r;
-    if (EXACT) {
-      r = recip(del);
-    } else {
-      t |= recip_tiny(del);
-      r = recip_fast(del);
-    }
-    const double w = gld(W2 + kk) * r;
-    a += w;
-    da = __builtin_fma(w, r, da);
-  }
-  *s = a;
-  *ds = da;
-  *tiny = *tiny || t;
-}
-
-template <bool REFL, bool EXACT>
-__device__ inline void secular_lane_all(const Reflect& R, int i, int ilo, int ihi, double po, double tau,
+// recip_fast's range repeats its sums in the exact form.
+template <bool REFL, bool SC, bool EXACT>
+__device__ inline void secular_lane_all(const Reflect& R, double sc, int i, int ilo, int ihi, double po, double tau,
                                         SecSums* S, bool* tiny) {
   double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
-  secular_lane_range<REFL, EXACT>(R.g, R.W2, R.K, 0, ilo + 1, po, tau, &psi, &dpsi, tiny);
+  secular_range<REFL, SC, EXACT, 1>(R, sc, 0, ilo + 1, po, tau, &psi, &dpsi, tiny);
   bool t = false;
   for (int k = ilo + 1; k <= ihi; ++k) {
-    const int kk = REFL ? R.K - 1 - k : k;
-    const double p = REFL ? -gld(R.g + kk) : gld(R.g + kk);
-    const double del = (p - po) - tau;
-    double r;
-    if (EXACT) {
-      r = recip(del);
-    } else {
-      t |= recip_tiny(del);
-      r = recip_fast(del);
-    }
-    const double w = gld(R.W2 + kk) * r;
-    if (k <= i) {
-      psi += w;
-      dpsi = __builtin_fma(w, r, dpsi);
-    } else {
-      phi += w;
-      dphi = __builtin_fma(w, r, dphi);
-    }
+    double p, wt;
+    sec_pole<REFL, SC>(R, k, sc, &p, &wt);
+    if (k <= i)
+      sec_add<EXACT>(wt, (p - po) - tau, &psi, &dpsi, &t);
+    else
+      sec_add<EXACT>(wt, (p - po) - tau, &phi, &dphi, &t);
   }
   *tiny = *tiny || t;
-  secular_lane_range<REFL, EXACT>(R.g, R.W2, R.K, ihi + 1, R.K, po, tau, &phi, &dphi, tiny);
+  secular_range<REFL, SC, EXACT, 1>(R, sc, ihi + 1, R.K, po, tau, &phi, &dphi, tiny);
   *S = SecSums{psi, dpsi, phi, dphi};
 }
 
-template <bool REFL>
-__device__ inline SecSums secular_lane_sums_t(const Reflect& R, int i, int ilo, int ihi, double po, double tau) {
+template <bool REFL, bool SC>
+__device__ inline SecSums secular_lane_sums_t(const Reflect& R, double sc, int i, int ilo, int ihi, double po,
+                                              double tau) {
   SecSums S;
   bool tiny = false;
-  secular_lane_all<REFL, false>(R, i, ilo, ihi, po, tau, &S, &tiny);
-  if (tiny) secular_lane_all<REFL, true>(R, i, ilo, ihi, po, tau, &S, &tiny);
+  secular_lane_all<REFL, SC, false>(R, sc, i, ilo, ihi, po, tau, &S, &tiny);
+  if (tiny) secular_lane_all<REFL, SC, true>(R, sc, i, ilo, ihi, po, tau, &S, &tiny);
   return S;
+}
+
+// A power of two near |x| (x finite and nonzero), else 1. Lengths divided by it
+// and derivatives multiplied by it scale exactly, so the quadratics below keep
+// their coefficients at the scale of the secular function itself: without it
+// products of two pole distances underflow once the poles are below about
+// 2^-511 (and overflow above 2^511).
+__device__ inline double length_unit(double x) {
+  if (!(x != 0.0) || !isfinite(x)) return 1.0;
+  return ldexp(1.0, ilogb(x));
 }
 
 // Root of c x^2 - a x + b = 0 inside (lo, hi); returns false when none is.
@@ -363,56 +351,78 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
   // LANE: the wave's roots r0 .. r1 are reflected indices ilo .. ihi
   const int r1 = (r0 + 63 < K - 1) ? r0 + 63 : K - 1;
   const int ilo = R.refl ? K - 1 - r1 : r0, ihi = R.refl ? K - 1 - r0 : r1;
+  // Work in units of S, a power of two near the largest |pole|, when that lies
+  // outside [2^-500, 2^500]: poles and weights divided by S (exactly) keep
+  // every sum and quadratic away from overflow and underflow; the roots are
+  // scaled back at the end. In between S = 1 and nothing is rescaled.
+  const double pmax = fmax(fabs(gld(g)), fabs(gld(g + K - 1)));   // the poles ascend
+  const bool scaled = pmax != 0.0 && (pmax < 0x1p-500 || pmax > 0x1p500);
+  const double S = scaled ? fmax(length_unit(pmax), 0x1p-1000) : 1.0;
+  const double sc = 1.0 / S;
+  auto pole = [&](int k) { return R.pole(k) * sc; };
+  auto wt = [&](int k) { return R.wt(k) * sc; };
   auto sums = [&](double po, double tau) -> SecSums {
-    if (LANE)
-      return R.refl ? secular_lane_sums_t<true>(R, i, ilo, ihi, po, tau)
-                    : secular_lane_sums_t<false>(R, i, ilo, ihi, po, tau);
-    return secular_sums(R, i, po, tau, lane);
+    if (LANE) {
+      if (scaled)
+        return R.refl ? secular_lane_sums_t<true, true>(R, sc, i, ilo, ihi, po, tau)
+                      : secular_lane_sums_t<false, true>(R, sc, i, ilo, ihi, po, tau);
+      return R.refl ? secular_lane_sums_t<true, false>(R, sc, i, ilo, ihi, po, tau)
+                    : secular_lane_sums_t<false, false>(R, sc, i, ilo, ihi, po, tau);
+    }
+    if (scaled)
+      return R.refl ? secular_sums_t<true, true>(R, sc, i, po, tau, lane)
+                    : secular_sums_t<false, true>(R, sc, i, po, tau, lane);
+    return R.refl ? secular_sums_t<true, false>(R, sc, i, po, tau, lane)
+                  : secular_sums_t<false, false>(R, sc, i, po, tau, lane);
   };
 
   int o;
   double lo, hi, tau;
   if (i < K - 1) {
-    const double pi = R.pole(i), pi1 = R.pole(i + 1);
+    const double pi = pole(i), pi1 = pole(i + 1);
     const double gap = pi1 - pi;
     const double half = 0.5 * gap;
     const SecSums m = sums(pi, half);
     const double fmid = rinv + m.psi + m.phi;
-    const double qi = R.wt(i), qi1 = R.wt(i + 1);
+    const double qi = wt(i), qi1 = wt(i + 1);
     // two-pole model at the midpoint: c + qi/(pi - x) + qi1/(pi1 - x)
     const double c = fmid + qi / half - qi1 / half;
+    // the same model in units of sg (exact scaling; see length_unit)
+    const double sg = length_unit(gap);
+    const double gs = gap / sg, qs = qi / sg, q1s = qi1 / sg;
     double a, b;
     if (fmid >= 0.0) {
       o = i;
       lo = 0.0;
       hi = half;
-      a = c * gap + qi + qi1;
-      b = qi * gap;
+      a = c * gs + qs + q1s;
+      b = qs * gs;
     } else {
       o = i + 1;
       lo = -half;
       hi = 0.0;
-      a = -c * gap + qi + qi1;
-      b = -qi1 * gap;
+      a = -c * gs + qs + q1s;
+      b = -q1s * gs;
     }
-    if (!quad_root_in(c, a, b, lo, hi, &tau)) tau = 0.5 * (lo + hi);
+    double ts = 0.0;
+    tau = quad_root_in(c, a, b, lo / sg, hi / sg, &ts) ? ts * sg : 0.5 * (lo + hi);
     if (fmid == 0.0) tau = (o == i) ? half : -half;
   } else {
     o = K - 1;
     double w = 0.0;
     if (LANE) {
-      for (int k = 0; k < K; ++k) w += R.wt(k);
+      for (int k = 0; k < K; ++k) w += wt(k);
     } else {
-      for (int k = lane; k < K; k += 64) w += R.wt(k);
+      for (int k = lane; k < K; k += 64) w += wt(k);
       w = wave_sum(w);
     }
     lo = 0.0;
     hi = rho * w;
     tau = 0.5 * hi;
   }
-  const double po = R.pole(o);
-  const double dl = (i < K - 1 || true) ? (R.pole(i) - po) : 0.0;       // left pole offset
-  const double dr = (i < K - 1) ? (R.pole(i + 1) - po) : 0.0;          // right pole offset
+  const double po = pole(o);
+  const double dl = pole(i) - po;                          // left pole offset
+  const double dr = (i < K - 1) ? (pole(i + 1) - po) : 0.0;  // right pole offset
   bool done = false;
   int it = 0;
   for (; it < maxit; ++it) {
@@ -426,15 +436,22 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
     bool ok;
     const double dL = dl - tau;
     if (i < K - 1) {
+      // the middle-way quadratic in units of su (exact scaling; see length_unit)
       const double dR = dr - tau;
-      const double c = f - dL * s.dpsi - dR * s.dphi;
-      const double a = f * (dL + dR) - dL * dR * (s.dpsi + s.dphi);
-      const double b = dL * dR * f;
-      ok = quad_root_in(c, a, b, lo - tau, hi - tau, &eta);
+      const double su = length_unit(fmax(fabs(dL), fabs(dR)));
+      const double dLs = dL / su, dRs = dR / su, dps = s.dpsi * su, dfs = s.dphi * su;
+      const double c = f - dLs * dps - dRs * dfs;
+      const double a = f * (dLs + dRs) - dLs * dRs * (dps + dfs);
+      const double b = dLs * dRs * f;
+      double es = 0.0;
+      ok = quad_root_in(c, a, b, (lo - tau) / su, (hi - tau) / su, &es);
+      eta = es * su;
     } else {
-      const double c = f - dL * s.dpsi;
+      const double su = length_unit(dL);
+      const double dLs = dL / su, dps = s.dpsi * su;
+      const double c = f - dLs * dps;
       ok = c > 0.0;
-      eta = ok ? dL + dL * dL * s.dpsi / c : 0.0;
+      eta = ok ? (dLs + dLs * dLs * dps / c) * su : 0.0;
     }
     if (!ok || f * eta >= 0.0) eta = -f / (s.dpsi + s.dphi);
     double tn = tau + eta;
@@ -450,7 +467,7 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
     if (!done) atomicOr(status, (int)kStNoConv);
     const int ow = R.refl ? K - 1 - o : o;
     org[idx] = ow;
-    tau_out[idx] = R.refl ? -tau : tau;
+    tau_out[idx] = (R.refl ? -tau : tau) * S;
     if (iters) iters[idx] = it + 1;
   }
 }
@@ -525,12 +542,12 @@ __device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restr
   double inv = 1.0;
   if (scaled) {
     mx = 0.0;
-    for (int k = lane; k < K; k += 64) mx = fmax(mx, fabs(gld(what + k) * recip((gld(g + k) - go) - ti)));
+    for (int k = lane; k < K; k += 64) mx = fmax(mx, fabs(div_by(gld(what + k), (gld(g + k) - go) - ti)));
     mx = wave_max(mx);
     inv = (mx > 0.0) ? 1.0 / mx : 1.0;
     ss = 0.0;
     for (int k = lane; k < K; k += 64) {
-      const double t = gld(what + k) * recip((gld(g + k) - go) - ti) * inv;
+      const double t = div_by(gld(what + k), (gld(g + k) - go) - ti) * inv;
       ss += t * t;
     }
   }

@@ -113,6 +113,40 @@ def test_secular_full_size_sampled_roots(lib):
         assert np.all(np.abs(tau_g[idx] - tau_o) <= tol)
 
 
+# Power-of-two scales that put every pole difference below 2^-1000, the range
+# where the kernels' fast reciprocal gives way to the exact one (and the column
+# norms to their scaled form). Scaling poles by S and z by sqrt(S) is exact and
+# scales every root by S, so the unscaled oracle stays the reference.
+TINY_S, TINY_R = 2.0 ** -1004, 2.0 ** -502
+
+
+def _spaced_poles(K, hi, rng):
+    """Poles at least hi / (2K) apart, so that the scaled gaps stay normal numbers."""
+    return (np.arange(K) + 0.5 * rng.uniform(size=K)) * hi / K
+
+
+@pytest.mark.parametrize("K", [64, 1000, 2100])
+@pytest.mark.parametrize("rho", [0.8, -0.8])
+def test_secular_roots_below_reciprocal_range(lib, K, rho):
+    """One root per lane (K <= 2048) and one per wave (K = 2100) on the
+    exact-reciprocal path: roots equal 2^-1004 times the oracle's roots of the
+    unscaled problem."""
+    rng = np.random.default_rng(K + 7)
+    d = _spaced_poles(K, 5.0, rng)
+    z = rng.choice([-1.0, 1.0], K) * rng.uniform(0.5, 1.5, K) / np.sqrt(K)
+    org_g, tau_g, its = lib.secular(dev(d * TINY_S), dev(z * TINY_R), rho)
+    org_g, tau_g = host(org_g).astype(np.int64), host(tau_g) / TINY_S
+    defl = O.deflate(d, z, rho)
+    assert defl.g.shape[0] == K
+    org_o, tau_o = O.secular_roots(defl.g, defl.W, rho)
+    mu_g, mu_o = d[org_g] + tau_g, d[org_o] + tau_o
+    same = org_g == org_o
+    tol = 64 * K * U64 * np.abs(tau_o) + 4 * U64 * np.abs(mu_o)
+    assert np.all(np.abs(tau_g - tau_o)[same] <= tol[same])
+    assert np.all(np.abs(mu_g - mu_o)[~same] <= tol[~same])
+    assert int(host(its).max()) < 60
+
+
 # ---------------------------------------------------------------------------
 # one eigen-update
 # ---------------------------------------------------------------------------
@@ -155,6 +189,28 @@ def test_eig_update_matches_oracle(lib, R, N, rho, variant):
     assert err <= 1e-9 * max(1.0, np.max(np.abs(X)))
     # the product is exactly X times the GPU's own C~ (same kernels) to rounding
     assert np.max(np.abs(Xo - X @ Ci)) <= 1e-12 * max(1.0, np.max(np.abs(X))) * np.sqrt(N)
+
+
+@pytest.mark.parametrize("R,N", [(64, 300), (40, 2100)])
+@pytest.mark.parametrize("rho", [0.9, -0.6])
+def test_eig_update_below_reciprocal_range(lib, R, N, rho):
+    """Poles scaled by 2^-1004 and z by 2^-502: the secular sums, Loewner
+    weights, column norms (scaled form) and product tiles (general entry) all
+    meet differences below 2^-1000. Eigenvalues are 2^-1004 times the oracle's
+    on the unscaled problem; eigenvector products are the same."""
+    rng = np.random.default_rng(N + 11)
+    lam = _spaced_poles(N, 3.0, rng)
+    z = rng.standard_normal(N) / np.sqrt(N)
+    X = rng.standard_normal((R, N))
+    Xo, lo, fl = lib.eig_update(dev(X), dev(lam * TINY_S), dev(z * TINY_R), rho)
+    Xo, lo, fl = host(Xo), host(lo) / TINY_S, host(fl)
+    st = O.rank_one_update_z(X, lam, z, rho)
+    assert np.array_equal(fl, st.flags)
+    assert np.max(np.abs(lo - st.lam)) <= 1e-13 * np.max(np.abs(lam))
+    ok = _separated(st.lam)
+    Xa = _align_cols(st.X, Xo)
+    assert np.any(ok)
+    assert np.max(np.abs(Xa - st.X)[:, ok]) <= 1e-9 * np.max(np.abs(X))
 
 
 # ---------------------------------------------------------------------------
