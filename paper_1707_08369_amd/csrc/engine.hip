@@ -303,7 +303,7 @@ StageLevel build_level(const std::vector<Stage>& st_in, const std::vector<TmvJob
     tv.push_back(i < (int)tv_in.size() ? tv_in[i] : TmvJob{0, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}});
     bw.push_back(cdiv(st_in[i].N, 4));
     bt.push_back(cdiv(st_in[i].N, 256));
-    bs.push_back(st_in[i].N <= kSecLaneMaxN ? cdiv(st_in[i].N, 256) : cdiv(st_in[i].N, 4));
+    bs.push_back(st_in[i].N <= kLaneMaxN ? cdiv(st_in[i].N, 256) : cdiv(st_in[i].N, 4));
   }
   const std::vector<int> ow = prefix(bw), ot = prefix(bt), os = prefix(bs);
   StageLevel S;
@@ -312,10 +312,10 @@ StageLevel build_level(const std::vector<Stage>& st_in, const std::vector<TmvJob
   S.tmv = B.put(tv);
   S.boff_w = B.put(ow);
   S.boff_t = B.put(ot);
-  S.boff_s = B.put(os);
+  S.boff_i = B.put(os);
   S.blocks_w = ow.back();
   S.blocks_t = ot.back();
-  S.blocks_s = os.back();
+  S.blocks_i = os.back();
   return S;
 }
 

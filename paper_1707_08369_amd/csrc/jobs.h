@@ -35,9 +35,11 @@ struct TmvJob {
 // three launch shapes used by the stage kernels: one block per job
 // (deflation), one wave per root or pole (4 per block), one thread per index
 // (256 per block).
-// Secular solves of eigenproblems up to this order run one root per lane
-// (many short sums per wave); larger ones one root per wave.
-constexpr int kSecLaneMaxN = 2048;
+// The kernels that sum over all K poles or roots for each of K items (secular
+// roots, Loewner weights, column norms, transposed Cauchy products) take one
+// item per lane for eigenproblems up to this order (many short sums per wave)
+// and one item per wave above it.
+constexpr int kLaneMaxN = 2048;
 
 struct StageLevel {
   int n = 0;
@@ -45,8 +47,8 @@ struct StageLevel {
   const TmvJob* tmv = nullptr;   // n entries, or nullptr
   const int* boff_w = nullptr;   // ceil(N / 4) blocks per job
   const int* boff_t = nullptr;   // ceil(N / 256) blocks per job
-  const int* boff_s = nullptr;   // secular solve: ceil(N / 256) if N <= kSecLaneMaxN, else ceil(N / 4)
-  int blocks_w = 0, blocks_t = 0, blocks_s = 0;
+  const int* boff_i = nullptr;   // item kernels: ceil(N / 256) if N <= kLaneMaxN, else ceil(N / 4)
+  int blocks_w = 0, blocks_t = 0, blocks_i = 0;
 };
 
 // One product X_out = X C~ in the tile grid of the list's tile shape.

@@ -32,18 +32,18 @@ __device__ void householder_dots_body(const Stage& s, int nv, const double* x0, 
   s.hx[3 * c + 2] = a2;
 }
 
-// One pass of y = C~^T x over the rows of a live column, NV vectors. Lane l
-// takes rows l, l + 64, ... in order; a zero weight adds a signed zero, which
-// leaves the sum as it is. The fast pass records whether any nonzero weight
-// met a |delta| below recip_fast's range; the exact pass (div_by) then repeats
-// it with the same terms in the same order.
-template <int NV, bool EXACT>
+// One pass of y = C~^T x over the rows of a live column, NV vectors, rows
+// j0, j0 + STEP, ... in order; a zero weight adds a signed zero, which leaves
+// the sum as it is. The fast pass records whether any nonzero weight met a
+// |delta| below recip_fast's range; the exact pass (div_by) then repeats it
+// with the same terms in the same order.
+template <int NV, bool EXACT, int STEP>
 __device__ inline void tmv_pass(const CauchyDesc& d, const ColDesc& cd, const double* x0, const double* x1,
-                                const double* x2, int lane, double (&acc)[3], bool* tiny) {
+                                const double* x2, int j0, double (&acc)[3], bool* tiny) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   bool t = false;
 #pragma unroll 4
-  for (int j = lane; j < d.N; j += 64) {
+  for (int j = j0; j < d.N; j += STEP) {
     const double z = gld(d.rzeta + j);
     const double del = (gld(d.rg + j) - cd.o) - cd.t;
     double w;
@@ -64,14 +64,20 @@ __device__ inline void tmv_pass(const CauchyDesc& d, const ColDesc& cd, const do
   *tiny = t;
 }
 
-template <int NV>
+// LANE = false: the wave shares the column (lanes over rows, summed across
+// the wave afterwards); LANE = true: the lane adds every row itself.
+template <int NV, bool LANE>
 __device__ inline void tmv_live(const CauchyDesc& d, const ColDesc& cd, const double* x0, const double* x1,
                                 const double* x2, int lane, double (&acc)[3]) {
+  constexpr int STEP = LANE ? 1 : 64;
+  const int j0 = LANE ? 0 : lane;
   bool tiny = false;
-  tmv_pass<NV, false>(d, cd, x0, x1, x2, lane, acc, &tiny);
-  if (__any(tiny)) tmv_pass<NV, true>(d, cd, x0, x1, x2, lane, acc, &tiny);
+  tmv_pass<NV, false, STEP>(d, cd, x0, x1, x2, j0, acc, &tiny);
+  if (LANE ? tiny : __any(tiny)) tmv_pass<NV, true, STEP>(d, cd, x0, x1, x2, j0, acc, &tiny);
 }
 
+// Column c of y = C~^T x, for the wave (LANE = false) or this lane (true).
+template <bool LANE>
 __device__ void cauchy_tmatvec_body(const CauchyDesc& d, const double* __restrict__ hx, int nv,
                                     const double* __restrict__ x0, const double* __restrict__ x1,
                                     const double* __restrict__ x2, double* y0, double* y1, double* y2, int c) {
@@ -82,20 +88,20 @@ __device__ void cauchy_tmatvec_body(const CauchyDesc& d, const double* __restric
   if (cd.type == 0) {
     double acc[3];
     if (nv > 2)
-      tmv_live<3>(d, cd, x0, x1, x2, lane, acc);
+      tmv_live<3, LANE>(d, cd, x0, x1, x2, lane, acc);
     else if (nv > 1)
-      tmv_live<2>(d, cd, x0, x1, x2, lane, acc);
+      tmv_live<2, LANE>(d, cd, x0, x1, x2, lane, acc);
     else
-      tmv_live<1>(d, cd, x0, x1, x2, lane, acc);
-    const double a0 = wave_sum(acc[0]);
-    const double a1 = nv > 1 ? wave_sum(acc[1]) : 0.0;
-    const double a2 = nv > 2 ? wave_sum(acc[2]) : 0.0;
-    if (lane == 0) {
+      tmv_live<1, LANE>(d, cd, x0, x1, x2, lane, acc);
+    const double a0 = LANE ? acc[0] : wave_sum(acc[0]);
+    const double a1 = nv > 1 ? (LANE ? acc[1] : wave_sum(acc[1])) : 0.0;
+    const double a2 = nv > 2 ? (LANE ? acc[2] : wave_sum(acc[2])) : 0.0;
+    if (LANE || lane == 0) {
       y0[c] = cd.s * a0;
       if (nv > 1) y1[c] = cd.s * a1;
       if (nv > 2) y2[c] = cd.s * a2;
     }
-  } else if (lane == 0 && cd.mem >= 0 && cd.mem < d.N) {
+  } else if ((LANE || lane == 0) && cd.mem >= 0 && cd.mem < d.N) {
     const bool hh = cd.h != 0.0 && cd.cl >= 0 && cd.cl < d.N;
     y0[c] = x0[cd.mem] - (hh ? 2.0 * cd.h * hx[3 * cd.cl] : 0.0);
     if (nv > 1) y1[c] = x1[cd.mem] - (hh ? 2.0 * cd.h * hx[3 * cd.cl + 1] : 0.0);
@@ -115,20 +121,24 @@ __global__ void householder_dots(StageLevel L) {
 }
 
 __global__ __launch_bounds__(256) void cauchy_tmatvec_kernel(StageLevel L) {
-  const int j = find_job(L.boff_w, L.n, blockIdx.x);
+  const int j = find_job(L.boff_i, L.n, blockIdx.x);
   const TmvJob t = L.tmv[j];
   if (t.nv <= 0) return;
   const Stage s = L.st[j];
   const double* x1 = t.nv > 1 ? t.x[1] : t.x[0];
   const double* x2 = t.nv > 2 ? t.x[2] : t.x[0];
-  cauchy_tmatvec_body(desc_of(s), s.hx, t.nv, t.x[0], x1, x2, t.y[0], t.y[1], t.y[2],
-                      (blockIdx.x - L.boff_w[j]) * 4 + (threadIdx.x >> 6));
+  const int b = blockIdx.x - L.boff_i[j];
+  if (s.N <= kLaneMaxN)
+    cauchy_tmatvec_body<true>(desc_of(s), s.hx, t.nv, t.x[0], x1, x2, t.y[0], t.y[1], t.y[2], b * 256 + threadIdx.x);
+  else
+    cauchy_tmatvec_body<false>(desc_of(s), s.hx, t.nv, t.x[0], x1, x2, t.y[0], t.y[1], t.y[2],
+                               b * 4 + (threadIdx.x >> 6));
 }
 
 void launch_cauchy_tmatvec_level(const StageLevel& L, hipStream_t st) {
-  if (L.n <= 0 || !L.tmv || L.blocks_w <= 0) return;
+  if (L.n <= 0 || !L.tmv || L.blocks_i <= 0) return;
   hipLaunchKernelGGL(householder_dots, dim3(L.blocks_t), dim3(256), 0, st, L);
-  hipLaunchKernelGGL(cauchy_tmatvec_kernel, dim3(L.blocks_w), dim3(256), 0, st, L);
+  hipLaunchKernelGGL(cauchy_tmatvec_kernel, dim3(L.blocks_i), dim3(256), 0, st, L);
 }
 
 }  // namespace svdu

@@ -473,27 +473,31 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Loewner weights, one pole per wave (lanes over roots), reflected for rho<0:
+// Loewner weights, reflected for rho<0:
 // |w_j|^2 = prod_i (mu_i - d_j) / (rho prod_{k != j} (d_k - d_j)), as K ratios
 // in (0, 1] pairing root i with pole i (i < j) or i+1 (i >= j), last with rho.
+// LANE = false: pole `idx` belongs to the wave (lanes over roots); LANE =
+// true: to this lane, which multiplies all K ratios in order.
 // ---------------------------------------------------------------------------
+template <bool LANE>
 __device__ void loewner_body(const int* __restrict__ Kdev, const double* __restrict__ g,
                              const double* __restrict__ rhop, const int* __restrict__ org,
                              const double* __restrict__ tau, double* __restrict__ what, const int* status,
-                             int wave) {
+                             int idx) {
   if (*status & kStFatal) return;
   const int K = *Kdev;
   const int lane = threadIdx.x & 63;
-  if (wave >= K) return;
+  if (idx >= K) return;
+  const int k0 = LANE ? 0 : lane, step = LANE ? 1 : 64;
   const double rho0 = *rhop;
   const bool refl = rho0 < 0.0;
   const double rho = fabs(rho0);
   Reflect R{g, nullptr, K, refl};
-  const int jr = refl ? K - 1 - wave : wave;  // pole index in the reflected problem
+  const int jr = refl ? K - 1 - idx : idx;  // pole index in the reflected problem
   const double pj = R.pole(jr);
   double prod = 1.0;
-  #pragma unroll 4
-  for (int ir = lane; ir < K; ir += 64) {   // branch-free body
+#pragma unroll 4
+  for (int ir = k0; ir < K; ir += step) {   // branch-free body
     const int io = refl ? K - 1 - ir : ir;
     const int o = gld(org + io);
     const double tv = gld(tau + io);
@@ -504,14 +508,16 @@ __device__ void loewner_body(const int* __restrict__ Kdev, const double* __restr
     const double den = (ir == K - 1) ? rho : (R.pole(pr) - pj);
     prod *= num / den;
   }
-  prod = wave_prod(prod);
-  if (lane == 0) what[wave] = sqrt(fabs(prod));
+  if (!LANE) prod = wave_prod(prod);
+  if (LANE || lane == 0) what[idx] = sqrt(fabs(prod));
 }
 
 // ---------------------------------------------------------------------------
 // Column scales 1/|c_i| with |c_i|^2 = sum_k what_k^2 / delta_ki^2, and mu.
-// One root per wave, two passes (max, then scaled sum of squares).
+// LANE = false: root i belongs to the wave (lanes over poles); LANE = true: to
+// this lane, which adds all K terms in order.
 // ---------------------------------------------------------------------------
+template <bool LANE>
 __device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restrict__ g,
                              const double* __restrict__ what, const int* __restrict__ org,
                              const double* __restrict__ tau, double* __restrict__ cs, double* __restrict__ mu,
@@ -520,6 +526,7 @@ __device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restr
   const int K = *Kdev;
   const int lane = threadIdx.x & 63;
   if (i >= K) return;
+  const int k0 = LANE ? 0 : lane, step = LANE ? 1 : 64;
   const double go = g[org[i]];
   const double ti = tau[i];
   // One branch-free pass for the largest term and the unscaled sum of
@@ -530,29 +537,29 @@ __device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restr
   double mx = 0.0, ss = 0.0;
   bool tiny = false;
 #pragma unroll 4
-  for (int k = lane; k < K; k += 64) {
+  for (int k = k0; k < K; k += step) {
     const double del = (gld(g + k) - go) - ti;
     tiny |= recip_tiny(del);
     const double t = gld(what + k) * recip_fast(del);
     mx = fmax(mx, fabs(t));
     ss = __builtin_fma(t, t, ss);
   }
-  mx = wave_max(mx);
-  const bool scaled = __any(tiny) || !(mx >= 0x1p-450 && mx <= 0x1p450);
+  if (!LANE) mx = wave_max(mx);
+  const bool scaled = (LANE ? tiny : __any(tiny)) || !(mx >= 0x1p-450 && mx <= 0x1p450);
   double inv = 1.0;
   if (scaled) {
     mx = 0.0;
-    for (int k = lane; k < K; k += 64) mx = fmax(mx, fabs(div_by(gld(what + k), (gld(g + k) - go) - ti)));
-    mx = wave_max(mx);
+    for (int k = k0; k < K; k += step) mx = fmax(mx, fabs(div_by(gld(what + k), (gld(g + k) - go) - ti)));
+    if (!LANE) mx = wave_max(mx);
     inv = (mx > 0.0) ? 1.0 / mx : 1.0;
     ss = 0.0;
-    for (int k = lane; k < K; k += 64) {
+    for (int k = k0; k < K; k += step) {
       const double t = div_by(gld(what + k), (gld(g + k) - go) - ti) * inv;
       ss += t * t;
     }
   }
-  ss = wave_sum(ss);
-  if (lane == 0) {
+  if (!LANE) ss = wave_sum(ss);
+  if (LANE || lane == 0) {
     cs[i] = (mx > 0.0) ? inv / sqrt(ss) : 0.0;
     mu[i] = go + ti;
   }
@@ -631,13 +638,14 @@ __global__ __launch_bounds__(kDeflThreads) void deflate_kernel(StageLevel L) {
   if (s.N > 0) deflate_body(s);
 }
 
-// Problems with N <= kSecLaneMaxN take one root per lane (256 per block),
-// larger ones one root per wave (4 per block); the host sizes boff_s to match.
+// Item kernels: problems with N <= kLaneMaxN take one item per lane (256 per
+// block), larger ones one item per wave (4 per block); the host sizes boff_i
+// to match.
 __global__ __launch_bounds__(256) void secular_kernel(StageLevel L, int maxit) {
-  const int j = find_job(L.boff_s, L.n, blockIdx.x);
+  const int j = find_job(L.boff_i, L.n, blockIdx.x);
   const Stage s = L.st[j];
-  const int b = blockIdx.x - L.boff_s[j];
-  if (s.N <= kSecLaneMaxN) {
+  const int b = blockIdx.x - L.boff_i[j];
+  if (s.N <= kLaneMaxN) {
     const int r0 = b * 256 + (threadIdx.x & ~63);
     secular_body<true>(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, r0 + (threadIdx.x & 63),
                        r0);
@@ -648,17 +656,23 @@ __global__ __launch_bounds__(256) void secular_kernel(StageLevel L, int maxit) {
 }
 
 __global__ __launch_bounds__(256) void loewner_kernel(StageLevel L) {
-  const int j = find_job(L.boff_w, L.n, blockIdx.x);
+  const int j = find_job(L.boff_i, L.n, blockIdx.x);
   const Stage s = L.st[j];
-  const int wave = (blockIdx.x - L.boff_w[j]) * 4 + (threadIdx.x >> 6);
-  loewner_body(s.counts, s.g, s.rho, s.org, s.tau, s.what, s.status, wave);
+  const int b = blockIdx.x - L.boff_i[j];
+  if (s.N <= kLaneMaxN)
+    loewner_body<true>(s.counts, s.g, s.rho, s.org, s.tau, s.what, s.status, b * 256 + threadIdx.x);
+  else
+    loewner_body<false>(s.counts, s.g, s.rho, s.org, s.tau, s.what, s.status, b * 4 + (threadIdx.x >> 6));
 }
 
 __global__ __launch_bounds__(256) void colnorm_kernel(StageLevel L) {
-  const int j = find_job(L.boff_w, L.n, blockIdx.x);
+  const int j = find_job(L.boff_i, L.n, blockIdx.x);
   const Stage s = L.st[j];
-  const int wave = (blockIdx.x - L.boff_w[j]) * 4 + (threadIdx.x >> 6);
-  colnorm_body(s.counts, s.g, s.what, s.org, s.tau, s.cs, s.mu, s.status, wave);
+  const int b = blockIdx.x - L.boff_i[j];
+  if (s.N <= kLaneMaxN)
+    colnorm_body<true>(s.counts, s.g, s.what, s.org, s.tau, s.cs, s.mu, s.status, b * 256 + threadIdx.x);
+  else
+    colnorm_body<false>(s.counts, s.g, s.what, s.org, s.tau, s.cs, s.mu, s.status, b * 4 + (threadIdx.x >> 6));
 }
 
 __global__ __launch_bounds__(256) void merge_kernel(StageLevel L) {
@@ -668,16 +682,16 @@ __global__ __launch_bounds__(256) void merge_kernel(StageLevel L) {
 }
 
 void launch_secular_level(const StageLevel& L, int maxit, hipStream_t st) {
-  if (L.blocks_s <= 0) return;
-  hipLaunchKernelGGL(secular_kernel, dim3(L.blocks_s), dim3(256), 0, st, L, maxit);
+  if (L.blocks_i <= 0) return;
+  hipLaunchKernelGGL(secular_kernel, dim3(L.blocks_i), dim3(256), 0, st, L, maxit);
 }
 
 void launch_stage_level(const StageLevel& L, int maxit, hipStream_t st) {
   if (L.n <= 0 || L.blocks_w <= 0) return;
   hipLaunchKernelGGL(deflate_kernel, dim3(L.n), dim3(kDeflThreads), 0, st, L);
   launch_secular_level(L, maxit, st);
-  hipLaunchKernelGGL(loewner_kernel, dim3(L.blocks_w), dim3(256), 0, st, L);
-  hipLaunchKernelGGL(colnorm_kernel, dim3(L.blocks_w), dim3(256), 0, st, L);
+  hipLaunchKernelGGL(loewner_kernel, dim3(L.blocks_i), dim3(256), 0, st, L);
+  hipLaunchKernelGGL(colnorm_kernel, dim3(L.blocks_i), dim3(256), 0, st, L);
   hipLaunchKernelGGL(merge_kernel, dim3(L.blocks_t), dim3(256), 0, st, L);
 }
 
