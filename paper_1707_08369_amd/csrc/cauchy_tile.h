@@ -32,6 +32,15 @@ __device__ __forceinline__ ColDesc load_col(const CauchyDesc& d, int c) {
   return r;
 }
 
+// Column descriptor for the product kernels. Columns past N become live
+// columns with scale 0 and a shift far from every pole: their entries are
+// zeros from the branch-free path (and are never stored), so a ragged last
+// column tile keeps its block on that path.
+__device__ __forceinline__ ColDesc load_col_tile(const CauchyDesc& d, int c) {
+  if (c < d.N) return load_col(d, c);
+  return ColDesc{0, 0.0, -0x1p1000, 0.0, 0.0, -1, -1};
+}
+
 __device__ __forceinline__ double cauchy_entry(const CauchyDesc& d, int j, const ColDesc& c) {
   if (j >= d.N || c.type < 0) return 0.0;
   if (c.type == 0) {

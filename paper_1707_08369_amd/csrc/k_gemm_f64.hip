@@ -209,7 +209,7 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmList& L, int item, doubl
   bool live = true;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    cc[c] = load_col(J.d, n0 + 64 * c + lane);
+    cc[c] = load_col_tile(J.d, n0 + 64 * c + lane);
     live = live && cc[c].type == 0;
   }
   if (__syncthreads_and(live))
