@@ -265,38 +265,38 @@ __device__ __forceinline__ void zero_acc(fd4 (&acc)[NT]) {
 }
 
 // Coefficients src[k][rows of the wave's tiles] for k < 4 KS, zero for k >= kvalid or r >= R.
+// Branch-free: every k-step is loaded (rows clamped into range, then zeroed).
 template <int KS, int NT>
-__device__ __forceinline__ void load_b(double (&b)[KS][NT], int ksteps, int kvalid, const double* src, int R,
-                                       int r0) {
+__device__ __forceinline__ void load_b(double (&b)[KS][NT], int kvalid, const double* src, int R, int r0) {
   const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
-    if (ks < ksteps) {
-      const int k = 4 * ks + kq;
-      const bool kok = k < kvalid;
-      const double* row = src + (size_t)(kok ? k : 0) * R;
+    const int k = 4 * ks + kq;
+    const bool kok = k < kvalid;
+    const double* row = src + (size_t)(kok ? k : 0) * R;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int r = r0 + 16 * t + i;
-        const double v = gld(row + (r < R ? r : R - 1));
-        b[ks][t] = (kok && r < R) ? v : 0.0;
-      }
+    for (int t = 0; t < NT; ++t) {
+      const int r = r0 + 16 * t + i;
+      const double v = gld(row + (r < R ? r : R - 1));
+      b[ks][t] = (kok && r < R) ? v : 0.0;
     }
   }
 }
 
-// acc[t] += Op[16 rows][0 .. 4 ksteps) x b[.][t]
+// acc[t] += Op[16 rows][0 .. 4 ksteps) x b[.][t]. Every k-step is issued, those
+// past ksteps with a zero operator entry (b is zero there too), so the MFMA
+// chain has no branches and its accumulators stay in place; op must be
+// readable for all 4 KS columns.
 template <int KS, int NT>
 __device__ __forceinline__ void mfma_b(const double* op, int ld, int ksteps, const double (&b)[KS][NT],
                                        fd4 (&acc)[NT]) {
   const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
-    if (ks < ksteps) {
-      const double a = op[i * ld + 4 * ks + kq];
+    const double av = op[i * ld + 4 * ks + kq];
+    const double a = (ks < ksteps) ? av : 0.0;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ks][t], acc[t], 0, 0, 0);
-    }
+    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ks][t], acc[t], 0, 0, 0);
   }
 }
 
@@ -326,7 +326,7 @@ __device__ __forceinline__ void row_chunk(int R, int rows, int* rbeg, int* rend)
 // ---------------------------------------------------------------------------
 // P2M on the leaves: W[leaf][kk][r] = sum_{j in leaf} u_kk((g_j - c)/rad) B[j][r]
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void fmm_p2m(FmmDev F, const double* __restrict__ g, const int* status) {
+__global__ __launch_bounds__(256, 2) void fmm_p2m(FmmDev F, const double* __restrict__ g, const int* status) {
   constexpr int ld = kS + 1;
   __shared__ double op[16 * ld];   // [kk][source in leaf]
   __shared__ ChebTab T;
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void fmm_p2m(FmmDev F, const double* __restric
   for (int rt = rbeg; rt < rend; rt += kRowsPerBlock) {
     const int r0 = rt + (threadIdx.x >> 6) * 16 * kNT;
     double b[kS / 4][kNT];
-    load_b(b, ksteps, ns, F.B + (size_t)a0 * F.R, F.R, r0);
+    load_b(b, ns, F.B + (size_t)a0 * F.R, F.R, r0);
     fd4 acc[kNT];
     zero_acc(acc);
     mfma_b(op, ld, ksteps, b, acc);
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(256) void fmm_p2m(FmmDev F, const double* __restric
 // ---------------------------------------------------------------------------
 // M2M for one level: W[parent][kp][r] = sum_children sum_kc M[kp][kc] W[child][kc][r]
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void fmm_m2m(FmmDev F, int level, const int* status) {
+__global__ __launch_bounds__(256, 2) void fmm_m2m(FmmDev F, int level, const int* status) {
   __shared__ double op[2][16 * kOpLd];   // [child][kp][kc]
   __shared__ int has[2];
   __shared__ ChebTab T;
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256) void fmm_m2m(FmmDev F, int level, const int* s
     for (int q = 0; q < 2; ++q) {
       if (!has[q]) continue;
       double b[kP / 4][kNT];
-      load_b(b, ksteps, F.p, F.W + (size_t)ch[q] * kP * F.R, F.R, r0);
+      load_b(b, F.p, F.W + (size_t)ch[q] * kP * F.R, F.R, r0);
       mfma_b(op[q], kOpLd, ksteps, b, acc);
     }
     store_rows(acc, F.W + (size_t)id * kP * F.R, F.p, F.R, r0);
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(256) void fmm_m2m(FmmDev F, int level, const int* s
 // Downward pass for one level: L[T] = L2L(L[parent]) + sum_S M2L(W[S]).
 // Operators in groups of kOpsMax (L2L first); one group in LDS at a time.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void fmm_down(FmmDev F, int level, const int* status) {
+__global__ __launch_bounds__(256, 2) void fmm_down(FmmDev F, int level, const int* status) {
   __shared__ double op[kOpsMax][16 * kOpLd];
   __shared__ const double* srcp[kOpsMax];
   __shared__ double oc[kOpsMax], orad[kOpsMax];
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(256) void fmm_down(FmmDev F, int level, const int* 
       const int cnt = min(kOpsMax, nops - gi * kOpsMax);
       for (int qi = 0; qi < cnt; ++qi) {
         double b[kP / 4][kNT];
-        load_b(b, ksteps, F.p, srcp[qi], F.R, r0);
+        load_b(b, F.p, srcp[qi], F.R, r0);
         mfma_b(op[qi], kOpLd, ksteps, b, acc);
       }
     }
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(256) void fmm_down(FmmDev F, int level, const int* 
 // positions of the roots. A leaf holds at most kS = 32 poles and roots; the
 // targets are two 16-row operator blocks that share every loaded coefficient.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* __restrict__ Xo, int ldo,
+__global__ __launch_bounds__(256, 2) void fmm_leaf_eval(FmmDev F, Stage s, double* __restrict__ Xo, int ldo,
                                                       const double* __restrict__ colscale) {
   constexpr int ldu = kOpLd, ldi = kS + 1;
   __shared__ double ul[kS * ldu];               // L2P weights [target][kk]
@@ -539,7 +539,6 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ksl = (F.p + 3) / 4;
-  const bool two = nt > 16;
   const double* Lsrc = F.L + (size_t)id * kP * F.R;
   int rbeg, rend;
   row_chunk(F.R, kLeafRows, &rbeg, &rend);
@@ -550,9 +549,9 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
     zero_acc(acc1);
     {
       double b[kP / 4][kLNT];
-      load_b(b, ksl, F.p, Lsrc, F.R, r0);
+      load_b(b, F.p, Lsrc, F.R, r0);
       mfma_b(ul, ldu, ksl, b, acc0);
-      if (two) mfma_b(ul + 16 * ldu, ldu, ksl, b, acc1);
+      mfma_b(ul + 16 * ldu, ldu, ksl, b, acc1);   // rows past nt are zero
     }
     for (int gi = 0; gi < ngroups; ++gi) {
       if (ngroups > 1) {
@@ -564,9 +563,9 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
       for (int qi = 0; qi < cnt; ++qi) {
         const int ns = nns[qi], ksn = (ns + 3) / 4;
         double b[kS / 4][kLNT];
-        load_b(b, ksn, ns, F.B + (size_t)nb0[qi] * F.R, F.R, r0);
+        load_b(b, ns, F.B + (size_t)nb0[qi] * F.R, F.R, r0);
         mfma_b(inv[qi], ldi, ksn, b, acc0);
-        if (two) mfma_b(inv[qi] + 16 * ldi, ldi, ksn, b, acc1);
+        mfma_b(inv[qi] + 16 * ldi, ldi, ksn, b, acc1);
       }
     }
     // stores: 64 rows (the rows of kWavesPerStage waves) at a time through
