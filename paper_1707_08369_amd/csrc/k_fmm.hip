@@ -480,7 +480,7 @@ __global__ __launch_bounds__(256, 2) void fmm_down(FmmDev F, int level, const in
 // positions of the roots. A leaf holds at most kS = 32 poles and roots; the
 // targets are two 16-row operator blocks that share every loaded coefficient.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 2) void fmm_leaf_eval(FmmDev F, Stage s, double* __restrict__ Xo, int ldo,
+__global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* __restrict__ Xo, int ldo,
                                                       const double* __restrict__ colscale) {
   constexpr int ldu = kOpLd, ldi = kS + 1;
   __shared__ double ul[kS * ldu];               // L2P weights [target][kk]
