@@ -67,6 +67,26 @@ def test_batched_equals_single_bitwise(lib, precision):
     b.close()
 
 
+def test_batched_mixes_lane_and_wave_item_kernels(lib):
+    """Orders on both sides of 2048 in one batch: the secular, Loewner,
+    column-norm and transposed-product launches then hold jobs that take one
+    item per lane next to jobs that take one item per wave. Every problem must
+    match its single-call result bitwise and reconstruct to 1e-12."""
+    sizes = [(2100, 2100), (64, 2200), (300, 457), (1, 2049), (2049, 2049)]
+    probs = [S.make_problem(m, n, "uniform", seed=90 + i) for i, (m, n) in enumerate(sizes)]
+    items = _items(probs)
+    singles = [lib.rank1_update(*it) for it in items]
+    b = lib.Batch(items)
+    b.launch()
+    assert b.status() == [lib.SVDU_OK] * len(items)
+    for i, (s, o) in enumerate(zip(singles, b.outs)):
+        for x, y in zip(s[:3], o):
+            assert torch.equal(x, y), i
+        recon, oU, oV = _invariants(items[i], o)
+        assert recon <= 1e-12 and oU <= 1e-12 and oV <= 1e-12, (i, recon, oU, oV)
+    b.close()
+
+
 def test_batched_graph_replays_and_persistent_schedule(lib):
     probs = _mixed_problems(seed0=20)
     items = _items(probs)
