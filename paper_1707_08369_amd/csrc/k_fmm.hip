@@ -479,6 +479,10 @@ __global__ __launch_bounds__(256, 2) void fmm_down(FmmDev F, int level, const in
 // Leaves: L2P + P2P, scaled by the column scale, written to the output
 // positions of the roots. A leaf holds at most kS = 32 poles and roots; the
 // targets are two 16-row operator blocks that share every loaded coefficient.
+// Unlike the translation kernels this one declares no blocks-per-CU minimum:
+// with the whole register file available its MFMA accumulators live in AGPRs,
+// which measured about a third faster than the VGPR form that a two-block
+// bound forces (more blocks per CU did not make up for it).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* __restrict__ Xo, int ldo,
                                                       const double* __restrict__ colscale) {
