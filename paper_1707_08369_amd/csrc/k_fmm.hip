@@ -216,14 +216,28 @@ __global__ __launch_bounds__(256) void fmm_charges(int R, const double* __restri
   const int K = s.counts[0];
   const int k0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  // the group of charge k (the same for all 32 rows): one member, or several
+  // exactly equal poles
+  const int k = k0 + tx;
+  int f = 0, sz = 0, j1 = 0;
+  double z1 = 0.0;
+  if (k < K) {
+    f = gld(s.cfirst + k);
+    sz = gld(s.csize + k);
+    j1 = gld(s.col_of + gld(s.Llist + f));
+    z1 = gld(s.rzeta + j1);
+  }
   for (int rr = ty; rr < 32; rr += 8) {
-    const int r = r0 + rr, k = k0 + tx;
+    const int r = r0 + rr;
     double v = 0.0;
     if (r < R && k < K) {
-      const int f = s.cfirst[k], sz = s.csize[k];
-      for (int q = f; q < f + sz; ++q) {
-        const int j = s.col_of[s.Llist[q]];
-        v += s.rzeta[j] * X[(size_t)r * ldx + j];
+      if (sz == 1) {
+        v += z1 * gld(X + (size_t)r * ldx + j1);
+      } else {
+        for (int q = f; q < f + sz; ++q) {
+          const int j = gld(s.col_of + gld(s.Llist + q));
+          v += gld(s.rzeta + j) * gld(X + (size_t)r * ldx + j);
+        }
       }
     }
     tile[rr][tx] = v;
