@@ -62,6 +62,35 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// The same over aligned groups of G lanes (G a power of two, at most 64):
+// every lane of a group ends with the same bits, and G = 64 is the whole wave
+// in the same order as the wave_* forms.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ double group_prod(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v *= __shfl_xor(v, o, 64);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ double group_max(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v = __builtin_fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ bool group_any(bool b) {
+  int x = b ? 1 : 0;
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
+  return x != 0;
+}
+
 // Block-wide inclusive scan of one int per thread (blockDim a multiple of 64,
 // at most 4096). `sh` holds at least 64 ints of shared memory. Returns the
 // inclusive prefix; *total receives the block total.

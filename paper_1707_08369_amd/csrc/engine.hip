@@ -303,7 +303,7 @@ StageLevel build_level(const std::vector<Stage>& st_in, const std::vector<TmvJob
     tv.push_back(i < (int)tv_in.size() ? tv_in[i] : TmvJob{0, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}});
     bw.push_back(cdiv(st_in[i].N, 4));
     bt.push_back(cdiv(st_in[i].N, 256));
-    bs.push_back(st_in[i].N <= kLaneMaxN ? cdiv(st_in[i].N, 256) : cdiv(st_in[i].N, 4));
+    bs.push_back(st_in[i].N <= kGroupMaxN ? cdiv(st_in[i].N, 256 / kSmallGroup) : cdiv(st_in[i].N, 4));
   }
   const std::vector<int> ow = prefix(bw), ot = prefix(bt), os = prefix(bs);
   StageLevel S;

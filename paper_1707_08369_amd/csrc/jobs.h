@@ -36,10 +36,14 @@ struct TmvJob {
 // (deflation), one wave per root or pole (4 per block), one thread per index
 // (256 per block).
 // The kernels that sum over all K poles or roots for each of K items (secular
-// roots, Loewner weights, column norms, transposed Cauchy products) take one
-// item per lane for eigenproblems up to this order (many short sums per wave)
-// and one item per wave above it.
-constexpr int kLaneMaxN = 2048;
+// roots, Loewner weights, column norms, transposed Cauchy products) give each
+// item a group of kSmallGroup lanes for eigenproblems up to order kGroupMaxN
+// (short sums: fewer lanes per item waste less on reductions and per-item
+// logic, yet one problem alone still spreads over many waves) and a whole
+// wave above it. The choice depends on the order alone, so a problem gets
+// the same arithmetic alone and in a batch.
+constexpr int kGroupMaxN = 2048;
+constexpr int kSmallGroup = 16;
 
 struct StageLevel {
   int n = 0;
@@ -47,7 +51,7 @@ struct StageLevel {
   const TmvJob* tmv = nullptr;   // n entries, or nullptr
   const int* boff_w = nullptr;   // ceil(N / 4) blocks per job
   const int* boff_t = nullptr;   // ceil(N / 256) blocks per job
-  const int* boff_i = nullptr;   // item kernels: ceil(N / 256) if N <= kLaneMaxN, else ceil(N / 4)
+  const int* boff_i = nullptr;   // item kernels: ceil(N / (256 / kSmallGroup)) if N <= kGroupMaxN, else ceil(N / 4)
   int blocks_w = 0, blocks_t = 0, blocks_i = 0;
 };
 

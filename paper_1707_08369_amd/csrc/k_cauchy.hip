@@ -64,44 +64,42 @@ __device__ inline void tmv_pass(const CauchyDesc& d, const ColDesc& cd, const do
   *tiny = t;
 }
 
-// LANE = false: the wave shares the column (lanes over rows, summed across
-// the wave afterwards); LANE = true: the lane adds every row itself.
-template <int NV, bool LANE>
+// The column belongs to an aligned group of G lanes (lanes over rows, summed
+// across the group afterwards).
+template <int NV, int G>
 __device__ inline void tmv_live(const CauchyDesc& d, const ColDesc& cd, const double* x0, const double* x1,
-                                const double* x2, int lane, double (&acc)[3]) {
-  constexpr int STEP = LANE ? 1 : 64;
-  const int j0 = LANE ? 0 : lane;
+                                const double* x2, int sub, double (&acc)[3]) {
   bool tiny = false;
-  tmv_pass<NV, false, STEP>(d, cd, x0, x1, x2, j0, acc, &tiny);
-  if (LANE ? tiny : __any(tiny)) tmv_pass<NV, true, STEP>(d, cd, x0, x1, x2, j0, acc, &tiny);
+  tmv_pass<NV, false, G>(d, cd, x0, x1, x2, sub, acc, &tiny);
+  if (group_any<G>(tiny)) tmv_pass<NV, true, G>(d, cd, x0, x1, x2, sub, acc, &tiny);
 }
 
-// Column c of y = C~^T x, for the wave (LANE = false) or this lane (true).
-template <bool LANE>
+// Column c of y = C~^T x, for an aligned group of G lanes.
+template <int G>
 __device__ void cauchy_tmatvec_body(const CauchyDesc& d, const double* __restrict__ hx, int nv,
                                     const double* __restrict__ x0, const double* __restrict__ x1,
                                     const double* __restrict__ x2, double* y0, double* y1, double* y2, int c) {
   if (*d.status & kStFatal) return;
-  const int lane = threadIdx.x & 63;
+  const int sub = threadIdx.x & (G - 1);
   if (c >= d.N) return;
   const ColDesc cd = load_col(d, c);
   if (cd.type == 0) {
     double acc[3];
     if (nv > 2)
-      tmv_live<3, LANE>(d, cd, x0, x1, x2, lane, acc);
+      tmv_live<3, G>(d, cd, x0, x1, x2, sub, acc);
     else if (nv > 1)
-      tmv_live<2, LANE>(d, cd, x0, x1, x2, lane, acc);
+      tmv_live<2, G>(d, cd, x0, x1, x2, sub, acc);
     else
-      tmv_live<1, LANE>(d, cd, x0, x1, x2, lane, acc);
-    const double a0 = LANE ? acc[0] : wave_sum(acc[0]);
-    const double a1 = nv > 1 ? (LANE ? acc[1] : wave_sum(acc[1])) : 0.0;
-    const double a2 = nv > 2 ? (LANE ? acc[2] : wave_sum(acc[2])) : 0.0;
-    if (LANE || lane == 0) {
+      tmv_live<1, G>(d, cd, x0, x1, x2, sub, acc);
+    const double a0 = group_sum<G>(acc[0]);
+    const double a1 = nv > 1 ? group_sum<G>(acc[1]) : 0.0;
+    const double a2 = nv > 2 ? group_sum<G>(acc[2]) : 0.0;
+    if (sub == 0) {
       y0[c] = cd.s * a0;
       if (nv > 1) y1[c] = cd.s * a1;
       if (nv > 2) y2[c] = cd.s * a2;
     }
-  } else if ((LANE || lane == 0) && cd.mem >= 0 && cd.mem < d.N) {
+  } else if (sub == 0 && cd.mem >= 0 && cd.mem < d.N) {
     const bool hh = cd.h != 0.0 && cd.cl >= 0 && cd.cl < d.N;
     y0[c] = x0[cd.mem] - (hh ? 2.0 * cd.h * hx[3 * cd.cl] : 0.0);
     if (nv > 1) y1[c] = x1[cd.mem] - (hh ? 2.0 * cd.h * hx[3 * cd.cl + 1] : 0.0);
@@ -128,11 +126,12 @@ __global__ __launch_bounds__(256) void cauchy_tmatvec_kernel(StageLevel L) {
   const double* x1 = t.nv > 1 ? t.x[1] : t.x[0];
   const double* x2 = t.nv > 2 ? t.x[2] : t.x[0];
   const int b = blockIdx.x - L.boff_i[j];
-  if (s.N <= kLaneMaxN)
-    cauchy_tmatvec_body<true>(desc_of(s), s.hx, t.nv, t.x[0], x1, x2, t.y[0], t.y[1], t.y[2], b * 256 + threadIdx.x);
+  if (s.N <= kGroupMaxN)
+    cauchy_tmatvec_body<kSmallGroup>(desc_of(s), s.hx, t.nv, t.x[0], x1, x2, t.y[0], t.y[1], t.y[2],
+                                     b * (256 / kSmallGroup) + threadIdx.x / kSmallGroup);
   else
-    cauchy_tmatvec_body<false>(desc_of(s), s.hx, t.nv, t.x[0], x1, x2, t.y[0], t.y[1], t.y[2],
-                               b * 4 + (threadIdx.x >> 6));
+    cauchy_tmatvec_body<64>(desc_of(s), s.hx, t.nv, t.x[0], x1, x2, t.y[0], t.y[1], t.y[2],
+                            b * 4 + (threadIdx.x >> 6));
 }
 
 void launch_cauchy_tmatvec_level(const StageLevel& L, hipStream_t st) {

@@ -240,59 +240,25 @@ __device__ inline void secular_range(const Reflect& R, double sc, int k0, int k1
 }
 
 // Sums over poles at x = P(o) + tau: psi/dpsi over poles k <= i, phi/dphi over
-// k > i, with one root per wave. Lane l takes k = l, l + 64, ... in increasing
-// order; the poles k <= i and k > i run as two loops and the reflection is a
-// template parameter, so the loops are branch-free and keep several loads in
-// flight. A wave that meets a |delta| below recip_fast's range repeats the
-// sums in the exact form, with the same terms in the same order.
-template <bool REFL, bool SC>
-__device__ inline SecSums secular_sums_t(const Reflect& R, double sc, int i, double po, double tau, int lane) {
+// k > i, for a root owned by a group of G lanes. Lane `sub` of the group takes
+// k = sub, sub + G, ... in increasing order; the poles k <= i and k > i run as
+// two loops and the reflection is a template parameter, so the loops are
+// branch-free and keep several loads in flight. A group that meets a |delta|
+// below recip_fast's range repeats its sums in the exact form, with the same
+// terms in the same order.
+template <bool REFL, bool SC, int G>
+__device__ inline SecSums secular_sums_t(const Reflect& R, double sc, int i, double po, double tau, int sub) {
   double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
   bool tiny = false;
-  const int kr = (i + 1) + ((lane - (i + 1)) & 63);   // first k > i with k = lane (mod 64)
-  secular_range<REFL, SC, false, 64>(R, sc, lane, i + 1, po, tau, &psi, &dpsi, &tiny);
-  secular_range<REFL, SC, false, 64>(R, sc, kr, R.K, po, tau, &phi, &dphi, &tiny);
-  if (__any(tiny)) {
+  const int kr = (i + 1) + ((sub - (i + 1)) & (G - 1));   // first k > i with k = sub (mod G)
+  secular_range<REFL, SC, false, G>(R, sc, sub, i + 1, po, tau, &psi, &dpsi, &tiny);
+  secular_range<REFL, SC, false, G>(R, sc, kr, R.K, po, tau, &phi, &dphi, &tiny);
+  if (group_any<G>(tiny)) {
     psi = dpsi = phi = dphi = 0.0;
-    secular_range<REFL, SC, true, 64>(R, sc, lane, i + 1, po, tau, &psi, &dpsi, &tiny);
-    secular_range<REFL, SC, true, 64>(R, sc, kr, R.K, po, tau, &phi, &dphi, &tiny);
+    secular_range<REFL, SC, true, G>(R, sc, sub, i + 1, po, tau, &psi, &dpsi, &tiny);
+    secular_range<REFL, SC, true, G>(R, sc, kr, R.K, po, tau, &phi, &dphi, &tiny);
   }
-  return SecSums{wave_sum(psi), wave_sum(dpsi), wave_sum(phi), wave_sum(dphi)};
-}
-
-// The same sums with one root per lane: the lane adds all K terms itself, in
-// increasing k, and the pole index is the same in every lane of the wave.
-// Poles up to the wave's lowest root index ilo are left of all its roots and
-// poles past the highest, ihi, right of all, so only (ilo, ihi] (fewer than 64
-// poles) needs the per-lane test. A lane that meets a |delta| below
-// recip_fast's range repeats its sums in the exact form.
-template <bool REFL, bool SC, bool EXACT>
-__device__ inline void secular_lane_all(const Reflect& R, double sc, int i, int ilo, int ihi, double po, double tau,
-                                        SecSums* S, bool* tiny) {
-  double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
-  secular_range<REFL, SC, EXACT, 1>(R, sc, 0, ilo + 1, po, tau, &psi, &dpsi, tiny);
-  bool t = false;
-  for (int k = ilo + 1; k <= ihi; ++k) {
-    double p, wt;
-    sec_pole<REFL, SC>(R, k, sc, &p, &wt);
-    if (k <= i)
-      sec_add<EXACT>(wt, (p - po) - tau, &psi, &dpsi, &t);
-    else
-      sec_add<EXACT>(wt, (p - po) - tau, &phi, &dphi, &t);
-  }
-  *tiny = *tiny || t;
-  secular_range<REFL, SC, EXACT, 1>(R, sc, ihi + 1, R.K, po, tau, &phi, &dphi, tiny);
-  *S = SecSums{psi, dpsi, phi, dphi};
-}
-
-template <bool REFL, bool SC>
-__device__ inline SecSums secular_lane_sums_t(const Reflect& R, double sc, int i, int ilo, int ihi, double po,
-                                              double tau) {
-  SecSums S;
-  bool tiny = false;
-  secular_lane_all<REFL, SC, false>(R, sc, i, ilo, ihi, po, tau, &S, &tiny);
-  if (tiny) secular_lane_all<REFL, SC, true>(R, sc, i, ilo, ihi, po, tau, &S, &tiny);
-  return S;
+  return SecSums{group_sum<G>(psi), group_sum<G>(dpsi), group_sum<G>(phi), group_sum<G>(dphi)};
 }
 
 // A power of two near |x| (x finite and nonzero), else 1. Lengths divided by it
@@ -331,26 +297,23 @@ __device__ inline bool quad_root_in(double c, double a, double b, double lo, dou
 }
 
 // One root: the midpoint two-pole start, then middle-way steps safeguarded
-// by bisection. LANE = false: root `idx` belongs to the whole wave, which
-// splits the sums over its lanes. LANE = true: root `idx` belongs to this lane
-// and r0 is the first root of the wave.
-template <bool LANE>
+// by bisection. Root `idx` belongs to an aligned group of G lanes of the wave
+// (G = 64: the whole wave), which splits the sums over its lanes; every lane
+// of the group takes the same decisions from the same reduced sums.
+template <int G>
 __device__ void secular_body(const int* __restrict__ Kdev, const double* __restrict__ g,
                              const double* __restrict__ W2, const double* __restrict__ rhop,
                              int* __restrict__ org, double* __restrict__ tau_out, int* __restrict__ iters,
-                             int* status, int maxit, int idx, int r0) {
+                             int* status, int maxit, int idx) {
   if (*status & kStFatal) return;
   const int K = *Kdev;
-  const int lane = threadIdx.x & 63;
+  const int sub = threadIdx.x & (G - 1);
   if (idx >= K) return;
   const double rho0 = *rhop;
   Reflect R{g, W2, K, rho0 < 0.0};
   const double rho = fabs(rho0);
   const double rinv = 1.0 / rho;
   const int i = R.refl ? K - 1 - idx : idx;  // root index in the reflected problem
-  // LANE: the wave's roots r0 .. r1 are reflected indices ilo .. ihi
-  const int r1 = (r0 + 63 < K - 1) ? r0 + 63 : K - 1;
-  const int ilo = R.refl ? K - 1 - r1 : r0, ihi = R.refl ? K - 1 - r0 : r1;
   // Work in units of S, a power of two near the largest |pole|, when that lies
   // outside [2^-500, 2^500]: poles and weights divided by S (exactly) keep
   // every sum and quadratic away from overflow and underflow; the roots are
@@ -362,18 +325,11 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
   auto pole = [&](int k) { return R.pole(k) * sc; };
   auto wt = [&](int k) { return R.wt(k) * sc; };
   auto sums = [&](double po, double tau) -> SecSums {
-    if (LANE) {
-      if (scaled)
-        return R.refl ? secular_lane_sums_t<true, true>(R, sc, i, ilo, ihi, po, tau)
-                      : secular_lane_sums_t<false, true>(R, sc, i, ilo, ihi, po, tau);
-      return R.refl ? secular_lane_sums_t<true, false>(R, sc, i, ilo, ihi, po, tau)
-                    : secular_lane_sums_t<false, false>(R, sc, i, ilo, ihi, po, tau);
-    }
     if (scaled)
-      return R.refl ? secular_sums_t<true, true>(R, sc, i, po, tau, lane)
-                    : secular_sums_t<false, true>(R, sc, i, po, tau, lane);
-    return R.refl ? secular_sums_t<true, false>(R, sc, i, po, tau, lane)
-                  : secular_sums_t<false, false>(R, sc, i, po, tau, lane);
+      return R.refl ? secular_sums_t<true, true, G>(R, sc, i, po, tau, sub)
+                    : secular_sums_t<false, true, G>(R, sc, i, po, tau, sub);
+    return R.refl ? secular_sums_t<true, false, G>(R, sc, i, po, tau, sub)
+                  : secular_sums_t<false, false, G>(R, sc, i, po, tau, sub);
   };
 
   int o;
@@ -410,12 +366,8 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
   } else {
     o = K - 1;
     double w = 0.0;
-    if (LANE) {
-      for (int k = 0; k < K; ++k) w += wt(k);
-    } else {
-      for (int k = lane; k < K; k += 64) w += wt(k);
-      w = wave_sum(w);
-    }
+    for (int k = sub; k < K; k += G) w += wt(k);
+    w = group_sum<G>(w);
     lo = 0.0;
     hi = rho * w;
     tau = 0.5 * hi;
@@ -463,7 +415,7 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
     tau = 0.0;
     done = false;
   }
-  if (LANE || lane == 0) {
+  if (sub == 0) {
     if (!done) atomicOr(status, (int)kStNoConv);
     const int ow = R.refl ? K - 1 - o : o;
     org[idx] = ow;
@@ -476,10 +428,9 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
 // Loewner weights, reflected for rho<0:
 // |w_j|^2 = prod_i (mu_i - d_j) / (rho prod_{k != j} (d_k - d_j)), as K ratios
 // in (0, 1] pairing root i with pole i (i < j) or i+1 (i >= j), last with rho.
-// LANE = false: pole `idx` belongs to the wave (lanes over roots); LANE =
-// true: to this lane, which multiplies all K ratios in order.
+// Pole `idx` belongs to an aligned group of G lanes (lanes over roots).
 // ---------------------------------------------------------------------------
-template <bool LANE>
+template <int G>
 __device__ void loewner_body(const int* __restrict__ Kdev, const double* __restrict__ g,
                              const double* __restrict__ rhop, const int* __restrict__ org,
                              const double* __restrict__ tau, double* __restrict__ what, const int* status,
@@ -488,7 +439,7 @@ __device__ void loewner_body(const int* __restrict__ Kdev, const double* __restr
   const int K = *Kdev;
   const int lane = threadIdx.x & 63;
   if (idx >= K) return;
-  const int k0 = LANE ? 0 : lane, step = LANE ? 1 : 64;
+  const int k0 = lane & (G - 1), step = G;
   const double rho0 = *rhop;
   const bool refl = rho0 < 0.0;
   const double rho = fabs(rho0);
@@ -508,16 +459,15 @@ __device__ void loewner_body(const int* __restrict__ Kdev, const double* __restr
     const double den = (ir == K - 1) ? rho : (R.pole(pr) - pj);
     prod *= num / den;
   }
-  if (!LANE) prod = wave_prod(prod);
-  if (LANE || lane == 0) what[idx] = sqrt(fabs(prod));
+  prod = group_prod<G>(prod);
+  if (k0 == 0) what[idx] = sqrt(fabs(prod));
 }
 
 // ---------------------------------------------------------------------------
 // Column scales 1/|c_i| with |c_i|^2 = sum_k what_k^2 / delta_ki^2, and mu.
-// LANE = false: root i belongs to the wave (lanes over poles); LANE = true: to
-// this lane, which adds all K terms in order.
+// Root i belongs to an aligned group of G lanes (lanes over poles).
 // ---------------------------------------------------------------------------
-template <bool LANE>
+template <int G>
 __device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restrict__ g,
                              const double* __restrict__ what, const int* __restrict__ org,
                              const double* __restrict__ tau, double* __restrict__ cs, double* __restrict__ mu,
@@ -526,7 +476,7 @@ __device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restr
   const int K = *Kdev;
   const int lane = threadIdx.x & 63;
   if (i >= K) return;
-  const int k0 = LANE ? 0 : lane, step = LANE ? 1 : 64;
+  const int k0 = lane & (G - 1), step = G;
   const double go = g[org[i]];
   const double ti = tau[i];
   // One branch-free pass for the largest term and the unscaled sum of
@@ -544,13 +494,13 @@ __device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restr
     mx = fmax(mx, fabs(t));
     ss = __builtin_fma(t, t, ss);
   }
-  if (!LANE) mx = wave_max(mx);
-  const bool scaled = (LANE ? tiny : __any(tiny)) || !(mx >= 0x1p-450 && mx <= 0x1p450);
+  mx = group_max<G>(mx);
+  const bool scaled = group_any<G>(tiny) || !(mx >= 0x1p-450 && mx <= 0x1p450);
   double inv = 1.0;
   if (scaled) {
     mx = 0.0;
     for (int k = k0; k < K; k += step) mx = fmax(mx, fabs(div_by(gld(what + k), (gld(g + k) - go) - ti)));
-    if (!LANE) mx = wave_max(mx);
+    mx = group_max<G>(mx);
     inv = (mx > 0.0) ? 1.0 / mx : 1.0;
     ss = 0.0;
     for (int k = k0; k < K; k += step) {
@@ -558,8 +508,8 @@ __device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restr
       ss += t * t;
     }
   }
-  if (!LANE) ss = wave_sum(ss);
-  if (LANE || lane == 0) {
+  ss = group_sum<G>(ss);
+  if (k0 == 0) {
     cs[i] = (mx > 0.0) ? inv / sqrt(ss) : 0.0;
     mu[i] = go + ti;
   }
@@ -638,41 +588,40 @@ __global__ __launch_bounds__(kDeflThreads) void deflate_kernel(StageLevel L) {
   if (s.N > 0) deflate_body(s);
 }
 
-// Item kernels: problems with N <= kLaneMaxN take one item per lane (256 per
-// block), larger ones one item per wave (4 per block); the host sizes boff_i
-// to match.
+// Item kernels: problems with N <= kGroupMaxN give each item a group of
+// kSmallGroup lanes (256 / kSmallGroup items per block), larger ones a whole
+// wave (4 per block); the host sizes boff_i to match.
+__device__ __forceinline__ int small_item(int b) { return b * (256 / kSmallGroup) + threadIdx.x / kSmallGroup; }
+__device__ __forceinline__ int wave_item(int b) { return b * 4 + (threadIdx.x >> 6); }
+
 __global__ __launch_bounds__(256) void secular_kernel(StageLevel L, int maxit) {
   const int j = find_job(L.boff_i, L.n, blockIdx.x);
   const Stage s = L.st[j];
   const int b = blockIdx.x - L.boff_i[j];
-  if (s.N <= kLaneMaxN) {
-    const int r0 = b * 256 + (threadIdx.x & ~63);
-    secular_body<true>(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, r0 + (threadIdx.x & 63),
-                       r0);
-  } else {
-    const int wave = b * 4 + (threadIdx.x >> 6);
-    secular_body<false>(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, wave, wave);
-  }
+  if (s.N <= kGroupMaxN)
+    secular_body<kSmallGroup>(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, small_item(b));
+  else
+    secular_body<64>(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, wave_item(b));
 }
 
 __global__ __launch_bounds__(256) void loewner_kernel(StageLevel L) {
   const int j = find_job(L.boff_i, L.n, blockIdx.x);
   const Stage s = L.st[j];
   const int b = blockIdx.x - L.boff_i[j];
-  if (s.N <= kLaneMaxN)
-    loewner_body<true>(s.counts, s.g, s.rho, s.org, s.tau, s.what, s.status, b * 256 + threadIdx.x);
+  if (s.N <= kGroupMaxN)
+    loewner_body<kSmallGroup>(s.counts, s.g, s.rho, s.org, s.tau, s.what, s.status, small_item(b));
   else
-    loewner_body<false>(s.counts, s.g, s.rho, s.org, s.tau, s.what, s.status, b * 4 + (threadIdx.x >> 6));
+    loewner_body<64>(s.counts, s.g, s.rho, s.org, s.tau, s.what, s.status, wave_item(b));
 }
 
 __global__ __launch_bounds__(256) void colnorm_kernel(StageLevel L) {
   const int j = find_job(L.boff_i, L.n, blockIdx.x);
   const Stage s = L.st[j];
   const int b = blockIdx.x - L.boff_i[j];
-  if (s.N <= kLaneMaxN)
-    colnorm_body<true>(s.counts, s.g, s.what, s.org, s.tau, s.cs, s.mu, s.status, b * 256 + threadIdx.x);
+  if (s.N <= kGroupMaxN)
+    colnorm_body<kSmallGroup>(s.counts, s.g, s.what, s.org, s.tau, s.cs, s.mu, s.status, small_item(b));
   else
-    colnorm_body<false>(s.counts, s.g, s.what, s.org, s.tau, s.cs, s.mu, s.status, b * 4 + (threadIdx.x >> 6));
+    colnorm_body<64>(s.counts, s.g, s.what, s.org, s.tau, s.cs, s.mu, s.status, wave_item(b));
 }
 
 __global__ __launch_bounds__(256) void merge_kernel(StageLevel L) {
