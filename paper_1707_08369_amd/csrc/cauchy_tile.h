@@ -41,17 +41,6 @@ __device__ __forceinline__ ColDesc load_col_tile(const CauchyDesc& d, int c) {
   return ColDesc{0, 0.0, -0x1p1000, 0.0, 0.0, -1, -1};
 }
 
-__device__ __forceinline__ double cauchy_entry(const CauchyDesc& d, int j, const ColDesc& c) {
-  if (j >= d.N || c.type < 0) return 0.0;
-  if (c.type == 0) {
-    const double z = d.rzeta[j];
-    if (z == 0.0) return 0.0;
-    return div_by(z * c.s, (d.rg[j] - c.o) - c.t);
-  }
-  if (d.rcl[j] != c.cl) return 0.0;
-  return ((j == c.mem) ? 1.0 : 0.0) - 2.0 * d.rh[j] * c.h;
-}
-
 struct RowVals {
   double z, g, h;
   int cl;

@@ -16,9 +16,8 @@ __device__ __forceinline__ double recip_fast(double x) {
   e = __builtin_fma(-x, r, 1.0);
   return __builtin_fma(r, e, r);
 }
-// recip_fast where it applies, the IEEE divide for smaller inputs.
+// Below this |x| recip_fast is not used (1 / x may overflow there).
 __device__ __forceinline__ bool recip_tiny(double x) { return __builtin_fabs(x) < 0x1p-1000; }
-__device__ __forceinline__ double recip(double x) { return recip_tiny(x) ? 1.0 / x : recip_fast(x); }
 // num / x: num times recip_fast(x) where that applies, a true division below
 // (where 1 / x alone can overflow although num / x does not).
 __device__ __forceinline__ double div_by(double num, double x) {
@@ -51,20 +50,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
-__device__ __forceinline__ double wave_prod(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = __builtin_fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
 // The same over aligned groups of G lanes (G a power of two, at most 64):
 // every lane of a group ends with the same bits, and G = 64 is the whole wave
-// in the same order as the wave_* forms.
+// in the same order as wave_sum.
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
