@@ -22,6 +22,12 @@ HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "
             "-Wno-unused-but-set-variable"]
 
 
+# Per-source additions. The FMM kernels keep their MFMA accumulators in
+# ordinary VGPRs: in AGPRs the loop-carried accumulators of the leaf kernel's
+# k-loop were copied out and back on every trip.
+EXTRA_FLAGS = {"k_fmm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def hipcc() -> str:
     exe = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(exe):
@@ -30,7 +36,7 @@ def hipcc() -> str:
 
 
 def _compile(src: str, obj: str, verbose: bool) -> None:
-    cmd = [hipcc(), *HIPFLAGS, "-c", src, "-o", obj]
+    cmd = [hipcc(), *HIPFLAGS, *EXTRA_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

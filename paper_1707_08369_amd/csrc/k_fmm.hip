@@ -66,7 +66,30 @@ static void build_plan(int K, const double* g, const double* mu, int p, FmmHostP
   P->outlier = -1;
   for (int i = 0; i < K; ++i)
     if (mu[i] > g[K - 1] || mu[i] < g[0]) P->outlier = i;
-  auto in_box = [&](int i) { return i != P->outlier; };
+  // An extreme pole far from the others (the previous level's extreme root
+  // becomes one) would stretch its leaf across the whole gap and leave it
+  // near to almost every leaf; such a pole stays out of the box intervals,
+  // the multipole expansions and the near fields, and its charge is applied
+  // to every root directly. The root that interlaces into that gap, when it
+  // lies farther out than the span of the leaf's other poles, is evaluated
+  // directly like the extreme root.
+  P->opole = -1;
+  P->outlier2 = -1;
+  if (nlev > 0) {
+    const int la = ((K - 1) / s) * s, fe = std::min(K, s);   // first pole of the last leaf, end of the first
+    if (K - la >= 3 && g[K - 1] - g[K - 2] > g[K - 2] - g[la]) {
+      P->opole = K - 1;
+      const double lim = g[K - 2] + (g[K - 2] - g[la]);
+      for (int i = la; i < K; ++i)
+        if (i != P->outlier && mu[i] > lim) P->outlier2 = i;
+    } else if (fe >= 3 && g[1] - g[0] > g[fe - 1] - g[1]) {
+      P->opole = 0;
+      const double lim = g[1] - (g[fe - 1] - g[1]);
+      for (int i = 0; i < fe; ++i)
+        if (i != P->outlier && mu[i] < lim) P->outlier2 = i;
+    }
+  }
+  auto in_box = [&](int i) { return i != P->outlier && i != P->outlier2; };
   P->nlev = nlev;
   P->nbox = (1 << (nlev + 1)) - 1;
   P->lo.assign(P->nbox, 0.0);
@@ -81,10 +104,13 @@ static void build_plan(int K, const double* g, const double* mu, int p, FmmHostP
     P->s0[id] = a0;
     P->s1[id] = a1;
     if (a0 < a1) {
-      double lo = g[a0], hi = g[a0];
+      const int f = (a0 == P->opole && a1 > a0 + 1) ? a0 + 1 : a0;
+      double lo = g[f], hi = g[f];
       for (int i = a0; i < a1; ++i) {
-        lo = std::min(lo, g[i]);
-        hi = std::max(hi, g[i]);
+        if (i != P->opole) {
+          lo = std::min(lo, g[i]);
+          hi = std::max(hi, g[i]);
+        }
         if (in_box(i)) {
           lo = std::min(lo, mu[i]);
           hi = std::max(hi, mu[i]);
@@ -161,7 +187,9 @@ static void build_plan(int K, const double* g, const double* mu, int p, FmmHostP
 // ---------------------------------------------------------------------------
 struct FmmDev {
   int p, s, K, nlev, nbox, R;
-  int outlier;  // root evaluated directly (-1: none)
+  int droot[2];   // roots evaluated directly (-1: none)
+  int ndroot;     // how many (the first ndroot entries)
+  int opole;      // pole applied to every root directly (-1: none)
   const double* lo;
   const double* hi;
   const int* s0;
@@ -268,7 +296,6 @@ constexpr int kRowsPerBlock = 4 * 16 * kNT;
 constexpr int kOpLd = kP + 1;              // LDS row stride of a p x p operator (odd: no bank conflicts)
 constexpr int kOpsMax = 8;                 // p x p operators held in LDS at once (down pass)
 constexpr int kS = 32;                     // largest leaf
-constexpr int kNearMax = 6;                // near-field operators held in LDS at once (leaves)
 constexpr int kLNT = 4;                    // row tiles of 16 per wave in the leaf kernel
 constexpr int kLeafRows = 4 * 16 * kLNT;
 
@@ -355,7 +382,7 @@ __global__ __launch_bounds__(256, 2) void fmm_p2m(FmmDev F, const double* __rest
   __syncthreads();
   for (int e = threadIdx.x; e < 16 * kS; e += blockDim.x) {
     const int kk = e / kS, j = e % kS;
-    op[kk * ld + j] = (kk < F.p && j < ns) ? lagrange(T, kk, F.p, (g[a0 + j] - c) / rad) : 0.0;
+    op[kk * ld + j] = (kk < F.p && j < ns && a0 + j != F.opole) ? lagrange(T, kk, F.p, (g[a0 + j] - c) / rad) : 0.0;
   }
   __syncthreads();
   int rbeg, rend;
@@ -491,25 +518,82 @@ __global__ __launch_bounds__(256, 2) void fmm_down(FmmDev F, int level, const in
 
 // ---------------------------------------------------------------------------
 // Leaves: L2P + P2P, scaled by the column scale, written to the output
-// positions of the roots. A leaf holds at most kS = 32 poles and roots; the
-// targets are two 16-row operator blocks that share every loaded coefficient.
-// Unlike the translation kernels this one declares no blocks-per-CU minimum:
-// with the whole register file available its MFMA accumulators live in AGPRs,
-// which measured about a third faster than the VGPR form that a two-block
-// bound forces (more blocks per CU did not make up for it).
+// positions of the roots. For the targets t of a leaf (at most kS = 32 roots,
+// two 16-row operator blocks) both parts are one contraction,
+//   Y[t][r] = sum_kk u_kk(y_t) L[leaf][kk][r]
+//           + sum_{near boxes S} sum_{j in S} B[j][r] / ((g_j - d_org(t)) - tau_t),
+// so the block lays the L2P weights and the near-field reciprocals side by
+// side in one LDS operator table, notes the first source row of every k-step
+// of 4, and runs one k-loop in chunks of kLeafChunk k-steps: the loads of the
+// next chunk are in flight while the current one is on the matrix cores. The
+// k-steps keep the order of the parts (L2P, then the near list), and padding
+// k-steps carry zero weights on a valid row. A near list longer than
+// kLeafNearPass boxes takes further passes over the same accumulators.
+// Blocks are (leaf, 256-row group) pairs in an XCD-aware order: the blocks of
+// one XCD take consecutive leaves of one row group, whose near fields read the
+// same charge rows, in that XCD's L2. Results go from the accumulators to the
+// output directly.
+// Like the translation kernels it declares no blocks-per-CU minimum: with the
+// whole register file available the MFMA accumulators live in AGPRs.
 // ---------------------------------------------------------------------------
+constexpr int kLeafKs = 48;                  // k-steps of 4 in the operator table
+constexpr int kLeafLd = 4 * kLeafKs + 1;     // its row stride in doubles (odd: conflict-free reads)
+constexpr int kLeafChunk = 4;                // k-steps per pipelined chunk
+constexpr int kLeafNearPass = 5;             // near boxes per pass: 4 + 5 * 8 <= kLeafKs k-steps
+#ifndef LEAF_ROW_GROUPS
+#define LEAF_ROW_GROUPS 4
+#endif
+constexpr int kLeafRowGroups = LEAF_ROW_GROUPS;   // 256-row groups per block (one table build each)
+static_assert(4 + 1 + kLeafNearPass * (kS / 4) <= kLeafKs, "a pass must fit the operator table");
+static_assert(kLeafKs % (2 * kLeafChunk) == 0, "the table holds whole chunk pairs");
+
+template <int NT>
+__device__ __forceinline__ void leaf_load(double (&b)[kLeafChunk][NT], int c, const double* const* ksrc,
+                                          const int* kcnt, int R, int r0) {
+  const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int ks = 0; ks < kLeafChunk; ++ks) {
+    const int k = c * kLeafChunk + ks;
+    const double* row = ksrc[k] + (size_t)min(kq, kcnt[k] - 1) * R;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) b[ks][t] = gld(row + min(r0 + 16 * t + i, R - 1));
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void leaf_mma(const double (&b)[kLeafChunk][NT], int c, const double* op, fd4 (&acc0)[NT],
+                                         fd4 (&acc1)[NT]) {
+  const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int ks = 0; ks < kLeafChunk; ++ks) {
+    const int col = 4 * (c * kLeafChunk + ks) + kq;
+    const double a0 = op[i * kLeafLd + col], a1 = op[(16 + i) * kLeafLd + col];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      acc0[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b[ks][t], acc0[t], 0, 0, 0);
+      acc1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b[ks][t], acc1[t], 0, 0, 0);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* __restrict__ Xo, int ldo,
-                                                      const double* __restrict__ colscale) {
-  constexpr int ldu = kOpLd, ldi = kS + 1;
-  __shared__ double ul[kS * ldu];               // L2P weights [target][kk]
-  __shared__ double inv[kNearMax][kS * ldi];    // 1/delta [near box][target][source]
-  __shared__ double out[64 * (kS + 1)];         // 64 rows of results, staged for row-wise stores
-  __shared__ int nb0[kNearMax], nns[kNearMax];
+                                                      const double* __restrict__ colscale, int nrb, int rgpb) {
+  __shared__ double op[kS * kLeafLd];          // [target][column = 4 k-step + kq]
+  __shared__ const double* ksrc[kLeafKs];      // first source row of each k-step
+  __shared__ int kcnt[kLeafKs];                // its valid rows (1..4)
+  __shared__ int kseg[kLeafKs];                // -1 L2P, -3 isolated pole, q near box q of the pass, -2 padding
+  __shared__ double colg[4 * kLeafKs];         // source pole of each near-field column
+  __shared__ int nb0[kLeafNearPass], nns[kLeafNearPass], nks0[kLeafNearPass + 1];
   __shared__ int pos[kS];
-  __shared__ double scl[kS], tgo[kS], tgt[kS], srcg[kNearMax][kS];
+  __shared__ double scl[kS], tgo[kS], tgt[kS];
   __shared__ ChebTab T;
   if (*s.status & kStFatal) return;
-  const int id = box_id(F.nlev, blockIdx.x);
+  // blocks with equal index mod 8 share an XCD: give them consecutive work
+  const int nleaf = 1 << F.nlev, total = nleaf * nrb;
+  const int xcd = blockIdx.x % 8, per = total / 8, extra = total % 8;
+  const int w = xcd * per + min(xcd, extra) + blockIdx.x / 8;
+  const int leaf = w % nleaf, rb = w / nleaf;
+  const int id = box_id(F.nlev, leaf);
   const int a0 = F.s0[id], a1 = F.s1[id];
   if (a1 <= a0) return;
   const int nt = a1 - a0;
@@ -517,143 +601,201 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
   box_cr(F, id, &ct, &rt);
   cheb_fill(&T, F.p);
   const int q0 = F.near_ptr[id], nnear = F.near_ptr[id + 1] - q0;
-  const int ngroups = (nnear + kNearMax - 1) / kNearMax;
   // per target: origin pole, offset, column position and scale (one load each)
-  for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+  for (int t = threadIdx.x; t < kS; t += blockDim.x) {
     const int i = a0 + t;
-    const int P = gld(s.rootpos + i);
+    int P = -1;
+    double sc = 0.0, go = 0.0, ta = 0.0;
+    if (t < nt) {
+      P = gld(s.rootpos + i);
+      sc = (colscale ? gld(colscale + P) : 1.0) * gld(s.cs + i);
+      go = gld(s.g + gld(s.org + i));
+      ta = gld(s.tau + i);
+      if (i == F.droot[0] || i == F.droot[1]) P = -1;   // evaluated by fmm_outlier_partial / fmm_outlier_reduce
+    }
     pos[t] = P;
-    scl[t] = (colscale ? gld(colscale + P) : 1.0) * gld(s.cs + i);
-    tgo[t] = gld(s.g + gld(s.org + i));
-    tgt[t] = gld(s.tau + i);
-    if (i == F.outlier) pos[t] = -1;   // evaluated by fmm_outlier_partial / fmm_outlier_reduce
+    scl[t] = sc;
+    tgo[t] = go;
+    tgt[t] = ta;
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < kS * 16; e += blockDim.x) {
-    const int t = e >> 4, kk = e & 15;
-    ul[t * ldu + kk] =
-        (t < nt && kk < F.p && pos[t] >= 0) ? lagrange(T, kk, F.p, ((tgo[t] + tgt[t]) - ct) / rt) : 0.0;
-  }
-  auto build_group = [&](int gidx) {
-    const int o0 = gidx * kNearMax, cnt = min(kNearMax, nnear - o0);
-    for (int e = threadIdx.x; e < cnt * kS; e += blockDim.x) {
-      const int qi = e / kS, j = e % kS;
-      const int nbx = F.near_src[q0 + o0 + qi];
-      const int b0 = F.s0[nbx], ns = F.s1[nbx] - b0;
-      srcg[qi][j] = (j < ns) ? gld(s.g + b0 + j) : 0.0;
-      if (j == 0) {
-        nb0[qi] = b0;
-        nns[qi] = ns;
-      }
+  const int lane = threadIdx.x & 63, kq = lane >> 4;
+  const double* Lsrc = F.L + (size_t)id * kP * F.R;
+  const int npass = max(1, (nnear + kLeafNearPass - 1) / kLeafNearPass);
+  // operator table of one pass (all threads; starts and ends with a barrier)
+  auto build_pass = [&](int pass) {
+    const int qa = pass * kLeafNearPass, nq = min(kLeafNearPass, nnear - qa);
+    __syncthreads();   // the previous table is read by every wave
+    if (threadIdx.x < nq) {
+      const int nbx = F.near_src[q0 + qa + threadIdx.x];
+      nb0[threadIdx.x] = F.s0[nbx];
+      nns[threadIdx.x] = F.s1[nbx] - F.s0[nbx];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < cnt * kS * kS; e += blockDim.x) {
-      const int qi = e / (kS * kS), rem = e % (kS * kS), t = rem / kS, j = rem % kS;
-      inv[qi][t * ldi + j] =
-          (t < nt && j < nns[qi] && pos[t] >= 0) ? 1.0 / ((srcg[qi][j] - tgo[t]) - tgt[t]) : 0.0;
+    if (threadIdx.x == 0) {
+      // the first pass starts with the 4 L2P k-steps and the isolated pole's
+      int k = (pass == 0) ? 4 + (F.opole >= 0 ? 1 : 0) : 0;
+      for (int q = 0; q < nq; ++q) {
+        nks0[q] = k;
+        k += (nns[q] + 3) / 4;
+      }
+      nks0[nq] = k;
+      nks0[kLeafNearPass] = k;       // the pass's k-step count, for readers that do not know nq
     }
+    __syncthreads();
+    const int nks = nks0[nq];
+    const int nksp = (nks + 2 * kLeafChunk - 1) / (2 * kLeafChunk) * (2 * kLeafChunk);
+    for (int k = threadIdx.x; k < nksp; k += blockDim.x) {
+      const double* src = Lsrc;   // padding: zero weights on a written row of L
+      int cnt = 1, seg = -2;
+      if (k < nks) {
+        if (pass == 0 && k < 4) {
+          // rows kk >= p of L are never written: clamp into the first p
+          src = Lsrc + (size_t)min(4 * k, F.p - 1) * F.R;
+          cnt = max(1, min(4, F.p - 4 * k));
+          seg = -1;
+        } else if (pass == 0 && k == 4 && F.opole >= 0) {
+          src = F.B + (size_t)F.opole * F.R;
+          seg = -3;
+          for (int e = 0; e < 4; ++e) colg[4 * k + e] = e == 0 ? gld(s.g + F.opole) : 0.0;
+        } else {
+          int q = 0;
+          while (q + 1 < nq && k >= nks0[q + 1]) ++q;
+          const int j0 = 4 * (k - nks0[q]);
+          src = F.B + (size_t)(nb0[q] + j0) * F.R;
+          cnt = min(4, nns[q] - j0);
+          seg = q;
+          for (int e = 0; e < 4; ++e) colg[4 * k + e] = (j0 + e < nns[q]) ? gld(s.g + nb0[q] + j0 + e) : 0.0;
+        }
+      }
+      ksrc[k] = src;
+      kcnt[k] = cnt;
+      kseg[k] = seg;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kS * 4 * nksp; e += blockDim.x) {
+      const int t = e & (kS - 1), col = e / kS, k = col >> 2;
+      const int seg = kseg[k];
+      double v = 0.0;
+      if (t < nt && pos[t] >= 0) {
+        if (seg == -1) {
+          if (col < F.p) v = lagrange(T, col, F.p, ((tgo[t] + tgt[t]) - ct) / rt);
+        } else if (seg == -3) {
+          if ((col & 3) == 0) v = 1.0 / ((colg[col] - tgo[t]) - tgt[t]);
+        } else if (seg >= 0) {
+          const int j = 4 * (k - nks0[seg]) + (col & 3);
+          if (j < nns[seg] && nb0[seg] + j != F.opole) v = 1.0 / ((colg[col] - tgo[t]) - tgt[t]);
+        }
+      }
+      op[t * kLeafLd + col] = v;
+    }
+    __syncthreads();
   };
-  if (ngroups == 1) build_group(0);
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ksl = (F.p + 3) / 4;
-  const double* Lsrc = F.L + (size_t)id * kP * F.R;
-  int rbeg, rend;
-  row_chunk(F.R, kLeafRows, &rbeg, &rend);
-  for (int rt0 = rbeg; rt0 < rend; rt0 += kLeafRows) {
-    const int r0 = rt0 + wave * 16 * kLNT;
+  __syncthreads();   // pos, scl, tgo, tgt are read by every wave from here on
+  if (npass == 1) build_pass(0);
+  // lane l holds targets l / 16 + 4 v (acc0) and 16 + l / 16 + 4 v (acc1) of rows r0 + 16 t + l % 16
+  int P0[4], P1[4];
+  double S0[4], S1[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    P0[v] = pos[kq + 4 * v];
+    S0[v] = scl[kq + 4 * v];
+    P1[v] = pos[16 + kq + 4 * v];
+    S1[v] = scl[16 + kq + 4 * v];
+  }
+  const int rg0 = rb * rgpb, rg1 = min(rg0 + rgpb, (F.R + kLeafRows - 1) / kLeafRows);
+  for (int rg = rg0; rg < rg1; ++rg) {
+    const int r0 = rg * kLeafRows + (threadIdx.x >> 6) * 16 * kLNT;
     fd4 acc0[kLNT], acc1[kLNT];
     zero_acc(acc0);
     zero_acc(acc1);
-    {
-      double b[kP / 4][kLNT];
-      load_b(b, F.p, Lsrc, F.R, r0);
-      mfma_b(ul, ldu, ksl, b, acc0);
-      mfma_b(ul + 16 * ldu, ldu, ksl, b, acc1);   // rows past nt are zero
-    }
-    for (int gi = 0; gi < ngroups; ++gi) {
-      if (ngroups > 1) {
-        __syncthreads();
-        build_group(gi);
-        __syncthreads();
-      }
-      const int cnt = min(kNearMax, nnear - gi * kNearMax);
-      for (int qi = 0; qi < cnt; ++qi) {
-        const int ns = nns[qi], ksn = (ns + 3) / 4;
-        double b[kS / 4][kLNT];
-        load_b(b, ns, F.B + (size_t)nb0[qi] * F.R, F.R, r0);
-        mfma_b(inv[qi], ldi, ksn, b, acc0);
-        mfma_b(inv[qi] + 16 * ldi, ldi, ksn, b, acc1);
+    for (int pass = 0; pass < npass; ++pass) {
+      if (npass > 1) build_pass(pass);
+      const int nks = nks0[kLeafNearPass];
+      const int nch = (nks + 2 * kLeafChunk - 1) / (2 * kLeafChunk) * 2;   // even
+      double bA[kLeafChunk][kLNT], bB[kLeafChunk][kLNT];
+      leaf_load(bA, 0, ksrc, kcnt, F.R, r0);
+      for (int c = 0; c < nch; c += 2) {
+        leaf_load(bB, c + 1, ksrc, kcnt, F.R, r0);
+        leaf_mma(bA, c, op, acc0, acc1);
+        // branch-free: the last pair reloads its own chunk, so the accumulators stay in place
+        leaf_load(bA, min(c + 2, nch - 1), ksrc, kcnt, F.R, r0);
+        leaf_mma(bB, c + 1, op, acc0, acc1);
       }
     }
-    // stores: 64 rows (the rows of kWavesPerStage waves) at a time through
-    // LDS, then each row's nt outputs by consecutive lanes
-    constexpr int kWavesPerStage = 64 / (16 * kLNT);
-    for (int h = 0; h < 4 / kWavesPerStage; ++h) {
-      __syncthreads();
-      if (wave / kWavesPerStage == h) {
-        const int rbase = (wave % kWavesPerStage) * 16 * kLNT;
 #pragma unroll
-        for (int t = 0; t < kLNT; ++t)
+    for (int t = 0; t < kLNT; ++t) {
+      const int row = r0 + 16 * t + (lane & 15);
+      if (row < F.R) {
+        double* o = Xo + (size_t)row * ldo;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int tg = (lane >> 4) + 4 * v;
-            double* o = out + (rbase + 16 * t + (lane & 15)) * (kS + 1);
-            if (tg < nt) o[tg] = scl[tg] * acc0[t][v];
-            if (tg + 16 < nt) o[tg + 16] = scl[tg + 16] * acc1[t][v];
-          }
-      }
-      __syncthreads();
-      const int rw = rt0 + h * 64;
-      for (int e = threadIdx.x; e < 64 * nt; e += blockDim.x) {
-        const int rr = e / nt, t = e - rr * nt;
-        const int row = rw + rr;
-        if (row < F.R && pos[t] >= 0) gst(Xo + (size_t)row * ldo + pos[t], out[rr * (kS + 1) + t]);
+        for (int v = 0; v < 4; ++v) {
+          if (P0[v] >= 0) gst(o + P0[v], S0[v] * acc0[t][v]);
+          if (P1[v] >= 0) gst(o + P1[v], S1[v] * acc1[t][v]);
+        }
       }
     }
-    __syncthreads();   // `out` and the near-field groups are reused by the next row group
   }
 }
 
 // ---------------------------------------------------------------------------
-// The outlier root, directly: Xo[r, P] = s_c sum_k B[k][r] / ((g_k - d_org) - tau),
-// as partial sums over kOutChunks ranges of poles (into `part`, chunk-major),
-// then a fixed-order reduction.
+// The roots evaluated directly (at most two, F.droot), each
+//   Xo[r, P] = s_c sum_k B[k][r] / ((g_k - d_org) - tau),
+// as partial sums over kOutChunks ranges of poles (into `part`, root-major,
+// then chunk-major) in one pass over the charges, then a fixed-order
+// reduction.
 // ---------------------------------------------------------------------------
 constexpr int kOutChunks = 32;
 
 __global__ __launch_bounds__(256) void fmm_outlier_partial(FmmDev F, Stage s, double* __restrict__ part) {
-  __shared__ double w[256];
+  __shared__ double w[2][256];
   if (*s.status & kStFatal) return;
-  const int i = F.outlier;
-  const double go = gld(s.g + gld(s.org + i)), ti = gld(s.tau + i);
+  const int nd = F.ndroot;
+  double go[2], ti[2];
+  for (int d = 0; d < 2; ++d) {
+    const int i = F.droot[d < nd ? d : 0];
+    go[d] = gld(s.g + gld(s.org + i));
+    ti[d] = gld(s.tau + i);
+  }
   const int per = (F.K + kOutChunks - 1) / kOutChunks;
   const int kb = blockIdx.y * per, ke = min(F.K, kb + per);
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  double acc = 0.0;
+  double acc0 = 0.0, acc1 = 0.0;
   for (int k0 = kb; k0 < ke; k0 += 256) {
     __syncthreads();
     const int k = k0 + threadIdx.x;
-    if (k < ke) w[threadIdx.x] = 1.0 / ((gld(s.g + k) - go) - ti);
+    if (k < ke) {
+      const double gk = gld(s.g + k);
+      w[0][threadIdx.x] = 1.0 / ((gk - go[0]) - ti[0]);
+      w[1][threadIdx.x] = 1.0 / ((gk - go[1]) - ti[1]);
+    }
     __syncthreads();
     const int kn = min(256, ke - k0);
     if (r < F.R)
-      for (int q = 0; q < kn; ++q) acc += gld(F.B + (size_t)(k0 + q) * F.R + r) * w[q];
+      for (int q = 0; q < kn; ++q) {
+        const double bq = gld(F.B + (size_t)(k0 + q) * F.R + r);
+        acc0 += bq * w[0][q];
+        acc1 += bq * w[1][q];
+      }
   }
-  if (r < F.R) gst(part + (size_t)blockIdx.y * F.R + r, acc);
+  if (r < F.R) {
+    gst(part + (size_t)blockIdx.y * F.R + r, acc0);
+    if (nd > 1) gst(part + (size_t)(kOutChunks + blockIdx.y) * F.R + r, acc1);
+  }
 }
 
+// grid.y = root
 __global__ __launch_bounds__(256) void fmm_outlier_reduce(FmmDev F, Stage s, const double* __restrict__ part,
                                                            double* __restrict__ Xo, int ldo,
                                                            const double* __restrict__ colscale) {
   if (*s.status & kStFatal) return;
-  const int i = F.outlier;
+  const int d = blockIdx.y, i = F.droot[d];
   const int P = gld(s.rootpos + i);
   const double sc = (colscale ? gld(colscale + P) : 1.0) * gld(s.cs + i);
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= F.R) return;
+  const double* pd = part + (size_t)d * kOutChunks * F.R;
   double acc = 0.0;
-  for (int c = 0; c < kOutChunks; ++c) acc += gld(part + (size_t)c * F.R + r);
+  for (int c = 0; c < kOutChunks; ++c) acc += gld(pd + (size_t)c * F.R + r);
   gst(Xo + (size_t)r * ldo + P, sc * acc);
 }
 
@@ -755,7 +897,11 @@ int fmm_launch(int R, const double* X, int ldx, const Stage& s, const FmmPrepare
   F.nlev = P.nlev;
   F.nbox = P.nbox;
   F.R = R;
-  F.outlier = P.outlier;
+  F.droot[0] = F.droot[1] = -1;
+  F.ndroot = 0;
+  if (P.outlier >= 0) F.droot[F.ndroot++] = P.outlier;
+  if (P.outlier2 >= 0) F.droot[F.ndroot++] = P.outlier2;
+  F.opole = P.opole;
   F.lo = reinterpret_cast<const double*>(plan_dev + pp.off[0]);
   F.hi = reinterpret_cast<const double*>(plan_dev + pp.off[1]);
   F.s0 = reinterpret_cast<const int*>(plan_dev + pp.off[2]);
@@ -785,14 +931,16 @@ int fmm_launch(int R, const double* X, int ldx, const Stage& s, const FmmPrepare
       hipLaunchKernelGGL(fmm_m2m, dim3(1 << l, chunks(1 << l)), dim3(256), 0, st, F, l, s.status);
     for (int l = 0; l <= P.nlev; ++l)
       hipLaunchKernelGGL(fmm_down, dim3(1 << l, chunks(1 << l)), dim3(256), 0, st, F, l, s.status);
-    hipLaunchKernelGGL(fmm_leaf_eval, dim3(1 << P.nlev, (R + kLeafRows - 1) / kLeafRows), dim3(256), 0, st, F, s,
-                       Xo, ldo, colscale);
-    if (P.outlier >= 0) {
-      // W and L (contiguous, 2 nbox kP R >= 32 R doubles) are no longer needed:
-      // their space holds the partial sums
-      static_assert(2 * kP >= kOutChunks, "partial sums must fit in W and L of a one-box tree");
+    const int nrg = (R + kLeafRows - 1) / kLeafRows, nrb = (nrg + kLeafRowGroups - 1) / kLeafRowGroups;
+    hipLaunchKernelGGL(fmm_leaf_eval, dim3((1 << P.nlev) * nrb), dim3(256), 0, st, F, s, Xo, ldo, colscale, nrb,
+                       kLeafRowGroups);
+    if (F.ndroot > 0) {
+      // W and L (contiguous, 2 nbox kP R doubles) are no longer needed: their
+      // space holds the partial sums, ndroot kOutChunks R doubles (a second
+      // direct root implies an isolated pole, so more than one box)
+      if ((size_t)F.ndroot * kOutChunks > 2 * nb * kP) return -2;
       hipLaunchKernelGGL(fmm_outlier_partial, dim3((R + 255) / 256, kOutChunks), dim3(256), 0, st, F, s, F.W);
-      hipLaunchKernelGGL(fmm_outlier_reduce, dim3((R + 255) / 256), dim3(256), 0, st, F, s, F.W, Xo, ldo,
+      hipLaunchKernelGGL(fmm_outlier_reduce, dim3((R + 255) / 256, F.ndroot), dim3(256), 0, st, F, s, F.W, Xo, ldo,
                          colscale);
     }
   }

@@ -373,7 +373,7 @@ def test_precision_form_keeps_roots_and_reports_its_error(lib, m, n, kind):
 @pytest.mark.parametrize("N,kind", [(33, "uniform"), (257, "uniform"), (1000, "geometric"), (1000, "uniform"),
                                     (3000, "geometric")])
 @pytest.mark.parametrize("rho", [0.9, -0.6])
-@pytest.mark.parametrize("variant", ["plain", "repeat_zeros"])
+@pytest.mark.parametrize("variant", ["plain", "repeat_zeros", "isolated_top", "isolated_bottom"])
 def test_fmm_product_matches_direct_sum(lib, N, kind, rho, variant):
     rng = np.random.default_rng(N)
     R = 200
@@ -383,6 +383,10 @@ def test_fmm_product_matches_direct_sum(lib, N, kind, rho, variant):
         lam[5:9] = lam[5]
         lam = np.sort(lam)
         z[[2, N // 3]] = 0.0
+    elif variant == "isolated_top":        # one pole far above the others, as a level's extreme root
+        lam[-1] = lam[-1] + 2.0 * (lam[-1] - lam[0])
+    elif variant == "isolated_bottom":
+        lam[0] = lam[0] - 2.0 * (lam[-1] - lam[0])
     X = rng.standard_normal((R, N))
     Xf, lf, ff = lib.eig_update(dev(X), dev(lam), dev(z), rho, path=lib.SVDU_PATH_FMM, eps=1e-10)
     Xd, ld, fd = lib.eig_update(dev(X), dev(lam), dev(z), rho)
