@@ -294,7 +294,10 @@ typedef double fd4 __attribute__((ext_vector_type(4)));
 constexpr int kNT = 4;                     // row tiles of 16 per wave
 constexpr int kRowsPerBlock = 4 * 16 * kNT;
 constexpr int kOpLd = kP + 1;              // LDS row stride of a p x p operator (odd: no bank conflicts)
-constexpr int kOpsMax = 8;                 // p x p operators held in LDS at once (down pass)
+#ifndef DOWN_ROW_GROUPS
+#define DOWN_ROW_GROUPS 4
+#endif
+constexpr int kDownRowGroups = DOWN_ROW_GROUPS;   // most 256-row groups per block in the downward pass
 constexpr int kS = 32;                     // largest leaf
 constexpr int kLNT = 4;                    // row tiles of 16 per wave in the leaf kernel
 constexpr int kLeafRows = 4 * 16 * kLNT;
@@ -445,71 +448,121 @@ __global__ __launch_bounds__(256, 2) void fmm_m2m(FmmDev F, int level, const int
 
 // ---------------------------------------------------------------------------
 // Downward pass for one level: L[T] = L2L(L[parent]) + sum_S M2L(W[S]).
-// Operators in groups of kOpsMax (L2L first); one group in LDS at a time.
+// The block lays its box's operators (L2L first, then the M2L list) side by
+// side in one LDS table, p rows by 16 columns each, notes the source rows of
+// every k-step, and runs one k-loop over them, one operator per chunk, with
+// the loads of the next operator in flight while the current one is on the
+// matrix cores. An odd operator count is padded with a zero operator on
+// valid rows; more than kDownOps operators take further passes. Blocks are
+// (box, group of row groups) pairs in the XCD-aware order of the leaf kernel.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 2) void fmm_down(FmmDev F, int level, const int* status) {
-  __shared__ double op[kOpsMax][16 * kOpLd];
-  __shared__ const double* srcp[kOpsMax];
-  __shared__ double oc[kOpsMax], orad[kOpsMax];
+constexpr int kDownOps = 8;                  // operators per pass
+constexpr int kDownLd = 16 * kDownOps + 1;   // table row stride (odd)
+
+template <int NT>
+__device__ __forceinline__ void down_load(double (&b)[4][NT], int c, const double* const* ksrc, const int* kcnt,
+                                          int R, int r0) {
+  const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int k = 4 * c + ks;
+    const double* row = ksrc[k] + (size_t)min(kq, kcnt[k] - 1) * R;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) b[ks][t] = gld(row + min(r0 + 16 * t + i, R - 1));
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void down_mma(const double (&b)[4][NT], int c, const double* op, fd4 (&acc)[NT]) {
+  const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const double a = op[i * kDownLd + 16 * c + 4 * ks + kq];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ks][t], acc[t], 0, 0, 0);
+  }
+}
+
+__global__ __launch_bounds__(256) void fmm_down(FmmDev F, int level, const int* status, int nrb, int rgpb) {
+  __shared__ double op[16 * kDownLd];           // [target node][16 operator + source node]
+  __shared__ const double* ksrc[4 * kDownOps];  // first source row of each k-step
+  __shared__ int kcnt[4 * kDownOps];            // its valid rows (1..4)
+  __shared__ double oc[kDownOps], orad[kDownOps];
+  __shared__ int okind[kDownOps];               // 0 L2L, 1 M2L, -1 padding
+  __shared__ int nopp;                          // operators of the pass, padded to even
   __shared__ ChebTab T;
   if (*status & kStFatal) return;
-  const int id = box_id(level, blockIdx.x);
+  const int nb = 1 << level, total = nb * nrb;
+  const int xcd = blockIdx.x % 8, per = total / 8, extra = total % 8;
+  const int w = xcd * per + min(xcd, extra) + blockIdx.x / 8;
+  const int bx = w % nb, rb = w / nb;
+  const int id = box_id(level, bx);
   if (F.s1[id] <= F.s0[id]) return;
   double ct, rt;
   box_cr(F, id, &ct, &rt);
   cheb_fill(&T, F.p);
   const int q0 = F.m2l_ptr[id], nm2l = F.m2l_ptr[id + 1] - q0;
   const int nops = (level > 0 ? 1 : 0) + nm2l;
-  const int ngroups = (nops + kOpsMax - 1) / kOpsMax;
-  __syncthreads();
-  // operator o of the box: o = 0 is L2L when level > 0, the rest M2L. The
-  // centre and radius of each operator's other box are staged first.
-  auto build_group = [&](int gidx) {
-    const int o0 = gidx * kOpsMax, cnt = min(kOpsMax, nops - o0);
-    for (int qi = threadIdx.x; qi < cnt; qi += blockDim.x) {
+  const int npass = max(1, (nops + kDownOps - 1) / kDownOps);
+  const double* pad_src = F.W + (size_t)id * kP * F.R;   // written rows, zero weights
+  auto build_pass = [&](int pass) {
+    const int o0 = pass * kDownOps, cnt = max(0, min(kDownOps, nops - o0));
+    const int cntp = max(2, (cnt + 1) & ~1);
+    __syncthreads();   // the previous table is read by every wave
+    for (int qi = threadIdx.x; qi < cntp; qi += blockDim.x) {
       const int o = o0 + qi;
-      const int other = (level > 0 && o == 0) ? box_id(level - 1, blockIdx.x >> 1)
-                                              : F.m2l_src[q0 + o - (level > 0 ? 1 : 0)];
-      double c, r;
-      box_cr(F, other, &c, &r);
+      const double* src = pad_src;
+      int kind = -1;
+      double c = 0.0, r = 1.0;
+      if (qi < cnt) {
+        const bool l2l = level > 0 && o == 0;
+        const int other = l2l ? box_id(level - 1, bx >> 1) : F.m2l_src[q0 + o - (level > 0 ? 1 : 0)];
+        box_cr(F, other, &c, &r);
+        src = (l2l ? F.L : F.W) + (size_t)other * kP * F.R;
+        kind = l2l ? 0 : 1;
+      }
       oc[qi] = c;
       orad[qi] = r;
-      srcp[qi] = ((level > 0 && o == 0) ? F.L : F.W) + (size_t)other * kP * F.R;
+      okind[qi] = kind;
+      for (int j = 0; j < 4; ++j) {
+        // rows >= p of W and L are never written: clamp into the first p
+        ksrc[4 * qi + j] = src + (size_t)min(4 * j, F.p - 1) * F.R;
+        kcnt[4 * qi + j] = max(1, min(4, F.p - 4 * j));
+      }
     }
+    if (threadIdx.x == 0) nopp = cntp;
     __syncthreads();
-    for (int e = threadIdx.x; e < cnt * 256; e += blockDim.x) {
-      const int qi = e >> 8, rem = e & 255, i = rem >> 4, k = rem & 15;
-      const int o = o0 + qi;
+    for (int e = threadIdx.x; e < cntp * 256; e += blockDim.x) {
+      const int qi = e >> 8, i = (e >> 4) & 15, k = e & 15;
       double v = 0.0;
-      if (i < F.p && k < F.p) {
-        if (level > 0 && o == 0)
+      if (i < F.p && k < F.p && okind[qi] >= 0) {
+        if (okind[qi] == 0)
           v = lagrange(T, k, F.p, (ct + rt * T.t[i] - oc[qi]) / orad[qi]);
         else
           v = 1.0 / ((oc[qi] + orad[qi] * T.t[k]) - (ct + rt * T.t[i]));
       }
-      op[qi][i * kOpLd + k] = v;
+      op[i * kDownLd + 16 * qi + k] = v;
     }
+    __syncthreads();
   };
-  if (ngroups == 1) build_group(0);
-  __syncthreads();
-  int rbeg, rend;
-  row_chunk(F.R, kRowsPerBlock, &rbeg, &rend);
-  const int ksteps = (F.p + 3) / 4;
-  for (int rt0 = rbeg; rt0 < rend; rt0 += kRowsPerBlock) {
-    const int r0 = rt0 + (threadIdx.x >> 6) * 16 * kNT;
+  if (npass == 1) build_pass(0);
+  const int nrg = (F.R + kRowsPerBlock - 1) / kRowsPerBlock;
+  const int rg0 = rb * rgpb, rg1 = min(rg0 + rgpb, nrg);
+  for (int rg = rg0; rg < rg1; ++rg) {
+    const int r0 = rg * kRowsPerBlock + (threadIdx.x >> 6) * 16 * kNT;
     fd4 acc[kNT];
     zero_acc(acc);
-    for (int gi = 0; gi < ngroups; ++gi) {
-      if (ngroups > 1) {
-        __syncthreads();
-        build_group(gi);
-        __syncthreads();
-      }
-      const int cnt = min(kOpsMax, nops - gi * kOpsMax);
-      for (int qi = 0; qi < cnt; ++qi) {
-        double b[kP / 4][kNT];
-        load_b(b, F.p, srcp[qi], F.R, r0);
-        mfma_b(op[qi], kOpLd, ksteps, b, acc);
+    for (int pass = 0; pass < npass; ++pass) {
+      if (npass > 1) build_pass(pass);
+      const int nch = nopp;   // even
+      double bA[4][kNT], bB[4][kNT];
+      down_load(bA, 0, ksrc, kcnt, F.R, r0);
+      for (int c = 0; c < nch; c += 2) {
+        down_load(bB, c + 1, ksrc, kcnt, F.R, r0);
+        down_mma(bA, c, op, acc);
+        // branch-free: the last pair reloads its own operator
+        down_load(bA, min(c + 2, nch - 1), ksrc, kcnt, F.R, r0);
+        down_mma(bB, c + 1, op, acc);
       }
     }
     store_rows(acc, F.L + (size_t)id * kP * F.R, F.p, F.R, r0);
@@ -929,8 +982,12 @@ int fmm_launch(int R, const double* X, int ldx, const Stage& s, const FmmPrepare
     hipLaunchKernelGGL(fmm_p2m, dim3(1 << P.nlev, chunks(1 << P.nlev)), dim3(256), 0, st, F, s.g, s.status);
     for (int l = P.nlev - 1; l >= 0; --l)
       hipLaunchKernelGGL(fmm_m2m, dim3(1 << l, chunks(1 << l)), dim3(256), 0, st, F, l, s.status);
-    for (int l = 0; l <= P.nlev; ++l)
-      hipLaunchKernelGGL(fmm_down, dim3(1 << l, chunks(1 << l)), dim3(256), 0, st, F, l, s.status);
+    for (int l = 0; l <= P.nlev; ++l) {
+      // enough blocks to fill the chip, then up to kDownRowGroups row groups per block
+      const int rgpb = std::max(1, std::min(kDownRowGroups, ((1 << l) * rb) / 2048));
+      const int nrb = (rb + rgpb - 1) / rgpb;
+      hipLaunchKernelGGL(fmm_down, dim3((1 << l) * nrb), dim3(256), 0, st, F, l, s.status, nrb, rgpb);
+    }
     const int nrg = (R + kLeafRows - 1) / kLeafRows, nrb = (nrg + kLeafRowGroups - 1) / kLeafRowGroups;
     hipLaunchKernelGGL(fmm_leaf_eval, dim3((1 << P.nlev) * nrb), dim3(256), 0, st, F, s, Xo, ldo, colscale, nrb,
                        kLeafRowGroups);
