@@ -678,7 +678,7 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
   auto build_pass = [&](int pass) {
     const int qa = pass * kLeafNearPass, nq = min(kLeafNearPass, nnear - qa);
     __syncthreads();   // the previous table is read by every wave
-    if (threadIdx.x < nq) {
+    if ((int)threadIdx.x < nq) {
       const int nbx = F.near_src[q0 + qa + threadIdx.x];
       nb0[threadIdx.x] = F.s0[nbx];
       nns[threadIdx.x] = F.s1[nbx] - F.s0[nbx];
