@@ -22,10 +22,11 @@ HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "
             "-Wno-unused-but-set-variable"]
 
 
-# Per-source additions. The FMM kernels keep their MFMA accumulators in
-# ordinary VGPRs: in AGPRs the loop-carried accumulators of the leaf kernel's
-# k-loop were copied out and back on every trip.
-EXTRA_FLAGS = {"k_fmm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# Per-source additions. The FMM and refinement kernels keep their MFMA
+# accumulators in ordinary VGPRs: in AGPRs the accumulators carried through
+# their runtime-length k-loops were copied out and back on every trip.
+_VGPR_MFMA = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+EXTRA_FLAGS = {"k_fmm.hip": _VGPR_MFMA, "k_refine.hip": _VGPR_MFMA}
 
 
 def hipcc() -> str:

@@ -526,7 +526,7 @@ void build_plan(const std::vector<Update>& ups_in, int precision, char* dev_base
         R.beta = L.rf_beta;
         jobs.push_back(R);
         bn.push_back(cdiv(u.n, 256));
-        bc.push_back(cdiv(u.m + 1, 64));
+        bc.push_back(cdiv(u.m + 1, 16));   // refine_vt_kernel: 16 columns of [V b] per block
         bw.push_back(cdiv(u.m, 4));
         bcl.push_back(std::min(32, L.cmax));
       }

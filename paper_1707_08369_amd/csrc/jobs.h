@@ -121,7 +121,7 @@ struct RefineList {
   int n = 0;
   int blocks_n = 0, blocks_c = 0, blocks_w = 0, blocks_cl = 0;
   const int* boff_n = nullptr;     // ceil(n / 256) per update (gather)
-  const int* boff_c = nullptr;     // ceil((m + 1) / 64) per update (V^T products)
+  const int* boff_c = nullptr;     // ceil((m + 1) / 16) per update (V^T products)
   const int* boff_w = nullptr;     // ceil(m / 4) per update (U products)
   const int* boff_cl = nullptr;    // blocks sharing the clusters of an update
   const RefineJob* job = nullptr;

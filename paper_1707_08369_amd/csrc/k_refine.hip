@@ -125,45 +125,69 @@ __global__ __launch_bounds__(256) void refine_gather_kernel(RefineList L) {
 }
 
 // ---------------------------------------------------------------------------
-// T[q][j] = sum_r V[r][j] Yv[q][r] for j < m, and beta[q] = b^T Yv[q] (j = m).
-// Block: 64 columns x 4 row groups, all n rows; chunks of kRefineChunk columns.
+// T[q][j] = sigma_j sum_r Yv[q][r] V[r][j] for j < m, and beta[q] = sum_r Yv[q][r] b[r]
+// (j = m): one pass over V for all k gathered columns, on the matrix cores.
+// Block: 16 columns of [V b] and all n rows; its 4 waves take interleaved
+// 4-row steps and are summed in a fixed order at the end. A operand: 16
+// gathered columns (lane l: Yv[16 qb + l % 16][r + l / 16]); B operand: lane l
+// holds V[r + l / 16][j0 + l % 16]; result register v of lane l holds
+// T[16 qb + l / 16 + 4 v][j0 + l % 16]. Rows q >= k read row k - 1 and rows
+// r >= n carry a zero B entry, so neither reaches a stored result.
 // ---------------------------------------------------------------------------
+typedef double rf4 __attribute__((ext_vector_type(4)));
+constexpr int kVtCols = 16;
+constexpr int kVtMaxQb = 8;   // 16-column groups of the gathered columns (kmax <= 128)
+
+template <int KB>
+__device__ void refine_vt_body(const RefineJob& J, int k, int j0, rf4 (*red)[kVtMaxQb][64]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, i = lane & 15, kq = lane >> 4;
+  const int j = j0 + i, jc = min(j, J.m - 1);
+  const double* yrow[KB];
+#pragma unroll
+  for (int qb = 0; qb < KB; ++qb) yrow[qb] = J.Yv + (size_t)min(16 * qb + i, k - 1) * J.n;
+  rf4 acc[KB];
+#pragma unroll
+  for (int qb = 0; qb < KB; ++qb) acc[qb] = rf4{0.0, 0.0, 0.0, 0.0};
+  const int nsteps = (J.n + 3) / 4;
+  for (int st = wv; st < nsteps; st += 4) {
+    const int r = 4 * st + kq, rc = min(r, J.n - 1);
+    const double vv = gld(J.V + (size_t)rc * J.ldv + jc), bb = gld(J.b + rc);
+    const double bv = (r < J.n) ? (j < J.m ? vv : (j == J.m ? bb : 0.0)) : 0.0;
+#pragma unroll
+    for (int qb = 0; qb < KB; ++qb)
+      acc[qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(gld(yrow[qb] + rc), bv, acc[qb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int qb = 0; qb < KB; ++qb) red[wv][qb][lane] = acc[qb];
+  __syncthreads();
+  for (int e = threadIdx.x; e < KB * 4 * 64; e += blockDim.x) {
+    const int qb = e >> 8, v = (e >> 6) & 3, l = e & 63;
+    const int q = 16 * qb + (l >> 4) + 4 * v, jj = j0 + (l & 15);
+    if (q >= k || jj > J.m) continue;
+    const double t = ((red[0][qb][l][v] + red[1][qb][l][v]) + red[2][qb][l][v]) + red[3][qb][l][v];
+    if (jj < J.m)
+      J.T[(size_t)q * J.m + jj] = J.sigma[jj] * t;   // S V^T v^
+    else
+      J.beta[q] = t;
+  }
+}
+
 __global__ __launch_bounds__(256) void refine_vt_kernel(RefineList L) {
-  __shared__ double red[4][kRefineChunk][64];
+  __shared__ rf4 red[4][kVtMaxQb][64];
   const int u = find_job(L.boff_c, L.n, blockIdx.x);
   const RefineJob J = L.job[u];
   const int k = J.info[0];
   if (k <= 0) return;
-  const int cl = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int j = (blockIdx.x - L.boff_c[u]) * 64 + cl;
-  const bool act = j <= J.m;
-  for (int q0 = 0; q0 < k; q0 += kRefineChunk) {
-    double acc[kRefineChunk];
-#pragma unroll
-    for (int v = 0; v < kRefineChunk; ++v) acc[v] = 0.0;
-    if (act) {
-      for (int r = g; r < J.n; r += 4) {
-        const double x = (j < J.m) ? J.V[(size_t)r * J.ldv + j] : J.b[r];
-#pragma unroll
-        for (int v = 0; v < kRefineChunk; ++v)
-          if (q0 + v < k) acc[v] += x * J.Yv[(size_t)(q0 + v) * J.n + r];
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < kRefineChunk; ++v) red[g][v][cl] = acc[v];
-    __syncthreads();
-    if (g == 0 && act) {
-#pragma unroll
-      for (int v = 0; v < kRefineChunk; ++v) {
-        if (q0 + v >= k) break;
-        const double t = ((red[0][v][cl] + red[1][v][cl]) + red[2][v][cl]) + red[3][v][cl];
-        if (j < J.m)
-          J.T[(size_t)(q0 + v) * J.m + j] = J.sigma[j] * t;   // S V^T v^
-        else
-          J.beta[q0 + v] = t;
-      }
-    }
-    __syncthreads();
+  const int j0 = (blockIdx.x - L.boff_c[u]) * kVtCols;
+  switch ((k + 15) / 16) {
+    case 1: refine_vt_body<1>(J, k, j0, red); break;
+    case 2: refine_vt_body<2>(J, k, j0, red); break;
+    case 3: refine_vt_body<3>(J, k, j0, red); break;
+    case 4: refine_vt_body<4>(J, k, j0, red); break;
+    case 5: refine_vt_body<5>(J, k, j0, red); break;
+    case 6: refine_vt_body<6>(J, k, j0, red); break;
+    case 7: refine_vt_body<7>(J, k, j0, red); break;
+    default: refine_vt_body<8>(J, k, j0, red); break;
   }
 }
 
