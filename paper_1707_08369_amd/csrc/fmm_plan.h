@@ -18,11 +18,15 @@ struct FmmHostPlan {
   std::vector<int> m2l_ptr, m2l_src;
   std::vector<int> near_ptr, near_src;
   std::vector<int> lev_off;         // first box id of each level
+  // the directly evaluated roots (outlier, then outlier2, those that exist):
+  // boxes whose expansion converges at the root, and leaves summed exactly
+  std::vector<int> dm2p, dp2p;
+  int dm2p_ptr[3] = {0, 0, 0}, dp2p_ptr[3] = {0, 0, 0};
 };
 
 struct FmmPrepared {
   FmmHostPlan P;
-  size_t off[8];
+  size_t off[10];
 };
 
 // Builds the plan of one product from host copies of the stage's K poles g

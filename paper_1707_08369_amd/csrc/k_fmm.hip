@@ -60,9 +60,9 @@ static void build_plan(int K, const double* g, const double* mu, int p, FmmHostP
   P->s = (K + (1 << nlev) - 1) >> nlev;
   const int s = P->s;
   // The extreme root (beyond the last pole for rho > 0, before the first for
-  // rho < 0) can lie far outside the spectrum; it is evaluated directly
-  // against all poles and kept out of the box intervals, which would
-  // otherwise make its leaf, and every box above it, inadmissible to all.
+  // rho < 0) can lie far outside the spectrum; it is kept out of the box
+  // intervals, which would otherwise make its leaf, and every box above it,
+  // inadmissible to all, and is evaluated on its own (fmm_direct_roots).
   P->outlier = -1;
   for (int i = 0; i < K; ++i)
     if (mu[i] > g[K - 1] || mu[i] < g[0]) P->outlier = i;
@@ -180,6 +180,39 @@ static void build_plan(int K, const double* g, const double* mu, int p, FmmHostP
     P->m2l_src.insert(P->m2l_src.end(), m2l[i].begin(), m2l[i].end());
     P->near_src.insert(P->near_src.end(), nearl[i].begin(), nearl[i].end());
   }
+  // Each directly evaluated root y takes the far field of every box whose gap
+  // to y is at least the box's width (the rule of the pairs above, for a
+  // point) from its multipole coefficients, and sums the leaves that never
+  // qualify exactly.
+  P->dm2p.clear();
+  P->dp2p.clear();
+  int nd = 0;
+  for (const int d : {P->outlier, P->outlier2}) {
+    if (d < 0) continue;
+    const double y = mu[d];
+    std::vector<int> st{0};
+    while (!st.empty()) {
+      const int b = st.back();
+      st.pop_back();
+      if (empty(b)) continue;
+      const double gap = std::max(P->lo[b] - y, y - P->hi[b]);
+      if (gap > 0.0 && gap >= P->hi[b] - P->lo[b]) {
+        P->dm2p.push_back(b);
+        continue;
+      }
+      const int l = level_of[b];
+      if (l == nlev) {
+        P->dp2p.push_back(b);
+        continue;
+      }
+      const int kb = b - P->lev_off[l];
+      st.push_back(box_id(l + 1, 2 * kb + 1));
+      st.push_back(box_id(l + 1, 2 * kb));
+    }
+    ++nd;
+    P->dm2p_ptr[nd] = (int)P->dm2p.size();
+    P->dp2p_ptr[nd] = (int)P->dp2p.size();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -190,6 +223,9 @@ struct FmmDev {
   int droot[2];   // roots evaluated directly (-1: none)
   int ndroot;     // how many (the first ndroot entries)
   int opole;      // pole applied to every root directly (-1: none)
+  int dm2p_ptr[3], dp2p_ptr[3];
+  const int* dm2p;   // per direct root: boxes taken from their multipole coefficients
+  const int* dp2p;   // per direct root: leaves summed exactly
   const double* lo;
   const double* hi;
   const int* s0;
@@ -664,7 +700,7 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
       sc = (colscale ? gld(colscale + P) : 1.0) * gld(s.cs + i);
       go = gld(s.g + gld(s.org + i));
       ta = gld(s.tau + i);
-      if (i == F.droot[0] || i == F.droot[1]) P = -1;   // evaluated by fmm_outlier_partial / fmm_outlier_reduce
+      if (i == F.droot[0] || i == F.droot[1]) P = -1;   // evaluated by fmm_direct_roots
     }
     pos[t] = P;
     scl[t] = sc;
@@ -791,65 +827,74 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
 }
 
 // ---------------------------------------------------------------------------
-// The roots evaluated directly (at most two, F.droot), each
-//   Xo[r, P] = s_c sum_k B[k][r] / ((g_k - d_org) - tau),
-// as partial sums over kOutChunks ranges of poles (into `part`, root-major,
-// then chunk-major) in one pass over the charges, then a fixed-order
-// reduction.
+// The roots evaluated directly (at most two, F.droot): for a root y at
+// d_org + tau, the far field from the multipole coefficients of the boxes
+// listed for it, f(y) = sum_k W_k / (x_k - y) over each box's Chebyshev nodes,
+// the listed leaves exactly with pole-relative differences (g_j - d_org) - tau,
+// and the isolated pole, summed in that order and scaled by the column scale.
+// Terms go through LDS in rounds of kDirTerms (weight and source row); a block
+// takes 64 rows, and its four waves add every fourth term of a round for
+// them, summed in a fixed order at the end.
 // ---------------------------------------------------------------------------
-constexpr int kOutChunks = 32;
+constexpr int kDirTerms = 512;
 
-__global__ __launch_bounds__(256) void fmm_outlier_partial(FmmDev F, Stage s, double* __restrict__ part) {
-  __shared__ double w[2][256];
-  if (*s.status & kStFatal) return;
-  const int nd = F.ndroot;
-  double go[2], ti[2];
-  for (int d = 0; d < 2; ++d) {
-    const int i = F.droot[d < nd ? d : 0];
-    go[d] = gld(s.g + gld(s.org + i));
-    ti[d] = gld(s.tau + i);
-  }
-  const int per = (F.K + kOutChunks - 1) / kOutChunks;
-  const int kb = blockIdx.y * per, ke = min(F.K, kb + per);
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  double acc0 = 0.0, acc1 = 0.0;
-  for (int k0 = kb; k0 < ke; k0 += 256) {
-    __syncthreads();
-    const int k = k0 + threadIdx.x;
-    if (k < ke) {
-      const double gk = gld(s.g + k);
-      w[0][threadIdx.x] = 1.0 / ((gk - go[0]) - ti[0]);
-      w[1][threadIdx.x] = 1.0 / ((gk - go[1]) - ti[1]);
-    }
-    __syncthreads();
-    const int kn = min(256, ke - k0);
-    if (r < F.R)
-      for (int q = 0; q < kn; ++q) {
-        const double bq = gld(F.B + (size_t)(k0 + q) * F.R + r);
-        acc0 += bq * w[0][q];
-        acc1 += bq * w[1][q];
-      }
-  }
-  if (r < F.R) {
-    gst(part + (size_t)blockIdx.y * F.R + r, acc0);
-    if (nd > 1) gst(part + (size_t)(kOutChunks + blockIdx.y) * F.R + r, acc1);
-  }
-}
-
-// grid.y = root
-__global__ __launch_bounds__(256) void fmm_outlier_reduce(FmmDev F, Stage s, const double* __restrict__ part,
-                                                           double* __restrict__ Xo, int ldo,
-                                                           const double* __restrict__ colscale) {
+__global__ __launch_bounds__(256) void fmm_direct_roots(FmmDev F, Stage s, double* __restrict__ Xo, int ldo,
+                                                        const double* __restrict__ colscale) {
+  __shared__ double wt[kDirTerms];
+  __shared__ const double* src[kDirTerms];
+  __shared__ double part[4][64];
+  __shared__ ChebTab T;
   if (*s.status & kStFatal) return;
   const int d = blockIdx.y, i = F.droot[d];
-  const int P = gld(s.rootpos + i);
-  const double sc = (colscale ? gld(colscale + P) : 1.0) * gld(s.cs + i);
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= F.R) return;
-  const double* pd = part + (size_t)d * kOutChunks * F.R;
+  const double go = gld(s.g + gld(s.org + i)), ta = gld(s.tau + i), y = go + ta;
+  const int m0 = F.dm2p_ptr[d], nm = F.dm2p_ptr[d + 1] - m0;
+  const int p0 = F.dp2p_ptr[d], np = F.dp2p_ptr[d + 1] - p0;
+  // term t: far (box m0 + t / kP, node t % kP), near (leaf p0 + u / kS, pole u % kS), then the isolated pole
+  const int nfar = nm * kP, nterm = nfar + np * kS + (F.opole >= 0 ? 1 : 0);
+  cheb_fill(&T, F.p);
+  const int ph = threadIdx.x >> 6, r = blockIdx.x * 64 + (threadIdx.x & 63);
   double acc = 0.0;
-  for (int c = 0; c < kOutChunks; ++c) acc += gld(pd + (size_t)c * F.R + r);
-  gst(Xo + (size_t)r * ldo + P, sc * acc);
+  for (int t0 = 0; t0 < nterm; t0 += kDirTerms) {
+    __syncthreads();   // T is written, and the previous round is read
+    for (int e = threadIdx.x; e < kDirTerms && t0 + e < nterm; e += blockDim.x) {
+      const int t = t0 + e;
+      double w = 0.0;
+      const double* sr = F.B;   // zero weights point at row 0 of the charges
+      if (t < nfar) {
+        const int bx = F.dm2p[m0 + t / kP], kk = t % kP;
+        double c, rad;
+        box_cr(F, bx, &c, &rad);
+        // rows kk >= p of W are never written
+        sr = F.W + ((size_t)bx * kP + min(kk, F.p - 1)) * F.R;
+        if (kk < F.p) w = 1.0 / ((c + rad * T.t[kk]) - y);
+      } else if (t < nfar + np * kS) {
+        const int u = t - nfar, lf = F.dp2p[p0 + u / kS], j = F.s0[lf] + u % kS;
+        if (j < F.s1[lf] && j != F.opole) {
+          sr = F.B + (size_t)j * F.R;
+          w = 1.0 / ((gld(s.g + j) - go) - ta);
+        }
+      } else {
+        sr = F.B + (size_t)F.opole * F.R;
+        w = 1.0 / ((gld(s.g + F.opole) - go) - ta);
+      }
+      wt[e] = w;
+      src[e] = sr;
+    }
+    __syncthreads();
+    const int ne = min(kDirTerms, nterm - t0);
+    if (r < F.R) {
+#pragma unroll 8
+      for (int e = ph; e < ne; e += 4) acc += wt[e] * gld(src[e] + r);
+    }
+  }
+  part[ph][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (ph == 0 && r < F.R) {
+    const int l = threadIdx.x;
+    const int P = gld(s.rootpos + i);
+    const double sc = (colscale ? gld(colscale + P) : 1.0) * gld(s.cs + i);
+    gst(Xo + (size_t)r * ldo + P, sc * (((part[0][l] + part[1][l]) + part[2][l]) + part[3][l]));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -904,8 +949,9 @@ size_t fmm_workspace_elems(int R, int N) {
 
 size_t fmm_plan_bytes(int N) {
   const size_t nbox = tree_boxes(N);
-  // intervals, ranges, CSR pointers, and list space (<= 64 entries per box)
-  return sizeof(double) * 2 * nbox + sizeof(int) * (4 * nbox + 2 + 2 * 64 * nbox) + 16 * 256;
+  // intervals, ranges, CSR pointers, list space (<= 64 entries per box), the
+  // direct roots' lists (each box at most once per root), 256-byte alignment
+  return sizeof(double) * 2 * nbox + sizeof(int) * (4 * nbox + 2 + 2 * 64 * nbox + 4 * nbox) + 16 * 256;
 }
 
 // Builds the plan of one product from host copies of the stage's poles g (K)
@@ -932,6 +978,8 @@ void fmm_prepare(int K, const double* g_host, const double* mu_host, double eps,
   out->off[5] = add(P.m2l_src.data(), P.m2l_src.size() * sizeof(int));
   out->off[6] = add(P.near_ptr.data(), P.near_ptr.size() * sizeof(int));
   out->off[7] = add(P.near_src.data(), P.near_src.size() * sizeof(int));
+  out->off[8] = add(P.dm2p.data(), P.dm2p.size() * sizeof(int));
+  out->off[9] = add(P.dp2p.data(), P.dp2p.size() * sizeof(int));
 }
 
 // Enqueues the FMM product X_out = X C~ for stage `s` with a prepared plan
@@ -963,6 +1011,12 @@ int fmm_launch(int R, const double* X, int ldx, const Stage& s, const FmmPrepare
   F.m2l_src = reinterpret_cast<const int*>(plan_dev + pp.off[5]);
   F.near_ptr = reinterpret_cast<const int*>(plan_dev + pp.off[6]);
   F.near_src = reinterpret_cast<const int*>(plan_dev + pp.off[7]);
+  F.dm2p = reinterpret_cast<const int*>(plan_dev + pp.off[8]);
+  F.dp2p = reinterpret_cast<const int*>(plan_dev + pp.off[9]);
+  for (int d = 0; d < 3; ++d) {
+    F.dm2p_ptr[d] = P.dm2p_ptr[d];
+    F.dp2p_ptr[d] = P.dp2p_ptr[d];
+  }
   const size_t hx_elems = (size_t)N * R;   // indexed by group id < K <= N
   if ((size_t)K * R + 2 * nb * kP * (size_t)R + hx_elems > work_elems) return -2;
   F.B = work;
@@ -991,15 +1045,8 @@ int fmm_launch(int R, const double* X, int ldx, const Stage& s, const FmmPrepare
     const int nrg = (R + kLeafRows - 1) / kLeafRows, nrb = (nrg + kLeafRowGroups - 1) / kLeafRowGroups;
     hipLaunchKernelGGL(fmm_leaf_eval, dim3((1 << P.nlev) * nrb), dim3(256), 0, st, F, s, Xo, ldo, colscale, nrb,
                        kLeafRowGroups);
-    if (F.ndroot > 0) {
-      // W and L (contiguous, 2 nbox kP R doubles) are no longer needed: their
-      // space holds the partial sums, ndroot kOutChunks R doubles (a second
-      // direct root implies an isolated pole, so more than one box)
-      if ((size_t)F.ndroot * kOutChunks > 2 * nb * kP) return -2;
-      hipLaunchKernelGGL(fmm_outlier_partial, dim3((R + 255) / 256, kOutChunks), dim3(256), 0, st, F, s, F.W);
-      hipLaunchKernelGGL(fmm_outlier_reduce, dim3((R + 255) / 256, F.ndroot), dim3(256), 0, st, F, s, F.W, Xo, ldo,
-                         colscale);
-    }
+    if (F.ndroot > 0)
+      hipLaunchKernelGGL(fmm_direct_roots, dim3((R + 63) / 64, F.ndroot), dim3(256), 0, st, F, s, Xo, ldo, colscale);
   }
   if (K < N) {
     hipLaunchKernelGGL(fmm_group_dots, dim3(std::max(K, 1), rb), dim3(256), 0, st, R, X, ldx, s, hX);
