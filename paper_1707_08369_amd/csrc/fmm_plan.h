@@ -26,7 +26,7 @@ struct FmmHostPlan {
 
 struct FmmPrepared {
   FmmHostPlan P;
-  size_t off[10];
+  size_t off[11];
 };
 
 // Builds the plan of one product from host copies of the stage's K poles g

@@ -234,27 +234,25 @@ struct FmmDev {
   const int* m2l_src;
   const int* near_ptr;
   const int* near_src;
+  const double* cheb;   // ChebTab of order p (kChebWords doubles)
   double* B;   // [K][R] charges
   double* W;   // [nbox][kP][R] far-field coefficients
   double* L;   // [nbox][kP][R] local coefficients
 };
 
-__device__ __forceinline__ double cheb_node(int k, int p) { return cos((2.0 * k + 1.0) * M_PI / (2.0 * p)); }
-
 // Chebyshev nodes t_k (Appendix D Step 3) and the inverse node differences
-// 1/(t_k - t_m), built once per block in LDS; then each Lagrange basis value
+// 1/(t_k - t_m), built once per plan on the host (cheb_table) and copied into
+// LDS by every block; then each Lagrange basis value
 // u_k(t) = prod_{m != k} (t - t_m) / (t_k - t_m) (Step 4) costs p multiplies.
 struct ChebTab {
   double t[kP];
   double inv[kP * kP];
 };
+constexpr int kChebWords = kP + kP * kP;
 
-__device__ __forceinline__ void cheb_fill(ChebTab* T, int p) {
-  for (int e = threadIdx.x; e < p; e += blockDim.x) T->t[e] = cheb_node(e, p);
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
-    const int k = e / p, m = e - k * p;
-    T->inv[k * kP + m] = (k == m) ? 0.0 : 1.0 / (cheb_node(k, p) - cheb_node(m, p));
-  }
+__device__ __forceinline__ void cheb_fill(ChebTab* T, const FmmDev& F) {
+  double* dst = T->t;   // t and inv are contiguous
+  for (int e = threadIdx.x; e < kChebWords; e += blockDim.x) dst[e] = gld(F.cheb + e);
 }
 
 __device__ __forceinline__ double lagrange(const ChebTab& T, int k, int p, double x) {
@@ -417,7 +415,7 @@ __global__ __launch_bounds__(256, 2) void fmm_p2m(FmmDev F, const double* __rest
   double c, rad;
   box_cr(F, id, &c, &rad);
   const int ns = a1 - a0;
-  cheb_fill(&T, F.p);
+  cheb_fill(&T, F);
   __syncthreads();
   for (int e = threadIdx.x; e < 16 * kS; e += blockDim.x) {
     const int kk = e / kS, j = e % kS;
@@ -452,7 +450,7 @@ __global__ __launch_bounds__(256, 2) void fmm_m2m(FmmDev F, int level, const int
   box_cr(F, id, &cp, &rp);
   const int ch[2] = {box_id(level + 1, 2 * blockIdx.x), box_id(level + 1, 2 * blockIdx.x + 1)};
   if (threadIdx.x < 2) has[threadIdx.x] = F.s1[ch[threadIdx.x]] > F.s0[ch[threadIdx.x]];
-  cheb_fill(&T, F.p);
+  cheb_fill(&T, F);
   __syncthreads();
   for (int e = threadIdx.x; e < 2 * 16 * 16; e += blockDim.x) {
     const int q = e >> 8, rem = e & 255, kp = rem >> 4, kc = rem & 15;
@@ -536,7 +534,7 @@ __global__ __launch_bounds__(256) void fmm_down(FmmDev F, int level, const int* 
   if (F.s1[id] <= F.s0[id]) return;
   double ct, rt;
   box_cr(F, id, &ct, &rt);
-  cheb_fill(&T, F.p);
+  cheb_fill(&T, F);
   const int q0 = F.m2l_ptr[id], nm2l = F.m2l_ptr[id + 1] - q0;
   const int nops = (level > 0 ? 1 : 0) + nm2l;
   const int npass = max(1, (nops + kDownOps - 1) / kDownOps);
@@ -688,7 +686,7 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
   const int nt = a1 - a0;
   double ct, rt;
   box_cr(F, id, &ct, &rt);
-  cheb_fill(&T, F.p);
+  cheb_fill(&T, F);
   const int q0 = F.near_ptr[id], nnear = F.near_ptr[id + 1] - q0;
   // per target: origin pole, offset, column position and scale (one load each)
   for (int t = threadIdx.x; t < kS; t += blockDim.x) {
@@ -851,7 +849,7 @@ __global__ __launch_bounds__(256) void fmm_direct_roots(FmmDev F, Stage s, doubl
   const int p0 = F.dp2p_ptr[d], np = F.dp2p_ptr[d + 1] - p0;
   // term t: far (box m0 + t / kP, node t % kP), near (leaf p0 + u / kS, pole u % kS), then the isolated pole
   const int nfar = nm * kP, nterm = nfar + np * kS + (F.opole >= 0 ? 1 : 0);
-  cheb_fill(&T, F.p);
+  cheb_fill(&T, F);
   const int ph = threadIdx.x >> 6, r = blockIdx.x * 64 + (threadIdx.x & 63);
   double acc = 0.0;
   for (int t0 = 0; t0 < nterm; t0 += kDirTerms) {
@@ -951,7 +949,8 @@ size_t fmm_plan_bytes(int N) {
   const size_t nbox = tree_boxes(N);
   // intervals, ranges, CSR pointers, list space (<= 64 entries per box), the
   // direct roots' lists (each box at most once per root), 256-byte alignment
-  return sizeof(double) * 2 * nbox + sizeof(int) * (4 * nbox + 2 + 2 * 64 * nbox + 4 * nbox) + 16 * 256;
+  return sizeof(double) * (2 * nbox + kP + kP * kP) + sizeof(int) * (4 * nbox + 2 + 2 * 64 * nbox + 4 * nbox) +
+         16 * 256;
 }
 
 // Builds the plan of one product from host copies of the stage's poles g (K)
@@ -980,6 +979,12 @@ void fmm_prepare(int K, const double* g_host, const double* mu_host, double eps,
   out->off[7] = add(P.near_src.data(), P.near_src.size() * sizeof(int));
   out->off[8] = add(P.dm2p.data(), P.dm2p.size() * sizeof(int));
   out->off[9] = add(P.dp2p.data(), P.dp2p.size() * sizeof(int));
+  // Chebyshev nodes of order p and their inverse differences (ChebTab layout)
+  std::vector<double> cheb(kP + kP * kP, 0.0);
+  for (int k = 0; k < p; ++k) cheb[k] = std::cos((2.0 * k + 1.0) * M_PI / (2.0 * p));
+  for (int k = 0; k < p; ++k)
+    for (int m = 0; m < p; ++m) cheb[kP + k * kP + m] = (k == m) ? 0.0 : 1.0 / (cheb[k] - cheb[m]);
+  out->off[10] = add(cheb.data(), cheb.size() * sizeof(double));
 }
 
 // Enqueues the FMM product X_out = X C~ for stage `s` with a prepared plan
@@ -1013,6 +1018,7 @@ int fmm_launch(int R, const double* X, int ldx, const Stage& s, const FmmPrepare
   F.near_src = reinterpret_cast<const int*>(plan_dev + pp.off[7]);
   F.dm2p = reinterpret_cast<const int*>(plan_dev + pp.off[8]);
   F.dp2p = reinterpret_cast<const int*>(plan_dev + pp.off[9]);
+  F.cheb = reinterpret_cast<const double*>(plan_dev + pp.off[10]);
   for (int d = 0; d < 3; ++d) {
     F.dm2p_ptr[d] = P.dm2p_ptr[d];
     F.dp2p_ptr[d] = P.dp2p_ptr[d];
