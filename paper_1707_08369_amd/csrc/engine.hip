@@ -297,15 +297,16 @@ StageLevel build_level(const std::vector<Stage>& st_in, const std::vector<TmvJob
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return st_in[x].N > st_in[y].N; });
   std::vector<Stage> st;
   std::vector<TmvJob> tv;
-  std::vector<int> bw, bt, bs;
+  std::vector<int> bw, bt, bs, bq;
   for (int i : order) {
     st.push_back(st_in[i]);
     tv.push_back(i < (int)tv_in.size() ? tv_in[i] : TmvJob{0, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}});
     bw.push_back(cdiv(st_in[i].N, 4));
     bt.push_back(cdiv(st_in[i].N, 256));
     bs.push_back(st_in[i].N <= kGroupMaxN ? cdiv(st_in[i].N, 256 / kSmallGroup) : cdiv(st_in[i].N, 4));
+    bq.push_back(cdiv(bs.back(), 4));
   }
-  const std::vector<int> ow = prefix(bw), ot = prefix(bt), os = prefix(bs);
+  const std::vector<int> ow = prefix(bw), ot = prefix(bt), os = prefix(bs), oq = prefix(bq);
   StageLevel S;
   S.n = (int)st.size();
   S.st = B.put(st);
@@ -313,9 +314,12 @@ StageLevel build_level(const std::vector<Stage>& st_in, const std::vector<TmvJob
   S.boff_w = B.put(ow);
   S.boff_t = B.put(ot);
   S.boff_i = B.put(os);
+  S.boff_s = B.put(oq);
   S.blocks_w = ow.back();
   S.blocks_t = ot.back();
   S.blocks_i = os.back();
+  S.blocks_s = oq.back();
+  for (const Stage& x : st) S.nmax = std::max(S.nmax, x.N);
   return S;
 }
 

@@ -52,7 +52,9 @@ struct StageLevel {
   const int* boff_w = nullptr;   // ceil(N / 4) blocks per job
   const int* boff_t = nullptr;   // ceil(N / 256) blocks per job
   const int* boff_i = nullptr;   // item kernels: ceil(N / (256 / kSmallGroup)) if N <= kGroupMaxN, else ceil(N / 4)
-  int blocks_w = 0, blocks_t = 0, blocks_i = 0;
+  const int* boff_s = nullptr;   // secular kernel: ceil(item blocks / 4) blocks of 1024 threads per job
+  int blocks_w = 0, blocks_t = 0, blocks_i = 0, blocks_s = 0;
+  int nmax = 0;                  // largest order of the level (host side)
 };
 
 // One product X_out = X C~ in the tile grid of the list's tile shape.

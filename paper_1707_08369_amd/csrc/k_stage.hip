@@ -176,17 +176,24 @@ __device__ void deflate_body(const Stage& s) {
 // Works in the reflected problem when rho < 0 so that the iteration always
 // sees rho > 0 and roots to the right of their left pole.
 // ---------------------------------------------------------------------------
+// The poles and weights are read from global memory, or (LDS) from a copy the
+// block staged in LDS; the arithmetic is the same either way.
+template <bool LDS>
 struct Reflect {
   const double* g;
   const double* W2;
   int K;
   bool refl;
+  static __device__ __forceinline__ double ld(const double* p) {
+    if (LDS) return *((const __attribute__((address_space(3))) double*)p);
+    return gld(p);
+  }
   // branch-free (index and sign by select), so loops over k keep several loads in flight
   __device__ __forceinline__ double pole(int k) const {
-    const double v = gld(g + (refl ? K - 1 - k : k));
+    const double v = ld(g + (refl ? K - 1 - k : k));
     return refl ? -v : v;
   }
-  __device__ __forceinline__ double wt(int k) const { return gld(W2 + (refl ? K - 1 - k : k)); }
+  __device__ __forceinline__ double wt(int k) const { return ld(W2 + (refl ? K - 1 - k : k)); }
 };
 
 struct SecSums {
@@ -195,10 +202,10 @@ struct SecSums {
 
 // Pole k and its weight z_k^2 of the (reflected) problem, in units of 1 / sc
 // when SC (an exact power-of-two scaling).
-template <bool REFL, bool SC>
-__device__ __forceinline__ void sec_pole(const Reflect& R, int k, double sc, double* p, double* wt) {
+template <bool REFL, bool SC, bool LDS>
+__device__ __forceinline__ void sec_pole(const Reflect<LDS>& R, int k, double sc, double* p, double* wt) {
   const int kk = REFL ? R.K - 1 - k : k;
-  const double v = gld(R.g + kk), w = gld(R.W2 + kk);
+  const double v = R.ld(R.g + kk), w = R.ld(R.W2 + kk);
   *p = SC ? (REFL ? -v : v) * sc : (REFL ? -v : v);
   *wt = SC ? w * sc : w;
 }
@@ -223,15 +230,15 @@ __device__ __forceinline__ void sec_add(double wt, double del, double* a, double
 }
 
 // Terms k = k0, k0 + STEP, ... < k1 added in increasing k.
-template <bool REFL, bool SC, bool EXACT, int STEP>
-__device__ inline void secular_range(const Reflect& R, double sc, int k0, int k1, double po, double tau, double* s,
-                                     double* ds, bool* tiny) {
+template <bool REFL, bool SC, bool EXACT, int STEP, bool LDS>
+__device__ inline void secular_range(const Reflect<LDS>& R, double sc, int k0, int k1, double po, double tau,
+                                     double* s, double* ds, bool* tiny) {
   double a = *s, da = *ds;
   bool t = false;
 #pragma unroll 4
   for (int k = k0; k < k1; k += STEP) {
     double p, wt;
-    sec_pole<REFL, SC>(R, k, sc, &p, &wt);
+    sec_pole<REFL, SC, LDS>(R, k, sc, &p, &wt);
     sec_add<EXACT>(wt, (p - po) - tau, &a, &da, &t);
   }
   *s = a;
@@ -246,17 +253,17 @@ __device__ inline void secular_range(const Reflect& R, double sc, int k0, int k1
 // branch-free and keep several loads in flight. A group that meets a |delta|
 // below recip_fast's range repeats its sums in the exact form, with the same
 // terms in the same order.
-template <bool REFL, bool SC, int G>
-__device__ inline SecSums secular_sums_t(const Reflect& R, double sc, int i, double po, double tau, int sub) {
+template <bool REFL, bool SC, int G, bool LDS>
+__device__ inline SecSums secular_sums_t(const Reflect<LDS>& R, double sc, int i, double po, double tau, int sub) {
   double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
   bool tiny = false;
   const int kr = (i + 1) + ((sub - (i + 1)) & (G - 1));   // first k > i with k = sub (mod G)
-  secular_range<REFL, SC, false, G>(R, sc, sub, i + 1, po, tau, &psi, &dpsi, &tiny);
-  secular_range<REFL, SC, false, G>(R, sc, kr, R.K, po, tau, &phi, &dphi, &tiny);
+  secular_range<REFL, SC, false, G, LDS>(R, sc, sub, i + 1, po, tau, &psi, &dpsi, &tiny);
+  secular_range<REFL, SC, false, G, LDS>(R, sc, kr, R.K, po, tau, &phi, &dphi, &tiny);
   if (group_any<G>(tiny)) {
     psi = dpsi = phi = dphi = 0.0;
-    secular_range<REFL, SC, true, G>(R, sc, sub, i + 1, po, tau, &psi, &dpsi, &tiny);
-    secular_range<REFL, SC, true, G>(R, sc, kr, R.K, po, tau, &phi, &dphi, &tiny);
+    secular_range<REFL, SC, true, G, LDS>(R, sc, sub, i + 1, po, tau, &psi, &dpsi, &tiny);
+    secular_range<REFL, SC, true, G, LDS>(R, sc, kr, R.K, po, tau, &phi, &dphi, &tiny);
   }
   return SecSums{group_sum<G>(psi), group_sum<G>(dpsi), group_sum<G>(phi), group_sum<G>(dphi)};
 }
@@ -300,7 +307,7 @@ __device__ inline bool quad_root_in(double c, double a, double b, double lo, dou
 // by bisection. Root `idx` belongs to an aligned group of G lanes of the wave
 // (G = 64: the whole wave), which splits the sums over its lanes; every lane
 // of the group takes the same decisions from the same reduced sums.
-template <int G>
+template <int G, bool LDS>
 __device__ void secular_body(const int* __restrict__ Kdev, const double* __restrict__ g,
                              const double* __restrict__ W2, const double* __restrict__ rhop,
                              int* __restrict__ org, double* __restrict__ tau_out, int* __restrict__ iters,
@@ -310,7 +317,7 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
   const int sub = threadIdx.x & (G - 1);
   if (idx >= K) return;
   const double rho0 = *rhop;
-  Reflect R{g, W2, K, rho0 < 0.0};
+  Reflect<LDS> R{g, W2, K, rho0 < 0.0};
   const double rho = fabs(rho0);
   const double rinv = 1.0 / rho;
   const int i = R.refl ? K - 1 - idx : idx;  // root index in the reflected problem
@@ -318,7 +325,7 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
   // outside [2^-500, 2^500]: poles and weights divided by S (exactly) keep
   // every sum and quadratic away from overflow and underflow; the roots are
   // scaled back at the end. In between S = 1 and nothing is rescaled.
-  const double pmax = fmax(fabs(gld(g)), fabs(gld(g + K - 1)));   // the poles ascend
+  const double pmax = fmax(fabs(R.ld(g)), fabs(R.ld(g + K - 1)));   // the poles ascend
   const bool scaled = pmax != 0.0 && (pmax < 0x1p-500 || pmax > 0x1p500);
   const double S = scaled ? fmax(length_unit(pmax), 0x1p-1000) : 1.0;
   const double sc = 1.0 / S;
@@ -326,10 +333,10 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
   auto wt = [&](int k) { return R.wt(k) * sc; };
   auto sums = [&](double po, double tau) -> SecSums {
     if (scaled)
-      return R.refl ? secular_sums_t<true, true, G>(R, sc, i, po, tau, sub)
-                    : secular_sums_t<false, true, G>(R, sc, i, po, tau, sub);
-    return R.refl ? secular_sums_t<true, false, G>(R, sc, i, po, tau, sub)
-                  : secular_sums_t<false, false, G>(R, sc, i, po, tau, sub);
+      return R.refl ? secular_sums_t<true, true, G, LDS>(R, sc, i, po, tau, sub)
+                    : secular_sums_t<false, true, G, LDS>(R, sc, i, po, tau, sub);
+    return R.refl ? secular_sums_t<true, false, G, LDS>(R, sc, i, po, tau, sub)
+                  : secular_sums_t<false, false, G, LDS>(R, sc, i, po, tau, sub);
   };
 
   int o;
@@ -443,7 +450,7 @@ __device__ void loewner_body(const int* __restrict__ Kdev, const double* __restr
   const double rho0 = *rhop;
   const bool refl = rho0 < 0.0;
   const double rho = fabs(rho0);
-  Reflect R{g, nullptr, K, refl};
+  Reflect<false> R{g, nullptr, K, refl};
   const int jr = refl ? K - 1 - idx : idx;  // pole index in the reflected problem
   const double pj = R.pole(jr);
   double prod = 1.0;
@@ -594,14 +601,44 @@ __global__ __launch_bounds__(kDeflThreads) void deflate_kernel(StageLevel L) {
 __device__ __forceinline__ int small_item(int b) { return b * (256 / kSmallGroup) + threadIdx.x / kSmallGroup; }
 __device__ __forceinline__ int wave_item(int b) { return b * 4 + (threadIdx.x >> 6); }
 
-__global__ __launch_bounds__(256) void secular_kernel(StageLevel L, int maxit) {
-  const int j = find_job(L.boff_i, L.n, blockIdx.x);
+// Poles and weights are copied into LDS before the sums, so that every sum
+// reads them there rather than through the vector memory path, which bounded
+// the global form. A level whose orders are all at most kGroupMaxN runs in
+// 256-thread blocks (boff_i) with room for kGroupMaxN poles; otherwise a block
+// is four such item blocks of one job (boff_s, 1024 threads) with room for
+// kSecLdsN poles, and larger orders read global memory. The item layout and
+// every root's arithmetic are those of the 256-thread item kernels.
+constexpr int kSecLdsN = 8192;
+
+template <int G, bool LDS>
+__device__ __forceinline__ void secular_item(const Stage& s, const double* g, const double* W2, int maxit, int b,
+                                             int t) {
+  const int item = G == 64 ? b * 4 + (t >> 6) : b * (256 / kSmallGroup) + t / kSmallGroup;
+  secular_body<G, LDS>(s.counts, g, W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, item);
+}
+
+template <int BT>
+__global__ __launch_bounds__(BT) void secular_kernel(StageLevel L, int maxit) {
+  constexpr int CAP = BT == 1024 ? kSecLdsN : kGroupMaxN;
+  __shared__ double sm[2 * CAP];   // poles, then weights
+  const int* boff = BT == 1024 ? L.boff_s : L.boff_i;
+  const int j = find_job(boff, L.n, blockIdx.x);
   const Stage s = L.st[j];
-  const int b = blockIdx.x - L.boff_i[j];
-  if (s.N <= kGroupMaxN)
-    secular_body<kSmallGroup>(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, small_item(b));
-  else
-    secular_body<64>(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, wave_item(b));
+  const int b = (blockIdx.x - boff[j]) * (BT / 256) + (threadIdx.x >> 8), t = threadIdx.x & 255;
+  if (s.N <= CAP) {
+    const int K = min(max(*s.counts, 0), s.N);
+    for (int e = threadIdx.x; e < K; e += blockDim.x) {
+      sm[e] = gld(s.g + e);
+      sm[CAP + e] = gld(s.W2 + e);
+    }
+    __syncthreads();
+    if (s.N <= kGroupMaxN)
+      secular_item<kSmallGroup, true>(s, sm, sm + CAP, maxit, b, t);
+    else
+      secular_item<64, true>(s, sm, sm + CAP, maxit, b, t);
+  } else {
+    secular_item<64, false>(s, s.g, s.W2, maxit, b, t);
+  }
 }
 
 __global__ __launch_bounds__(256) void loewner_kernel(StageLevel L) {
@@ -632,7 +669,10 @@ __global__ __launch_bounds__(256) void merge_kernel(StageLevel L) {
 
 void launch_secular_level(const StageLevel& L, int maxit, hipStream_t st) {
   if (L.blocks_i <= 0) return;
-  hipLaunchKernelGGL(secular_kernel, dim3(L.blocks_i), dim3(256), 0, st, L, maxit);
+  if (L.nmax <= kGroupMaxN)
+    hipLaunchKernelGGL(secular_kernel<256>, dim3(L.blocks_i), dim3(256), 0, st, L, maxit);
+  else
+    hipLaunchKernelGGL(secular_kernel<1024>, dim3(L.blocks_s), dim3(1024), 0, st, L, maxit);
 }
 
 void launch_stage_level(const StageLevel& L, int maxit, hipStream_t st) {
