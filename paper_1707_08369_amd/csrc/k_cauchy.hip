@@ -37,15 +37,24 @@ __device__ void householder_dots_body(const Stage& s, int nv, const double* x0, 
 // the sum as it is. The fast pass records whether any nonzero weight met a
 // |delta| below recip_fast's range; the exact pass (div_by) then repeats it
 // with the same terms in the same order.
-template <int NV, bool EXACT, int STEP>
-__device__ inline void tmv_pass(const CauchyDesc& d, const ColDesc& cd, const double* x0, const double* x1,
-                                const double* x2, int j0, double (&acc)[3], bool* tiny) {
+// Row poles rg and weights rz: the descriptor's arrays in global memory, or
+// (LDS) the block's copy of them.
+template <bool LDS>
+__device__ __forceinline__ double tmv_ld(const double* p) {
+  if (LDS) return *((const __attribute__((address_space(3))) double*)p);
+  return gld(p);
+}
+
+template <int NV, bool EXACT, int STEP, bool LDS>
+__device__ inline void tmv_pass(const CauchyDesc& d, const ColDesc& cd, const double* rg, const double* rz,
+                                const double* x0, const double* x1, const double* x2, int j0, double (&acc)[3],
+                                bool* tiny) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   bool t = false;
 #pragma unroll 4
   for (int j = j0; j < d.N; j += STEP) {
-    const double z = gld(d.rzeta + j);
-    const double del = (gld(d.rg + j) - cd.o) - cd.t;
+    const double z = tmv_ld<LDS>(rz + j);
+    const double del = (tmv_ld<LDS>(rg + j) - cd.o) - cd.t;
     double w;
     if (EXACT) {
       w = (z == 0.0) ? 0.0 : div_by(z, del);
@@ -66,19 +75,20 @@ __device__ inline void tmv_pass(const CauchyDesc& d, const ColDesc& cd, const do
 
 // The column belongs to an aligned group of G lanes (lanes over rows, summed
 // across the group afterwards).
-template <int NV, int G>
-__device__ inline void tmv_live(const CauchyDesc& d, const ColDesc& cd, const double* x0, const double* x1,
-                                const double* x2, int sub, double (&acc)[3]) {
+template <int NV, int G, bool LDS>
+__device__ inline void tmv_live(const CauchyDesc& d, const ColDesc& cd, const double* rg, const double* rz,
+                                const double* x0, const double* x1, const double* x2, int sub, double (&acc)[3]) {
   bool tiny = false;
-  tmv_pass<NV, false, G>(d, cd, x0, x1, x2, sub, acc, &tiny);
-  if (group_any<G>(tiny)) tmv_pass<NV, true, G>(d, cd, x0, x1, x2, sub, acc, &tiny);
+  tmv_pass<NV, false, G, LDS>(d, cd, rg, rz, x0, x1, x2, sub, acc, &tiny);
+  if (group_any<G>(tiny)) tmv_pass<NV, true, G, LDS>(d, cd, rg, rz, x0, x1, x2, sub, acc, &tiny);
 }
 
 // Column c of y = C~^T x, for an aligned group of G lanes.
-template <int G>
-__device__ void cauchy_tmatvec_body(const CauchyDesc& d, const double* __restrict__ hx, int nv,
-                                    const double* __restrict__ x0, const double* __restrict__ x1,
-                                    const double* __restrict__ x2, double* y0, double* y1, double* y2, int c) {
+template <int G, bool LDS>
+__device__ void cauchy_tmatvec_body(const CauchyDesc& d, const double* rg, const double* rz,
+                                    const double* __restrict__ hx, int nv, const double* __restrict__ x0,
+                                    const double* __restrict__ x1, const double* __restrict__ x2, double* y0,
+                                    double* y1, double* y2, int c) {
   if (*d.status & kStFatal) return;
   const int sub = threadIdx.x & (G - 1);
   if (c >= d.N) return;
@@ -86,11 +96,11 @@ __device__ void cauchy_tmatvec_body(const CauchyDesc& d, const double* __restric
   if (cd.type == 0) {
     double acc[3];
     if (nv > 2)
-      tmv_live<3, G>(d, cd, x0, x1, x2, sub, acc);
+      tmv_live<3, G, LDS>(d, cd, rg, rz, x0, x1, x2, sub, acc);
     else if (nv > 1)
-      tmv_live<2, G>(d, cd, x0, x1, x2, sub, acc);
+      tmv_live<2, G, LDS>(d, cd, rg, rz, x0, x1, x2, sub, acc);
     else
-      tmv_live<1, G>(d, cd, x0, x1, x2, sub, acc);
+      tmv_live<1, G, LDS>(d, cd, rg, rz, x0, x1, x2, sub, acc);
     const double a0 = group_sum<G>(acc[0]);
     const double a1 = nv > 1 ? group_sum<G>(acc[1]) : 0.0;
     const double a2 = nv > 2 ? group_sum<G>(acc[2]) : 0.0;
@@ -118,26 +128,49 @@ __global__ void householder_dots(StageLevel L) {
   householder_dots_body(s, t.nv, t.x[0], x1, x2, (blockIdx.x - L.boff_t[j]) * 256 + threadIdx.x);
 }
 
-__global__ __launch_bounds__(256) void cauchy_tmatvec_kernel(StageLevel L) {
-  const int j = find_job(L.boff_i, L.n, blockIdx.x);
+// Block shapes as in the secular kernel: 256 threads (boff_i) when every order
+// of the level is at most kGroupMaxN, else four item blocks of one job (boff_s).
+// The row poles and weights are copied into LDS first for orders up to the
+// block's room; the vectors stream from global memory.
+constexpr int kTmvLdsN = 8192;
+
+template <int BT>
+__global__ __launch_bounds__(BT) void cauchy_tmatvec_kernel(StageLevel L) {
+  constexpr int CAP = BT == 1024 ? kTmvLdsN : kGroupMaxN;
+  __shared__ double sm[2 * CAP];   // row poles, then weights
+  const int* boff = BT == 1024 ? L.boff_s : L.boff_i;
+  const int j = find_job(boff, L.n, blockIdx.x);
   const TmvJob t = L.tmv[j];
   if (t.nv <= 0) return;
   const Stage s = L.st[j];
+  const CauchyDesc d = desc_of(s);
   const double* x1 = t.nv > 1 ? t.x[1] : t.x[0];
   const double* x2 = t.nv > 2 ? t.x[2] : t.x[0];
-  const int b = blockIdx.x - L.boff_i[j];
-  if (s.N <= kGroupMaxN)
-    cauchy_tmatvec_body<kSmallGroup>(desc_of(s), s.hx, t.nv, t.x[0], x1, x2, t.y[0], t.y[1], t.y[2],
-                                     b * (256 / kSmallGroup) + threadIdx.x / kSmallGroup);
-  else
-    cauchy_tmatvec_body<64>(desc_of(s), s.hx, t.nv, t.x[0], x1, x2, t.y[0], t.y[1], t.y[2],
-                            b * 4 + (threadIdx.x >> 6));
+  const int b = (blockIdx.x - boff[j]) * (BT / 256) + (threadIdx.x >> 8), tt = threadIdx.x & 255;
+  const int item = s.N <= kGroupMaxN ? b * (256 / kSmallGroup) + tt / kSmallGroup : b * 4 + (tt >> 6);
+  if (s.N <= CAP) {
+    for (int e = threadIdx.x; e < s.N; e += blockDim.x) {
+      sm[e] = gld(d.rg + e);
+      sm[CAP + e] = gld(d.rzeta + e);
+    }
+    __syncthreads();
+    if (s.N <= kGroupMaxN)
+      cauchy_tmatvec_body<kSmallGroup, true>(d, sm, sm + CAP, s.hx, t.nv, t.x[0], x1, x2, t.y[0], t.y[1], t.y[2],
+                                             item);
+    else
+      cauchy_tmatvec_body<64, true>(d, sm, sm + CAP, s.hx, t.nv, t.x[0], x1, x2, t.y[0], t.y[1], t.y[2], item);
+  } else {
+    cauchy_tmatvec_body<64, false>(d, d.rg, d.rzeta, s.hx, t.nv, t.x[0], x1, x2, t.y[0], t.y[1], t.y[2], item);
+  }
 }
 
 void launch_cauchy_tmatvec_level(const StageLevel& L, hipStream_t st) {
   if (L.n <= 0 || !L.tmv || L.blocks_i <= 0) return;
   hipLaunchKernelGGL(householder_dots, dim3(L.blocks_t), dim3(256), 0, st, L);
-  hipLaunchKernelGGL(cauchy_tmatvec_kernel, dim3(L.blocks_i), dim3(256), 0, st, L);
+  if (L.nmax <= kGroupMaxN)
+    hipLaunchKernelGGL(cauchy_tmatvec_kernel<256>, dim3(L.blocks_i), dim3(256), 0, st, L);
+  else
+    hipLaunchKernelGGL(cauchy_tmatvec_kernel<1024>, dim3(L.blocks_s), dim3(1024), 0, st, L);
 }
 
 }  // namespace svdu

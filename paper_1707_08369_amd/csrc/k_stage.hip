@@ -437,7 +437,7 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
 // in (0, 1] pairing root i with pole i (i < j) or i+1 (i >= j), last with rho.
 // Pole `idx` belongs to an aligned group of G lanes (lanes over roots).
 // ---------------------------------------------------------------------------
-template <int G>
+template <int G, bool LDS>
 __device__ void loewner_body(const int* __restrict__ Kdev, const double* __restrict__ g,
                              const double* __restrict__ rhop, const int* __restrict__ org,
                              const double* __restrict__ tau, double* __restrict__ what, const int* status,
@@ -450,7 +450,7 @@ __device__ void loewner_body(const int* __restrict__ Kdev, const double* __restr
   const double rho0 = *rhop;
   const bool refl = rho0 < 0.0;
   const double rho = fabs(rho0);
-  Reflect<false> R{g, nullptr, K, refl};
+  Reflect<LDS> R{g, nullptr, K, refl};
   const int jr = refl ? K - 1 - idx : idx;  // pole index in the reflected problem
   const double pj = R.pole(jr);
   double prod = 1.0;
@@ -474,7 +474,7 @@ __device__ void loewner_body(const int* __restrict__ Kdev, const double* __restr
 // Column scales 1/|c_i| with |c_i|^2 = sum_k what_k^2 / delta_ki^2, and mu.
 // Root i belongs to an aligned group of G lanes (lanes over poles).
 // ---------------------------------------------------------------------------
-template <int G>
+template <int G, bool LDS>
 __device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restrict__ g,
                              const double* __restrict__ what, const int* __restrict__ org,
                              const double* __restrict__ tau, double* __restrict__ cs, double* __restrict__ mu,
@@ -484,7 +484,8 @@ __device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restr
   const int lane = threadIdx.x & 63;
   if (i >= K) return;
   const int k0 = lane & (G - 1), step = G;
-  const double go = g[org[i]];
+  auto ld = [](const double* p) { return Reflect<LDS>::ld(p); };   // poles and weights: LDS copy or global
+  const double go = ld(g + org[i]);
   const double ti = tau[i];
   // One branch-free pass for the largest term and the unscaled sum of
   // squares. With the largest term in [2^-450, 2^450] no square overflows and
@@ -495,9 +496,9 @@ __device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restr
   bool tiny = false;
 #pragma unroll 4
   for (int k = k0; k < K; k += step) {
-    const double del = (gld(g + k) - go) - ti;
+    const double del = (ld(g + k) - go) - ti;
     tiny |= recip_tiny(del);
-    const double t = gld(what + k) * recip_fast(del);
+    const double t = ld(what + k) * recip_fast(del);
     mx = fmax(mx, fabs(t));
     ss = __builtin_fma(t, t, ss);
   }
@@ -506,12 +507,12 @@ __device__ void colnorm_body(const int* __restrict__ Kdev, const double* __restr
   double inv = 1.0;
   if (scaled) {
     mx = 0.0;
-    for (int k = k0; k < K; k += step) mx = fmax(mx, fabs(div_by(gld(what + k), (gld(g + k) - go) - ti)));
+    for (int k = k0; k < K; k += step) mx = fmax(mx, fabs(div_by(ld(what + k), (ld(g + k) - go) - ti)));
     mx = group_max<G>(mx);
     inv = (mx > 0.0) ? 1.0 / mx : 1.0;
     ss = 0.0;
     for (int k = k0; k < K; k += step) {
-      const double t = div_by(gld(what + k), (gld(g + k) - go) - ti) * inv;
+      const double t = div_by(ld(what + k), (ld(g + k) - go) - ti) * inv;
       ss += t * t;
     }
   }
@@ -596,10 +597,9 @@ __global__ __launch_bounds__(kDeflThreads) void deflate_kernel(StageLevel L) {
 }
 
 // Item kernels: problems with N <= kGroupMaxN give each item a group of
-// kSmallGroup lanes (256 / kSmallGroup items per block), larger ones a whole
-// wave (4 per block); the host sizes boff_i to match.
-__device__ __forceinline__ int small_item(int b) { return b * (256 / kSmallGroup) + threadIdx.x / kSmallGroup; }
-__device__ __forceinline__ int wave_item(int b) { return b * 4 + (threadIdx.x >> 6); }
+// kSmallGroup lanes (256 / kSmallGroup items per 256 threads), larger ones a
+// whole wave (4 per 256 threads); the host sizes boff_i (256-thread blocks)
+// and boff_s (1024-thread blocks, four of those) to match.
 
 // Poles and weights are copied into LDS before the sums, so that every sum
 // reads them there rather than through the vector memory path, which bounded
@@ -641,24 +641,54 @@ __global__ __launch_bounds__(BT) void secular_kernel(StageLevel L, int maxit) {
   }
 }
 
-__global__ __launch_bounds__(256) void loewner_kernel(StageLevel L) {
-  const int j = find_job(L.boff_i, L.n, blockIdx.x);
+// Block shapes and the LDS copy of the poles as in the secular kernel; the
+// roots' origins and offsets stream from global memory.
+template <int BT>
+__global__ __launch_bounds__(BT) void loewner_kernel(StageLevel L) {
+  constexpr int CAP = BT == 1024 ? kSecLdsN : kGroupMaxN;
+  __shared__ double sg[CAP];
+  const int* boff = BT == 1024 ? L.boff_s : L.boff_i;
+  const int j = find_job(boff, L.n, blockIdx.x);
   const Stage s = L.st[j];
-  const int b = blockIdx.x - L.boff_i[j];
-  if (s.N <= kGroupMaxN)
-    loewner_body<kSmallGroup>(s.counts, s.g, s.rho, s.org, s.tau, s.what, s.status, small_item(b));
-  else
-    loewner_body<64>(s.counts, s.g, s.rho, s.org, s.tau, s.what, s.status, wave_item(b));
+  const int b = (blockIdx.x - boff[j]) * (BT / 256) + (threadIdx.x >> 8), t = threadIdx.x & 255;
+  if (s.N <= CAP) {
+    const int K = min(max(*s.counts, 0), s.N);
+    for (int e = threadIdx.x; e < K; e += blockDim.x) sg[e] = gld(s.g + e);
+    __syncthreads();
+    if (s.N <= kGroupMaxN)
+      loewner_body<kSmallGroup, true>(s.counts, sg, s.rho, s.org, s.tau, s.what, s.status,
+                                      b * (256 / kSmallGroup) + t / kSmallGroup);
+    else
+      loewner_body<64, true>(s.counts, sg, s.rho, s.org, s.tau, s.what, s.status, b * 4 + (t >> 6));
+  } else {
+    loewner_body<64, false>(s.counts, s.g, s.rho, s.org, s.tau, s.what, s.status, b * 4 + (t >> 6));
+  }
 }
 
-__global__ __launch_bounds__(256) void colnorm_kernel(StageLevel L) {
-  const int j = find_job(L.boff_i, L.n, blockIdx.x);
+// Block shapes and the LDS copy of the poles and weights as in the secular kernel.
+template <int BT>
+__global__ __launch_bounds__(BT) void colnorm_kernel(StageLevel L) {
+  constexpr int CAP = BT == 1024 ? kSecLdsN : kGroupMaxN;
+  __shared__ double sm[2 * CAP];   // poles, then weights
+  const int* boff = BT == 1024 ? L.boff_s : L.boff_i;
+  const int j = find_job(boff, L.n, blockIdx.x);
   const Stage s = L.st[j];
-  const int b = blockIdx.x - L.boff_i[j];
-  if (s.N <= kGroupMaxN)
-    colnorm_body<kSmallGroup>(s.counts, s.g, s.what, s.org, s.tau, s.cs, s.mu, s.status, small_item(b));
-  else
-    colnorm_body<64>(s.counts, s.g, s.what, s.org, s.tau, s.cs, s.mu, s.status, wave_item(b));
+  const int b = (blockIdx.x - boff[j]) * (BT / 256) + (threadIdx.x >> 8), t = threadIdx.x & 255;
+  if (s.N <= CAP) {
+    const int K = min(max(*s.counts, 0), s.N);
+    for (int e = threadIdx.x; e < K; e += blockDim.x) {
+      sm[e] = gld(s.g + e);
+      sm[CAP + e] = gld(s.what + e);
+    }
+    __syncthreads();
+    if (s.N <= kGroupMaxN)
+      colnorm_body<kSmallGroup, true>(s.counts, sm, sm + CAP, s.org, s.tau, s.cs, s.mu, s.status,
+                                      b * (256 / kSmallGroup) + t / kSmallGroup);
+    else
+      colnorm_body<64, true>(s.counts, sm, sm + CAP, s.org, s.tau, s.cs, s.mu, s.status, b * 4 + (t >> 6));
+  } else {
+    colnorm_body<64, false>(s.counts, s.g, s.what, s.org, s.tau, s.cs, s.mu, s.status, b * 4 + (t >> 6));
+  }
 }
 
 __global__ __launch_bounds__(256) void merge_kernel(StageLevel L) {
@@ -679,8 +709,14 @@ void launch_stage_level(const StageLevel& L, int maxit, hipStream_t st) {
   if (L.n <= 0 || L.blocks_w <= 0) return;
   hipLaunchKernelGGL(deflate_kernel, dim3(L.n), dim3(kDeflThreads), 0, st, L);
   launch_secular_level(L, maxit, st);
-  hipLaunchKernelGGL(loewner_kernel, dim3(L.blocks_i), dim3(256), 0, st, L);
-  hipLaunchKernelGGL(colnorm_kernel, dim3(L.blocks_i), dim3(256), 0, st, L);
+  if (L.nmax <= kGroupMaxN)
+    hipLaunchKernelGGL(loewner_kernel<256>, dim3(L.blocks_i), dim3(256), 0, st, L);
+  else
+    hipLaunchKernelGGL(loewner_kernel<1024>, dim3(L.blocks_s), dim3(1024), 0, st, L);
+  if (L.nmax <= kGroupMaxN)
+    hipLaunchKernelGGL(colnorm_kernel<256>, dim3(L.blocks_i), dim3(256), 0, st, L);
+  else
+    hipLaunchKernelGGL(colnorm_kernel<1024>, dim3(L.blocks_s), dim3(1024), 0, st, L);
   hipLaunchKernelGGL(merge_kernel, dim3(L.blocks_t), dim3(256), 0, st, L);
 }
 
