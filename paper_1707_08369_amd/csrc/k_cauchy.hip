@@ -11,25 +11,25 @@ namespace svdu {
 // ---------------------------------------------------------------------------
 // y = C~^T x
 // ---------------------------------------------------------------------------
-__device__ void householder_dots_body(const Stage& s, int nv, const double* x0, const double* x1,
-                                      const double* x2, int c) {
-  if (*s.status & kStFatal) return;
-  const int K = s.counts[0];
-  if (c >= K) return;
-  const int sz = s.csize[c];
-  if (sz < 2) return;
-  const int f = s.cfirst[c];
+// Dot products of the Householder vectors of clusters of equal poles with up
+// to three vectors: hx[3 c + v] = sum over members of rh_j x_v[j]. A block
+// takes 256 clusters, one thread each; clusters of more than kWideDots
+// members are listed and done by the whole block (fixed-order block sums).
+constexpr int kWideDots = 64;
+
+__device__ void householder_dots_member_sum(const Stage& s, int f, int e, int k0, int step, int nv,
+                                            const double* x0, const double* x1, const double* x2, double* a) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int k = f; k < f + sz; ++k) {
+  for (int k = f + k0; k < e; k += step) {
     const int j = s.col_of[s.Llist[k]];
     const double h = s.rh[j];
     a0 += h * x0[j];
     if (nv > 1) a1 += h * x1[j];
     if (nv > 2) a2 += h * x2[j];
   }
-  s.hx[3 * c] = a0;
-  s.hx[3 * c + 1] = a1;
-  s.hx[3 * c + 2] = a2;
+  a[0] = a0;
+  a[1] = a1;
+  a[2] = a2;
 }
 
 // One pass of y = C~^T x over the rows of a live column, NV vectors, rows
@@ -118,14 +118,43 @@ __device__ void cauchy_tmatvec_body(const CauchyDesc& d, const double* rg, const
 }
 
 // Level kernels over the jobs of a StageLevel (jobs with nv = 0 do nothing).
-__global__ void householder_dots(StageLevel L) {
+__global__ __launch_bounds__(256) void householder_dots(StageLevel L) {
+  __shared__ int nwide, wide[256];
+  __shared__ double shd[4];
   const int j = find_job(L.boff_t, L.n, blockIdx.x);
   const TmvJob t = L.tmv[j];
   if (t.nv <= 0) return;
   const Stage s = L.st[j];
+  if (*s.status & kStFatal) return;
   const double* x1 = t.nv > 1 ? t.x[1] : t.x[0];
   const double* x2 = t.nv > 2 ? t.x[2] : t.x[0];
-  householder_dots_body(s, t.nv, t.x[0], x1, x2, (blockIdx.x - L.boff_t[j]) * 256 + threadIdx.x);
+  const int K = s.counts[0];
+  const int c = (blockIdx.x - L.boff_t[j]) * 256 + threadIdx.x;
+  if (threadIdx.x == 0) nwide = 0;
+  __syncthreads();
+  if (c < K) {
+    const int sz = s.csize[c];
+    if (sz > kWideDots) {
+      wide[atomicAdd(&nwide, 1)] = c;
+    } else if (sz >= 2) {
+      const int f = s.cfirst[c];
+      double a[3];
+      householder_dots_member_sum(s, f, f + sz, 0, 1, t.nv, t.x[0], x1, x2, a);
+      s.hx[3 * c] = a[0];
+      s.hx[3 * c + 1] = a[1];
+      s.hx[3 * c + 2] = a[2];
+    }
+  }
+  __syncthreads();
+  for (int q = 0; q < nwide; ++q) {
+    const int cw = wide[q], f = s.cfirst[cw];
+    double a[3];
+    householder_dots_member_sum(s, f, f + s.csize[cw], threadIdx.x, blockDim.x, t.nv, t.x[0], x1, x2, a);
+    for (int v = 0; v < 3; ++v) {
+      const double r = block_sum(a[v], shd);
+      if (threadIdx.x == 0) s.hx[3 * cw + v] = r;
+    }
+  }
 }
 
 // Block shapes as in the secular kernel: 256 threads (boff_i) when every order

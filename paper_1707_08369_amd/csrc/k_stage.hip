@@ -25,6 +25,8 @@ namespace svdu {
 // Deflation: one block of 1024 threads walks the N sorted poles.
 // ---------------------------------------------------------------------------
 constexpr int kDeflThreads = 1024;
+constexpr int kWideCluster = 64;   // larger clusters of equal poles are handled by a whole block
+constexpr int kWideMax = 64;       // such clusters listed per block (more: one thread each, as the rest)
 
 __device__ void deflate_body(const Stage& s) {
   __shared__ int shi[64];
@@ -106,13 +108,24 @@ __device__ void deflate_body(const Stage& s) {
     carry += tot;
   }
   const int K = carry;
+  __shared__ int nwide, wide[kWideMax];
+  if (tid == 0) nwide = 0;
   __syncthreads();
-  // per cluster: pole, weight, Householder vector, row descriptors of members
+  // per cluster: pole, weight, Householder vector, row descriptors of members;
+  // a cluster of more than kWideCluster members (the exact zero block of D_v
+  // is one) is listed for the whole block instead of one thread
   for (int c = tid; c < K; c += nt) {
     const int f = s.cfirst[c];
     const int e = (c + 1 < K) ? s.cfirst[c + 1] : Nl;
     const int sz = e - f;
     s.csize[c] = sz;
+    if (sz > kWideCluster) {
+      const int q = atomicAdd(&nwide, 1);
+      if (q < kWideMax) {
+        wide[q] = c;
+        continue;
+      }
+    }
     const double gc = s.dsort[s.Llist[f]];
     s.g[c] = gc;
     double w2 = 0.0;
@@ -136,6 +149,38 @@ __device__ void deflate_body(const Stage& s) {
       s.rcl[j] = c;
       s.flags[j] = (k == f) ? 0 : 2;
       s.rh[j] = (sz >= 2) ? (s.zs[t] / w + (k == f ? sg : 0.0)) / hn : 0.0;
+    }
+  }
+  __syncthreads();
+  // the listed clusters, each by the whole block (weight by a fixed-order block sum)
+  const int nw = min(nwide, kWideMax);
+  for (int q = 0; q < nw; ++q) {
+    const int c = wide[q];
+    const int f = s.cfirst[c];
+    const int e = (c + 1 < K) ? s.cfirst[c + 1] : Nl;
+    double loc = 0.0;
+    for (int k = f + tid; k < e; k += nt) {
+      const double zz = s.zs[s.Llist[k]];
+      loc += zz * zz;
+    }
+    const double w2 = block_sum(loc, shd);
+    const double w = sqrt(w2);
+    const double gc = s.dsort[s.Llist[f]];
+    if (tid == 0) {
+      s.g[c] = gc;
+      s.W2[c] = w2;
+      s.W[c] = w;
+    }
+    const double v0 = s.zs[s.Llist[f]] / w;
+    const double sg = (v0 >= 0.0) ? 1.0 : -1.0;
+    const double hn = sqrt(2.0 * (1.0 + fabs(v0)));
+    for (int k = f + tid; k < e; k += nt) {
+      const int t = s.Llist[k];
+      const int j = s.col_of[t];
+      s.rg[j] = gc;
+      s.rcl[j] = c;
+      s.flags[j] = (k == f) ? 0 : 2;
+      s.rh[j] = (s.zs[t] / w + (k == f ? sg : 0.0)) / hn;
     }
   }
   __syncthreads();
