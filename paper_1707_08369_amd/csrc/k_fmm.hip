@@ -269,17 +269,72 @@ __device__ __forceinline__ void box_cr(const FmmDev& F, int id, double* c, doubl
 }
 
 // ---------------------------------------------------------------------------
+// Wide groups (more than kWideGroup members; with n > m the exact zero block
+// of the right-hand eigen-updates is one): sum_{q in group} w_j X[r, j] for the
+// rows r0 + 32 u + tid / 8 (u < NSUB) by a whole 256-thread block. The
+// members' columns and weights go through LDS in rounds of kGroupChunk; the 8
+// threads of a row add every eighth member and are summed in a fixed order.
+// Called by the whole block; every thread of a row receives its sum.
+// ---------------------------------------------------------------------------
+constexpr int kWideGroup = 64;
+constexpr int kGroupChunk = 1024;
+struct GroupStage {
+  int col[kGroupChunk];
+  double w[kGroupChunk];
+};
+
+template <int NSUB>
+__device__ void wide_group_rows(const double* X, int ldx, int R, int r0, const Stage& s, int f, int sz,
+                                const double* wt, GroupStage& gs, double (&acc)[NSUB]) {
+  const int rr = threadIdx.x >> 3, p = threadIdx.x & 7;
+#pragma unroll
+  for (int u = 0; u < NSUB; ++u) acc[u] = 0.0;
+  for (int m0 = 0; m0 < sz; m0 += kGroupChunk) {
+    const int n = min(kGroupChunk, sz - m0);
+    __syncthreads();   // the previous round is read
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+      const int j = gld(s.col_of + gld(s.Llist + f + m0 + e));
+      gs.col[e] = j;
+      gs.w[e] = gld(wt + j);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NSUB; ++u) {
+      const int r = r0 + 32 * u + rr;
+      if (r < R) {
+        const double* xr = X + (size_t)r * ldx;
+        double a = acc[u];
+        for (int e = p; e < n; e += 8) a += gs.w[e] * gld(xr + gs.col[e]);
+        acc[u] = a;
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NSUB; ++u) {
+    double a = acc[u];
+    a += __shfl_xor(a, 1, 64);
+    a += __shfl_xor(a, 2, 64);
+    a += __shfl_xor(a, 4, 64);
+    acc[u] = a;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // charges B[k][r] = sum_{j in group k} zeta_j X[r, j]  (transpose through LDS)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void fmm_charges(int R, const double* __restrict__ X, int ldx, Stage s,
                                                    double* __restrict__ B) {
   __shared__ double tile[32][33];
+  __shared__ int nwide, widek[32];
+  __shared__ GroupStage gs;
   if (*s.status & kStFatal) return;
   const int K = s.counts[0];
   const int k0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  if (threadIdx.x == 0) nwide = 0;
+  __syncthreads();
   // the group of charge k (the same for all 32 rows): one member, or several
-  // exactly equal poles
+  // exactly equal poles; wide groups are left to the whole block below
   const int k = k0 + tx;
   int f = 0, sz = 0, j1 = 0;
   double z1 = 0.0;
@@ -289,10 +344,12 @@ __global__ __launch_bounds__(256) void fmm_charges(int R, const double* __restri
     j1 = gld(s.col_of + gld(s.Llist + f));
     z1 = gld(s.rzeta + j1);
   }
+  const bool wide = k < K && sz > kWideGroup;
+  if (ty == 0 && wide) widek[atomicAdd(&nwide, 1)] = tx;
   for (int rr = ty; rr < 32; rr += 8) {
     const int r = r0 + rr;
     double v = 0.0;
-    if (r < R && k < K) {
+    if (r < R && k < K && !wide) {
       if (sz == 1) {
         v += z1 * gld(X + (size_t)r * ldx + j1);
       } else {
@@ -303,6 +360,13 @@ __global__ __launch_bounds__(256) void fmm_charges(int R, const double* __restri
       }
     }
     tile[rr][tx] = v;
+  }
+  __syncthreads();
+  for (int q = 0; q < nwide; ++q) {
+    const int kx = widek[q], kk = k0 + kx;
+    double acc[1];
+    wide_group_rows<1>(X, ldx, R, r0, s, gld(s.cfirst + kk), gld(s.csize + kk), s.rzeta, gs, acc);
+    if ((threadIdx.x & 7) == 0) tile[threadIdx.x >> 3][kx] = acc[0];
   }
   __syncthreads();
   for (int kk = ty; kk < 32; kk += 8) {
@@ -898,14 +962,27 @@ __global__ __launch_bounds__(256) void fmm_direct_roots(FmmDev F, Stage s, doubl
 // ---------------------------------------------------------------------------
 // Deflated output columns: Xo[r, c] = X[r, mem] - 2 h_c sum_{j in group} rh_j X[r, j]
 // ---------------------------------------------------------------------------
-__global__ void fmm_group_dots(int R, const double* __restrict__ X, int ldx, Stage s, double* __restrict__ hX) {
+__global__ __launch_bounds__(256) void fmm_group_dots(int R, const double* __restrict__ X, int ldx, Stage s,
+                                                      double* __restrict__ hX) {
+  __shared__ GroupStage gs;
   if (*s.status & kStFatal) return;
   const int c = blockIdx.x;
   const int K = s.counts[0];
   if (c >= K || s.csize[c] < 2) return;
+  const int f = s.cfirst[c], sz = s.csize[c];
+  if (sz > kWideGroup) {   // the block's 256 rows together
+    double acc[8];
+    const int r0 = blockIdx.y * blockDim.x;
+    wide_group_rows<8>(X, ldx, R, r0, s, f, sz, s.rh, gs, acc);
+    if ((threadIdx.x & 7) == 0)
+      for (int u = 0; u < 8; ++u) {
+        const int r = r0 + 32 * u + (threadIdx.x >> 3);
+        if (r < R) hX[(size_t)c * R + r] = acc[u];
+      }
+    return;
+  }
   const int r = blockIdx.y * blockDim.x + threadIdx.x;
   if (r >= R) return;
-  const int f = s.cfirst[c], sz = s.csize[c];
   double a = 0.0;
   for (int q = f; q < f + sz; ++q) {
     const int j = s.col_of[s.Llist[q]];
@@ -914,21 +991,21 @@ __global__ void fmm_group_dots(int R, const double* __restrict__ X, int ldx, Sta
   hX[(size_t)c * R + r] = a;
 }
 
-__global__ void fmm_deflated_cols(int R, const double* __restrict__ X, int ldx, Stage s,
-                                  const double* __restrict__ hX, double* __restrict__ Xo, int ldo,
-                                  const double* __restrict__ colscale) {
+// Block: 32 deflated columns (consecutive output and source columns for a
+// merged group) x 8 rows, so that loads and stores run along the rows.
+__global__ __launch_bounds__(256) void fmm_deflated_cols(int R, const double* __restrict__ X, int ldx, Stage s,
+                                                         const double* __restrict__ hX, double* __restrict__ Xo,
+                                                         int ldo, const double* __restrict__ colscale) {
   if (*s.status & kStFatal) return;
   const int Kd = s.counts[1], K = s.counts[0];
-  const int r = blockIdx.y * blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  for (int kd = blockIdx.x; kd < Kd; kd += gridDim.x) {
-    const int P = s.dpos[kd];
-    const int mem = s.cmem[P], cl = s.ccl[P];
-    const double h = s.ch[P];
-    double v = X[(size_t)r * ldx + mem];
-    if (h != 0.0 && cl >= 0 && cl < K) v -= 2.0 * h * hX[(size_t)cl * R + r];
-    Xo[(size_t)r * ldo + P] = (colscale ? colscale[P] : 1.0) * v;
-  }
+  const int kd = blockIdx.x * 32 + (threadIdx.x & 31), r = blockIdx.y * 8 + (threadIdx.x >> 5);
+  if (kd >= Kd || r >= R) return;
+  const int P = s.dpos[kd];
+  const int mem = s.cmem[P], cl = s.ccl[P];
+  const double h = s.ch[P];
+  double v = X[(size_t)r * ldx + mem];
+  if (h != 0.0 && cl >= 0 && cl < K) v -= 2.0 * h * hX[(size_t)cl * R + r];
+  Xo[(size_t)r * ldo + P] = (colscale ? colscale[P] : 1.0) * v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1056,7 +1133,7 @@ int fmm_launch(int R, const double* X, int ldx, const Stage& s, const FmmPrepare
   }
   if (K < N) {
     hipLaunchKernelGGL(fmm_group_dots, dim3(std::max(K, 1), rb), dim3(256), 0, st, R, X, ldx, s, hX);
-    hipLaunchKernelGGL(fmm_deflated_cols, dim3(std::min(N - K, 4096), rb), dim3(256), 0, st, R, X, ldx, s, hX,
+    hipLaunchKernelGGL(fmm_deflated_cols, dim3((N - K + 31) / 32, (R + 7) / 8), dim3(256), 0, st, R, X, ldx, s, hX,
                        Xo, ldo, colscale);
   }
   return 0;
