@@ -25,6 +25,11 @@
 // singularity at >= 3 radii (error ~ (3 + sqrt 8)^-p per interpolation).
 // Leaf pairs that never become admissible are summed directly (P2P) with the
 // pole-relative differences (g_k - d_org) - tau of the direct path.
+// Points that would stretch a box across a gap stay out of the intervals: the
+// extreme root outside the pole range, an extreme pole far from the others
+// (applied to every root directly) and the root in its gap; those roots are
+// evaluated on their own, from the expansions of the boxes admissible for them
+// plus their near leaves exactly (M2P + P2P).
 #include <math.h>
 #include <stdint.h>
 
