@@ -357,7 +357,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(the update shards by rows with one all-reduce of the projections; not built).",
               file=sys.stderr)
         sys.exit(2)
