@@ -354,6 +354,7 @@ GemmList build_gemm_list(std::vector<GemmJob> jobs, int* counter, BlobWriter& B)
   G.boff = B.put(o);
   G.job = B.put(jobs);
   G.counter = counter;
+  for (const GemmJob& j : jobs) G.copy |= (j.d.Llist != nullptr) ? 1 : 0;
   return G;
 }
 
@@ -464,10 +465,13 @@ void build_plan(const std::vector<Update>& ups_in, int precision, char* dev_base
       GemmJob g[2];
       if (lev == 0) {
         g[0] = make_gemm_job(u.m, u.U, u.ldu, desc_of(L.st[0]), L.TL, u.m, precision);
-        g[1] = make_gemm_job(u.n, u.V, u.ldv, desc_of(L.st[2]), L.TR, u.n, precision);
+        const CauchyDesc dr = desc_of(L.st[2]);
+        g[1] = make_gemm_job(u.n, u.V, u.ldv, u.n > u.m ? with_members(dr, L.st[2]) : dr, L.TR, u.n, precision);
       } else {
         g[0] = make_gemm_job(u.m, L.TL, u.m, desc_of(L.st[1]), u.U_out, u.ldu_out, precision);
-        g[1] = make_gemm_job(u.n, L.TR, u.n, desc_of(L.st[3], L.signs), u.V_out, u.ldv_out, precision);
+        const CauchyDesc dr = desc_of(L.st[3], L.signs);
+        g[1] = make_gemm_job(u.n, L.TR, u.n, u.n > u.m ? with_members(dr, L.st[3]) : dr, u.V_out, u.ldv_out,
+                             precision);
       }
       for (int k = 0; k < 2; ++k) by_shape[g[k].shape].push_back(g[k]);
     }

@@ -72,6 +72,7 @@ struct GemmList {
   const int* boff = nullptr;
   const GemmJob* job = nullptr;
   int* counter = nullptr;       // persistent schedule: next tile (zeroed before the launch)
+  int copy = 0;                 // some job carries cluster members (FP64 copy-path kernels)
 };
 
 // X^T [v0 v1 v2] for X row-major R x N, in column blocks x row chunks.

@@ -19,12 +19,14 @@
 // A block whose columns are all secular roots (the usual case) runs the
 // Cauchy formula without any branch; other blocks use the general entry,
 // which gives the same values. Out-of-range rows of X load row 0 instead of
-// zeros: their accumulators are never stored.
+// zeros: their accumulators are never stored. Chunks of 64 deflated columns
+// (the zero block of a rectangular problem, for one) are written as copies
+// and one reflection instead; a block made only of such chunks runs no MFMA.
 //
 // Every output element is accumulated by the same sequence of MFMAs (the
 // K order and permutation do not depend on the tile shape or on the other
-// jobs), so the result is bitwise the same for every tile shape, schedule and
-// batch composition.
+// jobs), or by the same copy-path sum, so the result is bitwise the same for
+// every tile shape, schedule and batch composition.
 //
 // MFMA v_mfma_f64_16x16x4f64 operand layout (lane l): A[l % 16][l / 16],
 // B[l / 16][l % 16]; result register v holds D[l / 16 + 4 v][l % 16].
@@ -59,9 +61,11 @@ __device__ __forceinline__ double prod_entry(const CauchyDesc& d, int j, int N, 
   return prod_live_entry(z, gld(d.rg + jj), c, mind);
 }
 
+// `skip`: 64-column chunks of the tile whose results are not stored (the
+// copy path below writes them); always 0 for an all-live block.
 template <int MB, int NC, int KH, int W, bool LIVE>
 __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, const ColDesc (&cc)[NC],
-                                              double* Bs0, double* Bs1) {
+                                              double* Bs0, double* Bs1, unsigned skip) {
   // RPW: C~ rows each wave generates per half-step; SPR: MFMA groups per row
   constexpr int BN = 64 * NC, NB = 4 * NC, RPW = 16 / W, SPR = 4 / RPW;
   static_assert(W == 4 || W == 8, "4 or 8 waves");
@@ -182,7 +186,7 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int col = n0 + nb * 16 + (lane & 15);
-    if (col >= N) continue;
+    if (col >= N || (!LIVE && ((skip >> (nb >> 2)) & 1u))) continue;
     const double sc = d.colscale ? gld(d.colscale + col) : 1.0;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
@@ -195,8 +199,127 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
   }
 }
 
-// One tile (work item) of a GemmList.
+// Deflated columns without the MFMA loop. A deflated column c of C~ is a
+// unit vector e_mem, or one column of the Householder reflection of its
+// cluster (RankOneUpdate, deflation of repeated poles):
+//   X C~[:, c] = X[:, mem] - 2 h_c sum_{j in cluster} rh_j X[:, j].
+// A 64-column chunk (aligned to 64 in the output) takes this path when every
+// in-range column of it is deflated and all its reflected columns belong to
+// one cluster. The test depends only on the chunk's descriptors, and the row
+// sums below have a fixed order, so a column's value does not depend on the
+// tile shape, the schedule or the batch. Every wave holds the same 64 columns,
+// so the test is a wave-level reduction with a block-uniform result.
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Mask of the chunks that take the copy path; cl[c] is the chunk's cluster
+// (-1: unit columns only).
+template <int NC>
+__device__ __forceinline__ unsigned copy_chunks(const CauchyDesc& d, int n0, const ColDesc (&cc)[NC], int (&cl)[NC]) {
+  if (d.Llist == nullptr) return 0u;
+  const int lane = threadIdx.x & 63;
+  const int K = gld(d.counts);
+  unsigned mask = 0u;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const bool in = n0 + 64 * c + lane < d.N;
+    const bool refl = in && cc[c].type == 1 && cc[c].h != 0.0 && cc[c].cl >= 0;
+    const bool bad = in && (cc[c].type != 1 || cc[c].mem < 0 || cc[c].mem >= d.N || (refl && cc[c].cl >= K));
+    const int key = refl ? cc[c].cl : -1;
+    const int kmax = wave_max_int(key);
+    cl[c] = kmax;
+    if (n0 + 64 * c < d.N && !group_any<64>(bad || (refl && key != kmax))) mask |= 1u << c;
+  }
+  return mask;
+}
+
+// dots[rr] = sum over the members j of cluster cl of rh_j X[m0 + rr, j], for
+// the BM rows of the tile. Eight lanes share a row; lane t takes the members
+// q = t (mod 8) in increasing order, then the eight partial sums are added
+// by a butterfly. Members are staged through LDS in chunks of S.
+template <int BM, int T, int S>
+__device__ __forceinline__ void cluster_dots(const GemmJob& J, int m0, int cl, double* rhs, int* js, double* dots) {
+  constexpr int RPP = T / 8, NP = BM / RPP;
+  static_assert(BM % RPP == 0, "row passes");
+  const CauchyDesc& d = J.d;
+  const int tid = threadIdx.x, t8 = tid & 7;
+  const int f = gld(d.cfirst + cl);
+  int sz = gld(d.csize + cl);
+  if (f < 0 || sz < 0 || f + sz > d.N) sz = 0;   // never from a valid stage; keeps every index in range
+  double acc[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) acc[p] = 0.0;
+  for (int q0 = 0; q0 < sz; q0 += S) {
+    const int len = min(S, sz - q0);
+    __syncthreads();   // LDS free: C~ buffers, or the previous member chunk
+    for (int q = tid; q < len; q += T) {
+      const int t = min(max(gld(d.Llist + f + q0 + q), 0), d.N - 1);
+      const int j = min(max(gld(d.col_of + t), 0), d.N - 1);
+      js[q] = j;
+      rhs[q] = gld(d.rh + j);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int r = m0 + p * RPP + (tid >> 3);
+      if (r < J.R) {
+        const double* xr = J.X + (size_t)r * J.ldx;
+        double a = acc[p];
+#pragma unroll 4
+        for (int q = t8; q < len; q += 8) a = __builtin_fma(rhs[q], gld(xr + js[q]), a);
+        acc[p] = a;
+      }
+    }
+  }
+  __syncthreads();   // the last member chunk has been read
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const double a = group_sum<8>(acc[p]);
+    if (t8 == 0) dots[p * RPP + (tid >> 3)] = a;
+  }
+  __syncthreads();
+}
+
 template <int MB, int NC, int KH, int W>
+__device__ __forceinline__ void copy_path(const GemmJob& J, int m0, int n0, const ColDesc (&cc)[NC],
+                                          const int (&cl)[NC], unsigned mask, double* Bs0, double* Bs1) {
+  constexpr int BM = 16 * MB * W, T = 64 * W, S = KH * kBK * 64 * NC;
+  static_assert(2 * BM <= S, "dots and member rows share one C~ buffer");
+  double* rhs = Bs0;
+  double* dots = Bs1;
+  int* js = reinterpret_cast<int*>(Bs1 + BM);
+  const CauchyDesc& d = J.d;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int have = -1;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    if (!((mask >> c) & 1u)) continue;
+    if (cl[c] >= 0 && cl[c] != have) {
+      cluster_dots<BM, T, S>(J, m0, cl[c], rhs, js, dots);
+      have = cl[c];
+    }
+    const int col = n0 + 64 * c + lane;
+    if (col >= d.N) continue;
+    const double sc = d.colscale ? gld(d.colscale + col) : 1.0;
+    const bool refl = cc[c].h != 0.0 && cc[c].cl >= 0;
+    const double h2 = -2.0 * cc[c].h;
+    for (int rr = wave; rr < BM; rr += W) {
+      const int r = m0 + rr;
+      if (r >= J.R) break;
+      const double x = gld(J.X + (size_t)r * J.ldx + cc[c].mem);
+      const double v = refl ? __builtin_fma(h2, dots[rr], x) : x;
+      gst(J.Xo + (size_t)r * J.ldo + col, sc * v);
+    }
+  }
+}
+
+// One tile (work item) of a GemmList. COPY: the copy path is compiled in (for
+// lists with a job that carries cluster members); the kernels without it keep
+// the register allocation of the plain product.
+template <int MB, int NC, int KH, int W, bool COPY>
 __device__ __forceinline__ void gemm_f64_tile(const GemmList& L, int item, double* Bs0, double* Bs1) {
   constexpr int BM = 16 * MB * W, BN = 64 * NC;
   const int j = find_job(L.boff, L.n, item);
@@ -212,10 +335,20 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmList& L, int item, doubl
     cc[c] = load_col_tile(J.d, n0 + 64 * c + lane);
     live = live && cc[c].type == 0;
   }
-  if (__syncthreads_and(live))
-    gemm_f64_body<MB, NC, KH, W, true>(J, m0, n0, cc, Bs0, Bs1);
-  else
-    gemm_f64_body<MB, NC, KH, W, false>(J, m0, n0, cc, Bs0, Bs1);
+  if (__syncthreads_and(live)) {
+    gemm_f64_body<MB, NC, KH, W, true>(J, m0, n0, cc, Bs0, Bs1, 0u);
+  } else if (!COPY) {
+    gemm_f64_body<MB, NC, KH, W, false>(J, m0, n0, cc, Bs0, Bs1, 0u);
+  } else {
+    int cl[NC];
+    const unsigned cp = copy_chunks<NC>(J.d, n0, cc, cl);
+    unsigned inr = 0u;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (n0 + 64 * c < J.d.N) inr |= 1u << c;
+    if ((cp & inr) != inr) gemm_f64_body<MB, NC, KH, W, false>(J, m0, n0, cc, Bs0, Bs1, cp);
+    if (cp) copy_path<MB, NC, KH, W>(J, m0, n0, cc, cl, cp, Bs0, Bs1);
+  }
 }
 
 // Grid schedule: one block per tile, in list order. KH half-steps of 16 k
@@ -224,25 +357,38 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmList& L, int item, doubl
 template <int MB, int NC, int KH, int W>
 __global__ __launch_bounds__(64 * W, 8 / W) void gemm_cauchy_f64_kernel(GemmList L) {
   __shared__ double Bs[2][KH * kBK * 64 * NC];
-  gemm_f64_tile<MB, NC, KH, W>(L, blockIdx.x, Bs[0], Bs[1]);
+  gemm_f64_tile<MB, NC, KH, W, false>(L, blockIdx.x, Bs[0], Bs[1]);
+}
+template <int MB, int NC, int KH, int W>
+__global__ __launch_bounds__(64 * W, 8 / W) void gemm_cauchy_f64_copy_kernel(GemmList L) {
+  __shared__ double Bs[2][KH * kBK * 64 * NC];
+  gemm_f64_tile<MB, NC, KH, W, true>(L, blockIdx.x, Bs[0], Bs[1]);
 }
 
 // Persistent schedule: as many blocks as fit on the device at once; each
 // takes tiles in list order from a counter until the list is exhausted.
-template <int MB, int NC, int KH, int W>
-__global__ __launch_bounds__(64 * W, 8 / W) void gemm_cauchy_f64_persistent(GemmList L) {
+template <int MB, int NC, int KH, int W, bool COPY>
+__device__ __forceinline__ void gemm_f64_persistent_loop(const GemmList& L) {
   __shared__ double Bs[2][KH * kBK * 64 * NC];
   __shared__ int next;
   if (threadIdx.x == 0) next = atomicAdd(L.counter, 1);
   __syncthreads();
   int item = next;
   while (item < L.blocks) {
-    gemm_f64_tile<MB, NC, KH, W>(L, item, Bs[0], Bs[1]);
+    gemm_f64_tile<MB, NC, KH, W, COPY>(L, item, Bs[0], Bs[1]);
     __syncthreads();   // every thread has read `next` and finished with Bs
     if (threadIdx.x == 0) next = atomicAdd(L.counter, 1);
     __syncthreads();
     item = next;
   }
+}
+template <int MB, int NC, int KH, int W>
+__global__ __launch_bounds__(64 * W, 8 / W) void gemm_cauchy_f64_persistent(GemmList L) {
+  gemm_f64_persistent_loop<MB, NC, KH, W, false>(L);
+}
+template <int MB, int NC, int KH, int W>
+__global__ __launch_bounds__(64 * W, 8 / W) void gemm_cauchy_f64_copy_persistent(GemmList L) {
+  gemm_f64_persistent_loop<MB, NC, KH, W, true>(L);
 }
 
 namespace {
@@ -250,7 +396,12 @@ template <int MB, int NC, int KH, int W>
 void launch_shape(const GemmList& L, bool persistent, int grid_cap, hipStream_t st) {
   if (persistent) {
     const int g = L.blocks < grid_cap ? L.blocks : grid_cap;
-    hipLaunchKernelGGL((gemm_cauchy_f64_persistent<MB, NC, KH, W>), dim3(g), dim3(64 * W), 0, st, L);
+    if (L.copy)
+      hipLaunchKernelGGL((gemm_cauchy_f64_copy_persistent<MB, NC, KH, W>), dim3(g), dim3(64 * W), 0, st, L);
+    else
+      hipLaunchKernelGGL((gemm_cauchy_f64_persistent<MB, NC, KH, W>), dim3(g), dim3(64 * W), 0, st, L);
+  } else if (L.copy) {
+    hipLaunchKernelGGL((gemm_cauchy_f64_copy_kernel<MB, NC, KH, W>), dim3(L.blocks), dim3(64 * W), 0, st, L);
   } else {
     hipLaunchKernelGGL((gemm_cauchy_f64_kernel<MB, NC, KH, W>), dim3(L.blocks), dim3(64 * W), 0, st, L);
   }

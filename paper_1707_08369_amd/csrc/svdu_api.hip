@@ -303,7 +303,7 @@ int svdu_eig_update(int R, int N, const double* X, int ldx, const double* lam, c
   GemmList G;
   int shape = 0;
   if (path == SVDU_PATH_DIRECT && R > 0) {
-    const GemmJob J = make_gemm_job(R, X, ldx, desc_of(s), X_out, ldo, SVDU_PREC_FP64);
+    const GemmJob J = make_gemm_job(R, X, ldx, with_members(desc_of(s), s), X_out, ldo, SVDU_PREC_FP64);
     shape = J.shape;
     G = build_gemm_list({J}, nullptr, B);
   }

@@ -97,11 +97,30 @@ struct CauchyDesc {
   const double* ch;
   const double* colscale;  // optional per-output-column sign (nullptr: none)
   const int* status;       // device status word; fatal bits make the kernels return
+  // cluster members (with_members): the FP64 product then writes whole
+  // 64-column chunks of deflated columns as copies and one reflection.
+  // nullptr: those columns are generated like any other.
+  const int* counts;   // [0] number of clusters
+  const int* cfirst;   // per cluster: first index into Llist
+  const int* csize;    // per cluster: member count
+  const int* Llist;    // sorted positions of kept components
+  const int* col_of;   // sorted position -> row of C~
 };
 
 __host__ __device__ inline CauchyDesc desc_of(const Stage& s, const double* colscale = nullptr) {
   return CauchyDesc{s.N, s.rg, s.rzeta, s.rh, s.rcl, s.ctype, s.co, s.ctau, s.ccs, s.ccl, s.cmem, s.ch,
-                    colscale, s.status};
+                    colscale, s.status, nullptr, nullptr, nullptr, nullptr, nullptr};
+}
+
+// For products that can hold whole chunks of deflated columns (the zero block
+// of the right-hand products when n > m).
+__host__ __device__ inline CauchyDesc with_members(CauchyDesc d, const Stage& s) {
+  d.counts = s.counts;
+  d.cfirst = s.cfirst;
+  d.csize = s.csize;
+  d.Llist = s.Llist;
+  d.col_of = s.col_of;
+  return d;
 }
 
 // Launchers over job lists are declared in jobs.h.

@@ -213,6 +213,41 @@ def test_eig_update_below_reciprocal_range(lib, R, N, rho):
     assert np.max(np.abs(Xa - st.X)[:, ok]) <= 1e-9 * np.max(np.abs(X))
 
 
+@pytest.mark.parametrize("shape", [-1, 3])
+@pytest.mark.parametrize("rho", [0.9, -0.6])
+def test_eig_update_wide_cluster_copy_columns(lib, shape, rho):
+    """1200 equal poles: 1199 deflated columns of one Householder reflection.
+    Whole 64-column chunks of them are written as copies plus the reflection,
+    without MFMA work (with the 64 x 64 tile the member rows pass through LDS
+    in two chunks). C~ recovered from the identity must be orthogonal with the
+    new eigenvalues on its diagonal, X C~ must equal X times it, and on
+    separated eigenvalues X times the oracle's C~."""
+    R, N, W = 200, 1500, 1200
+    rng = np.random.default_rng(31)
+    lam = np.sort(np.concatenate([np.zeros(W), rng.uniform(0.5, 3.0, N - W)]))
+    z = rng.standard_normal(N) / np.sqrt(N)
+    X = rng.standard_normal((R, N))
+    old = lib.svdu_set_option(lib.SVDU_OPT_TILE_SHAPE, shape)
+    try:
+        Xo, lo, fl = lib.eig_update(dev(X), dev(lam), dev(z), rho)
+        Ci, lci, _ = lib.eig_update(dev(np.eye(N)), dev(lam), dev(z), rho)
+    finally:
+        lib.svdu_set_option(lib.SVDU_OPT_TILE_SHAPE, old)
+    Xo, lo, fl, Ci, lci = host(Xo), host(lo), host(fl), host(Ci), host(lci)
+    st = O.rank_one_update_z(X, lam, z, rho)
+    assert np.count_nonzero(st.flags == 2) == W - 1
+    assert np.array_equal(fl, st.flags)
+    assert np.max(np.abs(lo - st.lam)) <= 1e-13 * 3.0
+    assert np.max(np.abs(Ci.T @ Ci - np.eye(N))) <= 1e-13
+    M = np.diag(lam) + rho * np.outer(z, z)
+    assert np.max(np.abs(M @ Ci - Ci * lci[None, :])) <= 1e-13 * np.max(np.abs(M))
+    assert np.max(np.abs(Xo - X @ Ci)) <= 1e-12 * np.max(np.abs(X)) * np.sqrt(N)
+    ok = _separated(st.lam)
+    assert np.any(ok)
+    Xa = _align_cols(st.X, Xo)
+    assert np.max(np.abs(Xa - st.X)[:, ok]) <= 1e-9 * np.max(np.abs(X))
+
+
 # ---------------------------------------------------------------------------
 # the whole update
 # ---------------------------------------------------------------------------
