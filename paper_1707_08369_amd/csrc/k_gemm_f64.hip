@@ -317,8 +317,10 @@ __device__ __forceinline__ void copy_path(const GemmJob& J, int m0, int n0, cons
 }
 
 // One tile (work item) of a GemmList. COPY: the copy path is compiled in (for
-// lists with a job that carries cluster members); the kernels without it keep
-// the register allocation of the plain product.
+// lists with a job that carries cluster members). The kernels without it keep
+// the register allocation of the plain product; with it, the chunk test runs
+// ahead of the MFMA branch, where it leaves the all-live loop's waits as in
+// the plain kernels (placed after the branch, it added two vmcnt waits).
 template <int MB, int NC, int KH, int W, bool COPY>
 __device__ __forceinline__ void gemm_f64_tile(const GemmList& L, int item, double* Bs0, double* Bs1) {
   constexpr int BM = 16 * MB * W, BN = 64 * NC;
@@ -335,20 +337,24 @@ __device__ __forceinline__ void gemm_f64_tile(const GemmList& L, int item, doubl
     cc[c] = load_col_tile(J.d, n0 + 64 * c + lane);
     live = live && cc[c].type == 0;
   }
-  if (__syncthreads_and(live)) {
-    gemm_f64_body<MB, NC, KH, W, true>(J, m0, n0, cc, Bs0, Bs1, 0u);
-  } else if (!COPY) {
-    gemm_f64_body<MB, NC, KH, W, false>(J, m0, n0, cc, Bs0, Bs1, 0u);
-  } else {
-    int cl[NC];
-    const unsigned cp = copy_chunks<NC>(J.d, n0, cc, cl);
+  int cl[NC];
+  unsigned cp = 0u;
+  if (COPY) {
+    cp = copy_chunks<NC>(J.d, n0, cc, cl);
     unsigned inr = 0u;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
       if (n0 + 64 * c < J.d.N) inr |= 1u << c;
-    if ((cp & inr) != inr) gemm_f64_body<MB, NC, KH, W, false>(J, m0, n0, cc, Bs0, Bs1, cp);
-    if (cp) copy_path<MB, NC, KH, W>(J, m0, n0, cc, cl, cp, Bs0, Bs1);
+    if (cp && (cp & inr) == inr) {
+      copy_path<MB, NC, KH, W>(J, m0, n0, cc, cl, cp, Bs0, Bs1);
+      return;
+    }
   }
+  if (__syncthreads_and(live))
+    gemm_f64_body<MB, NC, KH, W, true>(J, m0, n0, cc, Bs0, Bs1, 0u);
+  else
+    gemm_f64_body<MB, NC, KH, W, false>(J, m0, n0, cc, Bs0, Bs1, cp);
+  if (COPY && cp) copy_path<MB, NC, KH, W>(J, m0, n0, cc, cl, cp, Bs0, Bs1);
 }
 
 // Grid schedule: one block per tile, in list order. KH half-steps of 16 k
