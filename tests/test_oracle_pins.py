@@ -150,6 +150,29 @@ def test_stage_eigvecs_orthogonal_and_eigen_residual(rho):
     assert sorted(st.flags[10:13].tolist()) == [0, 2, 2]
 
 
+@pytest.mark.parametrize("rho", [0.9, -0.9])
+def test_stage_zero_block_cluster(rho):
+    """A block of 30 exactly equal zero poles, as the right-hand eigen-updates
+    carry when n > m. One root leaves the block; the other 29 eigenvectors keep
+    eigenvalue 0, vanish outside the block's rows and are orthogonal to z on
+    them (they span the complement of z within the block)."""
+    rng = np.random.default_rng(9)
+    N, W = 70, 30
+    d = np.sort(np.concatenate([np.zeros(W), rng.uniform(0.5, 2.0, N - W)]))
+    v = rng.standard_normal(N) / np.sqrt(N)
+    st = OS.rank_one_update(np.eye(N), d, v, rho)
+    C = st.X
+    assert np.max(np.abs(C.T @ C - np.eye(N))) <= 1e-14
+    M = np.diag(d) + rho * np.outer(v, v)
+    assert np.max(np.abs(M @ C - C * st.lam[None, :])) <= 1e-14 * np.max(np.abs(M))
+    assert np.count_nonzero(st.flags == 2) == W - 1
+    zero = st.lam == 0.0
+    assert np.count_nonzero(zero) == W - 1
+    Cz = C[:, zero]
+    assert np.all(Cz[W:, :] == 0.0)
+    assert np.max(np.abs(v[:W] @ Cz[:W, :])) <= 1e-15
+
+
 def test_appendix_b_two_by_two_eigenvector_form():
     """Appendix B: for a 2x2 problem the i-th eigenvector is proportional to
     [a1 / (mu_i - lam_1), a2 / (mu_i - lam_2)]. Worked case: D = diag(1, 2),
