@@ -412,3 +412,18 @@ def test_planted_missing_column_norm_fails(monkeypatch):
     monkeypatch.setattr(OS, "cauchy_eigvecs", bad_norm)
     with pytest.raises(AssertionError):
         test_stage_eigvecs_orthogonal_and_eigen_residual(0.9)
+
+
+def test_planted_householder_column_off_by_one_fails(monkeypatch):
+    """The merged cluster's deflated columns taken as reflection columns 0..k-2
+    instead of 1..k-1: column 0 is parallel to z, so the zero-block pin fails."""
+    import inspect
+    src = inspect.getsource(OS.cauchy_eigvecs)
+    good = "for t in range(1, mm.shape[0]):"
+    assert good in src
+    ns = dict(vars(OS))
+    exec(src.replace(good, "for t in range(0, mm.shape[0] - 1):"), ns)
+    monkeypatch.setattr(OS, "cauchy_eigvecs", ns["cauchy_eigvecs"])
+    with pytest.raises(AssertionError):
+        test_stage_zero_block_cluster(0.9)
+
