@@ -88,7 +88,9 @@ size_t svdu_workspace_bytes(int m, int n, int path, int precision);
  *  V, ldv      n x n orthogonal, ldv >= n.             (input, not modified)
  *  a, b        update vectors of length m and n.       (input)
  *  eps         FMM tolerance (ignored by SVDU_PATH_DIRECT), 0 < eps < 1; the
- *              expansion order is p = ceil(log_5(1/eps)), at most 16.
+ *              expansion order is p = ceil(log_5(1/eps)) (Appendix D Step 1),
+ *              at least 8. An eps that needs p > 16 (eps < 5^-16, about
+ *              6.6e-12) is rejected with SVDU_ENOTSUP.
  *  path        SVDU_PATH_DIRECT or SVDU_PATH_FMM. The FMM path copies the
  *              roots to the host once per call to build its trees (the call
  *              then returns after that synchronisation of `stream`); it works

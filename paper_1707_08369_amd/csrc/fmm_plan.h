@@ -4,25 +4,10 @@
 
 #include <vector>
 
+#include "fmm_tree.h"
 #include "svdu_internal.h"
 
 namespace svdu {
-
-struct FmmHostPlan {
-  int p = 0, s = 0, K = 0, nlev = 0, nbox = 0;
-  int outlier = -1;                 // root outside [g_0, g_K-1], evaluated directly
-  int outlier2 = -1;                // root in the gap next to an isolated pole, evaluated directly
-  int opole = -1;                   // isolated extreme pole: in no box interval, applied to every root directly
-  std::vector<double> lo, hi;       // box intervals
-  std::vector<int> s0, s1;          // source / target index range of each box
-  std::vector<int> m2l_ptr, m2l_src;
-  std::vector<int> near_ptr, near_src;
-  std::vector<int> lev_off;         // first box id of each level
-  // the directly evaluated roots (outlier, then outlier2, those that exist):
-  // boxes whose expansion converges at the root, and leaves summed exactly
-  std::vector<int> dm2p, dp2p;
-  int dm2p_ptr[3] = {0, 0, 0}, dp2p_ptr[3] = {0, 0, 0};
-};
 
 struct FmmPrepared {
   FmmHostPlan P;

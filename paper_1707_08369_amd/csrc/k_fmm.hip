@@ -43,182 +43,9 @@
 
 namespace svdu {
 
-constexpr int kP = 16;  // padded expansion length (p <= 16)
+constexpr int kP = kFmmMaxOrder;  // padded expansion length (p <= 16)
 
-// ---------------------------------------------------------------------------
-// host plan
-// ---------------------------------------------------------------------------
-__host__ __device__ static inline int box_id(int l, int k) { return (1 << l) - 1 + k; }
-
-int fmm_order(double eps) {
-  // p = ceil(log_5(1/eps)), clamped to [8, 16] (leaves of 16 to 32 poles)
-  const double p = ceil(log(1.0 / eps) / log(5.0));
-  return (int)std::min(16.0, std::max(8.0, p));
-}
-
-static void build_plan(int K, const double* g, const double* mu, int p, FmmHostPlan* P) {
-  P->p = p;
-  P->K = K;
-  // a full binary tree whose leaves hold at most 32 poles each
-  int nlev = 0;
-  while ((K + (1 << nlev) - 1) >> nlev > 32) ++nlev;
-  P->s = (K + (1 << nlev) - 1) >> nlev;
-  const int s = P->s;
-  // The extreme root (beyond the last pole for rho > 0, before the first for
-  // rho < 0) can lie far outside the spectrum; it is kept out of the box
-  // intervals, which would otherwise make its leaf, and every box above it,
-  // inadmissible to all, and is evaluated on its own (fmm_direct_roots).
-  P->outlier = -1;
-  for (int i = 0; i < K; ++i)
-    if (mu[i] > g[K - 1] || mu[i] < g[0]) P->outlier = i;
-  // An extreme pole far from the others (the previous level's extreme root
-  // becomes one) would stretch its leaf across the whole gap and leave it
-  // near to almost every leaf; such a pole stays out of the box intervals,
-  // the multipole expansions and the near fields, and its charge is applied
-  // to every root directly. The root that interlaces into that gap, when it
-  // lies farther out than the span of the leaf's other poles, is evaluated
-  // directly like the extreme root.
-  P->opole = -1;
-  P->outlier2 = -1;
-  if (nlev > 0) {
-    const int la = ((K - 1) / s) * s, fe = std::min(K, s);   // first pole of the last leaf, end of the first
-    if (K - la >= 3 && g[K - 1] - g[K - 2] > g[K - 2] - g[la]) {
-      P->opole = K - 1;
-      const double lim = g[K - 2] + (g[K - 2] - g[la]);
-      for (int i = la; i < K; ++i)
-        if (i != P->outlier && mu[i] > lim) P->outlier2 = i;
-    } else if (fe >= 3 && g[1] - g[0] > g[fe - 1] - g[1]) {
-      P->opole = 0;
-      const double lim = g[1] - (g[fe - 1] - g[1]);
-      for (int i = 0; i < fe; ++i)
-        if (i != P->outlier && mu[i] < lim) P->outlier2 = i;
-    }
-  }
-  auto in_box = [&](int i) { return i != P->outlier && i != P->outlier2; };
-  P->nlev = nlev;
-  P->nbox = (1 << (nlev + 1)) - 1;
-  P->lo.assign(P->nbox, 0.0);
-  P->hi.assign(P->nbox, 0.0);
-  P->s0.assign(P->nbox, 0);
-  P->s1.assign(P->nbox, 0);
-  P->lev_off.resize(nlev + 2);
-  for (int l = 0; l <= nlev + 1; ++l) P->lev_off[l] = (1 << l) - 1;
-  for (int b = 0; b < (1 << nlev); ++b) {
-    const int id = box_id(nlev, b);
-    const int a0 = std::min(K, b * s), a1 = std::min(K, (b + 1) * s);
-    P->s0[id] = a0;
-    P->s1[id] = a1;
-    if (a0 < a1) {
-      const int f = (a0 == P->opole && a1 > a0 + 1) ? a0 + 1 : a0;
-      double lo = g[f], hi = g[f];
-      for (int i = a0; i < a1; ++i) {
-        if (i != P->opole) {
-          lo = std::min(lo, g[i]);
-          hi = std::max(hi, g[i]);
-        }
-        if (in_box(i)) {
-          lo = std::min(lo, mu[i]);
-          hi = std::max(hi, mu[i]);
-        }
-      }
-      P->lo[id] = lo;
-      P->hi[id] = hi;
-    }
-  }
-  for (int l = nlev - 1; l >= 0; --l) {
-    for (int b = 0; b < (1 << l); ++b) {
-      const int id = box_id(l, b), c0 = box_id(l + 1, 2 * b), c1 = box_id(l + 1, 2 * b + 1);
-      P->s0[id] = P->s0[c0];
-      P->s1[id] = std::max(P->s1[c0], P->s1[c1]);
-      if (P->s1[c1] > P->s0[c1] && P->s1[c0] > P->s0[c0]) {
-        P->lo[id] = std::min(P->lo[c0], P->lo[c1]);
-        P->hi[id] = std::max(P->hi[c0], P->hi[c1]);
-      } else if (P->s1[c0] > P->s0[c0]) {
-        P->lo[id] = P->lo[c0];
-        P->hi[id] = P->hi[c0];
-      }
-      if (P->s1[c1] > P->s0[c1] && P->s1[c0] <= P->s0[c0]) P->s0[id] = P->s0[c1];
-    }
-  }
-  // dual traversal: M2L lists for every box, near lists for leaves
-  std::vector<std::vector<int>> m2l(P->nbox), nearl(P->nbox);
-  auto empty = [&](int id) { return P->s1[id] <= P->s0[id]; };
-  auto adm = [&](int a, int b) {
-    if (a == b) return false;
-    const double wa = P->hi[a] - P->lo[a], wb = P->hi[b] - P->lo[b];
-    const double gap = std::max(P->lo[b] - P->hi[a], P->lo[a] - P->hi[b]);
-    return gap > 0.0 && gap >= std::max(wa, wb);
-  };
-  std::vector<std::pair<int, int>> stack;
-  stack.push_back({0, 0});
-  std::vector<int> level_of(P->nbox);
-  for (int l = 0; l <= nlev; ++l)
-    for (int b = 0; b < (1 << l); ++b) level_of[box_id(l, b)] = l;
-  while (!stack.empty()) {
-    auto [a, b] = stack.back();
-    stack.pop_back();
-    if (empty(a) || empty(b)) continue;
-    if (adm(a, b)) {
-      m2l[a].push_back(b);
-      continue;
-    }
-    const int l = level_of[a];
-    if (l == nlev) {
-      nearl[a].push_back(b);
-      continue;
-    }
-    const int ka = a - P->lev_off[l], kb = b - P->lev_off[l];
-    for (int ca = 0; ca < 2; ++ca)
-      for (int cb = 0; cb < 2; ++cb) stack.push_back({box_id(l + 1, 2 * ka + ca), box_id(l + 1, 2 * kb + cb)});
-  }
-  P->m2l_ptr.assign(P->nbox + 1, 0);
-  P->near_ptr.assign(P->nbox + 1, 0);
-  for (int i = 0; i < P->nbox; ++i) {
-    std::sort(m2l[i].begin(), m2l[i].end());
-    std::sort(nearl[i].begin(), nearl[i].end());
-    P->m2l_ptr[i + 1] = P->m2l_ptr[i] + (int)m2l[i].size();
-    P->near_ptr[i + 1] = P->near_ptr[i] + (int)nearl[i].size();
-  }
-  P->m2l_src.clear();
-  P->near_src.clear();
-  for (int i = 0; i < P->nbox; ++i) {
-    P->m2l_src.insert(P->m2l_src.end(), m2l[i].begin(), m2l[i].end());
-    P->near_src.insert(P->near_src.end(), nearl[i].begin(), nearl[i].end());
-  }
-  // Each directly evaluated root y takes the far field of every box whose gap
-  // to y is at least the box's width (the rule of the pairs above, for a
-  // point) from its multipole coefficients, and sums the leaves that never
-  // qualify exactly.
-  P->dm2p.clear();
-  P->dp2p.clear();
-  int nd = 0;
-  for (const int d : {P->outlier, P->outlier2}) {
-    if (d < 0) continue;
-    const double y = mu[d];
-    std::vector<int> st{0};
-    while (!st.empty()) {
-      const int b = st.back();
-      st.pop_back();
-      if (empty(b)) continue;
-      const double gap = std::max(P->lo[b] - y, y - P->hi[b]);
-      if (gap > 0.0 && gap >= P->hi[b] - P->lo[b]) {
-        P->dm2p.push_back(b);
-        continue;
-      }
-      const int l = level_of[b];
-      if (l == nlev) {
-        P->dp2p.push_back(b);
-        continue;
-      }
-      const int kb = b - P->lev_off[l];
-      st.push_back(box_id(l + 1, 2 * kb + 1));
-      st.push_back(box_id(l + 1, 2 * kb));
-    }
-    ++nd;
-    P->dm2p_ptr[nd] = (int)P->dm2p.size();
-    P->dp2p_ptr[nd] = (int)P->dp2p.size();
-  }
-}
+// The host tree (box intervals, interaction lists) is built in fmm_tree.h.
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -478,7 +305,7 @@ __global__ __launch_bounds__(256, 2) void fmm_p2m(FmmDev F, const double* __rest
   __shared__ double op[16 * ld];   // [kk][source in leaf]
   __shared__ ChebTab T;
   if (*status & kStFatal) return;
-  const int id = box_id(F.nlev, blockIdx.x);
+  const int id = fmm_box_id(F.nlev, blockIdx.x);
   const int a0 = F.s0[id], a1 = F.s1[id];
   if (a1 <= a0) return;
   double c, rad;
@@ -513,11 +340,11 @@ __global__ __launch_bounds__(256, 2) void fmm_m2m(FmmDev F, int level, const int
   __shared__ int has[2];
   __shared__ ChebTab T;
   if (*status & kStFatal) return;
-  const int id = box_id(level, blockIdx.x);
+  const int id = fmm_box_id(level, blockIdx.x);
   if (F.s1[id] <= F.s0[id]) return;
   double cp, rp;
   box_cr(F, id, &cp, &rp);
-  const int ch[2] = {box_id(level + 1, 2 * blockIdx.x), box_id(level + 1, 2 * blockIdx.x + 1)};
+  const int ch[2] = {fmm_box_id(level + 1, 2 * blockIdx.x), fmm_box_id(level + 1, 2 * blockIdx.x + 1)};
   if (threadIdx.x < 2) has[threadIdx.x] = F.s1[ch[threadIdx.x]] > F.s0[ch[threadIdx.x]];
   cheb_fill(&T, F);
   __syncthreads();
@@ -599,7 +426,7 @@ __global__ __launch_bounds__(256) void fmm_down(FmmDev F, int level, const int* 
   const int xcd = blockIdx.x % 8, per = total / 8, extra = total % 8;
   const int w = xcd * per + min(xcd, extra) + blockIdx.x / 8;
   const int bx = w % nb, rb = w / nb;
-  const int id = box_id(level, bx);
+  const int id = fmm_box_id(level, bx);
   if (F.s1[id] <= F.s0[id]) return;
   double ct, rt;
   box_cr(F, id, &ct, &rt);
@@ -619,7 +446,7 @@ __global__ __launch_bounds__(256) void fmm_down(FmmDev F, int level, const int* 
       double c = 0.0, r = 1.0;
       if (qi < cnt) {
         const bool l2l = level > 0 && o == 0;
-        const int other = l2l ? box_id(level - 1, bx >> 1) : F.m2l_src[q0 + o - (level > 0 ? 1 : 0)];
+        const int other = l2l ? fmm_box_id(level - 1, bx >> 1) : F.m2l_src[q0 + o - (level > 0 ? 1 : 0)];
         box_cr(F, other, &c, &r);
         src = (l2l ? F.L : F.W) + (size_t)other * kP * F.R;
         kind = l2l ? 0 : 1;
@@ -749,7 +576,7 @@ __global__ __launch_bounds__(256) void fmm_leaf_eval(FmmDev F, Stage s, double* 
   const int xcd = blockIdx.x % 8, per = total / 8, extra = total % 8;
   const int w = xcd * per + min(xcd, extra) + blockIdx.x / 8;
   const int leaf = w % nleaf, rb = w / nleaf;
-  const int id = box_id(F.nlev, leaf);
+  const int id = fmm_box_id(F.nlev, leaf);
   const int a0 = F.s0[id], a1 = F.s1[id];
   if (a1 <= a0) return;
   const int nt = a1 - a0;
@@ -1017,7 +844,7 @@ __global__ __launch_bounds__(256) void fmm_deflated_cols(int R, const double* __
 // host side: plan building, upload and launch
 // ---------------------------------------------------------------------------
 static size_t tree_boxes(int N) {
-  int nlev = 0;   // as in build_plan: leaves of at most 32 poles
+  int nlev = 0;   // as in fmm_build_tree: leaves of at most 32 poles
   while ((N + (1 << nlev) - 1) >> nlev > 32) ++nlev;
   return (size_t(1) << (nlev + 1)) - 1;
 }
@@ -1040,7 +867,7 @@ size_t fmm_plan_bytes(int N) {
 void fmm_prepare(int K, const double* g_host, const double* mu_host, double eps, std::vector<char>* blob,
                  FmmPrepared* out) {
   const int p = fmm_order(eps);
-  if (K > 0) build_plan(K, g_host, mu_host, p, &out->P);
+  if (K > 0) fmm_build_tree(K, g_host, mu_host, p, &out->P);
   out->P.p = p;
   out->P.K = K;
   const FmmHostPlan& P = out->P;

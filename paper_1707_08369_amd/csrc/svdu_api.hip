@@ -108,9 +108,16 @@ int fmm_products_impl(int nst, Stage* stages, const int* Rs, const double* const
   std::vector<char> blob;
   std::vector<FmmPrepared> prep(nst);
   for (int k = 0; k < nst; ++k) {
+    // The host reads indices that the device produced: check them before use,
+    // so that inconsistent device results give an error instead of a host fault.
     const int K = h[k].counts[0];
+    if (K < 0 || K > stages[k].N) return SVDU_EHIP;
     std::vector<double> mu(K);
-    for (int i = 0; i < K; ++i) mu[i] = h[k].g[h[k].org[i]] + h[k].tau[i];
+    for (int i = 0; i < K; ++i) {
+      const int o = h[k].org[i];
+      if (o < 0 || o >= K) return SVDU_EHIP;
+      mu[i] = h[k].g[o] + h[k].tau[i];
+    }
     fmm_prepare(K, h[k].g.data(), mu.data(), eps, &blob, &prep[k]);
   }
   if (blob.size() > plan_bytes) return SVDU_ENOMEM;
@@ -187,6 +194,7 @@ int svdu_rank1_update(int m, int n, const double* U, int ldu, const double* sigm
   if (path != SVDU_PATH_DIRECT && path != SVDU_PATH_FMM) return SVDU_EINVAL;
   if (precision != SVDU_PREC_FP64 && precision != SVDU_PREC_SPLIT32) return SVDU_EINVAL;
   if (path == SVDU_PATH_FMM && !(eps > 0.0 && eps < 1.0)) return SVDU_EINVAL;
+  if (path == SVDU_PATH_FMM && fmm_required_order(eps) > kFmmMaxOrder) return SVDU_ENOTSUP;
   if (path == SVDU_PATH_FMM && precision != SVDU_PREC_FP64) return SVDU_ENOTSUP;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return SVDU_EINVAL;
   const size_t ub = ((size_t)(m - 1) * ldu + m) * 8, vb = ((size_t)(n - 1) * ldv + n) * 8;
@@ -286,6 +294,7 @@ int svdu_eig_update(int R, int N, const double* X, int ldx, const double* lam, c
   if (!(rho != 0.0) || !isfinite(rho)) return SVDU_EINVAL;
   if (path != SVDU_PATH_DIRECT && path != SVDU_PATH_FMM) return SVDU_EINVAL;
   if (path == SVDU_PATH_FMM && !(eps > 0.0 && eps < 1.0)) return SVDU_EINVAL;
+  if (path == SVDU_PATH_FMM && fmm_required_order(eps) > kFmmMaxOrder) return SVDU_ENOTSUP;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return SVDU_EINVAL;
   if (R > 0 && overlaps(X, ((size_t)(R - 1) * ldx + N) * 8, X_out, ((size_t)(R - 1) * ldo + N) * 8))
     return SVDU_EINVAL;

@@ -129,7 +129,6 @@ __host__ __device__ inline CauchyDesc with_members(CauchyDesc d, const Stage& s)
 // host from host copies of the stage's K poles and roots, all plans of a call
 // are uploaded in one copy, then the kernels are enqueued.
 struct FmmPrepared;
-int fmm_order(double eps);
 size_t fmm_workspace_elems(int R, int N);
 size_t fmm_plan_bytes(int N);
 

@@ -29,6 +29,7 @@
 
 #include "../../include/svdu.h"
 #include "engine.h"
+#include "fmm_tree.h"
 
 namespace svdu {
 Sched current_sched(bool persistent);
@@ -392,6 +393,7 @@ int svdu_server_create(svdu_server** out, const svdu_server_config* cfg, void* a
   if (cfg->workers < 1 || cfg->workers > 8 || cfg->max_batch < 1) return SVDU_EINVAL;
   if (cfg->precision != SVDU_PREC_FP64 && cfg->precision != SVDU_PREC_SPLIT32) return SVDU_EINVAL;
   if (cfg->fmm_min_n > 0 && !(cfg->fmm_eps > 0.0 && cfg->fmm_eps < 1.0)) return SVDU_EINVAL;
+  if (cfg->fmm_min_n > 0 && fmm_required_order(cfg->fmm_eps) > kFmmMaxOrder) return SVDU_ENOTSUP;
   if (!(cfg->batch_cost_factor >= 1.0) || cfg->min_batch_cost < 0.0) return SVDU_EINVAL;
   if (!(cfg->min_cost_ratio >= 0.0 && cfg->min_cost_ratio <= 1.0)) return SVDU_EINVAL;
   if ((reinterpret_cast<uintptr_t>(arena) & 255) != 0 || arena_bytes < (1u << 20)) return SVDU_EINVAL;

@@ -82,12 +82,18 @@ def test_host_argument_errors_return_before_enqueue(lib):
     assert call(workspace=_p(0x100010)) == svdu.SVDU_EINVAL  # misaligned
     assert call(workspace_bytes=16) == svdu.SVDU_ENOMEM
     assert call(path=1, eps=0.0) == svdu.SVDU_EINVAL
+    # p = ceil(log_5(1/eps)) above the largest order the kernels hold (16)
+    assert call(path=1, eps=1e-13) == svdu.SVDU_ENOTSUP
+    assert call(path=1, eps=5.0 ** -16 * 0.99) == svdu.SVDU_ENOTSUP
+    assert call(path=1, eps=1e-13, workspace_bytes=16) == svdu.SVDU_ENOTSUP   # refused before sizing
     assert svdu.svdu_eig_update(3, 0, fake, 1, fake, fake, 1.0, 0, 0.0, _p(0x50000), 1, fake, None, ws, 1 << 20,
                                 None) == svdu.SVDU_EINVAL
     assert svdu.svdu_eig_update(3, 4, fake, 4, fake, fake, 0.0, 0, 0.0, _p(0x50000), 4, fake, None, ws, 1 << 20,
                                 None) == svdu.SVDU_EINVAL
     assert svdu.svdu_eig_update(3, 4, fake, 4, fake, fake, 1.0, 1, 0.0, _p(0x50000), 4, fake, None, ws, 1 << 20,
                                 None) == svdu.SVDU_EINVAL   # FMM needs 0 < eps < 1
+    assert svdu.svdu_eig_update(3, 4, fake, 4, fake, fake, 1.0, 1, 1e-13, _p(0x50000), 4, fake, None, ws, 1 << 20,
+                                None) == svdu.SVDU_ENOTSUP  # order above 16
     assert svdu.svdu_secular(0, fake, fake, 1.0, fake, fake, None, ws, 1 << 20, None) == svdu.SVDU_EINVAL
     assert svdu.svdu_secular(4, fake, fake, 1.0, fake, fake, None, ws, 8, None) == svdu.SVDU_ENOMEM
 

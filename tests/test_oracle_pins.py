@@ -336,6 +336,70 @@ def test_zeroed_projections_preserve_singular_triplets():
 
 
 # ---------------------------------------------------------------------------
+# Deflation threshold and scale (Section 3.1 case (1)): the secular equation
+# 1 + rho sum z_k^2 / (d_k - mu) = 0 is unchanged by d -> S d, z -> sqrt(S) z,
+# mu -> S mu, so the decisions must be unchanged and the roots exactly scaled.
+# S = 2^-600 keeps every quantity normal, so the scaled arithmetic is exact.
+# ---------------------------------------------------------------------------
+def _scaled_pair():
+    rng = np.random.default_rng(600)
+    N = 60
+    d = np.sort(rng.uniform(0.1, 2.0, N))
+    z = rng.standard_normal(N)
+    z[[3, 17, 40]] = [1e-17, -3e-18, 2e-16]     # below 8 u sqrt(N) |z| ~ 6.6e-15
+    z[[9, 25]] = [1e-13, -2e-13]                # above it
+    return d, z
+
+
+def test_deflation_decisions_and_roots_invariant_under_scaling():
+    d, z = _scaled_pair()
+    rho = 0.8
+    S, sS = 2.0 ** -600, 2.0 ** -300
+    r1 = OS.deflate(d, z, rho)
+    r2 = OS.deflate(d * S, z * sS, rho)
+    assert np.array_equal(r1.tiny, r2.tiny)
+    assert np.array_equal(np.nonzero(r1.tiny)[0], [3, 17, 40])
+    assert np.array_equal(r1.cluster, r2.cluster)
+    o1, t1 = OS.secular_roots(r1.g, r1.W, rho)
+    o2, t2 = OS.secular_roots(r2.g, r2.W, rho)
+    assert np.array_equal(o1, o2)
+    assert np.array_equal(t1 * S, t2)          # bitwise: every step scales exactly
+    st1 = OS.rank_one_update_z(np.eye(60), d, z, rho)
+    st2 = OS.rank_one_update_z(np.eye(60), d * S, z * sS, rho)
+    assert np.array_equal(st1.flags, st2.flags)
+    assert np.array_equal(st1.lam * S, st2.lam)
+
+
+def test_planted_absolute_deflation_threshold_fails(monkeypatch):
+    """A threshold that forgets the |z| factor drops every component of the
+    scaled problem, which the scale pin catches."""
+    import inspect
+    src = inspect.getsource(OS.deflate)
+    good = "tol = 8.0 * U64 * np.sqrt(max(N, 1)) * znorm"
+    assert good in src
+    ns = dict(vars(OS))
+    exec(src.replace(good, "tol = 8.0 * U64 * np.sqrt(max(N, 1))"), ns)
+    monkeypatch.setattr(OS, "deflate", ns["deflate"])
+    with pytest.raises(AssertionError):
+        test_deflation_decisions_and_roots_invariant_under_scaling()
+
+
+# ---------------------------------------------------------------------------
+# The paper's error measure (Section 7, eq. error) on a hand-computed case.
+# ---------------------------------------------------------------------------
+def test_paper_error_hand_computed():
+    # A^ is 2 x 3; U^ = I, S^ = diag(2, 1), V^ = I, so U^ S^ V^[:, :2]^T =
+    # [[2, 0, 0], [0, 1, 0]] and A^ minus it is [[-1, 2, 0], [0, 0, 0]]:
+    # max |.| = 2, divided by max sigma^ = 2 gives 1.
+    Ah = np.array([[1.0, 2.0, 0.0], [0.0, 1.0, 0.0]])
+    assert O.paper_error(Ah, np.eye(2), np.array([2.0, 1.0]), np.eye(3)) == 1.0
+    # scaling sigma^ and A^ by 4 leaves the measure unchanged
+    assert O.paper_error(4 * Ah, np.eye(2), np.array([8.0, 4.0]), np.eye(3)) == 1.0
+    # an exact factorisation gives 0
+    assert O.paper_error(np.array([[2.0, 0, 0], [0, 1.0, 0]]), np.eye(2), np.array([2.0, 1.0]), np.eye(3)) == 0.0
+
+
+# ---------------------------------------------------------------------------
 # The paper's Table 2: an upper bound for any correct implementation.
 # ---------------------------------------------------------------------------
 def test_error_far_below_paper_table_two():
