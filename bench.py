@@ -407,7 +407,7 @@ def main():
     Vo = torch.empty((n, n), dtype=torch.float64, device=dev)
     path = svdu.SVDU_PATH_FMM if args.path == "fmm" else svdu.SVDU_PATH_DIRECT
     if args.tile >= 0:
-        svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, args.tile)
+        svdu.set_option(svdu.SVDU_OPT_TILE_SHAPE, args.tile)
     ws = svdu.new_workspace(svdu.svdu_workspace_bytes(m, n, path), dev)
     stream = torch.cuda.current_stream()
 
@@ -420,7 +420,7 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] m={m} n={n} warmup={W} done", file=sys.stderr, flush=True)
 
-    svdu.svdu_set_option(svdu.SVDU_OPT_TIMING, 1)
+    svdu.set_option(svdu.SVDU_OPT_TIMING, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(W, W + K):
@@ -428,7 +428,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     phases = svdu.timing_read(K)
-    svdu.svdu_set_option(svdu.SVDU_OPT_TIMING, 0)
+    svdu.set_option(svdu.SVDU_OPT_TIMING, 0)
     status = svdu.svdu_get_status(svdu._aligned(ws)[0], svdu._stream_handle(stream))
     if status != 0:
         print(f"[bench] device status {svdu.svdu_status_string(status)}", file=sys.stderr)

@@ -11,6 +11,12 @@
  * CTildeFinalForm1) and the product X C~ (equation UCTildeProduct).
  *
  * Conventions for every entry point:
+ *  - Calls that enqueue work take a context (svdu_ctx, from svdu_create): it
+ *    holds the options, the tile-shape tables and the phase-timing record of
+ *    the calls made with it, and is bound to one device, which must be the
+ *    current HIP device when such a call is made (SVDU_EINVAL otherwise).
+ *    Contexts share no state: two threads may each use their own context at
+ *    the same time; one context is used by one thread at a time.
  *  - Matrices are row-major float64 with an explicit leading dimension
  *    (element (r, c) of X is X[r * ldx + c]).
  *  - Every pointer argument is a DEVICE pointer owned by the caller, unless
@@ -52,7 +58,7 @@ extern "C" {
 #define SVDU_PREC_SPLIT32 1     /* split FP32 hi/lo, three FP32 MFMA passes, FP32 accumulation drained to
                                    FP64 every 16 k; then every column of U^ and V^ rescaled to unit FP64 norm */
 
-/* options for svdu_set_option */
+/* options of a context (svdu_set_option) */
 #define SVDU_OPT_SECULAR_MAXIT 1 /* iteration cap of the secular solver (default 200) */
 #define SVDU_OPT_TIMING 2        /* 1: record phase timings of svdu_rank1_update (resets the record) */
 #define SVDU_OPT_TILE_SHAPE 3    /* -1 (default): tile shape of the products from the tuning table;
@@ -77,6 +83,28 @@ extern "C" {
 #define SVDU_TILE_256x128_K32 5  /* 256 x 128 on 8 waves, 32-k stages: each generated C~ entry serves 256 rows */
 #define SVDU_TILE_SHAPES 6
 #define SVDU_TILE_BUCKETS 8      /* tuning-table buckets by order N: (0,64], (64,128], ..., (4096, inf) */
+
+/* ---- contexts ---------------------------------------------------------------
+ * The interface of Section 6.1 (input A = U Sigma V^T, a, b; output U^,
+ * Sigma^, V^) is svdu_rank1_update below; the context carries what stays the
+ * same between such calls. */
+typedef struct svdu_ctx svdu_ctx;
+
+/* Creates a context for HIP device `device` (>= 0) with the default options
+ * (secular cap 200, refinement on, grid schedule, tile shapes from the
+ * built-in tables, timing off). It allocates host memory only. Returns
+ * SVDU_OK (*ctx set), SVDU_EINVAL or SVDU_ENOMEM (*ctx = NULL). */
+int svdu_create(svdu_ctx** ctx, int device);
+
+/* Frees a context (NULL: nothing). Work already enqueued with it is not
+ * affected; batches created with it must be destroyed first (they record
+ * their eager launches in its timing ring). */
+void svdu_destroy(svdu_ctx* ctx);
+
+/* Sets option `option` (SVDU_OPT_*) of `ctx`; returns the previous value, or
+ * SVDU_EINVAL. A change applies to the calls enqueued after it; a batch or
+ * server keeps the options its context had when it was created. */
+int svdu_set_option(svdu_ctx* ctx, int option, int value);
 
 /* Bytes of device workspace svdu_rank1_update needs for (m, n, path, precision). */
 size_t svdu_workspace_bytes(int m, int n, int path, int precision);
@@ -107,12 +135,18 @@ size_t svdu_workspace_bytes(int m, int n, int path, int precision);
  *              (right, rho-); entry j of a row describes input column j of that
  *              update (left side: entries m..n-1 are 0): 0 kept, 1 zero
  *              component dropped, 2 merged into an exactly repeated pole.
+ *              (Section 3.1 names the deflation cases; code 1 is the case of a
+ *              zero component. Poles that are close but distinct are never
+ *              merged -- pole-relative roots resolve them -- so no rotation of
+ *              a near-equal pair exists; exact repeats, including the n - m
+ *              zero poles of the right-hand updates when n > m, all get code 2,
+ *              one reflection per repeated group.)
  *  workspace   device buffer of workspace_bytes >= svdu_workspace_bytes(...),
  *              256-byte aligned; it also holds the device status word, so one
  *              workspace serves one call in flight at a time.
  * Returns 0 or a negative SVDU_E* code (see the conventions above). */
-int svdu_rank1_update(int m, int n, const double* U, int ldu, const double* sigma, const double* V, int ldv,
-                      const double* a, const double* b, double eps, int path, int precision, double* U_out,
+int svdu_rank1_update(svdu_ctx* ctx, int m, int n, const double* U, int ldu, const double* sigma, const double* V,
+                      int ldv, const double* a, const double* b, double eps, int path, int precision, double* U_out,
                       int ldu_out, double* sigma_out, double* V_out, int ldv_out, int8_t* defl,
                       void* workspace, size_t workspace_bytes, void* stream);
 
@@ -137,9 +171,9 @@ size_t svdu_eig_update_workspace_bytes(int R, int N, int path);
  *  lam_out     N new eigenvalues, ascending.
  *  defl        NULL or N int8 flags (as for svdu_rank1_update).
  *  workspace   >= svdu_eig_update_workspace_bytes(R, N, path) bytes. */
-int svdu_eig_update(int R, int N, const double* X, int ldx, const double* lam, const double* z, double rho,
-                    int path, double eps, double* X_out, int ldo, double* lam_out, int8_t* defl, void* workspace,
-                    size_t workspace_bytes, void* stream);
+int svdu_eig_update(svdu_ctx* ctx, int R, int N, const double* X, int ldx, const double* lam, const double* z,
+                    double rho, int path, double eps, double* X_out, int ldo, double* lam_out, int8_t* defl,
+                    void* workspace, size_t workspace_bytes, void* stream);
 
 /* Roots of the secular equation w(mu) = 1 + rho sum_k z_k^2 / (d_k - mu)
  * (equation GolubEigenvalUpdate) for K distinct poles d (ascending) and
@@ -148,15 +182,12 @@ int svdu_eig_update(int R, int N, const double* X, int ldx, const double* lam, c
  * iters (may be NULL) receives the iteration count per root.
  * workspace >= svdu_secular_workspace_bytes(K). */
 size_t svdu_secular_workspace_bytes(int K);
-int svdu_secular(int K, const double* d, const double* z, double rho, int* org, double* tau, int* iters,
-                 void* workspace, size_t workspace_bytes, void* stream);
+int svdu_secular(svdu_ctx* ctx, int K, const double* d, const double* z, double rho, int* org, double* tau,
+                 int* iters, void* workspace, size_t workspace_bytes, void* stream);
 
-/* Process-wide tuning/test options (host); returns the previous value. */
-int svdu_set_option(int option, int value);
-
-/* Phase timings recorded while SVDU_OPT_TIMING is on (at most 256 calls since
- * it was switched on; svdu_rank1_update and eager svdu_batch_launch calls
- * are recorded). For call c, ms[5 c + k] (host array of 5 max_calls doubles)
+/* Phase timings recorded in `ctx` while its SVDU_OPT_TIMING is on (at most
+ * 256 calls since it was switched on; svdu_rank1_update and eager
+ * svdu_batch_launch calls made with the context are recorded). For call c, ms[5 c + k] (host array of 5 max_calls doubles)
  * receives the milliseconds of phase k, measured with HIP events on the
  * call's stream: 0 projections, 1 the O(n^2) eigen-update work of all four
  * updates (deflation, secular roots, weights, signs, singular values), 2 and
@@ -164,7 +195,7 @@ int svdu_set_option(int option, int value);
  * second level U~ C~_L- and V~ C~_R-, with the column rescaling of the
  * precision form; FMM path: left side, then right side), 4 the flag copies.
  * Waits for those events. Returns the number of calls filled, or SVDU_EHIP. */
-int svdu_timing_read(double* ms, int max_calls);
+int svdu_timing_read(svdu_ctx* ctx, double* ms, int max_calls);
 
 /* ---- batched updates (many independent problems of uneven sizes) ----------
  * Every step of the update is one launch over all problems of the batch (a
@@ -197,9 +228,12 @@ size_t svdu_batch_workspace_bytes(int count, const svdu_problem* probs, int prec
  * builds the job tables (ordered largest first), and enqueues their upload on
  * `stream`. The problem array may be freed on return; the buffers it names
  * and the workspace must stay valid until svdu_batch_destroy. flags: 0 or
- * SVDU_BATCH_PERSISTENT. Returns 0 or a negative SVDU_E* code (*out = NULL). */
-int svdu_batch_create(svdu_batch** out, int count, const svdu_problem* probs, int precision, int flags,
-                      void* workspace, size_t workspace_bytes, void* stream);
+ * SVDU_BATCH_PERSISTENT. The batch keeps a copy of the options of `ctx`
+ * (tile shapes, secular cap, refinement) and records its eager launches in
+ * the context's timing ring, so `ctx` must outlive it. Returns 0 or a
+ * negative SVDU_E* code (*out = NULL). */
+int svdu_batch_create(svdu_ctx* ctx, svdu_batch** out, int count, const svdu_problem* probs, int precision,
+                      int flags, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Enqueues one update of every problem on `stream` (it may differ from the
  * creation stream; the table upload is waited for). use_graph = 0: the
@@ -217,8 +251,9 @@ int svdu_batch_status(svdu_batch* b, int* status, void* stream);
 /* Waits for the table upload and frees the batch (not the workspace). */
 void svdu_batch_destroy(svdu_batch* b);
 
-/* create + eager launch + wait for `stream` + destroy. */
-int svdu_rank1_update_batched(int count, const svdu_problem* probs, int precision, void* workspace,
+/* create + eager launch + wait for `stream` + destroy (persistent schedule
+ * when the context's SVDU_OPT_PERSISTENT is set). */
+int svdu_rank1_update_batched(svdu_ctx* ctx, int count, const svdu_problem* probs, int precision, void* workspace,
                               size_t workspace_bytes, void* stream);
 
 /* ---- tile-shape autotuner --------------------------------------------------
@@ -226,17 +261,17 @@ int svdu_rank1_update_batched(int count, const svdu_problem* probs, int precisio
  * kernel of every tile shape on the same set of synthetic products of order
  * N (the bucket's upper end, or max_n), as many as make 4096 tiles of
  * 128 x 128 (16 per compute unit, so every shape runs on a full device), and stores the
- * fastest shape in the process-wide table used by every later call of that
- * precision. times_ms (host, SVDU_TILE_BUCKETS x SVDU_TILE_SHAPES, may be NULL) receives the
+ * fastest shape in the table of `ctx` used by every later call of that
+ * precision made with it. times_ms (host, SVDU_TILE_BUCKETS x SVDU_TILE_SHAPES, may be NULL) receives the
  * best of three timed launches per shape (-1 for buckets above max_n), table
  * (host, SVDU_TILE_BUCKETS, may be NULL) the chosen shapes. Synchronises
  * `stream`. */
 size_t svdu_autotune_workspace_bytes(int max_n);
-int svdu_autotune(int precision, int max_n, double* times_ms, int* table, void* workspace,
+int svdu_autotune(svdu_ctx* ctx, int precision, int max_n, double* times_ms, int* table, void* workspace,
                   size_t workspace_bytes, void* stream);
-/* Reads (set = 0) or writes (set = 1) the process-wide tuning table of a
- * precision (host array of SVDU_TILE_BUCKETS shapes). */
-int svdu_tile_table(int precision, int* table, int set);
+/* Reads (set = 0) or writes (set = 1) the tuning table of a precision in
+ * `ctx` (host array of SVDU_TILE_BUCKETS shapes). */
+int svdu_tile_table(svdu_ctx* ctx, int precision, int* table, int set);
 
 /* ---- serving runtime (resident matrices, memory admission, continuous batching)
  * The server holds matrices registered with two buffer sets each (U m x m,
@@ -279,8 +314,12 @@ typedef struct {
 typedef struct svdu_server svdu_server;
 
 /* arena: device memory of arena_bytes (>= 1 MiB, 256-byte aligned) that the
- * server carves its workspaces from; it allocates no device memory itself. */
-int svdu_server_create(svdu_server** out, const svdu_server_config* cfg, void* arena, size_t arena_bytes);
+ * server carves its workspaces from; it allocates no device memory itself.
+ * The server runs on the device of `ctx` with a copy of its options taken
+ * here: later changes to `ctx` do not reach the server, and `ctx` may be
+ * destroyed while the server runs. */
+int svdu_server_create(svdu_ctx* ctx, svdu_server** out, const svdu_server_config* cfg, void* arena,
+                       size_t arena_bytes);
 /* Registers a matrix (before svdu_server_start); *id receives its index. */
 int svdu_server_add_matrix(svdu_server* s, int m, int n, double* U0, double* sigma0, double* V0, double* U1,
                            double* sigma1, double* V1, int* id);

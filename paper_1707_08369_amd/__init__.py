@@ -44,7 +44,7 @@ SVDU_TILE_BUCKETS = 8
 SVDU_BATCH_PERSISTENT = 1
 TIMING_PHASES = 5
 
-EXPORTS = ("svdu_workspace_bytes", "svdu_rank1_update", "svdu_get_status", "svdu_eig_update_workspace_bytes",
+EXPORTS = ("svdu_create", "svdu_destroy", "svdu_workspace_bytes", "svdu_rank1_update", "svdu_get_status", "svdu_eig_update_workspace_bytes",
            "svdu_eig_update", "svdu_secular_workspace_bytes", "svdu_secular", "svdu_set_option",
            "svdu_status_string", "svdu_timing_read", "svdu_batch_workspace_bytes", "svdu_batch_create",
            "svdu_batch_launch", "svdu_batch_status", "svdu_batch_destroy", "svdu_rank1_update_batched",
@@ -101,32 +101,36 @@ def load():
         raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
     lib = ctypes.CDLL(LIB_PATH)
     c_int, c_size, c_dbl, c_vp = ctypes.c_int, ctypes.c_size_t, ctypes.c_double, ctypes.c_void_p
+    lib.svdu_create.argtypes = [ctypes.POINTER(c_vp), c_int]
+    lib.svdu_create.restype = c_int
+    lib.svdu_destroy.argtypes = [c_vp]
+    lib.svdu_destroy.restype = None
     lib.svdu_workspace_bytes.argtypes = [c_int, c_int, c_int, c_int]
     lib.svdu_workspace_bytes.restype = c_size
-    lib.svdu_rank1_update.argtypes = [c_int, c_int, c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_vp, c_dbl, c_int, c_int,
+    lib.svdu_rank1_update.argtypes = [c_vp, c_int, c_int, c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_vp, c_dbl, c_int, c_int,
                                       c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_vp, c_size, c_vp]
     lib.svdu_rank1_update.restype = c_int
     lib.svdu_get_status.argtypes = [c_vp, c_vp]
     lib.svdu_get_status.restype = c_int
     lib.svdu_eig_update_workspace_bytes.argtypes = [c_int, c_int, c_int]
     lib.svdu_eig_update_workspace_bytes.restype = c_size
-    lib.svdu_eig_update.argtypes = [c_int, c_int, c_vp, c_int, c_vp, c_vp, c_dbl, c_int, c_dbl, c_vp, c_int, c_vp,
+    lib.svdu_eig_update.argtypes = [c_vp, c_int, c_int, c_vp, c_int, c_vp, c_vp, c_dbl, c_int, c_dbl, c_vp, c_int, c_vp,
                                     c_vp, c_vp, c_size, c_vp]
     lib.svdu_eig_update.restype = c_int
     lib.svdu_secular_workspace_bytes.argtypes = [c_int]
     lib.svdu_secular_workspace_bytes.restype = c_size
-    lib.svdu_secular.argtypes = [c_int, c_vp, c_vp, c_dbl, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]
+    lib.svdu_secular.argtypes = [c_vp, c_int, c_vp, c_vp, c_dbl, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]
     lib.svdu_secular.restype = c_int
-    lib.svdu_set_option.argtypes = [c_int, c_int]
+    lib.svdu_set_option.argtypes = [c_vp, c_int, c_int]
     lib.svdu_set_option.restype = c_int
-    lib.svdu_timing_read.argtypes = [c_vp, c_int]
+    lib.svdu_timing_read.argtypes = [c_vp, c_vp, c_int]
     lib.svdu_timing_read.restype = c_int
     lib.svdu_status_string.argtypes = [c_int]
     lib.svdu_status_string.restype = ctypes.c_char_p
     c_pp = ctypes.POINTER(svdu_problem)
     lib.svdu_batch_workspace_bytes.argtypes = [c_int, c_pp, c_int]
     lib.svdu_batch_workspace_bytes.restype = c_size
-    lib.svdu_batch_create.argtypes = [ctypes.POINTER(c_vp), c_int, c_pp, c_int, c_int, c_vp, c_size, c_vp]
+    lib.svdu_batch_create.argtypes = [c_vp, ctypes.POINTER(c_vp), c_int, c_pp, c_int, c_int, c_vp, c_size, c_vp]
     lib.svdu_batch_create.restype = c_int
     lib.svdu_batch_launch.argtypes = [c_vp, c_int, c_vp]
     lib.svdu_batch_launch.restype = c_int
@@ -134,15 +138,15 @@ def load():
     lib.svdu_batch_status.restype = c_int
     lib.svdu_batch_destroy.argtypes = [c_vp]
     lib.svdu_batch_destroy.restype = None
-    lib.svdu_rank1_update_batched.argtypes = [c_int, c_pp, c_int, c_vp, c_size, c_vp]
+    lib.svdu_rank1_update_batched.argtypes = [c_vp, c_int, c_pp, c_int, c_vp, c_size, c_vp]
     lib.svdu_rank1_update_batched.restype = c_int
     lib.svdu_autotune_workspace_bytes.argtypes = [c_int]
     lib.svdu_autotune_workspace_bytes.restype = c_size
-    lib.svdu_autotune.argtypes = [c_int, c_int, c_vp, c_vp, c_vp, c_size, c_vp]
+    lib.svdu_autotune.argtypes = [c_vp, c_int, c_int, c_vp, c_vp, c_vp, c_size, c_vp]
     lib.svdu_autotune.restype = c_int
-    lib.svdu_tile_table.argtypes = [c_int, c_vp, c_int]
+    lib.svdu_tile_table.argtypes = [c_vp, c_int, c_vp, c_int]
     lib.svdu_tile_table.restype = c_int
-    lib.svdu_server_create.argtypes = [ctypes.POINTER(c_vp), ctypes.POINTER(svdu_server_config), c_vp, c_size]
+    lib.svdu_server_create.argtypes = [c_vp, ctypes.POINTER(c_vp), ctypes.POINTER(svdu_server_config), c_vp, c_size]
     lib.svdu_server_create.restype = c_int
     lib.svdu_server_add_matrix.argtypes = [c_vp, c_int, c_int, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                            ctypes.POINTER(c_int)]
@@ -175,9 +179,17 @@ def svdu_workspace_bytes(m, n, path=SVDU_PATH_DIRECT, precision=SVDU_PREC_FP64) 
     return int(load().svdu_workspace_bytes(m, n, path, precision))
 
 
-def svdu_rank1_update(m, n, U, ldu, sigma, V, ldv, a, b, eps, path, precision, U_out, ldu_out, sigma_out, V_out,
-                      ldv_out, defl, workspace, workspace_bytes, stream) -> int:
-    return int(load().svdu_rank1_update(m, n, U, ldu, sigma, V, ldv, a, b, eps, path, precision, U_out, ldu_out,
+def svdu_create(ctx_out, device) -> int:
+    return int(load().svdu_create(ctx_out, device))
+
+
+def svdu_destroy(ctx) -> None:
+    load().svdu_destroy(ctx)
+
+
+def svdu_rank1_update(ctx, m, n, U, ldu, sigma, V, ldv, a, b, eps, path, precision, U_out, ldu_out, sigma_out,
+                      V_out, ldv_out, defl, workspace, workspace_bytes, stream) -> int:
+    return int(load().svdu_rank1_update(ctx, m, n, U, ldu, sigma, V, ldv, a, b, eps, path, precision, U_out, ldu_out,
                                         sigma_out, V_out, ldv_out, defl, workspace, workspace_bytes, stream))
 
 
@@ -189,9 +201,9 @@ def svdu_eig_update_workspace_bytes(R, N, path=SVDU_PATH_DIRECT) -> int:
     return int(load().svdu_eig_update_workspace_bytes(R, N, path))
 
 
-def svdu_eig_update(R, N, X, ldx, lam, z, rho, path, eps, X_out, ldo, lam_out, defl, workspace, workspace_bytes,
-                    stream) -> int:
-    return int(load().svdu_eig_update(R, N, X, ldx, lam, z, rho, path, eps, X_out, ldo, lam_out, defl, workspace,
+def svdu_eig_update(ctx, R, N, X, ldx, lam, z, rho, path, eps, X_out, ldo, lam_out, defl, workspace,
+                    workspace_bytes, stream) -> int:
+    return int(load().svdu_eig_update(ctx, R, N, X, ldx, lam, z, rho, path, eps, X_out, ldo, lam_out, defl, workspace,
                                       workspace_bytes, stream))
 
 
@@ -199,23 +211,79 @@ def svdu_secular_workspace_bytes(K) -> int:
     return int(load().svdu_secular_workspace_bytes(K))
 
 
-def svdu_secular(K, d, z, rho, org, tau, iters, workspace, workspace_bytes, stream) -> int:
-    return int(load().svdu_secular(K, d, z, rho, org, tau, iters, workspace, workspace_bytes, stream))
+def svdu_secular(ctx, K, d, z, rho, org, tau, iters, workspace, workspace_bytes, stream) -> int:
+    return int(load().svdu_secular(ctx, K, d, z, rho, org, tau, iters, workspace, workspace_bytes, stream))
 
 
-def svdu_set_option(option, value) -> int:
-    return int(load().svdu_set_option(option, value))
+def svdu_set_option(ctx, option, value) -> int:
+    return int(load().svdu_set_option(ctx, option, value))
 
 
-def svdu_timing_read(ms, max_calls) -> int:
-    return int(load().svdu_timing_read(ms, max_calls))
+def svdu_timing_read(ctx, ms, max_calls) -> int:
+    return int(load().svdu_timing_read(ctx, ms, max_calls))
 
 
-def timing_read(max_calls=256):
+class Context:
+    """A libsvdu context (svdu_create / svdu_destroy): options, tile tables and
+    the timing record of the calls made with it, bound to one device."""
+
+    def __init__(self, device=None):
+        torch = _torch()
+        dev = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        rc = svdu_create(ctypes.byref(h), dev)
+        if rc != SVDU_OK:
+            raise SvduError(rc, "svdu_create")
+        self._h = h
+        self.device = dev
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_option(self, option, value):
+        """Sets an option; returns the previous value (or SVDU_EINVAL)."""
+        return svdu_set_option(self._h, option, value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            svdu_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def default_context(device=None):
+    """The context the helpers below use when none is given (one per device)."""
+    torch = _torch()
+    dev = torch.cuda.current_device() if device is None else int(device)
+    c = _default_ctx.get(dev)
+    if c is None:
+        c = _default_ctx[dev] = Context(dev)
+    return c
+
+
+def _ctx(ctx):
+    return (ctx if ctx is not None else default_context()).handle
+
+
+def set_option(option, value, ctx=None) -> int:
+    """Sets an option of ``ctx`` (default: the default context); returns the previous value."""
+    return svdu_set_option(_ctx(ctx), option, value)
+
+
+def timing_read(max_calls=256, ctx=None):
     """Phase timings (ms) of the calls recorded since SVDU_OPT_TIMING was set: list of 5-tuples."""
     P = TIMING_PHASES
     buf = (ctypes.c_double * (P * max_calls))()
-    n = svdu_timing_read(ctypes.cast(buf, ctypes.c_void_p), max_calls)
+    n = svdu_timing_read(_ctx(ctx), ctypes.cast(buf, ctypes.c_void_p), max_calls)
     if n < 0:
         raise SvduError(n, "svdu_timing_read")
     return [tuple(buf[P * c + k] for k in range(P)) for c in range(n)]
@@ -225,8 +293,8 @@ def svdu_batch_workspace_bytes(count, probs, precision) -> int:
     return int(load().svdu_batch_workspace_bytes(count, probs, precision))
 
 
-def svdu_batch_create(out, count, probs, precision, flags, workspace, workspace_bytes, stream) -> int:
-    return int(load().svdu_batch_create(out, count, probs, precision, flags, workspace, workspace_bytes, stream))
+def svdu_batch_create(ctx, out, count, probs, precision, flags, workspace, workspace_bytes, stream) -> int:
+    return int(load().svdu_batch_create(ctx, out, count, probs, precision, flags, workspace, workspace_bytes, stream))
 
 
 def svdu_batch_launch(batch, use_graph, stream) -> int:
@@ -241,20 +309,20 @@ def svdu_batch_destroy(batch) -> None:
     load().svdu_batch_destroy(batch)
 
 
-def svdu_rank1_update_batched(count, probs, precision, workspace, workspace_bytes, stream) -> int:
-    return int(load().svdu_rank1_update_batched(count, probs, precision, workspace, workspace_bytes, stream))
+def svdu_rank1_update_batched(ctx, count, probs, precision, workspace, workspace_bytes, stream) -> int:
+    return int(load().svdu_rank1_update_batched(ctx, count, probs, precision, workspace, workspace_bytes, stream))
 
 
 def svdu_autotune_workspace_bytes(max_n) -> int:
     return int(load().svdu_autotune_workspace_bytes(max_n))
 
 
-def svdu_autotune(precision, max_n, times_ms, table, workspace, workspace_bytes, stream) -> int:
-    return int(load().svdu_autotune(precision, max_n, times_ms, table, workspace, workspace_bytes, stream))
+def svdu_autotune(ctx, precision, max_n, times_ms, table, workspace, workspace_bytes, stream) -> int:
+    return int(load().svdu_autotune(ctx, precision, max_n, times_ms, table, workspace, workspace_bytes, stream))
 
 
-def svdu_tile_table(precision, table, set_) -> int:
-    return int(load().svdu_tile_table(precision, table, set_))
+def svdu_tile_table(ctx, precision, table, set_) -> int:
+    return int(load().svdu_tile_table(ctx, precision, table, set_))
 
 
 def svdu_status_string(code) -> str:
@@ -306,7 +374,7 @@ def _aligned(ws):
 
 
 def rank1_update(U, sigma, V, a, b, eps=1e-10, path=SVDU_PATH_DIRECT, precision=SVDU_PREC_FP64, out=None,
-                 workspace=None, want_defl=True, stream=None, check=True):
+                 workspace=None, want_defl=True, stream=None, check=True, ctx=None):
     """SVD of U diag(sigma) V^T + a b^T. Returns (U^, sigma^, V^, defl flags or None).
 
     ``out`` may pass preallocated (U_out, sigma_out, V_out); ``workspace`` a uint8
@@ -335,7 +403,7 @@ def rank1_update(U, sigma, V, a, b, eps=1e-10, path=SVDU_PATH_DIRECT, precision=
     wp, wb = _aligned(workspace)
     defl = torch.empty((4, n), dtype=torch.int8, device=dev) if want_defl else None
     sh = _stream_handle(stream)
-    rc = svdu_rank1_update(m, n, _ptr(U), ldu, _ptr(sigma), _ptr(V), ldv, _ptr(a), _ptr(b), float(eps), path,
+    rc = svdu_rank1_update(_ctx(ctx), m, n, _ptr(U), ldu, _ptr(sigma), _ptr(V), ldv, _ptr(a), _ptr(b), float(eps), path,
                            precision, _ptr(Uo), lduo, _ptr(so), _ptr(Vo), ldvo, _ptr(defl), wp, wb, sh)
     if rc != SVDU_OK:
         raise SvduError(rc, "svdu_rank1_update")
@@ -346,7 +414,7 @@ def rank1_update(U, sigma, V, a, b, eps=1e-10, path=SVDU_PATH_DIRECT, precision=
     return Uo, so, Vo, defl
 
 
-def eig_update(X, lam, z, rho, path=SVDU_PATH_DIRECT, eps=1e-10, stream=None, check=True):
+def eig_update(X, lam, z, rho, path=SVDU_PATH_DIRECT, eps=1e-10, stream=None, check=True, ctx=None):
     """One RankOneUpdate: returns (X C~, new eigenvalues ascending, flags)."""
     torch = _torch()
     R, N = X.shape
@@ -359,7 +427,7 @@ def eig_update(X, lam, z, rho, path=SVDU_PATH_DIRECT, eps=1e-10, stream=None, ch
     ws = new_workspace(svdu_eig_update_workspace_bytes(R, N, path), X.device)
     wp, wb = _aligned(ws)
     sh = _stream_handle(stream)
-    rc = svdu_eig_update(R, N, _ptr(X), ldx, _ptr(lam), _ptr(z), float(rho), path, float(eps), _ptr(Xo), max(N, 1),
+    rc = svdu_eig_update(_ctx(ctx), R, N, _ptr(X), ldx, _ptr(lam), _ptr(z), float(rho), path, float(eps), _ptr(Xo), max(N, 1),
                          _ptr(lo), _ptr(fl), wp, wb, sh)
     if rc != SVDU_OK:
         raise SvduError(rc, "svdu_eig_update")
@@ -370,7 +438,7 @@ def eig_update(X, lam, z, rho, path=SVDU_PATH_DIRECT, eps=1e-10, stream=None, ch
     return Xo, lo, fl
 
 
-def secular(d, z, rho, stream=None, check=True):
+def secular(d, z, rho, stream=None, check=True, ctx=None):
     """Roots of 1 + rho sum z^2/(d - mu) for distinct ascending d: (org, tau, iters)."""
     torch = _torch()
     K = d.shape[0]
@@ -382,7 +450,7 @@ def secular(d, z, rho, stream=None, check=True):
     ws = new_workspace(svdu_secular_workspace_bytes(K), d.device)
     wp, wb = _aligned(ws)
     sh = _stream_handle(stream)
-    rc = svdu_secular(K, _ptr(d), _ptr(z), float(rho), _ptr(org), _ptr(tau), _ptr(its), wp, wb, sh)
+    rc = svdu_secular(_ctx(ctx), K, _ptr(d), _ptr(z), float(rho), _ptr(org), _ptr(tau), _ptr(its), wp, wb, sh)
     if rc != SVDU_OK:
         raise SvduError(rc, "svdu_secular")
     if check:
@@ -404,9 +472,10 @@ class Batch:
     """
 
     def __init__(self, items, precision=SVDU_PREC_FP64, persistent=False, outs=None, want_defl=False,
-                 stream=None):
+                 stream=None, ctx=None):
         torch = _torch()
         self._lib = load()
+        self._ctx_obj = ctx if ctx is not None else default_context()   # must outlive the batch
         self.precision = precision
         self.items = list(items)
         self.count = len(self.items)
@@ -444,7 +513,7 @@ class Batch:
         self.workspace = new_workspace(need, self.items[0][0].device)
         wp, wb = _aligned(self.workspace)
         h = ctypes.c_void_p()
-        rc = svdu_batch_create(ctypes.byref(h), self.count, arr, precision,
+        rc = svdu_batch_create(self._ctx_obj.handle, ctypes.byref(h), self.count, arr, precision,
                                SVDU_BATCH_PERSISTENT if persistent else 0, wp, wb, _stream_handle(stream))
         if rc != SVDU_OK:
             raise SvduError(rc, "svdu_batch_create")
@@ -476,9 +545,9 @@ class Batch:
 
 
 def rank1_update_batched(items, precision=SVDU_PREC_FP64, use_graph=False, persistent=False, stream=None,
-                         check=True):
+                         check=True, ctx=None):
     """Updates every (U, sigma, V, a, b) of ``items`` in one batch; returns [(U^, sigma^, V^), ...]."""
-    b = Batch(items, precision=precision, persistent=persistent, stream=stream)
+    b = Batch(items, precision=precision, persistent=persistent, stream=stream, ctx=ctx)
     b.launch(use_graph=use_graph, stream=stream)
     if check:
         st = b.status(stream)
@@ -490,7 +559,7 @@ def rank1_update_batched(items, precision=SVDU_PREC_FP64, use_graph=False, persi
     return outs
 
 
-def autotune(precision=SVDU_PREC_FP64, max_n=4096, stream=None):
+def autotune(precision=SVDU_PREC_FP64, max_n=4096, stream=None, ctx=None):
     """Runs the tile-shape autotuner; returns (table, times_ms[bucket][shape])."""
     torch = _torch()
     need = svdu_autotune_workspace_bytes(max_n)
@@ -498,7 +567,7 @@ def autotune(precision=SVDU_PREC_FP64, max_n=4096, stream=None):
     wp, wb = _aligned(ws)
     times = (ctypes.c_double * (SVDU_TILE_BUCKETS * SVDU_TILE_SHAPES))()
     table = (ctypes.c_int * SVDU_TILE_BUCKETS)()
-    rc = svdu_autotune(precision, max_n, ctypes.cast(times, ctypes.c_void_p), ctypes.cast(table, ctypes.c_void_p),
+    rc = svdu_autotune(_ctx(ctx), precision, max_n, ctypes.cast(times, ctypes.c_void_p), ctypes.cast(table, ctypes.c_void_p),
                        wp, wb, _stream_handle(stream))
     if rc != SVDU_OK:
         raise SvduError(rc, "svdu_autotune")
@@ -506,10 +575,10 @@ def autotune(precision=SVDU_PREC_FP64, max_n=4096, stream=None):
                          for b in range(SVDU_TILE_BUCKETS)]
 
 
-def tile_table(precision=SVDU_PREC_FP64, table=None):
-    """Reads the tuning table, or sets it when ``table`` is given."""
+def tile_table(precision=SVDU_PREC_FP64, table=None, ctx=None):
+    """Reads the tuning table of ``ctx``, or sets it when ``table`` is given."""
     buf = (ctypes.c_int * SVDU_TILE_BUCKETS)(*(table or [0] * SVDU_TILE_BUCKETS))
-    rc = svdu_tile_table(precision, ctypes.cast(buf, ctypes.c_void_p), 1 if table is not None else 0)
+    rc = svdu_tile_table(_ctx(ctx), precision, ctypes.cast(buf, ctypes.c_void_p), 1 if table is not None else 0)
     if rc != SVDU_OK:
         raise SvduError(rc, "svdu_tile_table")
     return list(buf)
@@ -518,8 +587,8 @@ def tile_table(precision=SVDU_PREC_FP64, table=None):
 # ---------------------------------------------------------------------------
 # serving runtime
 # ---------------------------------------------------------------------------
-def svdu_server_create(out, cfg, arena, arena_bytes) -> int:
-    return int(load().svdu_server_create(out, cfg, arena, arena_bytes))
+def svdu_server_create(ctx, out, cfg, arena, arena_bytes) -> int:
+    return int(load().svdu_server_create(ctx, out, cfg, arena, arena_bytes))
 
 
 def svdu_server_add_matrix(server, m, n, U0, s0, V0, U1, s1, V1, id_out) -> int:
@@ -567,14 +636,14 @@ class Server:
     """
 
     def __init__(self, arena_bytes, workers=2, max_batch=64, precision=SVDU_PREC_FP64, fmm_min_n=0,
-                 fmm_eps=1e-10, batch_cost_factor=2.0, min_batch_cost=4e9, min_cost_ratio=0.25):
+                 fmm_eps=1e-10, batch_cost_factor=2.0, min_batch_cost=4e9, min_cost_ratio=0.25, ctx=None):
         torch = _torch()
         self._arena = new_workspace(int(arena_bytes), torch.device("cuda"))
         ap, ab = _aligned(self._arena)
         cfg = svdu_server_config(workers, max_batch, precision, fmm_min_n, fmm_eps, batch_cost_factor,
                                  min_batch_cost, min_cost_ratio)
         h = ctypes.c_void_p()
-        rc = svdu_server_create(ctypes.byref(h), ctypes.byref(cfg), ap, ab)
+        rc = svdu_server_create(_ctx(ctx), ctypes.byref(h), ctypes.byref(cfg), ap, ab)
         if rc != SVDU_OK:
             raise SvduError(rc, "svdu_server_create")
         self._h = h

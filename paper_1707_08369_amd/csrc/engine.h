@@ -16,6 +16,41 @@
 
 namespace svdu {
 
+// ---- options of a context (svdu_ctx) -----------------------------------------------
+constexpr int kShapeBuckets = 8;   // N in (0,64], (64,128], ..., (4096, inf)
+constexpr int kNumPrec = 2;        // SVDU_PREC_FP64, SVDU_PREC_SPLIT32
+int shape_bucket(int N);
+// The tile shapes the autotuner measured on MI355X, per precision and bucket.
+void default_shape_table(int (&t)[kNumPrec][kShapeBuckets]);
+
+struct Options {
+  int maxit = 200;                          // secular iteration cap
+  bool refine = true;                       // close-cluster refinement of FP64 results
+  bool persistent = false;                  // persistent product schedule
+  int forced_shape = -1;                    // -1: the table
+  int shape_table[kNumPrec][kShapeBuckets];
+  Options() { default_shape_table(shape_table); }
+};
+int choose_shape(int N, int precision, const Options& o);
+int gemm_grid_cap(int shape, int precision);   // blocks resident at once (persistent schedule)
+
+// ---- timing ring ------------------------------------------------------------------
+// HIP events at the boundaries of the phases of each recorded call
+// (projections | O(n^2) eigen-update work | products, first level | products,
+// second level | flags), for up to kRingCalls calls.
+constexpr int kRingCalls = 256, kRingEvents = 6;
+struct TimingRing {
+  bool on = false;
+  int count = 0;
+  bool made[kRingCalls] = {};
+  hipEvent_t ev[kRingCalls][kRingEvents];
+  ~TimingRing();
+  int begin();                                // call index, or -1 when off or full
+  void mark(int call, int k, hipStream_t st);
+  int set(bool on);                           // returns the previous state; resets the record
+  int read(double* ms, int max_calls);
+};
+
 // ---- workspace carving ------------------------------------------------------
 struct Carver {
   char* base;
@@ -130,14 +165,15 @@ struct BlobWriter {
 // A level of eigen-updates (largest first) with its block offsets.
 StageLevel build_level(const std::vector<Stage>& st, const std::vector<TmvJob>& tmv, BlobWriter& B);
 // A product job in the tile shape the chooser gives for (R, N, precision).
-GemmJob make_gemm_job(int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo, int precision);
+GemmJob make_gemm_job(int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo, int precision,
+                      const Options& opt);
 // A list of products of one tile shape, largest first.
 GemmList build_gemm_list(std::vector<GemmJob> jobs, int* counter, BlobWriter& B);
 
 // Tables of `ups` appended to `blob`, with device views relative to
 // dev_base (the device address the blob will be copied to; nullptr to size
 // the blob only). `counters` points at 2 * kNumShapes ints of device memory.
-void build_plan(const std::vector<Update>& ups, int precision, char* dev_base, int* counters,
+void build_plan(const std::vector<Update>& ups, int precision, const Options& opt, char* dev_base, int* counters,
                 std::vector<char>* blob, Plan* plan);
 
 // Bytes reserved in a single update's workspace for its tables.
@@ -154,31 +190,41 @@ struct Sched {
   int maxit = 200;
   bool persistent = false;
   bool refine = true;
-  int grid_cap[2][kNumShapes] = {};   // [precision][shape]
+  int grid_cap[kNumPrec][kNumShapes] = {};   // [precision][shape]
+  TimingRing* ring = nullptr;                // phase events of call `tcall` (nullptr: none)
+  int tcall = -1;
+  void mark(int k, hipStream_t st) const {
+    if (ring) ring->mark(tcall, k, st);
+  }
 };
 // Enqueues the sequence (or a part of it: the FMM path runs the products
 // itself between the two parts).
-void enqueue_plan(const Plan& P, const Sched& S, int tcall, int part, hipStream_t st);
+void enqueue_plan(const Plan& P, const Sched& S, int part, hipStream_t st);
 
 // Gathers the status words of the plan's updates into out[0..n-1] (device).
 void enqueue_status_gather(const Plan& P, int* out, hipStream_t st);
 
-// ---- tile-shape choice ---------------------------------------------------------
-constexpr int kShapeBuckets = 8;   // N in (0,64], (64,128], ..., (4096, inf)
-int shape_bucket(int N);
-int choose_shape(int R, int N, int precision);
-int shape_table_get(int precision, int bucket);
-void shape_table_set(int precision, int bucket, int shape);
-int set_forced_shape(int shape);   // -1: use the table
-int gemm_grid_cap(int shape, int precision);   // blocks resident at once (persistent schedule)
-
-// ---- timing ring ---------------------------------------------------------------
-constexpr int kRingCalls = 256, kRingEvents = 6;
-int ring_begin();
-void ring_mark(int call, int k, hipStream_t st);
-int ring_set(bool on);
-int ring_read(double* ms, int max_calls);
-
 int status_code(int bits);
 
+}  // namespace svdu
+
+// A context: the options, tile tables and timing ring of the calls made with
+// it, bound to one device. Every context is independent of the others; one
+// context is used by one host thread at a time.
+struct svdu_ctx {
+  int device = 0;
+  svdu::Options opt;
+  svdu::TimingRing ring;
+  bool have_caps = false;
+  int grid_cap[svdu::kNumPrec][svdu::kNumShapes] = {};
+};
+
+namespace svdu {
+// The schedule of a call made with `ctx` (queries the device's capacity for
+// persistent blocks once per context when `persistent`); `timed`: record the
+// call's phases in the context's ring when it is on.
+Sched sched_of(svdu_ctx* ctx, const Options& o, bool persistent, bool timed);
+// SVDU_OK when the context's device is current, else SVDU_EINVAL (SVDU_EHIP
+// when the runtime cannot tell).
+int ctx_device_check(const svdu_ctx* ctx);
 }  // namespace svdu

@@ -323,8 +323,9 @@ StageLevel build_level(const std::vector<Stage>& st_in, const std::vector<TmvJob
   return S;
 }
 
-GemmJob make_gemm_job(int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo, int precision) {
-  const int sh = run_shape(choose_shape(R, d.N, precision), precision == SVDU_PREC_SPLIT32);
+GemmJob make_gemm_job(int R, const double* X, int ldx, const CauchyDesc& d, double* Xo, int ldo, int precision,
+                      const Options& opt) {
+  const int sh = run_shape(choose_shape(d.N, precision, opt), precision == SVDU_PREC_SPLIT32);
   GemmJob J{};
   J.R = R;
   J.ldx = ldx;
@@ -358,7 +359,7 @@ GemmList build_gemm_list(std::vector<GemmJob> jobs, int* counter, BlobWriter& B)
   return G;
 }
 
-void build_plan(const std::vector<Update>& ups_in, int precision, char* dev_base, int* counters,
+void build_plan(const std::vector<Update>& ups_in, int precision, const Options& opt, char* dev_base, int* counters,
                 std::vector<char>* blob, Plan* plan) {
   std::vector<Update> ups = ups_in;
   for (Update& u : ups) stage_inputs(u);
@@ -464,14 +465,15 @@ void build_plan(const std::vector<Update>& ups_in, int precision, char* dev_base
       const Layout& L = u.L;
       GemmJob g[2];
       if (lev == 0) {
-        g[0] = make_gemm_job(u.m, u.U, u.ldu, desc_of(L.st[0]), L.TL, u.m, precision);
+        g[0] = make_gemm_job(u.m, u.U, u.ldu, desc_of(L.st[0]), L.TL, u.m, precision, opt);
         const CauchyDesc dr = desc_of(L.st[2]);
-        g[1] = make_gemm_job(u.n, u.V, u.ldv, u.n > u.m ? with_members(dr, L.st[2]) : dr, L.TR, u.n, precision);
+        g[1] = make_gemm_job(u.n, u.V, u.ldv, u.n > u.m ? with_members(dr, L.st[2]) : dr, L.TR, u.n, precision,
+                             opt);
       } else {
-        g[0] = make_gemm_job(u.m, L.TL, u.m, desc_of(L.st[1]), u.U_out, u.ldu_out, precision);
+        g[0] = make_gemm_job(u.m, L.TL, u.m, desc_of(L.st[1]), u.U_out, u.ldu_out, precision, opt);
         const CauchyDesc dr = desc_of(L.st[3], L.signs);
         g[1] = make_gemm_job(u.n, L.TR, u.n, u.n > u.m ? with_members(dr, L.st[3]) : dr, u.V_out, u.ldv_out,
-                             precision);
+                             precision, opt);
       }
       for (int k = 0; k < 2; ++k) by_shape[g[k].shape].push_back(g[k]);
     }
@@ -581,14 +583,14 @@ void write_blob(const std::vector<char>& blob, char* dst, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // the sequence
 // ---------------------------------------------------------------------------
-void enqueue_plan(const Plan& P, const Sched& S, int tcall, int part, hipStream_t st) {
+void enqueue_plan(const Plan& P, const Sched& S, int part, hipStream_t st) {
   const bool s32 = P.precision == SVDU_PREC_SPLIT32;
   if (part != kStepProductsOnward) {
-    ring_mark(tcall, 0, st);
+    S.mark(0, st);
     if (P.prob.blocks_n > 0)
       hipLaunchKernelGGL(prob_init_kernel, dim3(P.prob.blocks_n), dim3(256), 0, st, P.prob);
     launch_gemv_list(P.gemv, st);
-    ring_mark(tcall, 1, st);
+    S.mark(1, st);
     if (P.prob.n > 0) hipLaunchKernelGGL(prob_setup_kernel, dim3(P.prob.n), dim3(1024), 0, st, P.prob);
     for (int lev = 0; lev < 2; ++lev) {
       launch_stage_level(P.lev[lev], S.maxit, st);
@@ -596,7 +598,7 @@ void enqueue_plan(const Plan& P, const Sched& S, int tcall, int part, hipStream_
     }
     if (P.prob.blocks_n > 0)
       hipLaunchKernelGGL(prob_finalize_kernel, dim3(P.prob.blocks_n), dim3(256), 0, st, P.prob);
-    ring_mark(tcall, 2, st);
+    S.mark(2, st);
   }
   if (part == kStepUpToRoots) return;
   if (part == kStepAll) {
@@ -611,13 +613,13 @@ void enqueue_plan(const Plan& P, const Sched& S, int tcall, int part, hipStream_
           launch_gemm_f64(G, sh, pers, cap, st);
       }
       if (lev == 1 && s32) launch_column_renorm(P.renorm, st);
-      ring_mark(tcall, 3 + lev, st);
+      S.mark(3 + lev, st);
     }
   }
   if (S.refine) launch_refine(P.refine, st);
   if (P.any_defl && P.prob.blocks_n > 0)
     hipLaunchKernelGGL(prob_flags_kernel, dim3(P.prob.blocks_n), dim3(256), 0, st, P.prob);
-  ring_mark(tcall, 5, st);
+  S.mark(5, st);
 }
 
 void enqueue_status_gather(const Plan& P, int* out, hipStream_t st) {
@@ -626,15 +628,16 @@ void enqueue_status_gather(const Plan& P, int* out, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// tile shapes: a table per precision and size bucket, filled by the autotuner
-// (svdu_autotune); the defaults are what it measured on MI355X.
+// tile shapes: a table per precision and size bucket in every context, filled
+// by the autotuner (svdu_autotune); the defaults are what it measured on
+// MI355X.
 // ---------------------------------------------------------------------------
-namespace {
-int g_shape_table[2][kShapeBuckets] = {
-    {kT64x64, kT128x64, kT256x128k32, kT256x128k32, kT256x128k32, kT256x128k32, kT256x128k32, kT256x128k32},
-    {kT64x64, kT64x64, kT64x64, kT64x64, kT64x64, kT64x64, kT128x128, kT128x128}};
-int g_forced_shape = -1;
-}  // namespace
+void default_shape_table(int (&t)[kNumPrec][kShapeBuckets]) {
+  static const int def[kNumPrec][kShapeBuckets] = {
+      {kT64x64, kT128x64, kT256x128k32, kT256x128k32, kT256x128k32, kT256x128k32, kT256x128k32, kT256x128k32},
+      {kT64x64, kT64x64, kT64x64, kT64x64, kT64x64, kT64x64, kT128x128, kT128x128}};
+  memcpy(t, def, sizeof(def));
+}
 
 int shape_bucket(int N) {
   int b = 0;
@@ -646,19 +649,9 @@ int shape_bucket(int N) {
   return b;
 }
 
-int choose_shape(int R, int N, int precision) {
-  (void)R;
-  if (g_forced_shape >= 0) return g_forced_shape;
-  return g_shape_table[precision == SVDU_PREC_SPLIT32 ? 1 : 0][shape_bucket(N)];
-}
-
-int shape_table_get(int precision, int bucket) { return g_shape_table[precision ? 1 : 0][bucket]; }
-void shape_table_set(int precision, int bucket, int shape) { g_shape_table[precision ? 1 : 0][bucket] = shape; }
-
-int set_forced_shape(int shape) {
-  const int old = g_forced_shape;
-  g_forced_shape = shape;
-  return old;
+int choose_shape(int N, int precision, const Options& o) {
+  if (o.forced_shape >= 0) return o.forced_shape;
+  return o.shape_table[precision == SVDU_PREC_SPLIT32 ? 1 : 0][shape_bucket(N)];
 }
 
 int gemm_f64_grid_cap(int shape);
@@ -668,54 +661,69 @@ int gemm_grid_cap(int shape, int precision) {
 }
 
 // ---------------------------------------------------------------------------
-// timing ring: HIP events at the boundaries of the phases of each recorded
-// call (projections | O(n^2) eigen-update work | products, first level |
-// products, second level | flags), for up to kRingCalls calls.
+// timing ring of a context
 // ---------------------------------------------------------------------------
-namespace {
-struct TimingRing {
-  bool on = false;
-  int count = 0;
-  bool made[kRingCalls] = {};
-  hipEvent_t ev[kRingCalls][kRingEvents];
-};
-TimingRing g_ring;
-}  // namespace
+TimingRing::~TimingRing() {
+  for (int c = 0; c < kRingCalls; ++c)
+    if (made[c])
+      for (int k = 0; k < kRingEvents; ++k) (void)hipEventDestroy(ev[c][k]);
+}
 
-int ring_begin() {
-  if (!g_ring.on || g_ring.count >= kRingCalls) return -1;
-  const int c = g_ring.count;
-  if (!g_ring.made[c]) {
+int TimingRing::begin() {
+  if (!on || count >= kRingCalls) return -1;
+  const int c = count;
+  if (!made[c]) {
     for (int k = 0; k < kRingEvents; ++k)
-      if (hipEventCreate(&g_ring.ev[c][k]) != hipSuccess) return -1;
-    g_ring.made[c] = true;
+      if (hipEventCreate(&ev[c][k]) != hipSuccess) {
+        for (int j = 0; j < k; ++j) (void)hipEventDestroy(ev[c][j]);
+        return -1;
+      }
+    made[c] = true;
   }
-  ++g_ring.count;
+  ++count;
   return c;
 }
 
-void ring_mark(int call, int k, hipStream_t st) {
-  if (call >= 0) (void)hipEventRecord(g_ring.ev[call][k], st);
+void TimingRing::mark(int call, int k, hipStream_t st) {
+  if (call >= 0) (void)hipEventRecord(ev[call][k], st);
 }
 
-int ring_set(bool on) {
-  const int old = g_ring.on ? 1 : 0;
-  g_ring.on = on;
-  g_ring.count = 0;
+int TimingRing::set(bool v) {
+  const int old = on ? 1 : 0;
+  on = v;
+  count = 0;
   return old;
 }
 
-int ring_read(double* ms, int max_calls) {
-  const int n = std::min(g_ring.count, max_calls);
+int TimingRing::read(double* ms, int max_calls) {
+  const int n = std::min(count, max_calls);
   for (int c = 0; c < n; ++c) {
-    if (hipEventSynchronize(g_ring.ev[c][kRingEvents - 1]) != hipSuccess) return SVDU_EHIP;
+    if (hipEventSynchronize(ev[c][kRingEvents - 1]) != hipSuccess) return SVDU_EHIP;
     for (int k = 0; k + 1 < kRingEvents; ++k) {
       float t = 0.f;
-      if (hipEventElapsedTime(&t, g_ring.ev[c][k], g_ring.ev[c][k + 1]) != hipSuccess) return SVDU_EHIP;
+      if (hipEventElapsedTime(&t, ev[c][k], ev[c][k + 1]) != hipSuccess) return SVDU_EHIP;
       ms[c * (kRingEvents - 1) + k] = t;
     }
   }
   return n;
+}
+
+Sched sched_of(svdu_ctx* ctx, const Options& o, bool persistent, bool timed) {
+  Sched S;
+  S.maxit = o.maxit;
+  S.refine = o.refine;
+  S.persistent = persistent;
+  if (ctx && persistent && !ctx->have_caps) {
+    for (int p = 0; p < kNumPrec; ++p)
+      for (int s = 0; s < kNumShapes; ++s) ctx->grid_cap[p][s] = gemm_grid_cap(s, p);
+    ctx->have_caps = true;
+  }
+  if (ctx && ctx->have_caps) memcpy(S.grid_cap, ctx->grid_cap, sizeof(S.grid_cap));
+  if (ctx && timed) {
+    S.tcall = ctx->ring.begin();
+    S.ring = S.tcall >= 0 ? &ctx->ring : nullptr;
+  }
+  return S;
 }
 
 int status_code(int h) {

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <new>
 #include <vector>
 
 #include "../../include/svdu.h"
@@ -19,26 +20,13 @@
 
 namespace svdu {
 
-int g_maxit = 200;
-bool g_persistent = false;
-bool g_refine = true;
-
-// Schedule of a launch sequence: iteration cap, GEMM schedule, and the
-// device's capacity for persistent blocks (queried once per process).
-Sched current_sched(bool persistent) {
-  static int caps[2][kNumShapes];
-  static bool have = false;
-  Sched S;
-  S.maxit = g_maxit;
-  S.persistent = persistent;
-  S.refine = g_refine;
-  if (persistent && !have) {
-    for (int p = 0; p < 2; ++p)
-      for (int s = 0; s < kNumShapes; ++s) caps[p][s] = gemm_grid_cap(s, p);
-    have = true;
-  }
-  if (have) memcpy(S.grid_cap, caps, sizeof(caps));
-  return S;
+// A context is required by every call that enqueues work, and the call must
+// run with the context's device current (checked after the host-side argument
+// checks, right before the first HIP call).
+int ctx_device_check(const svdu_ctx* ctx) {
+  int d = -1;
+  if (hipGetDevice(&d) != hipSuccess) return SVDU_EHIP;
+  return d == ctx->device ? SVDU_OK : SVDU_EINVAL;
 }
 
 namespace {
@@ -98,7 +86,7 @@ void enqueue_root_copies(const Stage& s, HostRoots* h, hipStream_t st) {
 int fmm_products_impl(int nst, Stage* stages, const int* Rs, const double* const* Xs, const int* ldxs,
                       double* const* Xos, const int* ldos, const double* const* scales, const int* status_dev,
                       double* work, size_t work_elems, char* plan_dev, size_t plan_bytes, double eps,
-                      const int* marks, int tcall, hipStream_t st) {
+                      const int* marks, const Sched* S, hipStream_t st) {
   std::vector<HostRoots> h(nst);
   int status = 0;
   (void)hipMemcpyAsync(&status, status_dev, sizeof(int), hipMemcpyDeviceToHost, st);
@@ -129,12 +117,12 @@ int fmm_products_impl(int nst, Stage* stages, const int* Rs, const double* const
     if (fmm_launch(Rs[k], Xs[k], ldxs[k], stages[k], prep[k], plan_dev, Xos[k], ldos[k], scales[k], work,
                    work_elems, st) != 0)
       return SVDU_ENOMEM;
-    if (marks && marks[k] >= 0) ring_mark(tcall, marks[k], st);
+    if (marks && marks[k] >= 0 && S) S->mark(marks[k], st);
   }
   return SVDU_OK;
 }
 
-int fmm_products(const Update& u, const Plan& P, double eps, int tcall, hipStream_t st) {
+int fmm_products(const Update& u, const Plan& P, double eps, const Sched& S, hipStream_t st) {
   const Layout& L = u.L;
   // all four products in one host round trip; the two sides use TR in turn,
   // which stream order makes safe
@@ -147,7 +135,7 @@ int fmm_products(const Update& u, const Plan& P, double eps, int tcall, hipStrea
   const double* sc[4] = {nullptr, nullptr, nullptr, L.signs};
   const int marks[4] = {-1, 3, -1, 4};
   return fmm_products_impl(4, st4, Rs, Xs, ldx, Xo, ldo, sc, L.status, L.fmm_work, L.fmm_elems, L.fmm_plan,
-                           L.fmm_plan_bytes, eps, marks, tcall, st);
+                           L.fmm_plan_bytes, eps, marks, &S, st);
 }
 
 // Single-update workspace: the update's layout, then 2 kNumShapes tile
@@ -184,10 +172,24 @@ size_t svdu_workspace_bytes(int m, int n, int path, int precision) {
   return carve_single(nullptr, m, n, path, precision).bytes;
 }
 
-int svdu_rank1_update(int m, int n, const double* U, int ldu, const double* sigma, const double* V, int ldv,
-                      const double* a, const double* b, double eps, int path, int precision, double* U_out,
+int svdu_create(svdu_ctx** ctx, int device) {
+  if (!ctx) return SVDU_EINVAL;
+  *ctx = nullptr;
+  if (device < 0) return SVDU_EINVAL;
+  svdu_ctx* c = new (std::nothrow) svdu_ctx;
+  if (!c) return SVDU_ENOMEM;
+  c->device = device;
+  *ctx = c;
+  return SVDU_OK;
+}
+
+void svdu_destroy(svdu_ctx* ctx) { delete ctx; }
+
+int svdu_rank1_update(svdu_ctx* ctx, int m, int n, const double* U, int ldu, const double* sigma, const double* V,
+                      int ldv, const double* a, const double* b, double eps, int path, int precision, double* U_out,
                       int ldu_out, double* sigma_out, double* V_out, int ldv_out, int8_t* defl,
                       void* workspace, size_t workspace_bytes, void* stream) {
+  if (!ctx) return SVDU_EINVAL;
   if (m < 1 || n < m) return SVDU_EINVAL;
   if (!U || !sigma || !V || !a || !b || !U_out || !sigma_out || !V_out || !workspace) return SVDU_EINVAL;
   if (ldu < m || ldv < n || ldu_out < m || ldv_out < n) return SVDU_EINVAL;
@@ -204,6 +206,7 @@ int svdu_rank1_update(int m, int n, const double* U, int ldu, const double* sigm
   const SingleWs W = carve_single(workspace, m, n, path, precision);
   if (workspace_bytes < W.bytes) return SVDU_ENOMEM;
   if (overlaps(workspace, W.bytes, U_out, uob) || overlaps(workspace, W.bytes, V_out, vob)) return SVDU_EINVAL;
+  if (const int rc = ctx_device_check(ctx)) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
 
   Update u;
@@ -225,25 +228,24 @@ int svdu_rank1_update(int m, int n, const double* U, int ldu, const double* sigm
   u.L = W.L;
   std::vector<char> blob;
   Plan P;
-  build_plan({u}, precision, W.tables, W.counters, &blob, &P);
+  build_plan({u}, precision, ctx->opt, W.tables, W.counters, &blob, &P);
   if (blob.size() > kSingleTableBytes) return SVDU_ENOMEM;
   write_blob(blob, W.tables, st);
-  const Sched S = current_sched(g_persistent);
-  const int tcall = ring_begin();
+  const Sched S = sched_of(ctx, ctx->opt, ctx->opt.persistent, true);
   if (path == SVDU_PATH_FMM) {
-    enqueue_plan(P, S, tcall, kStepUpToRoots, st);
-    const int rc = fmm_products(u, P, eps, tcall, st);
+    enqueue_plan(P, S, kStepUpToRoots, st);
+    const int rc = fmm_products(u, P, eps, S, st);
     if (rc != SVDU_OK) return rc;
-    enqueue_plan(P, S, tcall, kStepProductsOnward, st);
+    enqueue_plan(P, S, kStepProductsOnward, st);
   } else {
-    enqueue_plan(P, S, tcall, kStepAll, st);
+    enqueue_plan(P, S, kStepAll, st);
   }
   return hip_ok();
 }
 
-int svdu_timing_read(double* ms, int max_calls) {
-  if (!ms || max_calls < 0) return SVDU_EINVAL;
-  return ring_read(ms, max_calls);
+int svdu_timing_read(svdu_ctx* ctx, double* ms, int max_calls) {
+  if (!ctx || !ms || max_calls < 0) return SVDU_EINVAL;
+  return ctx->ring.read(ms, max_calls);
 }
 
 int svdu_get_status(const void* workspace, void* stream) {
@@ -286,9 +288,10 @@ size_t svdu_eig_update_workspace_bytes(int R, int N, int path) {
   return carve_eig(nullptr, R, N, path).bytes;
 }
 
-int svdu_eig_update(int R, int N, const double* X, int ldx, const double* lam, const double* z, double rho, int path,
-                    double eps, double* X_out, int ldo, double* lam_out, int8_t* defl, void* workspace,
-                    size_t workspace_bytes, void* stream) {
+int svdu_eig_update(svdu_ctx* ctx, int R, int N, const double* X, int ldx, const double* lam, const double* z,
+                    double rho, int path, double eps, double* X_out, int ldo, double* lam_out, int8_t* defl,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+  if (!ctx) return SVDU_EINVAL;
   if (R < 0 || N < 1 || ldx < N || ldo < N || !lam || !z || !workspace || !lam_out) return SVDU_EINVAL;
   if (R > 0 && (!X || !X_out)) return SVDU_EINVAL;
   if (!(rho != 0.0) || !isfinite(rho)) return SVDU_EINVAL;
@@ -300,6 +303,7 @@ int svdu_eig_update(int R, int N, const double* X, int ldx, const double* lam, c
     return SVDU_EINVAL;
   EigLayout E = carve_eig(workspace, R, N, path);
   if (workspace_bytes < E.bytes) return SVDU_ENOMEM;
+  if (const int rc = ctx_device_check(ctx)) return rc;
   Stage& s = E.st;
   hipStream_t st = static_cast<hipStream_t>(stream);
   s.lam_in = lam;
@@ -312,7 +316,7 @@ int svdu_eig_update(int R, int N, const double* X, int ldx, const double* lam, c
   GemmList G;
   int shape = 0;
   if (path == SVDU_PATH_DIRECT && R > 0) {
-    const GemmJob J = make_gemm_job(R, X, ldx, with_members(desc_of(s), s), X_out, ldo, SVDU_PREC_FP64);
+    const GemmJob J = make_gemm_job(R, X, ldx, with_members(desc_of(s), s), X_out, ldo, SVDU_PREC_FP64, ctx->opt);
     shape = J.shape;
     G = build_gemm_list({J}, nullptr, B);
   }
@@ -321,7 +325,7 @@ int svdu_eig_update(int R, int N, const double* X, int ldx, const double* lam, c
   hipLaunchKernelGGL(set_scalar, dim3(1), dim3(64), 0, st, s.rho, rho, E.status);
   hipLaunchKernelGGL(identity_map, dim3((N + 255) / 256), dim3(256), 0, st, N, s.col_of);
   write_blob(blob, E.tables, st);
-  launch_stage_level(lev, g_maxit, st);
+  launch_stage_level(lev, ctx->opt.maxit, st);
   if (path == SVDU_PATH_FMM) {
     const int Rs[1] = {R};
     const double* Xs[1] = {X};
@@ -330,7 +334,7 @@ int svdu_eig_update(int R, int N, const double* X, int ldx, const double* lam, c
     const int ldos[1] = {ldo};
     const double* sc[1] = {nullptr};
     const int rc = fmm_products_impl(1, &s, Rs, Xs, ldxs, Xos, ldos, sc, E.status, E.fmm_work, E.fmm_elems,
-                                     E.fmm_plan, E.fmm_plan_bytes, eps, nullptr, -1, st);
+                                     E.fmm_plan, E.fmm_plan_bytes, eps, nullptr, nullptr, st);
     if (rc != SVDU_OK) return rc;
   } else {
     launch_gemm_f64(G, shape, false, 0, st);
@@ -352,12 +356,14 @@ size_t svdu_secular_workspace_bytes(int K) {
   return c.off + 256;
 }
 
-int svdu_secular(int K, const double* d, const double* z, double rho, int* org, double* tau, int* iters,
-                 void* workspace, size_t workspace_bytes, void* stream) {
+int svdu_secular(svdu_ctx* ctx, int K, const double* d, const double* z, double rho, int* org, double* tau,
+                 int* iters, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!ctx) return SVDU_EINVAL;
   if (K < 1 || !d || !z || !org || !tau || !workspace) return SVDU_EINVAL;
   if (!(rho != 0.0) || !isfinite(rho)) return SVDU_EINVAL;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return SVDU_EINVAL;
   if (workspace_bytes < svdu_secular_workspace_bytes(K)) return SVDU_ENOMEM;
+  if (const int rc = ctx_device_check(ctx)) return rc;
   Carver c(workspace);
   int* status = c.take<int>(16);
   int* Kdev = c.take<int>(4);
@@ -383,31 +389,35 @@ int svdu_secular(int K, const double* d, const double* z, double rho, int* org, 
   hipLaunchKernelGGL(set_scalar, dim3(1), dim3(64), 0, st, rhod, rho, status);
   hipLaunchKernelGGL(square_kernel, dim3((K + 255) / 256), dim3(256), 0, st, K, z, w2, Kdev, K);
   write_blob(blob, tables, st);
-  launch_secular_level(lev, g_maxit, st);
+  launch_secular_level(lev, ctx->opt.maxit, st);
   return hip_ok();
 }
 
-int svdu_set_option(int option, int value) {
+int svdu_set_option(svdu_ctx* ctx, int option, int value) {
+  if (!ctx) return SVDU_EINVAL;
+  Options& o = ctx->opt;
   if (option == SVDU_OPT_SECULAR_MAXIT) {
-    const int old = g_maxit;
-    g_maxit = value < 1 ? 1 : value;
+    const int old = o.maxit;
+    o.maxit = value < 1 ? 1 : value;
     return old;
   }
   if (option == SVDU_OPT_TILE_SHAPE) {
     if (value < -1 || value >= kNumShapes) return SVDU_EINVAL;
-    return set_forced_shape(value);
+    const int old = o.forced_shape;
+    o.forced_shape = value;
+    return old;
   }
   if (option == SVDU_OPT_PERSISTENT) {
-    const int old = g_persistent ? 1 : 0;
-    g_persistent = value != 0;
+    const int old = o.persistent ? 1 : 0;
+    o.persistent = value != 0;
     return old;
   }
   if (option == SVDU_OPT_REFINE) {
-    const int old = g_refine ? 1 : 0;
-    g_refine = value != 0;
+    const int old = o.refine ? 1 : 0;
+    o.refine = value != 0;
     return old;
   }
-  if (option == SVDU_OPT_TIMING) return ring_set(value != 0);
+  if (option == SVDU_OPT_TIMING) return ctx->ring.set(value != 0);
   return SVDU_EINVAL;
 }
 

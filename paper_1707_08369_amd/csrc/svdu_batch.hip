@@ -15,14 +15,11 @@
 #include "device_util.h"
 #include "engine.h"
 
-namespace svdu {
-Sched current_sched(bool persistent);
-extern bool g_persistent;
-}  // namespace svdu
-
 using namespace svdu;
 
 struct svdu_batch {
+  svdu_ctx* ctx = nullptr;       // records eager launches in its timing ring
+  Options opt;                   // the context's options when the batch was created
   int count = 0;
   int precision = 0;
   bool persistent = false;
@@ -64,7 +61,7 @@ bool problem_ok(const svdu_problem& p) {
   return true;
 }
 
-size_t table_bytes_for(int count, const svdu_problem* probs, int precision) {
+size_t table_bytes_for(int count, const svdu_problem* probs, int precision, const Options& opt) {
   std::vector<Update> ups(count);
   for (int i = 0; i < count; ++i) {
     ups[i].m = probs[i].m;
@@ -74,8 +71,10 @@ size_t table_bytes_for(int count, const svdu_problem* probs, int precision) {
   }
   std::vector<char> blob;
   Plan P;
-  build_plan(ups, precision, nullptr, nullptr, &blob, &P);
-  return blob.size();
+  build_plan(ups, precision, opt, nullptr, nullptr, &blob, &P);
+  // the lists per tile shape are padded to 16 bytes each, so the size
+  // depends a little on the shapes chosen: leave room for any choice
+  return blob.size() + 4096;
 }
 
 BatchWs carve_batch(void* ws, int count, const svdu_problem* probs, int precision, size_t table_bytes) {
@@ -166,21 +165,21 @@ size_t svdu_batch_workspace_bytes(int count, const svdu_problem* probs, int prec
   if (precision != SVDU_PREC_FP64 && precision != SVDU_PREC_SPLIT32) return 0;
   for (int i = 0; i < count; ++i)
     if (!(probs[i].m >= 1 && probs[i].n >= probs[i].m)) return 0;
-  const size_t tb = table_bytes_for(count, probs, precision);
+  const size_t tb = table_bytes_for(count, probs, precision, Options());
   return carve_batch(nullptr, count, probs, precision, tb).bytes;
 }
 
-int svdu_batch_create(svdu_batch** out, int count, const svdu_problem* probs, int precision, int flags,
+int svdu_batch_create(svdu_ctx* ctx, svdu_batch** out, int count, const svdu_problem* probs, int precision, int flags,
                       void* workspace, size_t workspace_bytes, void* stream) {
   if (!out) return SVDU_EINVAL;
   *out = nullptr;
-  if (count < 1 || !probs || !workspace) return SVDU_EINVAL;
+  if (!ctx || count < 1 || !probs || !workspace) return SVDU_EINVAL;
   if (precision != SVDU_PREC_FP64 && precision != SVDU_PREC_SPLIT32) return SVDU_EINVAL;
   if (flags & ~SVDU_BATCH_PERSISTENT) return SVDU_EINVAL;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return SVDU_EINVAL;
   for (int i = 0; i < count; ++i)
     if (!problem_ok(probs[i])) return SVDU_EINVAL;
-  const size_t tb = table_bytes_for(count, probs, precision);
+  const size_t tb = table_bytes_for(count, probs, precision, Options());
   BatchWs W = carve_batch(workspace, count, probs, precision, tb);
   if (workspace_bytes < W.bytes) return SVDU_ENOMEM;
   {
@@ -203,8 +202,11 @@ int svdu_batch_create(svdu_batch** out, int count, const svdu_problem* probs, in
     }
     if (!ranges_ok(r)) return SVDU_EINVAL;
   }
+  if (const int rc = ctx_device_check(ctx)) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   svdu_batch* b = new svdu_batch;
+  b->ctx = ctx;
+  b->opt = ctx->opt;
   b->count = count;
   b->precision = precision;
   b->persistent = (flags & SVDU_BATCH_PERSISTENT) != 0;
@@ -233,7 +235,7 @@ int svdu_batch_create(svdu_batch** out, int count, const svdu_problem* probs, in
     u.L = carve_update(static_cast<char*>(workspace) + W.layout_off[i], p.m, p.n, SVDU_PATH_DIRECT, precision);
   }
   std::vector<char> blob;
-  build_plan(b->ups, precision, W.tables, W.counters, &blob, &b->plan);
+  build_plan(b->ups, precision, b->opt, W.tables, W.counters, &blob, &b->plan);
   int rc = SVDU_OK;
   if (blob.size() > W.table_bytes) rc = SVDU_ENOMEM;
   if (rc == SVDU_OK && hipHostMalloc(reinterpret_cast<void**>(&b->pinned), std::max<size_t>(blob.size(), 16)) != hipSuccess)
@@ -265,10 +267,9 @@ int svdu_batch_launch(svdu_batch* b, int use_graph, void* stream) {
   if (!b) return SVDU_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (hipStreamWaitEvent(st, b->uploaded, 0) != hipSuccess) return SVDU_EHIP;
-  const Sched S = current_sched(b->persistent);
   if (!use_graph) {
-    const int tcall = ring_begin();
-    enqueue_plan(b->plan, S, tcall, kStepAll, st);
+    const Sched S = sched_of(b->ctx, b->opt, b->persistent, true);
+    enqueue_plan(b->plan, S, kStepAll, st);
     return hipGetLastError() == hipSuccess ? SVDU_OK : SVDU_EHIP;
   }
   if (!b->exec) {
@@ -276,7 +277,8 @@ int svdu_batch_launch(svdu_batch* b, int use_graph, void* stream) {
     if (!b->cap_stream && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
       return SVDU_EHIP;
     if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return SVDU_EHIP;
-    enqueue_plan(b->plan, S, -1, kStepAll, b->cap_stream);
+    const Sched S = sched_of(b->ctx, b->opt, b->persistent, false);
+    enqueue_plan(b->plan, S, kStepAll, b->cap_stream);
     const hipError_t e1 = hipGetLastError();
     const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &b->graph);
     if (e1 != hipSuccess || e2 != hipSuccess) {
@@ -321,11 +323,12 @@ void svdu_batch_destroy(svdu_batch* b) {
   delete b;
 }
 
-int svdu_rank1_update_batched(int count, const svdu_problem* probs, int precision, void* workspace,
+int svdu_rank1_update_batched(svdu_ctx* ctx, int count, const svdu_problem* probs, int precision, void* workspace,
                               size_t workspace_bytes, void* stream) {
+  if (!ctx) return SVDU_EINVAL;
   svdu_batch* b = nullptr;
-  int rc = svdu_batch_create(&b, count, probs, precision, g_persistent ? SVDU_BATCH_PERSISTENT : 0, workspace,
-                             workspace_bytes, stream);
+  int rc = svdu_batch_create(ctx, &b, count, probs, precision, ctx->opt.persistent ? SVDU_BATCH_PERSISTENT : 0,
+                             workspace, workspace_bytes, stream);
   if (rc != SVDU_OK) return rc;
   rc = svdu_batch_launch(b, 0, stream);
   if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess && rc == SVDU_OK) rc = SVDU_EHIP;
@@ -350,14 +353,17 @@ size_t svdu_autotune_workspace_bytes(int max_n) {
   return c.off + 256;
 }
 
-int svdu_autotune(int precision, int max_n, double* times_ms, int* table, void* workspace, size_t workspace_bytes,
-                  void* stream) {
+int svdu_autotune(svdu_ctx* ctx, int precision, int max_n, double* times_ms, int* table, void* workspace,
+                  size_t workspace_bytes, void* stream) {
+  if (!ctx) return SVDU_EINVAL;
   if (precision != SVDU_PREC_FP64 && precision != SVDU_PREC_SPLIT32) return SVDU_EINVAL;
   if (max_n < 16 || !workspace) return SVDU_EINVAL;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return SVDU_EINVAL;
   if (workspace_bytes < svdu_autotune_workspace_bytes(max_n)) return SVDU_ENOMEM;
+  if (const int rc = ctx_device_check(ctx)) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t n = (size_t)max_n;
+  int* tab = ctx->opt.shape_table[precision == SVDU_PREC_SPLIT32 ? 1 : 0];
   Carver c(workspace);
   int* status = c.take<int>(16);
   double* dd = c.take<double>(8 * n);
@@ -382,7 +388,7 @@ int svdu_autotune(int precision, int max_n, double* times_ms, int* table, void* 
     if (bk > 0 && (64 << (bk - 1)) >= max_n) {   // bucket beyond max_n: keep the table entry
       if (times_ms)
         for (int s = 0; s < kNumShapes; ++s) times_ms[bk * kNumShapes + s] = -1.0;
-      if (table) table[bk] = shape_table_get(precision, bk);
+      if (table) table[bk] = tab[bk];
       continue;
     }
     // the same set of products for every shape: 4096 tiles of 128 x 128 (16 per
@@ -392,7 +398,7 @@ int svdu_autotune(int precision, int max_n, double* times_ms, int* table, void* 
     count = (int)std::min<size_t>((size_t)count, out_elems / ((size_t)N * N));
     d = CauchyDesc{N, rg, rzeta, rh, rcl, ctype, co, ctau, ccs, ccl, cmem, ch, nullptr, status};
     double best = 1e30;
-    int best_s = shape_table_get(precision, bk);
+    int best_s = tab[bk];
     for (int s = 0; s < kNumShapes; ++s) {
       std::vector<GemmJob> jobs;
       for (int k = 0; k < count; ++k) {
@@ -442,7 +448,7 @@ int svdu_autotune(int precision, int max_n, double* times_ms, int* table, void* 
       }
     }
     if (rc != SVDU_OK) break;
-    shape_table_set(precision, bk, best_s);
+    tab[bk] = best_s;
     if (table) table[bk] = best_s;
   }
   (void)hipEventDestroy(e0);
@@ -451,9 +457,10 @@ int svdu_autotune(int precision, int max_n, double* times_ms, int* table, void* 
   return rc;
 }
 
-int svdu_tile_table(int precision, int* table, int set) {
+int svdu_tile_table(svdu_ctx* ctx, int precision, int* table, int set) {
   if (precision != SVDU_PREC_FP64 && precision != SVDU_PREC_SPLIT32) return SVDU_EINVAL;
-  if (!table) return SVDU_EINVAL;
+  if (!ctx || !table) return SVDU_EINVAL;
+  int* tab = ctx->opt.shape_table[precision == SVDU_PREC_SPLIT32 ? 1 : 0];
   for (int b = 0; b < kShapeBuckets; ++b) {
     if (set) {
       if (table[b] < 0 || table[b] >= kNumShapes) return SVDU_EINVAL;
@@ -461,9 +468,9 @@ int svdu_tile_table(int precision, int* table, int set) {
   }
   for (int b = 0; b < kShapeBuckets; ++b) {
     if (set)
-      shape_table_set(precision, b, table[b]);
+      tab[b] = table[b];
     else
-      table[b] = shape_table_get(precision, b);
+      table[b] = tab[b];
   }
   return SVDU_OK;
 }

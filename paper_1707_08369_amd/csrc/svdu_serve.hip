@@ -31,10 +31,6 @@
 #include "engine.h"
 #include "fmm_tree.h"
 
-namespace svdu {
-Sched current_sched(bool persistent);
-}  // namespace svdu
-
 using namespace svdu;
 
 namespace {
@@ -132,6 +128,7 @@ double cost_of(int m, int n) { return 4.0 * ((double)m * m * m + (double)n * n *
 
 struct svdu_server {
   svdu_server_config cfg{};
+  Options opt;                          // the context's options when the server was created
   int device = 0;
   char* arena_mem = nullptr;
   Arena arena;
@@ -240,6 +237,10 @@ bool form_batch(svdu_server* S, double now, Picked* out) {
 
 void svdu_server::worker_main(int w) {
   (void)hipSetDevice(device);
+  // a private context per worker (for the FMM requests), holding the server's options
+  svdu_ctx wctx;
+  wctx.device = device;
+  wctx.opt = opt;
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
     std::lock_guard<std::mutex> lk(mu);
@@ -282,7 +283,8 @@ void svdu_server::worker_main(int w) {
       const Request& r = P.reqs[0];
       Matrix& M = mats[r.matrix];
       const int c0 = M.cur, c1 = 1 - M.cur;
-      rc = svdu_rank1_update(M.m, M.n, M.U[c0], M.m, M.s[c0], M.V[c0], M.n, r.a, r.b, cfg.fmm_eps, SVDU_PATH_FMM,
+      rc = svdu_rank1_update(&wctx, M.m, M.n, M.U[c0], M.m, M.s[c0], M.V[c0], M.n, r.a, r.b, cfg.fmm_eps,
+                             SVDU_PATH_FMM,
                              SVDU_PREC_FP64, M.U[c1], M.m, M.s[c1], M.V[c1], M.n, nullptr, ws, P.ws_bytes, st);
       if (rc == SVDU_OK) rc = svdu_get_status(ws, st);
       st_codes[0] = rc;
@@ -322,7 +324,7 @@ void svdu_server::worker_main(int w) {
       blob.clear();
       Plan plan;
       if (rc == SVDU_OK) {
-        build_plan(ups, cfg.precision, tables, counters, &blob, &plan);
+        build_plan(ups, cfg.precision, opt, tables, counters, &blob, &plan);
         if (blob.size() > table_bytes) rc = SVDU_ENOMEM;
       }
       if (rc == SVDU_OK && blob.size() > pinned_bytes) {
@@ -348,7 +350,7 @@ void svdu_server::worker_main(int w) {
         if (hipMemcpyAsync(tables, pinned, blob.size(), hipMemcpyHostToDevice, st) != hipSuccess) rc = SVDU_EHIP;
       }
       if (rc == SVDU_OK) {
-        enqueue_plan(plan, current_sched(false), -1, kStepAll, st);
+        enqueue_plan(plan, sched_of(nullptr, opt, false, false), kStepAll, st);
         enqueue_status_gather(plan, status_dev, st);
         if (hipMemcpyAsync(status_host, status_dev, sizeof(int) * cnt, hipMemcpyDeviceToHost, st) != hipSuccess)
           rc = SVDU_EHIP;
@@ -387,8 +389,9 @@ out:
 
 extern "C" {
 
-int svdu_server_create(svdu_server** out, const svdu_server_config* cfg, void* arena, size_t arena_bytes) {
-  if (!out || !cfg || !arena) return SVDU_EINVAL;
+int svdu_server_create(svdu_ctx* ctx, svdu_server** out, const svdu_server_config* cfg, void* arena,
+                       size_t arena_bytes) {
+  if (!out || !ctx || !cfg || !arena) return SVDU_EINVAL;
   *out = nullptr;
   if (cfg->workers < 1 || cfg->workers > 8 || cfg->max_batch < 1) return SVDU_EINVAL;
   if (cfg->precision != SVDU_PREC_FP64 && cfg->precision != SVDU_PREC_SPLIT32) return SVDU_EINVAL;
@@ -397,12 +400,11 @@ int svdu_server_create(svdu_server** out, const svdu_server_config* cfg, void* a
   if (!(cfg->batch_cost_factor >= 1.0) || cfg->min_batch_cost < 0.0) return SVDU_EINVAL;
   if (!(cfg->min_cost_ratio >= 0.0 && cfg->min_cost_ratio <= 1.0)) return SVDU_EINVAL;
   if ((reinterpret_cast<uintptr_t>(arena) & 255) != 0 || arena_bytes < (1u << 20)) return SVDU_EINVAL;
+  if (const int rc = ctx_device_check(ctx)) return rc;
   svdu_server* S = new svdu_server;
   S->cfg = *cfg;
-  if (hipGetDevice(&S->device) != hipSuccess) {
-    delete S;
-    return SVDU_EHIP;
-  }
+  S->opt = ctx->opt;
+  S->device = ctx->device;
   S->arena_mem = static_cast<char*>(arena);
   S->arena.init(S->arena_mem, arena_bytes);
   S->t0 = std::chrono::steady_clock::now();

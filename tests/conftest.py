@@ -37,6 +37,6 @@ def _tile_shape_from_env(request):
         yield
         return
     import paper_1707_08369_amd as svdu
-    old = svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, int(v))
+    old = svdu.set_option(svdu.SVDU_OPT_TILE_SHAPE, int(v))
     yield
-    svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, old)
+    svdu.set_option(svdu.SVDU_OPT_TILE_SHAPE, old)

@@ -26,6 +26,34 @@ def lib():
     return svdu.load()
 
 
+@pytest.fixture()
+def ctx(lib):
+    """A raw context handle (svdu_create makes no HIP call)."""
+    h = ctypes.c_void_p()
+    assert svdu.svdu_create(ctypes.byref(h), 0) == svdu.SVDU_OK and h.value
+    yield h
+    svdu.svdu_destroy(h)
+
+
+def test_context_create_destroy(lib):
+    h = ctypes.c_void_p(1234)
+    assert svdu.svdu_create(ctypes.byref(h), -1) == svdu.SVDU_EINVAL
+    assert h.value is None
+    assert svdu.svdu_create(None, 0) == svdu.SVDU_EINVAL
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    assert svdu.svdu_create(ctypes.byref(a), 0) == svdu.SVDU_OK
+    assert svdu.svdu_create(ctypes.byref(b), 0) == svdu.SVDU_OK
+    assert a.value != b.value
+    # options live in the context: b does not see a's change
+    assert svdu.svdu_set_option(a, svdu.SVDU_OPT_SECULAR_MAXIT, 33) == 200
+    assert svdu.svdu_set_option(b, svdu.SVDU_OPT_SECULAR_MAXIT, 200) == 200
+    assert svdu.svdu_set_option(a, svdu.SVDU_OPT_SECULAR_MAXIT, 200) == 33
+    assert svdu.svdu_set_option(None, svdu.SVDU_OPT_SECULAR_MAXIT, 5) == svdu.SVDU_EINVAL
+    svdu.svdu_destroy(a)
+    svdu.svdu_destroy(b)
+    svdu.svdu_destroy(None)
+
+
 def test_library_exports_every_declared_symbol(lib):
     syms = declared_symbols()
     assert len(syms) >= 9
@@ -61,10 +89,10 @@ def _p(v):
     return ctypes.c_void_p(v)
 
 
-def test_host_argument_errors_return_before_enqueue(lib):
+def test_host_argument_errors_return_before_enqueue(lib, ctx):
     fake = _p(0x10000)       # never dereferenced: every call below fails its host checks
     ws = _p(0x100000)
-    args = dict(m=4, n=6, U=fake, ldu=4, sigma=fake, V=_p(0x20000), ldv=6, a=fake, b=fake, eps=1e-10, path=0,
+    args = dict(ctx=ctx, m=4, n=6, U=fake, ldu=4, sigma=fake, V=_p(0x20000), ldv=6, a=fake, b=fake, eps=1e-10, path=0,
                 precision=0, U_out=_p(0x30000), ldu_out=4, sigma_out=fake, V_out=_p(0x40000), ldv_out=6, defl=None,
                 workspace=ws, workspace_bytes=1 << 30, stream=None)
 
@@ -86,40 +114,55 @@ def test_host_argument_errors_return_before_enqueue(lib):
     assert call(path=1, eps=1e-13) == svdu.SVDU_ENOTSUP
     assert call(path=1, eps=5.0 ** -16 * 0.99) == svdu.SVDU_ENOTSUP
     assert call(path=1, eps=1e-13, workspace_bytes=16) == svdu.SVDU_ENOTSUP   # refused before sizing
-    assert svdu.svdu_eig_update(3, 0, fake, 1, fake, fake, 1.0, 0, 0.0, _p(0x50000), 1, fake, None, ws, 1 << 20,
+    assert call(ctx=None) == svdu.SVDU_EINVAL
+    assert svdu.svdu_eig_update(ctx, 3, 0, fake, 1, fake, fake, 1.0, 0, 0.0, _p(0x50000), 1, fake, None, ws, 1 << 20,
                                 None) == svdu.SVDU_EINVAL
-    assert svdu.svdu_eig_update(3, 4, fake, 4, fake, fake, 0.0, 0, 0.0, _p(0x50000), 4, fake, None, ws, 1 << 20,
+    assert svdu.svdu_eig_update(ctx, 3, 4, fake, 4, fake, fake, 0.0, 0, 0.0, _p(0x50000), 4, fake, None, ws, 1 << 20,
                                 None) == svdu.SVDU_EINVAL
-    assert svdu.svdu_eig_update(3, 4, fake, 4, fake, fake, 1.0, 1, 0.0, _p(0x50000), 4, fake, None, ws, 1 << 20,
+    assert svdu.svdu_eig_update(ctx, 3, 4, fake, 4, fake, fake, 1.0, 1, 0.0, _p(0x50000), 4, fake, None, ws, 1 << 20,
                                 None) == svdu.SVDU_EINVAL   # FMM needs 0 < eps < 1
-    assert svdu.svdu_eig_update(3, 4, fake, 4, fake, fake, 1.0, 1, 1e-13, _p(0x50000), 4, fake, None, ws, 1 << 20,
+    assert svdu.svdu_eig_update(ctx, 3, 4, fake, 4, fake, fake, 1.0, 1, 1e-13, _p(0x50000), 4, fake, None, ws, 1 << 20,
                                 None) == svdu.SVDU_ENOTSUP  # order above 16
-    assert svdu.svdu_secular(0, fake, fake, 1.0, fake, fake, None, ws, 1 << 20, None) == svdu.SVDU_EINVAL
-    assert svdu.svdu_secular(4, fake, fake, 1.0, fake, fake, None, ws, 8, None) == svdu.SVDU_ENOMEM
+    assert svdu.svdu_secular(ctx, 0, fake, fake, 1.0, fake, fake, None, ws, 1 << 20, None) == svdu.SVDU_EINVAL
+    assert svdu.svdu_secular(ctx, 4, fake, fake, 1.0, fake, fake, None, ws, 8, None) == svdu.SVDU_ENOMEM
+    assert svdu.svdu_secular(None, 4, fake, fake, 1.0, fake, fake, None, ws, 1 << 20, None) == svdu.SVDU_EINVAL
 
 
-def test_options(lib):
-    old = svdu.svdu_set_option(svdu.SVDU_OPT_SECULAR_MAXIT, 17)
-    assert svdu.svdu_set_option(svdu.SVDU_OPT_SECULAR_MAXIT, old) == 17
-    assert svdu.svdu_set_option(999, 1) == svdu.SVDU_EINVAL
-    old = svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, svdu.SVDU_TILE_64x64)
+def test_options(lib, ctx):
+    old = svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SECULAR_MAXIT, 17)
+    assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SECULAR_MAXIT, old) == 17
+    assert svdu.svdu_set_option(ctx, 999, 1) == svdu.SVDU_EINVAL
+    old = svdu.svdu_set_option(ctx, svdu.SVDU_OPT_TILE_SHAPE, svdu.SVDU_TILE_64x64)
     assert old == -1
-    assert svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, -1) == svdu.SVDU_TILE_64x64
-    assert svdu.svdu_set_option(svdu.SVDU_OPT_TILE_SHAPE, svdu.SVDU_TILE_SHAPES) == svdu.SVDU_EINVAL
-    assert svdu.svdu_set_option(svdu.SVDU_OPT_PERSISTENT, 1) == 0
-    assert svdu.svdu_set_option(svdu.SVDU_OPT_PERSISTENT, 0) == 1
+    assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_TILE_SHAPE, -1) == svdu.SVDU_TILE_64x64
+    assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_TILE_SHAPE, svdu.SVDU_TILE_SHAPES) == svdu.SVDU_EINVAL
+    assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_PERSISTENT, 1) == 0
+    assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_PERSISTENT, 0) == 1
 
 
-def test_tile_table_roundtrip(lib):
-    t = svdu.tile_table(svdu.SVDU_PREC_FP64)
+def _table(ctx, prec, new=None):
+    buf = (ctypes.c_int * svdu.SVDU_TILE_BUCKETS)(*(new or [0] * svdu.SVDU_TILE_BUCKETS))
+    rc = svdu.svdu_tile_table(ctx, prec, ctypes.cast(buf, ctypes.c_void_p), 1 if new is not None else 0)
+    return rc, list(buf)
+
+
+def test_tile_table_roundtrip(lib, ctx):
+    rc, t = _table(ctx, svdu.SVDU_PREC_FP64)
+    assert rc == svdu.SVDU_OK
     assert len(t) == svdu.SVDU_TILE_BUCKETS and all(0 <= x < svdu.SVDU_TILE_SHAPES for x in t)
     new = [(x + 1) % svdu.SVDU_TILE_SHAPES for x in t]
-    assert svdu.tile_table(svdu.SVDU_PREC_FP64, new) == new
-    assert svdu.tile_table(svdu.SVDU_PREC_FP64) == new
-    svdu.tile_table(svdu.SVDU_PREC_FP64, t)
+    assert _table(ctx, svdu.SVDU_PREC_FP64, new) == (svdu.SVDU_OK, new)
+    assert _table(ctx, svdu.SVDU_PREC_FP64)[1] == new
+    # another context keeps the built-in table
+    other = ctypes.c_void_p()
+    assert svdu.svdu_create(ctypes.byref(other), 0) == svdu.SVDU_OK
+    assert _table(other, svdu.SVDU_PREC_FP64)[1] == t
+    svdu.svdu_destroy(other)
+    _table(ctx, svdu.SVDU_PREC_FP64, t)
     bad = (ctypes.c_int * svdu.SVDU_TILE_BUCKETS)(*([0] * 7 + [9]))
-    assert svdu.svdu_tile_table(svdu.SVDU_PREC_FP64, ctypes.cast(bad, ctypes.c_void_p), 1) == svdu.SVDU_EINVAL
-    assert svdu.tile_table(svdu.SVDU_PREC_FP64) == t
+    assert svdu.svdu_tile_table(ctx, svdu.SVDU_PREC_FP64, ctypes.cast(bad, ctypes.c_void_p), 1) == svdu.SVDU_EINVAL
+    assert svdu.svdu_tile_table(None, svdu.SVDU_PREC_FP64, ctypes.cast(bad, ctypes.c_void_p), 0) == svdu.SVDU_EINVAL
+    assert _table(ctx, svdu.SVDU_PREC_FP64)[1] == t
 
 
 def _prob(m, n, base, ld_extra=0, defl=False):
@@ -146,7 +189,7 @@ def _prob(m, n, base, ld_extra=0, defl=False):
     return P, off[0]
 
 
-def test_batch_workspace_and_argument_errors(lib):
+def test_batch_workspace_and_argument_errors(lib, ctx):
     """Host-side checks of the batched entry points (nothing reaches the device)."""
     arr = (svdu.svdu_problem * 3)()
     base = 0x10000000
@@ -161,7 +204,7 @@ def test_batch_workspace_and_argument_errors(lib):
     h = ctypes.c_void_p()
 
     def create(a, count=3, prec=svdu.SVDU_PREC_FP64, flags=0, w=ws, wb=None):
-        return svdu.svdu_batch_create(ctypes.byref(h), count, a, prec, flags, _p(w), wsb if wb is None else wb,
+        return svdu.svdu_batch_create(ctx, ctypes.byref(h), count, a, prec, flags, _p(w), wsb if wb is None else wb,
                                       None)
 
     assert create(arr, wb=wsb - 1) == svdu.SVDU_ENOMEM
@@ -194,11 +237,13 @@ def test_batch_workspace_and_argument_errors(lib):
     svdu.svdu_batch_destroy(None)
     assert svdu.svdu_autotune_workspace_bytes(0) == 0
     assert svdu.svdu_autotune_workspace_bytes(256) > 8 * 256 * 256
-    assert svdu.svdu_autotune(5, 256, None, None, _p(ws), 1 << 30, None) == svdu.SVDU_EINVAL
-    assert svdu.svdu_autotune(0, 256, None, None, _p(ws), 16, None) == svdu.SVDU_ENOMEM
+    assert svdu.svdu_autotune(ctx, 5, 256, None, None, _p(ws), 1 << 30, None) == svdu.SVDU_EINVAL
+    assert svdu.svdu_autotune(ctx, 0, 256, None, None, _p(ws), 16, None) == svdu.SVDU_ENOMEM
+    assert svdu.svdu_autotune(None, 0, 256, None, None, _p(ws), 1 << 30, None) == svdu.SVDU_EINVAL
+    assert svdu.svdu_batch_create(None, ctypes.byref(h), 3, arr, 0, 0, _p(ws), wsb, None) == svdu.SVDU_EINVAL
 
 
-def test_server_argument_errors(lib):
+def test_server_argument_errors(lib, ctx):
     """Server configuration checks happen on the host before any device call."""
     h = ctypes.c_void_p()
     arena = _p(0x7000000000)
@@ -209,7 +254,7 @@ def test_server_argument_errors(lib):
         c.update(kw)
         cfg = svdu.svdu_server_config(c["workers"], c["max_batch"], c["precision"], c["fmm_min_n"], c["fmm_eps"],
                                       c["batch_cost_factor"], c["min_batch_cost"], c["min_cost_ratio"])
-        return svdu.svdu_server_create(ctypes.byref(h), ctypes.byref(cfg), kw.get("arena", arena),
+        return svdu.svdu_server_create(kw.get("ctx", ctx), ctypes.byref(h), ctypes.byref(cfg), kw.get("arena", arena),
                                        kw.get("bytes", 1 << 30))
 
     assert create(workers=0) == svdu.SVDU_EINVAL
@@ -222,7 +267,8 @@ def test_server_argument_errors(lib):
     assert create(min_cost_ratio=1.5) == svdu.SVDU_EINVAL
     assert create(arena=_p(0x7000000008)) == svdu.SVDU_EINVAL
     assert create(bytes=1000) == svdu.SVDU_EINVAL
-    assert svdu.svdu_server_create(ctypes.byref(h), None, arena, 1 << 30) == svdu.SVDU_EINVAL
+    assert svdu.svdu_server_create(ctx, ctypes.byref(h), None, arena, 1 << 30) == svdu.SVDU_EINVAL
+    assert create(ctx=None) == svdu.SVDU_EINVAL
     assert h.value is None
     assert svdu.svdu_server_start(None) == svdu.SVDU_EINVAL
     assert svdu.svdu_server_submit(None, 0, _p(8), _p(8), 0.0, None) == svdu.SVDU_EINVAL

@@ -155,18 +155,18 @@ def test_batched_per_problem_status(lib):
 def test_tile_shapes_give_identical_results(lib, shape):
     P = S.make_problem(300, 457, "uniform", seed=7)
     args = (dev(P.U), dev(P.sigma), dev(P.V), dev(P.a), dev(P.b))
-    old = lib.svdu_set_option(lib.SVDU_OPT_TILE_SHAPE, 0)
+    old = lib.set_option(lib.SVDU_OPT_TILE_SHAPE, 0)
     try:
         ref = lib.rank1_update(*args)
-        lib.svdu_set_option(lib.SVDU_OPT_TILE_SHAPE, shape)
+        lib.set_option(lib.SVDU_OPT_TILE_SHAPE, shape)
         got = lib.rank1_update(*args)
         ref32 = None
-        lib.svdu_set_option(lib.SVDU_OPT_TILE_SHAPE, 0)
+        lib.set_option(lib.SVDU_OPT_TILE_SHAPE, 0)
         ref32 = lib.rank1_update(*args, precision=lib.SVDU_PREC_SPLIT32)
-        lib.svdu_set_option(lib.SVDU_OPT_TILE_SHAPE, shape)
+        lib.set_option(lib.SVDU_OPT_TILE_SHAPE, shape)
         got32 = lib.rank1_update(*args, precision=lib.SVDU_PREC_SPLIT32)
     finally:
-        lib.svdu_set_option(lib.SVDU_OPT_TILE_SHAPE, old)
+        lib.set_option(lib.SVDU_OPT_TILE_SHAPE, old)
     for x, y in zip(ref, got):
         assert torch.equal(x, y)
     for x, y in zip(ref32, got32):
@@ -180,13 +180,13 @@ def test_persistent_single_update(lib, shape):
     P = S.make_problem(513, 700, "uniform", seed=8)
     args = (dev(P.U), dev(P.sigma), dev(P.V), dev(P.a), dev(P.b))
     ref = lib.rank1_update(*args)
-    old_s = lib.svdu_set_option(lib.SVDU_OPT_TILE_SHAPE, shape)
-    old = lib.svdu_set_option(lib.SVDU_OPT_PERSISTENT, 1)
+    old_s = lib.set_option(lib.SVDU_OPT_TILE_SHAPE, shape)
+    old = lib.set_option(lib.SVDU_OPT_PERSISTENT, 1)
     try:
         got = lib.rank1_update(*args)
     finally:
-        lib.svdu_set_option(lib.SVDU_OPT_PERSISTENT, old)
-        lib.svdu_set_option(lib.SVDU_OPT_TILE_SHAPE, old_s)
+        lib.set_option(lib.SVDU_OPT_PERSISTENT, old)
+        lib.set_option(lib.SVDU_OPT_TILE_SHAPE, old_s)
     for x, y in zip(ref, got):
         assert torch.equal(x, y)
 
@@ -299,11 +299,11 @@ def test_refinement_of_close_clusters(lib, m, n, npairs):
     U, s, V, a, b, Ah = _planted_close_output(m, n, seed=m + n, gaps=gaps)
     args = (dev(U), dev(s), dev(V), dev(a), dev(b))
     on = [host(t) for t in lib.rank1_update(*args)[:3]]
-    old = lib.svdu_set_option(lib.SVDU_OPT_REFINE, 0)
+    old = lib.set_option(lib.SVDU_OPT_REFINE, 0)
     try:
         off = [host(t) for t in lib.rank1_update(*args)[:3]]
     finally:
-        lib.svdu_set_option(lib.SVDU_OPT_REFINE, old)
+        lib.set_option(lib.SVDU_OPT_REFINE, old)
     r_on, r_off = _recon_np(Ah, *on), _recon_np(Ah, *off)
     # rounding of the refined products grows with the order: 8 u sqrt(m n), well
     # inside the 1e-12 the update is held to (1.8e-13 at 200, 4e-13 at 450)

@@ -1,0 +1,125 @@
+"""GPU tests of contexts (svdu_create / svdu_destroy): each context holds its
+own options, and two contexts used at the same time from two host threads
+give, bitwise, the results each gives alone. A server keeps the options its
+context had when it was created."""
+import threading
+
+import numpy as np
+import pytest
+import torch
+
+import synth_inputs as S
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64).cuda()
+
+
+def _problem(seed, m=300, n=333):
+    """Inputs whose updated matrix has planted close singular values (pairs at
+    relative gaps 1e-9 and 1e-11), so that the refinement option changes the
+    result bits: A^ is built first, then A = A^ - a b^T is decomposed on the
+    host (LAPACK, a library routine used only to make inputs)."""
+    rng = np.random.default_rng(seed)
+    Uh, Vh = S.haar(m, rng), S.haar(n, rng)
+    sh = np.sort(rng.uniform(0.5, 10.0, m))[::-1].copy()
+    for k, g in enumerate((1e-9, 1e-11, 1e-9, 1e-11)):
+        sh[8 * k + 2] = sh[8 * k + 1] * (1.0 - g)
+    sh = np.sort(sh)[::-1].copy()
+    a = rng.standard_normal(m) / np.sqrt(n)
+    b = rng.standard_normal(n) / np.sqrt(n)
+    A = (Uh * sh[None, :]) @ Vh[:, :m].T - np.outer(a, b)
+    Ua, sa, Vta = np.linalg.svd(A, full_matrices=True)
+    return [dev(Ua), dev(sa), dev(Vta.T), dev(a), dev(b)]
+
+
+def _run(lib, ctx, args, stream, reps):
+    outs = []
+    with torch.cuda.stream(stream):
+        for _ in range(reps):
+            Uo, so, Vo, _ = lib.rank1_update(*args, ctx=ctx, stream=stream, want_defl=False)
+            outs.append((Uo, so, Vo))
+    stream.synchronize()
+    return outs
+
+
+def test_two_contexts_two_threads_bitwise(lib):
+    ca, cb = lib.Context(), lib.Context()
+    try:
+        ca.set_option(lib.SVDU_OPT_REFINE, 1)
+        ca.set_option(lib.SVDU_OPT_TILE_SHAPE, lib.SVDU_TILE_128x128)
+        cb.set_option(lib.SVDU_OPT_REFINE, 0)
+        cb.set_option(lib.SVDU_OPT_TILE_SHAPE, lib.SVDU_TILE_64x64)
+        cb.set_option(lib.SVDU_OPT_PERSISTENT, 1)
+        args = _problem(11)
+        sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+        ref_a = _run(lib, ca, args, sa, 1)[0]
+        ref_b = _run(lib, cb, args, sb, 1)[0]
+        # the options differ in a way that shows in the bits (refinement on / off)
+        assert not torch.equal(ref_a[0], ref_b[0])
+        got = {}
+
+        def worker(name, ctx, stream):
+            got[name] = _run(lib, ctx, args, stream, 6)
+
+        ta = threading.Thread(target=worker, args=("a", ca, sa))
+        tb = threading.Thread(target=worker, args=("b", cb, sb))
+        ta.start()
+        tb.start()
+        ta.join()
+        tb.join()
+        for name, ref in (("a", ref_a), ("b", ref_b)):
+            assert len(got[name]) == 6
+            for o in got[name]:
+                for x, y in zip(o, ref):
+                    assert torch.equal(x, y), name
+    finally:
+        ca.close()
+        cb.close()
+
+
+def test_timing_record_is_per_context(lib):
+    ca, cb = lib.Context(), lib.Context()
+    try:
+        args = _problem(12)
+        ca.set_option(lib.SVDU_OPT_TIMING, 1)
+        lib.rank1_update(*args, ctx=ca, want_defl=False)
+        lib.rank1_update(*args, ctx=cb, want_defl=False)
+        lib.rank1_update(*args, ctx=ca, want_defl=False)
+        ta = lib.timing_read(16, ctx=ca)
+        tb = lib.timing_read(16, ctx=cb)
+        assert len(ta) == 2 and len(tb) == 0
+        assert all(t >= 0.0 for row in ta for t in row)
+    finally:
+        ca.close()
+        cb.close()
+
+
+def test_server_keeps_the_options_of_its_creation(lib):
+    ctx = lib.Context()
+    try:
+        ctx.set_option(lib.SVDU_OPT_REFINE, 0)
+        args = _problem(13)
+        U, s, V, a, b = args
+        ref = lib.rank1_update(U, s, V, a, b, ctx=ctx, want_defl=False)
+        srv = lib.Server(arena_bytes=1 << 28, workers=2, max_batch=4, ctx=ctx)
+        try:
+            ids = [srv.add_matrix(U.clone(), s.clone(), V.clone()) for _ in range(3)]
+            # changed after creation: the server must not see it
+            ctx.set_option(lib.SVDU_OPT_REFINE, 1)
+            srv.start()
+            for i in ids:
+                srv.submit(i, a, b, 0.0)
+            ctx.set_option(lib.SVDU_OPT_SECULAR_MAXIT, 1)   # would fail every update if it reached the server
+            assert srv.drain(120.0) == lib.SVDU_OK
+            done = srv.poll()
+            assert len(done) == 3 and all(c["status"] == lib.SVDU_OK for c in done)
+            for i in ids:
+                Uo, so, Vo = srv.current(i)
+                assert torch.equal(Uo, ref[0]) and torch.equal(so, ref[1]) and torch.equal(Vo, ref[2])
+        finally:
+            srv.close()
+    finally:
+        ctx.close()

@@ -227,12 +227,12 @@ def test_eig_update_wide_cluster_copy_columns(lib, shape, rho):
     lam = np.sort(np.concatenate([np.zeros(W), rng.uniform(0.5, 3.0, N - W)]))
     z = rng.standard_normal(N) / np.sqrt(N)
     X = rng.standard_normal((R, N))
-    old = lib.svdu_set_option(lib.SVDU_OPT_TILE_SHAPE, shape)
+    old = lib.set_option(lib.SVDU_OPT_TILE_SHAPE, shape)
     try:
         Xo, lo, fl = lib.eig_update(dev(X), dev(lam), dev(z), rho)
         Ci, lci, _ = lib.eig_update(dev(np.eye(N)), dev(lam), dev(z), rho)
     finally:
-        lib.svdu_set_option(lib.SVDU_OPT_TILE_SHAPE, old)
+        lib.set_option(lib.SVDU_OPT_TILE_SHAPE, old)
     Xo, lo, fl, Ci, lci = host(Xo), host(lo), host(fl), host(Ci), host(lci)
     st = O.rank_one_update_z(X, lam, z, rho)
     assert np.count_nonzero(st.flags == 2) == W - 1
@@ -356,13 +356,13 @@ def test_device_status_codes(lib):
     with pytest.raises(lib.SvduError) as e:
         lib.rank1_update(dev(P.U), dev(s), dev(P.V), dev(P.a), dev(P.b))
     assert e.value.code == lib.SVDU_EBADSIGMA
-    old = lib.svdu_set_option(lib.SVDU_OPT_SECULAR_MAXIT, 1)
+    old = lib.set_option(lib.SVDU_OPT_SECULAR_MAXIT, 1)
     try:
         with pytest.raises(lib.SvduError) as e:
             lib.rank1_update(dev(P.U), dev(P.sigma), dev(P.V), dev(P.a), dev(P.b))
         assert e.value.code == lib.SVDU_ENOCONV
     finally:
-        lib.svdu_set_option(lib.SVDU_OPT_SECULAR_MAXIT, old)
+        lib.set_option(lib.SVDU_OPT_SECULAR_MAXIT, old)
     lib.rank1_update(dev(P.U), dev(P.sigma), dev(P.V), dev(P.a), dev(P.b))   # clean again
 
 
