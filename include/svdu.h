@@ -150,6 +150,29 @@ int svdu_rank1_update(svdu_ctx* ctx, int m, int n, const double* U, int ldu, con
                       int ldu_out, double* sigma_out, double* V_out, int ldv_out, int8_t* defl,
                       void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---- the update without a caller workspace --------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The same
+ * update as svdu_rank1_update on SVDU_PATH_DIRECT (bitwise the same results),
+ * with its workspace in a device array of SVDU_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every device it runs on until the process ends; the call
+ * allocates no device memory. An update whose workspace
+ * (svdu_workspace_bytes(m, n, SVDU_PATH_DIRECT, precision)) exceeds the array
+ * is refused with SVDU_ENOMEM: the array holds one update up to m = n = 1024
+ * in either precision. All calls on one device share that device's array, so
+ * calls that overlap on a device (other streams, other threads, other
+ * contexts) race; a caller serialises them, e.g. on one stream.
+ *  status   NULL, or a device int that receives the call's device status
+ *           (SVDU_OK, SVDU_ENONFINITE, SVDU_EBADSIGMA or SVDU_ENOCONV) once
+ *           the stream has reached the end of the update.
+ * Other arguments as for svdu_rank1_update. Returns 0 or a negative SVDU_E*
+ * code found on the host (nothing is enqueued then). */
+#define SVDU_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int svdu_rank1_update_noalloc(svdu_ctx* ctx, int m, int n, const double* U, int ldu, const double* sigma,
+                              const double* V, int ldv, const double* a, const double* b, int precision,
+                              double* U_out, int ldu_out, double* sigma_out, double* V_out, int ldv_out,
+                              int8_t* defl, int* status, void* stream);
+
 /* Waits for `stream` and returns the device-side status of the last call that
  * used `workspace`: SVDU_OK, SVDU_ENONFINITE, SVDU_EBADSIGMA or SVDU_ENOCONV
  * (the first that applies, in that order), or SVDU_EHIP. */

@@ -51,7 +51,8 @@ EXPORTS = ("svdu_create", "svdu_destroy", "svdu_workspace_bytes", "svdu_rank1_up
            "svdu_autotune_workspace_bytes", "svdu_autotune", "svdu_tile_table", "svdu_server_create",
            "svdu_server_add_matrix", "svdu_server_start", "svdu_server_now", "svdu_server_submit",
            "svdu_server_poll", "svdu_server_stats", "svdu_server_drain", "svdu_server_current",
-           "svdu_server_destroy")
+           "svdu_server_destroy", "svdu_rank1_update_noalloc")
+SVDU_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class svdu_problem(ctypes.Structure):
@@ -110,6 +111,9 @@ def load():
     lib.svdu_rank1_update.argtypes = [c_vp, c_int, c_int, c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_vp, c_dbl, c_int, c_int,
                                       c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_vp, c_size, c_vp]
     lib.svdu_rank1_update.restype = c_int
+    lib.svdu_rank1_update_noalloc.argtypes = [c_vp, c_int, c_int, c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_vp, c_int,
+                                              c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_vp, c_vp]
+    lib.svdu_rank1_update_noalloc.restype = c_int
     lib.svdu_get_status.argtypes = [c_vp, c_vp]
     lib.svdu_get_status.restype = c_int
     lib.svdu_eig_update_workspace_bytes.argtypes = [c_int, c_int, c_int]
@@ -191,6 +195,12 @@ def svdu_rank1_update(ctx, m, n, U, ldu, sigma, V, ldv, a, b, eps, path, precisi
                       V_out, ldv_out, defl, workspace, workspace_bytes, stream) -> int:
     return int(load().svdu_rank1_update(ctx, m, n, U, ldu, sigma, V, ldv, a, b, eps, path, precision, U_out, ldu_out,
                                         sigma_out, V_out, ldv_out, defl, workspace, workspace_bytes, stream))
+
+
+def svdu_rank1_update_noalloc(ctx, m, n, U, ldu, sigma, V, ldv, a, b, precision, U_out, ldu_out, sigma_out,
+                              V_out, ldv_out, defl, status, stream) -> int:
+    return int(load().svdu_rank1_update_noalloc(ctx, m, n, U, ldu, sigma, V, ldv, a, b, precision, U_out, ldu_out,
+                                                sigma_out, V_out, ldv_out, defl, status, stream))
 
 
 def svdu_get_status(workspace, stream) -> int:
@@ -411,6 +421,43 @@ def rank1_update(U, sigma, V, a, b, eps=1e-10, path=SVDU_PATH_DIRECT, precision=
         rc = svdu_get_status(wp, sh)
         if rc != SVDU_OK:
             raise SvduError(rc, "svdu_rank1_update (device)")
+    return Uo, so, Vo, defl
+
+
+def rank1_update_noalloc(U, sigma, V, a, b, precision=SVDU_PREC_FP64, out=None, want_defl=True, stream=None,
+                         check=True, ctx=None):
+    """rank1_update on the direct path through svdu_rank1_update_noalloc (no
+    workspace: the library's per-device scratch array). Returns (U^, sigma^,
+    V^, defl flags or None)."""
+    torch = _torch()
+    m, n = U.shape[0], V.shape[0]
+    ldu = _check_mat(U, m, m, "U")
+    ldv = _check_mat(V, n, n, "V")
+    _check_vec(sigma, m, "sigma")
+    _check_vec(a, m, "a")
+    _check_vec(b, n, "b")
+    dev = U.device
+    if out is None:
+        Uo = torch.empty((m, m), dtype=torch.float64, device=dev)
+        so = torch.empty(m, dtype=torch.float64, device=dev)
+        Vo = torch.empty((n, n), dtype=torch.float64, device=dev)
+    else:
+        Uo, so, Vo = out
+    lduo = _check_mat(Uo, m, m, "U_out")
+    ldvo = _check_mat(Vo, n, n, "V_out")
+    _check_vec(so, m, "sigma_out")
+    defl = torch.empty((4, n), dtype=torch.int8, device=dev) if want_defl else None
+    st = torch.full((1,), -99, dtype=torch.int32, device=dev) if check else None
+    sh = _stream_handle(stream)
+    rc = svdu_rank1_update_noalloc(_ctx(ctx), m, n, _ptr(U), ldu, _ptr(sigma), _ptr(V), ldv, _ptr(a), _ptr(b),
+                                   precision, _ptr(Uo), lduo, _ptr(so), _ptr(Vo), ldvo, _ptr(defl), _ptr(st), sh)
+    if rc != SVDU_OK:
+        raise SvduError(rc, "svdu_rank1_update_noalloc")
+    if check:
+        (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+        code = int(st.item())
+        if code != SVDU_OK:
+            raise SvduError(code, "svdu_rank1_update_noalloc (device)")
     return Uo, so, Vo, defl
 
 

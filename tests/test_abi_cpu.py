@@ -128,6 +128,28 @@ def test_host_argument_errors_return_before_enqueue(lib, ctx):
     assert svdu.svdu_secular(None, 4, fake, fake, 1.0, fake, fake, None, ws, 1 << 20, None) == svdu.SVDU_EINVAL
 
 
+def test_noalloc_host_checks(lib, ctx):
+    """The update without a caller workspace refuses, on the host, sizes beyond
+    its scratch array and bad arguments (nothing reaches the device)."""
+    fake = _p(0x10000)
+    args = [4, 6, fake, 4, fake, _p(0x20000), 6, fake, fake, 0, _p(0x30000), 4, fake, _p(0x40000), 6, None, None,
+            None]
+    assert svdu.svdu_rank1_update_noalloc(None, *args) == svdu.SVDU_EINVAL
+    bad = list(args)
+    bad[0] = 7                      # m > n
+    assert svdu.svdu_rank1_update_noalloc(ctx, *bad) == svdu.SVDU_EINVAL
+    bad = list(args)
+    bad[9] = 9                      # precision
+    assert svdu.svdu_rank1_update_noalloc(ctx, *bad) == svdu.SVDU_EINVAL
+    big = 1400
+    assert svdu.svdu_workspace_bytes(big, big) > svdu.SVDU_NOALLOC_SCRATCH_BYTES
+    huge = [big, big, fake, big, fake, _p(0x20000), big, fake, fake, 0, _p(0x30000), big, fake, _p(0x40000), big,
+            None, None, None]
+    assert svdu.svdu_rank1_update_noalloc(ctx, *huge) == svdu.SVDU_ENOMEM
+    assert svdu.svdu_workspace_bytes(1024, 1024) <= svdu.SVDU_NOALLOC_SCRATCH_BYTES
+    assert svdu.svdu_workspace_bytes(1024, 1024, 0, 1) <= svdu.SVDU_NOALLOC_SCRATCH_BYTES
+
+
 def test_options(lib, ctx):
     old = svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SECULAR_MAXIT, 17)
     assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SECULAR_MAXIT, old) == 17
