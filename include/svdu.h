@@ -56,7 +56,13 @@ extern "C" {
 /* arithmetic of the product X C~ (roots, deflation and norms are always FP64) */
 #define SVDU_PREC_FP64 0
 #define SVDU_PREC_SPLIT32 1     /* split FP32 hi/lo, three FP32 MFMA passes, FP32 accumulation drained to
-                                   FP64 every 16 k; then every column of U^ and V^ rescaled to unit FP64 norm */
+                                   FP64 every 16 k; then every column of U^ and V^ rescaled to unit FP64 norm
+                                   (kept as a measured negative result: about 1e-7 error, slower than FP64) */
+#define SVDU_PREC_SLICED_INT8 2 /* exact slices on the INT8 matrix cores: every row of X and column of C~ is
+                                   scaled by a power of two and cut into S signed 7-bit slices
+                                   (SVDU_OPT_SLICES, default 7); the S (S + 1) / 2 slice products with
+                                   s + t <= S + 1 are exact in INT32 and combined in FP64. Error about
+                                   2^(1 - 7 S) relative to the largest entry (S = 7: about 1e-14) */
 
 /* options of a context (svdu_set_option) */
 #define SVDU_OPT_SECULAR_MAXIT 1 /* iteration cap of the secular solver (default 200) */
@@ -67,12 +73,13 @@ extern "C" {
                                     SVDU_TILE_256x128_K32 as 128 x 128) */
 #define SVDU_OPT_PERSISTENT 4    /* 1: products of svdu_rank1_update and svdu_rank1_update_batched use the
                                     persistent schedule (see SVDU_BATCH_PERSISTENT); default 0 */
+#define SVDU_OPT_SLICES 6        /* slices S of SVDU_PREC_SLICED_INT8: 6, 7 (default) or 8 */
 #define SVDU_OPT_REFINE 5        /* 1 (default): FP64 results get the close-cluster refinement (not in the
                                     paper): for consecutive sigma^ with relative gaps <= 1e-6, in clusters
                                     of up to 8 and up to min(m, 128) columns in all, the block
                                     U^_c^T A^ V^_c is formed from the inputs and its SVD rotates U^_c and
-                                    V^_c (sigma^ is kept). 0: off. Read when a call is enqueued (a batch
-                                    graph keeps the value it was captured with). */
+                                    V^_c (sigma^ is kept); also for SVDU_PREC_SLICED_INT8. 0: off. Read when
+                                    a call is enqueued (a batch graph keeps the value it was captured with). */
 
 /* tile shapes of the product kernels (rows x columns of one block tile) */
 #define SVDU_TILE_128x128 0
@@ -123,7 +130,10 @@ size_t svdu_workspace_bytes(int m, int n, int path, int precision);
  *              roots to the host once per call to build its trees (the call
  *              then returns after that synchronisation of `stream`); it works
  *              with SVDU_PREC_FP64 only.
- *  precision   SVDU_PREC_FP64 or SVDU_PREC_SPLIT32.
+ *  precision   SVDU_PREC_FP64, SVDU_PREC_SPLIT32 or SVDU_PREC_SLICED_INT8 (the
+ *              last two on SVDU_PATH_DIRECT only; SVDU_PREC_SLICED_INT8 for
+ *              n <= 32768, above which its INT32 sums could overflow:
+ *              SVDU_ENOTSUP).
  *  U_out       m x m, ldu_out >= m: left singular vectors of A^, columns by
  *              descending singular value. Must not overlap U.
  *  sigma_out   m singular values of A^, descending.
@@ -224,7 +234,7 @@ int svdu_timing_read(svdu_ctx* ctx, double* ms, int max_calls);
  * Every step of the update is one launch over all problems of the batch (a
  * product launch per tile shape in use); a problem's results are bitwise the
  * same as from svdu_rank1_update with the same inputs, whatever else is in
- * the batch. Direct path only (SVDU_PREC_FP64 or SVDU_PREC_SPLIT32). */
+ * the batch. Direct path only (any SVDU_PREC_*). */
 typedef struct {
   int m, n;                       /* 1 <= m <= n */
   const double* U; int ldu;       /* as for svdu_rank1_update (device pointers) */
@@ -318,7 +328,7 @@ int svdu_tile_table(svdu_ctx* ctx, int precision, int* table, int set);
 typedef struct {
   int workers;                 /* 1..8 batches in flight */
   int max_batch;               /* updates per batch at most */
-  int precision;               /* SVDU_PREC_FP64 or SVDU_PREC_SPLIT32 */
+  int precision;               /* SVDU_PREC_FP64, SVDU_PREC_SPLIT32 or SVDU_PREC_SLICED_INT8 */
   int fmm_min_n;
   double fmm_eps;
   double batch_cost_factor;    /* >= 1 */

@@ -28,11 +28,13 @@ SVDU_PATH_DIRECT = 0
 SVDU_PATH_FMM = 1
 SVDU_PREC_FP64 = 0
 SVDU_PREC_SPLIT32 = 1
+SVDU_PREC_SLICED_INT8 = 2
 SVDU_OPT_SECULAR_MAXIT = 1
 SVDU_OPT_TIMING = 2
 SVDU_OPT_TILE_SHAPE = 3
 SVDU_OPT_PERSISTENT = 4
 SVDU_OPT_REFINE = 5
+SVDU_OPT_SLICES = 6
 SVDU_TILE_128x128 = 0
 SVDU_TILE_64x128 = 1
 SVDU_TILE_128x64 = 2

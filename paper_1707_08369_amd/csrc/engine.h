@@ -11,14 +11,20 @@
 
 #include <vector>
 
+#include "../../include/svdu.h"
 #include "cauchy_tile.h"
 #include "jobs.h"
 
 namespace svdu {
 
+inline bool precision_ok(int p) {
+  return p == SVDU_PREC_FP64 || p == SVDU_PREC_SPLIT32 || p == SVDU_PREC_SLICED_INT8;
+}
+
 // ---- options of a context (svdu_ctx) -----------------------------------------------
 constexpr int kShapeBuckets = 8;   // N in (0,64], (64,128], ..., (4096, inf)
-constexpr int kNumPrec = 2;        // SVDU_PREC_FP64, SVDU_PREC_SPLIT32
+constexpr int kNumPrec = 2;        // tile-shape tables: SVDU_PREC_FP64, SVDU_PREC_SPLIT32 (the INT8
+                                   // product has one tile shape)
 int shape_bucket(int N);
 // The tile shapes the autotuner measured on MI355X, per precision and bucket.
 void default_shape_table(int (&t)[kNumPrec][kShapeBuckets]);
@@ -28,6 +34,7 @@ struct Options {
   bool refine = true;                       // close-cluster refinement of FP64 results
   bool persistent = false;                  // persistent product schedule
   int forced_shape = -1;                    // -1: the table
+  int slices = kDefaultSlices;              // slices of the exact-slice INT8 product
   int shape_table[kNumPrec][kShapeBuckets];
   Options() { default_shape_table(shape_table); }
 };
@@ -78,6 +85,8 @@ struct Layout {
   double *gemv_pu, *gemv_pv;      // partial sums of the projections through U and V
   double *renorm_u, *renorm_v;    // precision form: column sums of squares
   double *TL, *TR;                // intermediate bases U~ (m x m) and V~ (n x n)
+  int8_t *i8A[2], *i8B[2];        // exact-slice INT8 form, left / right side: slices of X and C~
+  int *i8ea[2], *i8eb[2];         // their row / column scale exponents
   int kmax, cmax;                 // cluster refinement: gathered columns, cluster records
   int *rf_info, *rf_start, *rf_size, *rf_off, *rf_idx;
   double *rf_Yu, *rf_Yv, *rf_T, *rf_W, *rf_beta;
@@ -142,6 +151,10 @@ struct Plan {
   GemvList gemv;
   StageLevel lev[2];
   GemmList gemm[2][kNumShapes];
+  int slices = kDefaultSlices;      // exact-slice INT8 form: slicing and products per level
+  SliceXList sx[2];
+  SliceCList sc[2];
+  I8List i8[2];
   RenormList renorm;
   RefineList refine;
   std::vector<Stage> host_stages;   // per update: L+, L-, R+, R- (host copies, for the FMM path)

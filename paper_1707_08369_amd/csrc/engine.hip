@@ -112,9 +112,18 @@ Layout carve_update(void* base, int m, int n, int path, int precision) {
   const bool fmm = path == SVDU_PATH_FMM;
   L.TL = fmm ? nullptr : c.take<double>((size_t)m * m);   // the FMM path runs the sides in turn through TR
   L.TR = c.take<double>((size_t)n * n);
+  const bool i8 = precision == SVDU_PREC_SLICED_INT8;
+  for (int k = 0; k < 2; ++k) {
+    const size_t N = (size_t)(k == 0 ? m : n);
+    const size_t Rp = i8_pad((int)N, kI8BM), Kp = i8_pad((int)N, kI8K), Cp = i8_pad((int)N, kI8BN);
+    L.i8A[k] = c.take<int8_t>(i8 ? kMaxSlices * Rp * Kp : 0);
+    L.i8B[k] = c.take<int8_t>(i8 ? kMaxSlices * Cp * Kp : 0);
+    L.i8ea[k] = c.take<int>(i8 ? Rp : 0);
+    L.i8eb[k] = c.take<int>(i8 ? Cp : 0);
+  }
   L.kmax = std::min(m, 128);
   L.cmax = std::max(1, L.kmax / 2);
-  const bool rf = precision == SVDU_PREC_FP64;
+  const bool rf = precision != SVDU_PREC_SPLIT32;   // refinement of FP64-accurate results
   const size_t km = rf ? (size_t)L.kmax : 0;
   L.rf_info = c.take<int>(4);
   L.rf_start = c.take<int>(rf ? L.cmax : 0);
@@ -458,8 +467,39 @@ void build_plan(const std::vector<Update>& ups_in, int precision, const Options&
     }
     P.lev[lev] = build_level(st, tv, B);
   }
-  // products, grouped by tile shape, largest first within a group
-  for (int lev = 0; lev < 2; ++lev) {
+  // products, grouped by tile shape, largest first within a group (FP64 and
+  // split FP32), or the slicing and slice products of the INT8 form
+  P.slices = opt.slices;
+  for (int lev = 0; lev < 2 && precision == SVDU_PREC_SLICED_INT8; ++lev) {
+    std::vector<SliceXJob> xs;
+    std::vector<SliceCJob> cs;
+    std::vector<I8Job> gs;
+    for (const Update& u : ups) {
+      const Layout& L = u.L;
+      for (int side = 0; side < 2; ++side) {
+        const int N = side == 0 ? u.m : u.n;
+        const double* X = lev == 0 ? (side == 0 ? u.U : u.V) : (side == 0 ? L.TL : L.TR);
+        const int ldx = lev == 0 ? (side == 0 ? u.ldu : u.ldv) : N;
+        double* Xo = lev == 0 ? (side == 0 ? L.TL : L.TR) : (side == 0 ? u.U_out : u.V_out);
+        const int ldo = lev == 0 ? N : (side == 0 ? u.ldu_out : u.ldv_out);
+        const CauchyDesc d = desc_of(L.st[2 * side + lev], (lev == 1 && side == 1) ? L.signs : nullptr);
+        const int KB = i8_pad(N, kI8K) / kI8K, Rp = i8_pad(N, kI8BM), Cp = i8_pad(N, kI8BN);
+        xs.push_back(SliceXJob{N, N, ldx, KB, Rp / 16, X, L.i8A[side], L.i8ea[side], L.status});
+        cs.push_back(SliceCJob{d, KB, Cp / 16, L.i8B[side], L.i8eb[side]});
+        gs.push_back(I8Job{N, N, ldo, KB, Rp / kI8BM, Cp / kI8BN, (Rp / kI8BM) * (Cp / kI8BN), L.i8A[side],
+                           L.i8B[side], L.i8ea[side], L.i8eb[side], Xo, d.colscale, L.status});
+      }
+    }
+    std::vector<int> bx, bc, bg;
+    for (const SliceXJob& j : xs) bx.push_back(j.rblocks);
+    for (const SliceCJob& j : cs) bc.push_back(j.cblocks);
+    for (const I8Job& j : gs) bg.push_back(j.tiles);
+    const std::vector<int> ox = prefix(bx), oc = prefix(bc), og = prefix(bg);
+    P.sx[lev] = SliceXList{(int)xs.size(), ox.back(), B.put(ox), B.put(xs)};
+    P.sc[lev] = SliceCList{(int)cs.size(), oc.back(), B.put(oc), B.put(cs)};
+    P.i8[lev] = I8List{(int)gs.size(), og.back(), B.put(og), B.put(gs)};
+  }
+  for (int lev = 0; lev < 2 && precision != SVDU_PREC_SLICED_INT8; ++lev) {
     std::vector<GemmJob> by_shape[kNumShapes];
     for (const Update& u : ups) {
       const Layout& L = u.L;
@@ -503,7 +543,7 @@ void build_plan(const std::vector<Update>& ups_in, int precision, const Options&
   {
     std::vector<RefineJob> jobs;
     std::vector<int> bn, bc, bw, bcl;
-    if (precision == SVDU_PREC_FP64) {
+    if (precision != SVDU_PREC_SPLIT32) {
       for (const Update& u : ups) {
         const Layout& L = u.L;
         RefineJob R{};
@@ -603,6 +643,13 @@ void enqueue_plan(const Plan& P, const Sched& S, int part, hipStream_t st) {
   if (part == kStepUpToRoots) return;
   if (part == kStepAll) {
     for (int lev = 0; lev < 2; ++lev) {
+      if (P.precision == SVDU_PREC_SLICED_INT8) {
+        launch_slice_x(P.sx[lev], P.slices, st);
+        launch_slice_c(P.sc[lev], P.slices, st);
+        launch_gemm_i8(P.i8[lev], P.slices, st);
+        S.mark(3 + lev, st);
+        continue;
+      }
       for (int sh = 0; sh < kNumShapes; ++sh) {
         const GemmList& G = P.gemm[lev][sh];
         const int cap = S.grid_cap[s32 ? 1 : 0][sh];

@@ -130,6 +130,68 @@ struct RefineList {
   const RefineJob* job = nullptr;
 };
 
+// ---- exact-slice INT8 product (precision form SVDU_PREC_SLICED_INT8) ------------
+// X (R x N, FP64) and C~ (N x N) are each split into S signed 7-bit slices
+// with a power-of-two scale per row of X and per column of C~; the slices sit
+// in HBM as 1 KiB tiles of 16 rows (or columns) x 64 k, one tile per slice,
+// each tile in the operand order of v_mfma_i32_16x16x64_i8 (lane l holds row
+// l % 16, k = 16 (l / 16) .. + 15). Rows are padded with zero slices to a
+// multiple of kI8BM, columns to kI8BN and k to 64.
+constexpr int kI8BM = 128, kI8BN = 64, kI8K = 64;
+constexpr int kMinSlices = 6, kMaxSlices = 8, kDefaultSlices = 7;
+// Largest order for the INT8 form: a group of S <= 8 slice dot products over N
+// terms of at most 64^2 stays below 2^31.
+constexpr int kI8MaxN = 32768;
+__host__ __device__ constexpr int i8_pad(int x, int q) { return (x + q - 1) / q * q; }
+
+// Slices of the rows of X: A tile (rb, kb, s) at A + ((rb * KB + kb) * S + s) * 1024.
+struct SliceXJob {
+  int R, N, ldx, KB, rblocks;   // rblocks = padded rows / 16
+  const double* X;
+  int8_t* A;
+  int* ea;                      // per padded row: exponent of its scale
+  const int* status;
+};
+// Slices of the columns of C~: B tile (cb, kb, s) at B + ((cb * KB + kb) * S + s) * 1024.
+struct SliceCJob {
+  CauchyDesc d;                 // N = d.N
+  int KB, cblocks;              // cblocks = padded columns / 16
+  int8_t* B;
+  int* eb;                      // per padded column
+};
+// X_out = X C~ from the slices, in tiles of kI8BM x kI8BN.
+struct I8Job {
+  int R, N, ldo, KB, tiles_m, tiles_n, tiles;
+  const int8_t* A;
+  const int8_t* B;
+  const int* ea;
+  const int* eb;
+  double* Xo;
+  const double* colscale;       // optional per-column sign
+  const int* status;
+};
+
+struct SliceXList {
+  int n = 0, blocks = 0;
+  const int* boff = nullptr;    // rblocks per job
+  const SliceXJob* job = nullptr;
+};
+struct SliceCList {
+  int n = 0, blocks = 0;
+  const int* boff = nullptr;    // cblocks per job
+  const SliceCJob* job = nullptr;
+};
+struct I8List {
+  int n = 0, blocks = 0;
+  const int* boff = nullptr;    // tiles per job
+  const I8Job* job = nullptr;
+};
+
+// Slices every job's X / C~, then the products from the slices (S slices).
+void launch_slice_x(const SliceXList& L, int S, hipStream_t st);
+void launch_slice_c(const SliceCList& L, int S, hipStream_t st);
+void launch_gemm_i8(const I8List& L, int S, hipStream_t st);
+
 // ---- launchers (each enqueues on `st`, no host synchronisation) ----------------
 // Projections of every GemvJob: partial sums per row chunk, then a
 // fixed-order reduction.

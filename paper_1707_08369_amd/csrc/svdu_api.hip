@@ -168,7 +168,7 @@ extern "C" {
 size_t svdu_workspace_bytes(int m, int n, int path, int precision) {
   if (m < 1 || n < m) return 0;
   if (path != SVDU_PATH_DIRECT && path != SVDU_PATH_FMM) return 0;
-  if (precision != SVDU_PREC_FP64 && precision != SVDU_PREC_SPLIT32) return 0;
+  if (!precision_ok(precision)) return 0;
   return carve_single(nullptr, m, n, path, precision).bytes;
 }
 
@@ -194,10 +194,11 @@ int svdu_rank1_update(svdu_ctx* ctx, int m, int n, const double* U, int ldu, con
   if (!U || !sigma || !V || !a || !b || !U_out || !sigma_out || !V_out || !workspace) return SVDU_EINVAL;
   if (ldu < m || ldv < n || ldu_out < m || ldv_out < n) return SVDU_EINVAL;
   if (path != SVDU_PATH_DIRECT && path != SVDU_PATH_FMM) return SVDU_EINVAL;
-  if (precision != SVDU_PREC_FP64 && precision != SVDU_PREC_SPLIT32) return SVDU_EINVAL;
+  if (!precision_ok(precision)) return SVDU_EINVAL;
   if (path == SVDU_PATH_FMM && !(eps > 0.0 && eps < 1.0)) return SVDU_EINVAL;
   if (path == SVDU_PATH_FMM && fmm_required_order(eps) > kFmmMaxOrder) return SVDU_ENOTSUP;
   if (path == SVDU_PATH_FMM && precision != SVDU_PREC_FP64) return SVDU_ENOTSUP;
+  if (precision == SVDU_PREC_SLICED_INT8 && n > kI8MaxN) return SVDU_ENOTSUP;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return SVDU_EINVAL;
   const size_t ub = ((size_t)(m - 1) * ldu + m) * 8, vb = ((size_t)(n - 1) * ldv + n) * 8;
   const size_t uob = ((size_t)(m - 1) * ldu_out + m) * 8, vob = ((size_t)(n - 1) * ldv_out + n) * 8;
@@ -415,6 +416,12 @@ int svdu_set_option(svdu_ctx* ctx, int option, int value) {
   if (option == SVDU_OPT_REFINE) {
     const int old = o.refine ? 1 : 0;
     o.refine = value != 0;
+    return old;
+  }
+  if (option == SVDU_OPT_SLICES) {
+    if (value < kMinSlices || value > kMaxSlices) return SVDU_EINVAL;
+    const int old = o.slices;
+    o.slices = value;
     return old;
   }
   if (option == SVDU_OPT_TIMING) return ctx->ring.set(value != 0);

@@ -162,7 +162,7 @@ extern "C" {
 
 size_t svdu_batch_workspace_bytes(int count, const svdu_problem* probs, int precision) {
   if (count < 1 || !probs) return 0;
-  if (precision != SVDU_PREC_FP64 && precision != SVDU_PREC_SPLIT32) return 0;
+  if (!precision_ok(precision)) return 0;
   for (int i = 0; i < count; ++i)
     if (!(probs[i].m >= 1 && probs[i].n >= probs[i].m)) return 0;
   const size_t tb = table_bytes_for(count, probs, precision, Options());
@@ -174,11 +174,13 @@ int svdu_batch_create(svdu_ctx* ctx, svdu_batch** out, int count, const svdu_pro
   if (!out) return SVDU_EINVAL;
   *out = nullptr;
   if (!ctx || count < 1 || !probs || !workspace) return SVDU_EINVAL;
-  if (precision != SVDU_PREC_FP64 && precision != SVDU_PREC_SPLIT32) return SVDU_EINVAL;
+  if (!precision_ok(precision)) return SVDU_EINVAL;
   if (flags & ~SVDU_BATCH_PERSISTENT) return SVDU_EINVAL;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return SVDU_EINVAL;
   for (int i = 0; i < count; ++i)
     if (!problem_ok(probs[i])) return SVDU_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (precision == SVDU_PREC_SLICED_INT8 && probs[i].n > kI8MaxN) return SVDU_ENOTSUP;
   const size_t tb = table_bytes_for(count, probs, precision, Options());
   BatchWs W = carve_batch(workspace, count, probs, precision, tb);
   if (workspace_bytes < W.bytes) return SVDU_ENOMEM;

@@ -394,7 +394,7 @@ int svdu_server_create(svdu_ctx* ctx, svdu_server** out, const svdu_server_confi
   if (!out || !ctx || !cfg || !arena) return SVDU_EINVAL;
   *out = nullptr;
   if (cfg->workers < 1 || cfg->workers > 8 || cfg->max_batch < 1) return SVDU_EINVAL;
-  if (cfg->precision != SVDU_PREC_FP64 && cfg->precision != SVDU_PREC_SPLIT32) return SVDU_EINVAL;
+  if (!precision_ok(cfg->precision)) return SVDU_EINVAL;
   if (cfg->fmm_min_n > 0 && !(cfg->fmm_eps > 0.0 && cfg->fmm_eps < 1.0)) return SVDU_EINVAL;
   if (cfg->fmm_min_n > 0 && fmm_required_order(cfg->fmm_eps) > kFmmMaxOrder) return SVDU_ENOTSUP;
   if (!(cfg->batch_cost_factor >= 1.0) || cfg->min_batch_cost < 0.0) return SVDU_EINVAL;
@@ -415,6 +415,7 @@ int svdu_server_create(svdu_ctx* ctx, svdu_server** out, const svdu_server_confi
 int svdu_server_add_matrix(svdu_server* S, int m, int n, double* U0, double* s0, double* V0, double* U1, double* s1,
                            double* V1, int* id) {
   if (!S || !id || m < 1 || n < m || !U0 || !s0 || !V0 || !U1 || !s1 || !V1) return SVDU_EINVAL;
+  if (S->cfg.precision == SVDU_PREC_SLICED_INT8 && n > kI8MaxN) return SVDU_ENOTSUP;
   std::lock_guard<std::mutex> lk(S->mu);
   if (!S->workers.empty()) return SVDU_EINVAL;   // matrices are registered before start
   Matrix M;

@@ -115,6 +115,10 @@ def test_host_argument_errors_return_before_enqueue(lib, ctx):
     assert call(path=1, eps=5.0 ** -16 * 0.99) == svdu.SVDU_ENOTSUP
     assert call(path=1, eps=1e-13, workspace_bytes=16) == svdu.SVDU_ENOTSUP   # refused before sizing
     assert call(ctx=None) == svdu.SVDU_EINVAL
+    assert call(precision=3) == svdu.SVDU_EINVAL
+    assert call(precision=svdu.SVDU_PREC_SLICED_INT8, path=1) == svdu.SVDU_ENOTSUP   # INT8 form: direct path only
+    # INT8 form: INT32 sums of S <= 8 slice products stay exact up to n = 32768
+    assert call(precision=svdu.SVDU_PREC_SLICED_INT8, n=40000, ldv=40000, ldv_out=40000) == svdu.SVDU_ENOTSUP
     assert svdu.svdu_eig_update(ctx, 3, 0, fake, 1, fake, fake, 1.0, 0, 0.0, _p(0x50000), 1, fake, None, ws, 1 << 20,
                                 None) == svdu.SVDU_EINVAL
     assert svdu.svdu_eig_update(ctx, 3, 4, fake, 4, fake, fake, 0.0, 0, 0.0, _p(0x50000), 4, fake, None, ws, 1 << 20,
@@ -160,6 +164,10 @@ def test_options(lib, ctx):
     assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_TILE_SHAPE, svdu.SVDU_TILE_SHAPES) == svdu.SVDU_EINVAL
     assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_PERSISTENT, 1) == 0
     assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_PERSISTENT, 0) == 1
+    assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SLICES, 8) == 7
+    assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SLICES, 5) == svdu.SVDU_EINVAL
+    assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SLICES, 9) == svdu.SVDU_EINVAL
+    assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SLICES, 7) == 8
 
 
 def _table(ctx, prec, new=None):
@@ -221,6 +229,7 @@ def test_batch_workspace_and_argument_errors(lib, ctx):
     single = sum(svdu.svdu_workspace_bytes(arr[i].m, arr[i].n) for i in range(3))
     assert wsb > 0 and wsb >= single - 3 * 32768
     assert svdu.svdu_batch_workspace_bytes(3, arr, svdu.SVDU_PREC_SPLIT32) > 0
+    assert svdu.svdu_batch_workspace_bytes(3, arr, svdu.SVDU_PREC_SLICED_INT8) > wsb
     assert svdu.svdu_batch_workspace_bytes(0, arr, 0) == 0
     ws = base + 0x100000
     h = ctypes.c_void_p()
