@@ -160,6 +160,27 @@ int svdu_rank1_update(svdu_ctx* ctx, int m, int n, const double* U, int ldu, con
                       int ldu_out, double* sigma_out, double* V_out, int ldv_out, int8_t* defl,
                       void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---- rank-k update ---------------------------------------------------------
+ * The SVD of A + sum_j a_j b_j^T (j = 0..k-1), the extension the paper's
+ * conclusion names, as k rank-1 updates (Section 6.1) applied in order, all
+ * enqueued by this one call: update j works on the factors update j - 1
+ * produced (each pairs its own signs). No host synchronisation on
+ * SVDU_PATH_DIRECT.
+ *  A, lda      k x m, row-major: row j is a_j (lda >= m).
+ *  B, ldb      k x n, row-major: row j is b_j (ldb >= n).
+ *  workspace   >= svdu_rankk_workspace_bytes(m, n, k, path, precision): one
+ *              update's workspace plus one intermediate factor set (k > 1).
+ *              svdu_get_status(workspace, ...) reports the first device error
+ *              of any of the k updates (their status bits combined).
+ * Other arguments as for svdu_rank1_update (no deflation flags). Returns 0 or
+ * a negative SVDU_E* code; on an argument error found on the host for some
+ * update j, updates before j have been enqueued. */
+size_t svdu_rankk_workspace_bytes(int m, int n, int k, int path, int precision);
+int svdu_rankk_update(svdu_ctx* ctx, int m, int n, int k, const double* U, int ldu, const double* sigma,
+                      const double* V, int ldv, const double* A, int lda, const double* B, int ldb, double eps,
+                      int path, int precision, double* U_out, int ldu_out, double* sigma_out, double* V_out,
+                      int ldv_out, void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---- the update without a caller workspace --------------------------------
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc. The same

@@ -5,6 +5,6 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 """
 from .svdu_oracle import (  # noqa: F401
     gram_split, deflate, secular_roots, secular_f, loewner_weights, rank_one_update, rank_one_update_z,
-    svd_rank1_update, dense_ahat, recon_error, paper_error, orth_error, U64,
+    svd_rank1_update, svd_rankk_update, dense_ahat, recon_error, paper_error, orth_error, U64,
 )
 from .jacobi import jacobi_svd  # noqa: F401

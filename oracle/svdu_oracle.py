@@ -391,6 +391,25 @@ def svd_rank1_update(U, sigma, V, a, b, pair_signs: bool = True) -> UpdateResult
 
 
 # ---------------------------------------------------------------------------
+# Rank-k update (Section 8, Conclusion: the extension to rank k), as k rank-1
+# updates applied in order.
+# ---------------------------------------------------------------------------
+def svd_rankk_update(U, sigma, V, A, B) -> UpdateResult:
+    """SVD of U diag(sigma) V^T + sum_j A[j]^T B[j] (row j of A and B is the
+    pair a_j, b_j): the rank-1 update of Section 6.1 applied to a_0 b_0^T, then
+    to a_1 b_1^T on its result, and so on. Returns the last update's result."""
+    A = np.atleast_2d(np.asarray(A, dtype=np.float64))
+    B = np.atleast_2d(np.asarray(B, dtype=np.float64))
+    if A.shape[0] != B.shape[0] or A.shape[0] < 1:
+        raise ValueError("A and B need the same k >= 1 rows")
+    r = None
+    for a, b in zip(A, B):
+        r = svd_rank1_update(U, sigma, V, a, b)
+        U, sigma, V = r.U, r.sigma, r.V
+    return r
+
+
+# ---------------------------------------------------------------------------
 # Checks used by the tests (plain definitions).
 # ---------------------------------------------------------------------------
 def dense_ahat(U, sigma, V, a, b):

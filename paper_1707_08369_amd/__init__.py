@@ -53,7 +53,7 @@ EXPORTS = ("svdu_create", "svdu_destroy", "svdu_workspace_bytes", "svdu_rank1_up
            "svdu_autotune_workspace_bytes", "svdu_autotune", "svdu_tile_table", "svdu_server_create",
            "svdu_server_add_matrix", "svdu_server_start", "svdu_server_now", "svdu_server_submit",
            "svdu_server_poll", "svdu_server_stats", "svdu_server_drain", "svdu_server_current",
-           "svdu_server_destroy", "svdu_rank1_update_noalloc")
+           "svdu_server_destroy", "svdu_rank1_update_noalloc", "svdu_rankk_workspace_bytes", "svdu_rankk_update")
 SVDU_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
@@ -116,6 +116,11 @@ def load():
     lib.svdu_rank1_update_noalloc.argtypes = [c_vp, c_int, c_int, c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_vp, c_int,
                                               c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_vp, c_vp]
     lib.svdu_rank1_update_noalloc.restype = c_int
+    lib.svdu_rankk_workspace_bytes.argtypes = [c_int, c_int, c_int, c_int, c_int]
+    lib.svdu_rankk_workspace_bytes.restype = c_size
+    lib.svdu_rankk_update.argtypes = [c_vp, c_int, c_int, c_int, c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_int, c_vp,
+                                      c_int, c_dbl, c_int, c_int, c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_size, c_vp]
+    lib.svdu_rankk_update.restype = c_int
     lib.svdu_get_status.argtypes = [c_vp, c_vp]
     lib.svdu_get_status.restype = c_int
     lib.svdu_eig_update_workspace_bytes.argtypes = [c_int, c_int, c_int]
@@ -203,6 +208,17 @@ def svdu_rank1_update_noalloc(ctx, m, n, U, ldu, sigma, V, ldv, a, b, precision,
                               V_out, ldv_out, defl, status, stream) -> int:
     return int(load().svdu_rank1_update_noalloc(ctx, m, n, U, ldu, sigma, V, ldv, a, b, precision, U_out, ldu_out,
                                                 sigma_out, V_out, ldv_out, defl, status, stream))
+
+
+def svdu_rankk_workspace_bytes(m, n, k, path=SVDU_PATH_DIRECT, precision=SVDU_PREC_FP64) -> int:
+    return int(load().svdu_rankk_workspace_bytes(m, n, k, path, precision))
+
+
+def svdu_rankk_update(ctx, m, n, k, U, ldu, sigma, V, ldv, A, lda, B, ldb, eps, path, precision, U_out, ldu_out,
+                      sigma_out, V_out, ldv_out, workspace, workspace_bytes, stream) -> int:
+    return int(load().svdu_rankk_update(ctx, m, n, k, U, ldu, sigma, V, ldv, A, lda, B, ldb, eps, path, precision,
+                                        U_out, ldu_out, sigma_out, V_out, ldv_out, workspace, workspace_bytes,
+                                        stream))
 
 
 def svdu_get_status(workspace, stream) -> int:
@@ -461,6 +477,42 @@ def rank1_update_noalloc(U, sigma, V, a, b, precision=SVDU_PREC_FP64, out=None, 
         if code != SVDU_OK:
             raise SvduError(code, "svdu_rank1_update_noalloc (device)")
     return Uo, so, Vo, defl
+
+
+def rankk_update(U, sigma, V, A, B, eps=1e-10, path=SVDU_PATH_DIRECT, precision=SVDU_PREC_FP64, out=None,
+                 stream=None, check=True, ctx=None):
+    """SVD of U diag(sigma) V^T + A^T B for A (k x m) and B (k x n): row j of A
+    and B is the pair (a_j, b_j). Returns (U^, sigma^, V^)."""
+    torch = _torch()
+    m, n = U.shape[0], V.shape[0]
+    ldu = _check_mat(U, m, m, "U")
+    ldv = _check_mat(V, n, n, "V")
+    _check_vec(sigma, m, "sigma")
+    k = A.shape[0]
+    lda = _check_mat(A, k, m, "A")
+    ldb = _check_mat(B, k, n, "B")
+    dev = U.device
+    if out is None:
+        Uo = torch.empty((m, m), dtype=torch.float64, device=dev)
+        so = torch.empty(m, dtype=torch.float64, device=dev)
+        Vo = torch.empty((n, n), dtype=torch.float64, device=dev)
+    else:
+        Uo, so, Vo = out
+    lduo = _check_mat(Uo, m, m, "U_out")
+    ldvo = _check_mat(Vo, n, n, "V_out")
+    _check_vec(so, m, "sigma_out")
+    ws = new_workspace(svdu_rankk_workspace_bytes(m, n, k, path, precision), dev)
+    wp, wb = _aligned(ws)
+    sh = _stream_handle(stream)
+    rc = svdu_rankk_update(_ctx(ctx), m, n, k, _ptr(U), ldu, _ptr(sigma), _ptr(V), ldv, _ptr(A), lda, _ptr(B), ldb,
+                           float(eps), path, precision, _ptr(Uo), lduo, _ptr(so), _ptr(Vo), ldvo, wp, wb, sh)
+    if rc != SVDU_OK:
+        raise SvduError(rc, "svdu_rankk_update")
+    if check:
+        rc = svdu_get_status(wp, sh)
+        if rc != SVDU_OK:
+            raise SvduError(rc, "svdu_rankk_update (device)")
+    return Uo, so, Vo
 
 
 def eig_update(X, lam, z, rho, path=SVDU_PATH_DIRECT, eps=1e-10, stream=None, check=True, ctx=None):

@@ -83,14 +83,33 @@ __device__ void slice_x_body(const SliceXJob& J, int rb) {
   __shared__ int sexp[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = J.R, N = J.N;
+  // 16-byte loads where the rows allow them (16-byte aligned rows of even length)
+  const bool vec = ((reinterpret_cast<uintptr_t>(J.X) & 15) == 0) && (J.ldx % 2 == 0) && (N % 2 == 0);
   {
-    // row maxima: 16 threads per row, 128 contiguous bytes per row and step
+    // row maxima: 16 threads per row, each 16 bytes of 256 contiguous bytes per
+    // step, four independent running maxima
     const int rr = tid >> 4, c0 = tid & 15, r = rb * 16 + rr;
-    double m = 0.0;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
     if (r < R) {
       const double* xr = J.X + (size_t)r * J.ldx;
-      for (int c = c0; c < N; c += 16) m = __builtin_fmax(m, __builtin_fabs(gld(xr + c)));
+      if (vec) {
+        int c = 2 * c0;
+        for (; c + 96 < N; c += 128) {
+          const double2 v0 = gld2(xr + c), v1 = gld2(xr + c + 32), v2 = gld2(xr + c + 64), v3 = gld2(xr + c + 96);
+          m0 = __builtin_fmax(m0, __builtin_fmax(__builtin_fabs(v0.x), __builtin_fabs(v0.y)));
+          m1 = __builtin_fmax(m1, __builtin_fmax(__builtin_fabs(v1.x), __builtin_fabs(v1.y)));
+          m2 = __builtin_fmax(m2, __builtin_fmax(__builtin_fabs(v2.x), __builtin_fabs(v2.y)));
+          m3 = __builtin_fmax(m3, __builtin_fmax(__builtin_fabs(v3.x), __builtin_fabs(v3.y)));
+        }
+        for (; c < N; c += 32) {
+          const double2 v = gld2(xr + c);
+          m0 = __builtin_fmax(m0, __builtin_fmax(__builtin_fabs(v.x), __builtin_fabs(v.y)));
+        }
+      } else {
+        for (int c = c0; c < N; c += 16) m0 = __builtin_fmax(m0, __builtin_fabs(gld(xr + c)));
+      }
     }
+    double m = __builtin_fmax(__builtin_fmax(m0, m1), __builtin_fmax(m2, m3));
     m = group_max<16>(m);
     if (c0 == 0) {
       const int e = scale_exp(m);
@@ -105,12 +124,22 @@ __device__ void slice_x_body(const SliceXJob& J, int rb) {
   for (int kb = wave; kb < J.KB; kb += 4) {
     const int k0 = kb * kI8K + 16 * (lane >> 4);
     double x[16];
+    if (vec && k0 + 16 <= N) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int k = k0 + j;
-      const double v = (r < R && k < N) ? gld(xr + k) : 0.0;
-      x[j] = __builtin_amdgcn_ldexp(v, -e);
+      for (int j = 0; j < 16; j += 2) {
+        const double2 v = gld2(xr + k0 + j);
+        x[j] = (r < R) ? v.x : 0.0;
+        x[j + 1] = (r < R) ? v.y : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int k = k0 + j;
+        x[j] = (r < R && k < N) ? gld(xr + k) : 0.0;
+      }
     }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = __builtin_amdgcn_ldexp(x[j], -e);
     v4i sl[S];
     slice16<S>(x, sl);
 #pragma unroll

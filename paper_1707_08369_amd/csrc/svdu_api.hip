@@ -44,6 +44,11 @@ __global__ void set_scalar(double* dst, double v, int* status) {
   }
 }
 
+// acc = bits (first) or acc |= bits: the status words of a sequence of updates.
+__global__ void or_status(int* acc, const int* bits, int first) {
+  if (threadIdx.x == 0) *acc = first ? *bits : (*acc | *bits);
+}
+
 __global__ void identity_map(int N, int* col) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < N) col[j] = j;
@@ -241,6 +246,71 @@ int svdu_rank1_update(svdu_ctx* ctx, int m, int n, const double* U, int ldu, con
   } else {
     enqueue_plan(P, S, kStepAll, st);
   }
+  return hip_ok();
+}
+
+// Rank-k workspace: one rank-1 update's workspace (its status word first),
+// the accumulated status of the sequence, and one intermediate factor set.
+struct RankkWs {
+  size_t single;
+  int* acc;
+  double *U, *s, *V;
+  size_t bytes;
+};
+
+static RankkWs carve_rankk(void* ws, int m, int n, int k, int path, int precision) {
+  RankkWs W;
+  W.single = svdu_workspace_bytes(m, n, path, precision);
+  Carver c(ws);
+  c.off = W.single;
+  W.acc = c.take<int>(16);
+  const size_t mm = k > 1 ? (size_t)m * m : 0, nn = k > 1 ? (size_t)n * n : 0;
+  W.U = c.take<double>(mm);
+  W.s = c.take<double>(k > 1 ? m : 0);
+  W.V = c.take<double>(nn);
+  W.bytes = c.off + 256;
+  return W;
+}
+
+size_t svdu_rankk_workspace_bytes(int m, int n, int k, int path, int precision) {
+  if (k < 1 || svdu_workspace_bytes(m, n, path, precision) == 0) return 0;
+  return carve_rankk(nullptr, m, n, k, path, precision).bytes;
+}
+
+int svdu_rankk_update(svdu_ctx* ctx, int m, int n, int k, const double* U, int ldu, const double* sigma,
+                      const double* V, int ldv, const double* A, int lda, const double* B, int ldb, double eps,
+                      int path, int precision, double* U_out, int ldu_out, double* sigma_out, double* V_out,
+                      int ldv_out, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!ctx || k < 1 || m < 1 || n < m || !A || !B || lda < m || ldb < n || !workspace) return SVDU_EINVAL;
+  if (svdu_workspace_bytes(m, n, path, precision) == 0) return SVDU_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return SVDU_EINVAL;
+  const RankkWs W = carve_rankk(workspace, m, n, k, path, precision);
+  if (workspace_bytes < W.bytes) return SVDU_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // update j reads the factors update j - 1 wrote; the outputs alternate
+  // between the caller's buffers and the workspace's so that the last update
+  // writes the caller's
+  const double *Ui = U, *si = sigma, *Vi = V;
+  int ldui = ldu, ldvi = ldv;
+  for (int j = 0; j < k; ++j) {
+    const bool to_out = ((k - 1 - j) % 2) == 0;
+    double* Uo = to_out ? U_out : W.U;
+    double* so = to_out ? sigma_out : W.s;
+    double* Vo = to_out ? V_out : W.V;
+    const int lduo = to_out ? ldu_out : m, ldvo = to_out ? ldv_out : n;
+    const int rc = svdu_rank1_update(ctx, m, n, Ui, ldui, si, Vi, ldvi, A + (size_t)j * lda, B + (size_t)j * ldb,
+                                     eps, path, precision, Uo, lduo, so, Vo, ldvo, nullptr, workspace, W.single,
+                                     stream);
+    if (rc != SVDU_OK) return rc;
+    hipLaunchKernelGGL(or_status, dim3(1), dim3(64), 0, st, W.acc, static_cast<const int*>(workspace), j == 0);
+    Ui = Uo;
+    si = so;
+    Vi = Vo;
+    ldui = lduo;
+    ldvi = ldvo;
+  }
+  // the workspace's status word reports every update of the sequence
+  hipLaunchKernelGGL(or_status, dim3(1), dim3(64), 0, st, static_cast<int*>(workspace), W.acc, 1);
   return hip_ok();
 }
 

@@ -491,3 +491,45 @@ def test_planted_householder_column_off_by_one_fails(monkeypatch):
     with pytest.raises(AssertionError):
         test_stage_zero_block_cluster(0.9)
 
+
+
+# ---------------------------------------------------------------------------
+# Rank-k update (the Conclusion's extension), as k rank-1 updates in order
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n,k", [(12, 12, 2), (20, 31, 3), (40, 40, 5)])
+def test_rankk_update_matches_jacobi_svd_of_the_sum(m, n, k):
+    """Against brute force: the one-sided Jacobi SVD of the explicit
+    U S V^T + sum_j a_j b_j^T."""
+    P = S.make_problem(m, n, "uniform", seed=m + k)
+    rng = np.random.default_rng(m * k)
+    A = rng.standard_normal((k, m)) / np.sqrt(n)
+    B = rng.standard_normal((k, n)) / np.sqrt(n)
+    r = O.svd_rankk_update(P.U, P.sigma, P.V, A, B)
+    Ah = (P.U * P.sigma[None, :]) @ P.V[:, :m].T + A.T @ B
+    _, sj, _ = O.jacobi_svd(Ah)
+    assert np.max(np.abs(r.sigma - sj)) <= 1e-13 * sj[0]
+    assert O.recon_error(Ah, r.U, r.sigma, r.V) <= 1e-13
+    assert O.orth_error(r.U) <= 1e-13 and O.orth_error(r.V) <= 1e-13
+
+
+def test_rankk_with_one_pair_is_the_rank1_update():
+    P = S.make_problem(16, 20, "uniform", seed=3)
+    r1 = O.svd_rank1_update(P.U, P.sigma, P.V, P.a, P.b)
+    rk = O.svd_rankk_update(P.U, P.sigma, P.V, P.a[None, :], P.b[None, :])
+    assert np.array_equal(r1.sigma, rk.sigma) and np.array_equal(r1.U, rk.U) and np.array_equal(r1.V, rk.V)
+
+
+def test_planted_rankk_skipping_the_last_pair_fails():
+    """A composition that drops one pair misses the Jacobi SVD of the sum."""
+    orig = OS.svd_rankk_update
+
+    def dropped(U, sigma, V, A, B):
+        return orig(U, sigma, V, A[:-1], B[:-1])
+    P = S.make_problem(12, 12, "uniform", seed=5)
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((3, 12)) / np.sqrt(12)
+    B = rng.standard_normal((3, 12)) / np.sqrt(12)
+    Ah = (P.U * P.sigma[None, :]) @ P.V.T + A.T @ B
+    _, sj, _ = O.jacobi_svd(Ah)
+    r = dropped(P.U, P.sigma, P.V, A, B)
+    assert np.max(np.abs(r.sigma - sj)) > 1e-6 * sj[0]
