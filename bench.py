@@ -12,10 +12,13 @@ Prints one JSON line. `roofline` describes the product kernel (the dominant
 one): algorithmic FP64 flops per launch over its mean launch time, measured
 with HIP events recorded on the launch stream by the library's timing ring.
 One launch computes the products of one level, U C~_L+ and V C~_R+ (or
-U~ C~_L- and V~ C~_R-): 2 m^3 + 2 n^3 flops. `forms` adds the precision form,
-the FMM path and the batched form (512 uneven problems in one captured graph)
-measured on the same box. `cpu_baseline` times the CPU oracle on a bounded sample (see
-cpu_baseline()). `traffic` comes from the rocprofv3 counter summary under
+U~ C~_L- and V~ C~_R-): 2 m^3 + 2 n^3 flops. `forms` adds the precision forms
+(exact-slice INT8, split FP32), the FMM path, the serving form and the batched
+form (512 uneven problems in one captured graph) measured on the same box;
+`configs` the other workloads (m = n = 256 latency, m = n = 4096 direct vs FMM
+with its clustered / zeroed variants, m = 4096 n = 8192 precision forms, and
+the FMM error against the expansion order). `cpu_baseline` times one CPU
+oracle update of the benchmark workload (see cpu_baseline()). `traffic` comes from the rocprofv3 counter summary under
 profiles/ when it was taken on the current product-kernel source, else null.
 """
 from __future__ import annotations
@@ -57,100 +60,267 @@ def load_traffic(m: int, n: int):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(n_s: int = 3072, seed: int = 77):
-    """The CPU oracle (as it stands) on a bounded sample of the workload.
+def host_info():
+    """CPU threads this process may use, and the CPU model."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return cores, model
 
-    Sample: one complete oracle update at m = n = n_s from the same workload
-    family (Haar factors, sigma ~ U[1e-3, 1], a, b ~ N(0, 1/n)). Its phases are
-    timed separately and scaled to m = n = 8192 by their complexity: the
-    secular solves, Loewner weights and eigenvector columns (O(n^2) each) by
-    (8192/n_s)^2, the rest (projections, dense products, sign pairing;
-    O(n^3) with BLAS) by (8192/n_s)^3.
+
+def cpu_baseline(U, sigma, V, a, b):
+    """The CPU oracle (as it stands) on one update of the benchmark workload.
+
+    Sample: one complete oracle update at the benchmark's size on host copies of
+    the inputs of the timed GPU steps (the first timed step's a, b), timed
+    wall-clock. The oracle's dense products and the dense A^ of its sign
+    pairing run in numpy's BLAS on the host's threads; its secular solves,
+    weights and eigenvector columns are single-threaded numpy.
     """
-    import numpy as np
     import threadpoolctl
 
     import oracle.svdu_oracle as OS
-    import synth_inputs as S
+    Uh, sh, Vh, ah, bh = (x.cpu().numpy() for x in (U, sigma, V, a, b))
+    orig = OS.rank_one_update
+    done = [0]
 
-    P = S.make_problem(n_s, n_s, "uniform", seed=seed, lo=1e-3, hi=1.0)
-    phases = {}
-    names = ("secular_roots", "loewner_weights", "cauchy_eigvecs", "deflate")
-    orig = {nm: getattr(OS, nm) for nm in names}
-
-    def timed(nm, f):
-        def g(*a, **k):
-            t = time.perf_counter()
-            r = f(*a, **k)
-            phases[nm] = phases.get(nm, 0.0) + time.perf_counter() - t
-            return r
-        return g
-
+    def staged(*args, **kw):      # reports each of the oracle's four eigen-updates as it completes
+        r = orig(*args, **kw)
+        done[0] += 1
+        print(f"[bench] oracle eigen-update {done[0]}/4 done at {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+        return r
+    t0 = time.perf_counter()
+    OS.rank_one_update = staged
     try:
-        for nm in names:
-            setattr(OS, nm, timed(nm, orig[nm]))
-        t0 = time.perf_counter()
-        OS.svd_rank1_update(P.U, P.sigma, P.V, P.a, P.b)
-        total = time.perf_counter() - t0
+        OS.svd_rank1_update(Uh, sh, Vh, ah, bh)
     finally:
-        for nm in names:
-            setattr(OS, nm, orig[nm])
-    quad = sum(phases.values())
-    rest = total - quad
-    f = 8192.0 / n_s
-    est = quad * f * f + rest * f ** 3
+        OS.rank_one_update = orig
+    secs = time.perf_counter() - t0
     info = threadpoolctl.threadpool_info()
-    threads = max([i.get("num_threads", 1) for i in info] + [1])
+    blas = max([i.get("num_threads", 1) for i in info] + [1])
+    cores, model = host_info()
+    m, n = Uh.shape[0], Vh.shape[0]
     return {
-        "value": 1.0 / est,
+        "value": 1.0 / secs,
         "unit": "updates/s",
-        "cores": int(threads),
+        "cores": int(max(blas, 1)),
         "kind": "oracle",
-        "sample": (f"one full oracle update at m=n={n_s} (same workload family), {total:.1f} s; "
-                   f"O(n^2) phases ({quad:.1f} s, single-threaded numpy) scaled by {f * f:.2f}, "
-                   f"O(n^3) BLAS phases ({rest:.1f} s, {threads} threads) by {f ** 3:.2f}; "
-                   f"estimated {est:.0f} s per m=n=8192 update"),
-        "seconds_per_update_est": est,
+        "sample": (f"one full oracle update at m={m} n={n} on the benchmark's inputs: {secs:.1f} s wall-clock "
+                   f"({blas} BLAS threads for the dense products; the O(n^2) phases single-threaded); "
+                   f"host: {cores} usable CPUs, {model}"),
+        "seconds_per_update": secs,
+        "host_cpus": cores,
+        "cpu_model": model,
     }
 
 
-def measure_forms(svdu, torch, U, sigma, V, A_vecs, B_vecs, Uo, so, Vo, ws, stream, fp64_ms, check, steps=4):
-    """The precision form on the same inputs: updates/s, speedup over the plain
-    FP64 path, and its reconstruction / orthogonality error."""
-    import numpy as np
+INT8_PEAK_TOPS = 5000.0
+
+
+def _recon_orth(torch, U, sigma, V, a, b, Uo, so, Vo):
+    m, n = U.shape[0], V.shape[0]
+    Ah = (U * sigma[None, :]) @ V[:, :m].T + torch.outer(a, b)
+    rec = ((Uo * so[None, :]) @ Vo[:, :m].T - Ah).norm().item() / Ah.norm().item()
+    ou = (Uo.T @ Uo - torch.eye(m, dtype=Uo.dtype, device=Uo.device)).abs().max().item()
+    ov = (Vo.T @ Vo - torch.eye(n, dtype=Vo.dtype, device=Vo.device)).abs().max().item()
+    return rec, ou, ov
+
+
+def measure_forms(svdu, torch, U, sigma, V, A_vecs, B_vecs, Uo, so, Vo, stream, fp64_ms, check, steps=4,
+                  fmm=True):
+    """The precision forms (exact-slice INT8 with 6, 7 and 8 slices; split FP32)
+    and the FMM path on the same inputs: updates/s, speedup over the plain FP64
+    path, and reconstruction / orthogonality error against the inputs. For the
+    INT8 form also the product phases from the context's timing ring (slicing
+    plus slice products, per level) and the slice products' INT8 rate against
+    the 5.0 POPS dense peak."""
     res = {}
     m, n = U.shape[0], V.shape[0]
-    ref = None
-    if check:   # the FP64 direct result of the inputs the forms end on, for the FMM comparison
-        k = steps % A_vecs.shape[0]
-        ref = svdu.rank1_update(U, sigma, V, A_vecs[k], B_vecs[k], workspace=ws, want_defl=False, stream=stream)
-    for name, prec, path in (("split32", svdu.SVDU_PREC_SPLIT32, svdu.SVDU_PATH_DIRECT),
-                             ("fmm_eps1e-10", svdu.SVDU_PREC_FP64, svdu.SVDU_PATH_FMM)):
+    k_ref = steps % A_vecs.shape[0]
+    ref = svdu.rank1_update(U, sigma, V, A_vecs[k_ref], B_vecs[k_ref], want_defl=False, stream=stream) \
+        if check else None
+    forms = [("int8_slices7", svdu.SVDU_PREC_SLICED_INT8, svdu.SVDU_PATH_DIRECT, 7),
+             ("int8_slices6", svdu.SVDU_PREC_SLICED_INT8, svdu.SVDU_PATH_DIRECT, 6),
+             ("int8_slices8", svdu.SVDU_PREC_SLICED_INT8, svdu.SVDU_PATH_DIRECT, 8),
+             ("split32", svdu.SVDU_PREC_SPLIT32, svdu.SVDU_PATH_DIRECT, 7)]
+    if fmm:
+        forms.append(("fmm_eps1e-10", svdu.SVDU_PREC_FP64, svdu.SVDU_PATH_FMM, 7))
+    for name, prec, path, slices in forms:
+        ctx = svdu.Context()
+        ctx.set_option(svdu.SVDU_OPT_SLICES, slices)
         wsf = svdu.new_workspace(svdu.svdu_workspace_bytes(m, n, path, prec), U.device)
 
         def run(k):
             svdu.rank1_update(U, sigma, V, A_vecs[k], B_vecs[k], eps=1e-10, path=path, precision=prec,
-                              out=(Uo, so, Vo), workspace=wsf, want_defl=False, stream=stream, check=False)
+                              out=(Uo, so, Vo), workspace=wsf, want_defl=False, stream=stream, check=False, ctx=ctx)
         run(0)
         torch.cuda.synchronize()
+        ctx.set_option(svdu.SVDU_OPT_TIMING, 1)
         t0 = time.perf_counter()
         for k in range(1, steps + 1):
             run(k % A_vecs.shape[0])
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0) / steps
+        ph = svdu.timing_read(steps, ctx=ctx)
+        ctx.close()
         rec = dict(updates_per_s=1e3 / ms, ms_per_update=ms, speedup_vs_fp64=fp64_ms / ms)
+        if prec == svdu.SVDU_PREC_SLICED_INT8:
+            lev_ms = [sum(p[2] for p in ph) / len(ph), sum(p[3] for p in ph) / len(ph)]
+            pairs = slices * (slices + 1) // 2
+            ops = 2.0 * pairs * (m ** 3 + n ** 3)          # slice-product integer ops of one level
+            rec["slices"] = slices
+            rec["product_level_ms"] = lev_ms
+            rec["int8_tops_per_level"] = ops / (sum(lev_ms) / 2 * 1e-3) / 1e12
+            rec["int8_frac_of_peak"] = rec["int8_tops_per_level"] / INT8_PEAK_TOPS
+            rec["fp64_equivalent_tflops"] = 2.0 * (m ** 3 + n ** 3) / (sum(lev_ms) / 2 * 1e-3) / 1e12
         if check:
             k = steps % A_vecs.shape[0]
-            Ah = (U * sigma[None, :]) @ V[:, :m].T + torch.outer(A_vecs[k], B_vecs[k])
-            rec["recon"] = ((Uo * so[None, :]) @ Vo[:, :m].T - Ah).norm().item() / Ah.norm().item()
-            rec["orth_U"] = (Uo.T @ Uo - torch.eye(m, dtype=Uo.dtype, device=Uo.device)).abs().max().item()
-            rec["orth_V"] = (Vo.T @ Vo - torch.eye(n, dtype=Vo.dtype, device=Vo.device)).abs().max().item()
-            rec["bound"] = 1e-10 if path == svdu.SVDU_PATH_DIRECT else 1e-9
+            r, ou, ov = _recon_orth(torch, U, sigma, V, A_vecs[k], B_vecs[k], Uo, so, Vo)
+            rec.update(recon=r, orth_U=ou, orth_V=ov, bound=1e-10 if path == svdu.SVDU_PATH_DIRECT else 1e-9)
+            rec["sigma_bitwise_fp64"] = bool(torch.equal(so, ref[1]))
             if path == svdu.SVDU_PATH_FMM:
                 rec["max_abs_diff_vs_direct_U"] = (Uo - ref[0]).abs().max().item()
                 rec["max_abs_diff_vs_direct_V"] = (Vo - ref[2]).abs().max().item()
         res[name] = rec
         del wsf
+    return res
+
+
+def haar_inputs(torch, S, m, n, seed, kind="uniform01"):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    U = S.haar_torch(m, seed=seed + 1, device="cuda")
+    V = S.haar_torch(n, seed=seed + 2, device="cuda")
+    sig = S.sigma_geometric(m) if kind == "geometric" else S.sigma_uniform(m, 1e-3, 1.0, rng)
+    a = rng.standard_normal(m) / np.sqrt(n)
+    b = rng.standard_normal(n) / np.sqrt(n)
+    d = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+    return U, d(sig), V, d(a), d(b)
+
+
+def _time_update(svdu, torch, args, reps=3, **kw):
+    out = svdu.rank1_update(*args, want_defl=False, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = svdu.rank1_update(*args, want_defl=False, check=False, **kw)
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / reps, out
+
+
+def measure_config_small(svdu, torch, reps=200):
+    """m = n = 256, sigma ~ U[0.1, 10], Haar factors: latency of one update,
+    called eagerly (enqueue + wait each time) and as a captured graph replay
+    (a batch of one problem)."""
+    import numpy as np
+
+    import synth_inputs as S
+    P = S.make_problem(256, 256, "uniform", seed=1001)
+    d = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+    args = (d(P.U), d(P.sigma), d(P.V), d(P.a), d(P.b))
+    outs = (torch.empty((256, 256), dtype=torch.float64, device="cuda"),
+            torch.empty(256, dtype=torch.float64, device="cuda"),
+            torch.empty((256, 256), dtype=torch.float64, device="cuda"))
+    ws = svdu.new_workspace(svdu.svdu_workspace_bytes(256, 256), "cuda")
+    eager = []
+    for i in range(reps + 10):
+        t0 = time.perf_counter()
+        svdu.rank1_update(*args, out=outs, workspace=ws, want_defl=False, check=False)
+        torch.cuda.synchronize()
+        if i >= 10:
+            eager.append(1e3 * (time.perf_counter() - t0))
+    b = svdu.Batch([args])
+    b.launch(use_graph=True)
+    torch.cuda.synchronize()
+    graph = []
+    for i in range(reps + 10):
+        t0 = time.perf_counter()
+        b.launch(use_graph=True)
+        torch.cuda.synchronize()
+        if i >= 10:
+            graph.append(1e3 * (time.perf_counter() - t0))
+    b.close()
+    pct = lambda v, q: float(np.percentile(np.asarray(v), q))
+    return {"workload": "m=n=256, sigma~U[0.1,10], haar U,V, a,b~N(0,1/n), fp64 direct",
+            "eager_ms": {"p50": pct(eager, 50), "p99": pct(eager, 99)},
+            "graph_ms": {"p50": pct(graph, 50), "p99": pct(graph, 99)},
+            "graph_updates_per_s": 1e3 / pct(graph, 50)}
+
+
+def measure_config_4096(svdu, torch):
+    """m = n = 4096 geometric spectrum sigma_i = 10^(-6 i / m): direct vs FMM at
+    eps = 1e-10; and the variant with 32 close pairs (relative spacing 1e-11)
+    and 5 % of a's projected components zeroed, in both readings (p zeroed
+    alone; p and q zeroed at the same indices)."""
+    import synth_inputs as S
+    res = {}
+    U, sig, V, a, b = haar_inputs(torch, S, 4096, 4096, 4096, "geometric")
+    cases = [("geometric", (U, sig, V, a, b))]
+    Uh, Vh = U.cpu().numpy(), V.cpu().numpy()
+    d = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda")
+    for name, zq in (("clustered_zero_p", False), ("clustered_zero_p_and_q", True)):
+        P = S.make_problem(4096, 4096, "clustered", seed=4097, zero_frac=0.05, zero_q=zq, U=Uh, V=Vh)
+        cases.append((name, (U, d(P.sigma), V, d(P.a), d(P.b))))
+    for name, args in cases:
+        md, od = _time_update(svdu, torch, args)
+        mf, of = _time_update(svdu, torch, args, path=svdu.SVDU_PATH_FMM, eps=1e-10)
+        r, ou, ov = _recon_orth(torch, *args, *of[:3])
+        res[name] = {"direct_ms": md, "fmm_ms": mf, "fmm_speedup": md / mf,
+                     "fmm_vs_direct_max_abs": max((of[0] - od[0]).abs().max().item(),
+                                                  (of[2] - od[2]).abs().max().item()),
+                     "fmm_recon": r, "fmm_orth": max(ou, ov)}
+    return res
+
+
+def measure_config_3a(svdu, torch):
+    """m = 4096, n = 8192, sigma ~ U[1e-3, 1]: the precision forms against the
+    plain FP64 path."""
+    import synth_inputs as S
+    args = haar_inputs(torch, S, 4096, 8192, 3000)
+    res = {}
+    mf, of = _time_update(svdu, torch, args)
+    res["fp64"] = {"ms_per_update": mf}
+    for name, prec, sl in (("int8_slices7", svdu.SVDU_PREC_SLICED_INT8, 7),
+                           ("int8_slices6", svdu.SVDU_PREC_SLICED_INT8, 6),
+                           ("split32", svdu.SVDU_PREC_SPLIT32, 7)):
+        ctx = svdu.Context()
+        ctx.set_option(svdu.SVDU_OPT_SLICES, sl)
+        ms, o = _time_update(svdu, torch, args, precision=prec, ctx=ctx)
+        ctx.close()
+        r, ou, ov = _recon_orth(torch, *args, *o[:3])
+        res[name] = {"ms_per_update": ms, "speedup_vs_fp64": mf / ms, "recon": r, "orth_U": ou, "orth_V": ov,
+                     "bound": 1e-10, "sigma_bitwise_fp64": bool(torch.equal(o[1], of[1]))}
+    return res
+
+
+def measure_fmm_order_sweep(svdu, torch, sizes=((4096, "geometric"), (8192, "uniform01"))):
+    """FMM error against the direct product as the expansion order p runs from
+    8 to 16 (eps = 1.5 * 5^-p, so that ceil(log_5(1/eps)) = p): the largest
+    difference of U^ and V^ from the direct path's, and the time per update.
+    The Chebyshev far field converges like (3 + sqrt(8))^-p."""
+    import synth_inputs as S
+    res = {}
+    for N, kind in sizes:
+        args = haar_inputs(torch, S, N, N, 5000 + N, kind)
+        md, od = _time_update(svdu, torch, args, reps=1)
+        rows = []
+        for p in range(8, 17):
+            eps = 1.5 * 5.0 ** (-p)
+            mf, of = _time_update(svdu, torch, args, reps=1, path=svdu.SVDU_PATH_FMM, eps=eps)
+            err = max((of[0] - od[0]).abs().max().item(), (of[2] - od[2]).abs().max().item())
+            rows.append({"p": p, "eps": eps, "max_abs_diff_vs_direct": err, "ms": mf,
+                         "rate_bound": (3.0 + 8.0 ** 0.5) ** (-p)})
+        res[f"n{N}_{kind}"] = {"direct_ms": md, "orders": rows}
     return res
 
 
@@ -250,9 +420,10 @@ def measure_serving(svdu, torch, arrival_s=4.0, rate=2000.0, workers=3, sustain_
     stated rate for `arrival_s` seconds (the offered load far exceeds the
     device, so the backlog grows; requests still queued when arrivals end are
     dropped), then at 70 % of the throughput measured there, drained, so that
-    latency is interpretable. Factors: one Haar pair per size, copied into every
-    matrix of that size; sigma ~ U[0.1, 10] descending; a, b ~ N(0, 1/n) from a
-    pool of 16 pairs per size."""
+    latency is interpretable. Factors: one Haar pair per size; every matrix of
+    that size gets its own orthogonal factors from it by a random permutation
+    of rows and of columns and random column signs; sigma ~ U[0.1, 10]
+    descending; a, b ~ N(0, 1/n) from a pool of 16 pairs per size."""
     import numpy as np
 
     import synth_inputs as S
@@ -264,9 +435,17 @@ def measure_serving(svdu, torch, arrival_s=4.0, rate=2000.0, workers=3, sustain_
                  torch.as_tensor(rng.standard_normal(n) / np.sqrt(n), device="cuda")) for _ in range(16)]
             for n in haar}
     factors = []
+
+    def scrambled(Q):
+        n = Q.shape[0]
+        pr = torch.as_tensor(rng.permutation(n), device="cuda")
+        pc = torch.as_tensor(rng.permutation(n), device="cuda")
+        sg = torch.as_tensor(rng.choice([-1.0, 1.0], n), device="cuda")
+        return (Q[pr][:, pc] * sg[None, :]).contiguous()
+
     for n in sizes:
         sig = torch.as_tensor(np.sort(rng.uniform(0.1, 10.0, n))[::-1].copy(), device="cuda")
-        factors.append((haar[n][0].clone(), sig, haar[n][1].clone()))
+        factors.append((scrambled(haar[n][0]), sig, scrambled(haar[n][1])))
     resident = sum(2 * (2 * n * n + n) * 8 for n in sizes)
 
     def run(rate_, span, drain, fmm_min_n=0):
@@ -344,6 +523,11 @@ def main():
                     help="product path of the timed steps (the metric is the direct path; fmm is for profiling)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving form")
+    ap.add_argument("--serving-window", type=float, default=50.0,
+                    help="seconds of arrivals at the stated rate (50 s: the 100k-request stream at 2000/s)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (m=n=256 latency, m=n=4096 direct vs FMM, m=4096 n=8192 "
+                         "precision forms, FMM order sweep)")
     ap.add_argument("--serving-only", action="store_true", help="measure only the serving form")
     ap.add_argument("--batch-reps", type=int, default=5, help="timed launches of the batched workload")
     ap.add_argument("--batched-only", action="store_true",
@@ -383,7 +567,7 @@ def main():
         return
 
     if args.serving_only:
-        print(json.dumps(measure_serving(svdu, torch)))
+        print(json.dumps(measure_serving(svdu, torch, arrival_s=args.serving_window)))
         return
     if args.batched_only:
         table = [int(x) for x in args.tile_table.split(",")] if args.tile_table else None
@@ -489,19 +673,31 @@ def main():
         },
     }
     if not args.no_forms:
-        out["forms"] = measure_forms(svdu, torch, U, sigma, V, A_vecs, B_vecs, Uo, so, Vo, ws, stream,
+        print("[bench] precision forms and FMM at the benchmark size ...", file=sys.stderr, flush=True)
+        out["forms"] = measure_forms(svdu, torch, U, sigma, V, A_vecs, B_vecs, Uo, so, Vo, stream,
                                      fp64_ms=1e3 * (t1 - t0) / K, check=not args.no_check)
-        del ws, Uo, Vo
+    del ws
+    base_inputs = (U, sigma, V, A_vecs[W], B_vecs[W])
+    if not args.no_configs:
+        cf = out.setdefault("configs", {})
+        print("[bench] m=n=256 latency ...", file=sys.stderr, flush=True)
+        cf["m256_latency"] = measure_config_small(svdu, torch)
+        print("[bench] m=n=4096 direct vs FMM ...", file=sys.stderr, flush=True)
+        cf["m4096_direct_vs_fmm"] = measure_config_4096(svdu, torch)
+        print("[bench] m=4096 n=8192 precision forms ...", file=sys.stderr, flush=True)
+        cf["m4096_n8192_precision"] = measure_config_3a(svdu, torch)
+        print("[bench] FMM order sweep ...", file=sys.stderr, flush=True)
+        cf["fmm_order_sweep"] = measure_fmm_order_sweep(svdu, torch)
     if not args.no_serving:
         print("[bench] serving form ...", file=sys.stderr, flush=True)
-        out.setdefault("forms", {})["serving"] = measure_serving(svdu, torch)
+        out.setdefault("forms", {})["serving"] = measure_serving(svdu, torch, arrival_s=args.serving_window)
     if not args.no_batched:
         print("[bench] batched form ...", file=sys.stderr, flush=True)
         out.setdefault("forms", {})["batched_512"] = measure_batched(svdu, torch, reps=args.batch_reps,
                                                                      check=not args.no_check)
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline()
+        print("[bench] cpu baseline (one oracle update) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(*base_inputs)
     print(json.dumps(out))
 
 
