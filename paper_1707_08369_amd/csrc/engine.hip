@@ -482,12 +482,13 @@ void build_plan(const std::vector<Update>& ups_in, int precision, const Options&
         const int ldx = lev == 0 ? (side == 0 ? u.ldu : u.ldv) : N;
         double* Xo = lev == 0 ? (side == 0 ? L.TL : L.TR) : (side == 0 ? u.U_out : u.V_out);
         const int ldo = lev == 0 ? N : (side == 0 ? u.ldu_out : u.ldv_out);
-        const CauchyDesc d = desc_of(L.st[2 * side + lev], (lev == 1 && side == 1) ? L.signs : nullptr);
+        CauchyDesc d = desc_of(L.st[2 * side + lev], (lev == 1 && side == 1) ? L.signs : nullptr);
+        if (side == 1 && u.n > u.m) d = with_members(d, L.st[2 * side + lev]);
         const int KB = i8_pad(N, kI8K) / kI8K, Rp = i8_pad(N, kI8BM), Cp = i8_pad(N, kI8BN);
         xs.push_back(SliceXJob{N, N, ldx, KB, Rp / 16, X, L.i8A[side], L.i8ea[side], L.status});
         cs.push_back(SliceCJob{d, KB, Cp / 16, L.i8B[side], L.i8eb[side]});
         gs.push_back(I8Job{N, N, ldo, KB, Rp / kI8BM, Cp / kI8BN, (Rp / kI8BM) * (Cp / kI8BN), L.i8A[side],
-                           L.i8B[side], L.i8ea[side], L.i8eb[side], Xo, d.colscale, L.status});
+                           L.i8B[side], L.i8ea[side], L.i8eb[side], Xo, X, ldx, d});
       }
     }
     std::vector<int> bx, bc, bg;

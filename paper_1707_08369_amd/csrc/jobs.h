@@ -159,7 +159,9 @@ struct SliceCJob {
   int8_t* B;
   int* eb;                      // per padded column
 };
-// X_out = X C~ from the slices, in tiles of kI8BM x kI8BN.
+// X_out = X C~ from the slices, in tiles of kI8BM x kI8BN. Column tiles made
+// only of deflated columns (the zero block of a rectangular problem) are
+// written from the FP64 X by the copy path instead (copy_path.h).
 struct I8Job {
   int R, N, ldo, KB, tiles_m, tiles_n, tiles;
   const int8_t* A;
@@ -167,8 +169,9 @@ struct I8Job {
   const int* ea;
   const int* eb;
   double* Xo;
-  const double* colscale;       // optional per-column sign
-  const int* status;
+  const double* X;              // the FP64 X, for the copy path
+  int ldx;
+  CauchyDesc d;                 // C~ (colscale: optional per-column sign; members when n > m)
 };
 
 struct SliceXList {

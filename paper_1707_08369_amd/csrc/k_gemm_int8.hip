@@ -40,6 +40,7 @@
 #include <stdint.h>
 
 #include "cauchy_tile.h"
+#include "copy_path.h"
 #include "jobs.h"
 
 namespace svdu {
@@ -239,10 +240,26 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_kernel(I8List L) {
   __shared__ v4i Bs[2][4 * TILE];
   const int jb = find_job(L.boff, L.n, blockIdx.x);
   const I8Job J = L.job[jb];
-  if (*J.status & kStFatal) return;
+  if (*J.d.status & kStFatal) return;
   int tm, tn;
   i8_tile_order(blockIdx.x - L.boff[jb], J.tiles_m, J.tiles_n, &tm, &tn);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  {
+    // a column tile of deflated columns only: copies and one reflection from
+    // the FP64 X, as in the FP64 product (the LDS buffers hold the members)
+    const ColDesc cc[1] = {load_col_tile(J.d, tn * kI8BN + lane)};
+    int cl[1];
+    const unsigned cp = copy_chunks<1>(J.d, tn * kI8BN, cc, cl);
+    if (cp) {
+      constexpr int SM = 2048;   // members staged per pass
+      static_assert(SM * 12 + kI8BM * 8 <= (int)sizeof(Bs), "copy-path staging fits the LDS buffers");
+      double* rhs = reinterpret_cast<double*>(&Bs[0][0]);
+      int* js = reinterpret_cast<int*>(rhs + SM);
+      double* dots = reinterpret_cast<double*>(js + SM);
+      copy_path<kI8BM, 256, 1, SM>(J, tm * kI8BM, tn * kI8BN, cc, cl, cp, rhs, js, dots);
+      return;
+    }
+  }
   const int KB = J.KB;
   const v4i* A = reinterpret_cast<const v4i*>(J.A);
   const v4i* B = reinterpret_cast<const v4i*>(J.B);
@@ -315,7 +332,7 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_kernel(I8List L) {
     const int col = colx + 16 * c;
     if (col >= J.N) continue;
     const int ec = gld(J.eb + col) - 12;
-    const double sc = J.colscale ? gld(J.colscale + col) : 1.0;
+    const double sc = J.d.colscale ? gld(J.d.colscale + col) : 1.0;
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
