@@ -344,7 +344,7 @@ def batched_workload(torch, count=512, seed=4):
 
 
 def measure_batched(svdu, torch, reps=5, check=True,
-                    modes=("fp64_graph", "fp64_graph_persistent", "fp64_eager", "split32_graph"),
+                    modes=("fp64_graph", "fp64_graph_persistent", "fp64_eager", "int8_graph", "split32_graph"),
                     table=None, one_by_one=True):
     """The batched form: the 512-problem workload as one batch, launched as one
     captured graph (or eagerly), against the same problems updated one call at
@@ -360,13 +360,14 @@ def measure_batched(svdu, torch, reps=5, check=True,
         svdu.tile_table(svdu.SVDU_PREC_FP64, table)
         tuned["fp64"] = {"table": table, "ms": None}
     else:
-        for prec in (svdu.SVDU_PREC_FP64, svdu.SVDU_PREC_SPLIT32):
+        for prec in (svdu.SVDU_PREC_FP64, svdu.SVDU_PREC_SPLIT32):   # the INT8 product has one tile shape
             tab, times = svdu.autotune(prec, max_n=2048)
             tuned["fp64" if prec == 0 else "split32"] = {"table": tab, "ms": [[round(t, 4) for t in row]
                                                                              for row in times[:6]]}
     res["autotune"] = tuned
     for mode in modes:
-        prec = svdu.SVDU_PREC_SPLIT32 if mode.startswith("split32") else svdu.SVDU_PREC_FP64
+        prec = (svdu.SVDU_PREC_SPLIT32 if mode.startswith("split32") else
+                svdu.SVDU_PREC_SLICED_INT8 if mode.startswith("int8") else svdu.SVDU_PREC_FP64)
         b = svdu.Batch(items, precision=prec, persistent="persistent" in mode)
         graph = "graph" in mode
         b.launch(use_graph=graph)                 # warm-up (and capture)
@@ -383,7 +384,7 @@ def measure_batched(svdu, torch, reps=5, check=True,
         ms = float(np.median(times))
         rec = {"ms_per_batch": ms, "ms_min": float(min(times)), "updates_per_s": count / (ms * 1e-3),
                "product_tflops_effective": flops / (ms * 1e-3) / 1e12, "status_ok": all(c == 0 for c in st)}
-        if check and prec == svdu.SVDU_PREC_FP64:
+        if check and prec != svdu.SVDU_PREC_SPLIT32:
             worst = 0.0
             for it, o in zip(items[:64], b.outs[:64]):
                 U, sg, V, a, bb = it
@@ -408,7 +409,7 @@ def measure_batched(svdu, torch, reps=5, check=True,
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0)
     res["one_call_per_problem"] = {"ms_per_batch": ms, "updates_per_s": count / (ms * 1e-3)}
-    best = min(res[mo]["ms_per_batch"] for mo in modes if not mo.startswith("split32"))
+    best = min(res[mo]["ms_per_batch"] for mo in modes if mo.startswith("fp64"))
     res["speedup_batched_vs_one_call_per_problem"] = ms / best
     return res
 
@@ -521,6 +522,10 @@ def main():
                     help="skip the short measurements of the other forms (precision form) on the same inputs")
     ap.add_argument("--path", choices=("direct", "fmm"), default="direct",
                     help="product path of the timed steps (the metric is the direct path; fmm is for profiling)")
+    ap.add_argument("--precision", choices=("fp64", "int8", "split32"), default="fp64",
+                    help="arithmetic of the products in the timed steps (the metric is fp64; the others are for "
+                         "profiling the precision forms)")
+    ap.add_argument("--slices", type=int, default=7, help="slices of the int8 form in the timed steps")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched form")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving form")
     ap.add_argument("--serving-window", type=float, default=50.0,
@@ -590,14 +595,17 @@ def main():
     so = torch.empty(m, dtype=torch.float64, device=dev)
     Vo = torch.empty((n, n), dtype=torch.float64, device=dev)
     path = svdu.SVDU_PATH_FMM if args.path == "fmm" else svdu.SVDU_PATH_DIRECT
+    prec = {"fp64": svdu.SVDU_PREC_FP64, "int8": svdu.SVDU_PREC_SLICED_INT8,
+            "split32": svdu.SVDU_PREC_SPLIT32}[args.precision]
     if args.tile >= 0:
         svdu.set_option(svdu.SVDU_OPT_TILE_SHAPE, args.tile)
-    ws = svdu.new_workspace(svdu.svdu_workspace_bytes(m, n, path), dev)
+    svdu.set_option(svdu.SVDU_OPT_SLICES, args.slices)
+    ws = svdu.new_workspace(svdu.svdu_workspace_bytes(m, n, path, prec), dev)
     stream = torch.cuda.current_stream()
 
     def step(k, check=False):
-        svdu.rank1_update(U, sigma, V, A_vecs[k], B_vecs[k], eps=1e-10, path=path, out=(Uo, so, Vo), workspace=ws,
-                          want_defl=False, stream=stream, check=check)
+        svdu.rank1_update(U, sigma, V, A_vecs[k], B_vecs[k], eps=1e-10, path=path, precision=prec,
+                          out=(Uo, so, Vo), workspace=ws, want_defl=False, stream=stream, check=check)
 
     for k in range(W):
         step(k, check=(k == 0))
@@ -635,10 +643,11 @@ def main():
     traffic = load_traffic(m, n)
 
     value = K / (t1 - t0)
+    plain = args.path == "direct" and args.precision == "fp64"
     out = {
-        "metric": ("rank-1 SVD updates/s at m=n=8192 (plain FP64 GPU path); p50/p99 update latency"
-                   if args.path == "direct" else
-                   "rank-1 SVD updates/s at m=n=8192 (FP64 GPU path, FMM product); p50/p99 update latency"),
+        "metric": ("rank-1 SVD updates/s at m=n=8192 (plain FP64 GPU path); p50/p99 update latency" if plain else
+                   f"rank-1 SVD updates/s at m=n=8192 ({args.precision} products, {args.path} path; not the metric's "
+                   f"plain FP64 path); p50/p99 update latency"),
         "value": value,
         "unit": "updates/s",
         "n_gpus": 1,
@@ -648,10 +657,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "int8": "i8 slices (exact i32 sums, f64 results)", "split32": "f32x3"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"rank1_svd_update m={m} n={n} sigma~U[1e-3,1] haar U,V a,b~N(0,1/n) "
-                               f"fp64 {args.path} product", "m": m, "n": n, "path": args.path, "precision": "fp64",
+                               f"{args.precision} {args.path} product", "m": m, "n": n, "path": args.path,
+                   "precision": args.precision,
                    "seed": args.seed},
         "latency_ms": {"p50": float(np.percentile(per_update, 50)), "p99": float(np.percentile(per_update, 99)),
                        "mean": float(per_update.mean())},
@@ -660,7 +670,7 @@ def main():
         "recon_last": recon,
         # the product-phase times of the FMM path cover a dozen kernels, so the
         # GEMM roofline below only describes the direct path
-        "roofline": None if args.path != "direct" else {
+        "roofline": None if not plain else {
             "bound": "mfma",
             "kernel": "gemm_cauchy_f64_kernel<2, 2, 2, 8> (256x128 tiles on 8 waves, 32-k LDS stages)",
             "achieved": achieved,

@@ -383,7 +383,11 @@ def test_bitwise_deterministic_and_stream_ordered(lib):
 # vectors within the FP32-accumulation error
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("m,n,kind", [(256, 256, "uniform"), (300, 457, "uniform"), (512, 512, "geometric")])
-def test_precision_form_keeps_roots_and_reports_its_error(lib, m, n, kind):
+def test_split32_negative_result_keeps_roots_and_reports_its_error(lib, m, n, kind):
+    """The split-FP32 form, kept as a measured negative result: it cannot meet
+    the precision form's 1e-10 bound (its FP32 accumulation floors at about
+    1e-7), so this checks what it delivers. The precision form that meets the
+    bound, the exact-slice INT8 form, is tested at 1e-10 in test_gpu_int8.py."""
     P = S.make_problem(m, n, kind, seed=4)
     args = (dev(P.U), dev(P.sigma), dev(P.V), dev(P.a), dev(P.b))
     U64_, s64, V64, f64 = lib.rank1_update(*args)
