@@ -324,6 +324,51 @@ def measure_fmm_order_sweep(svdu, torch, sizes=((4096, "geometric"), (8192, "uni
     return res
 
 
+def measure_secular_far_field(svdu, torch, reps=20):
+    """The secular solve alone (poles sigma^2, sigma ~ U[1e-3, 1]; z ~ N(0, 1/K);
+    rho = 2.6) with the direct sums and with the far field from per-leaf
+    interpolants (SVDU_OPT_SECULAR_FMM 0 and 2), and the m = n = 8192 update on
+    both product paths with the direct sums and with the default (the far field
+    at this order)."""
+    import numpy as np
+
+    import synth_inputs as S
+    ctxs = {}
+    for name, mode in (("direct_sums", 0), ("far_field", 2)):
+        ctxs[name] = svdu.Context()
+        ctxs[name].set_option(svdu.SVDU_OPT_SECULAR_FMM, mode)
+    res = {"workload": "secular roots: d = sigma^2, sigma~U[1e-3,1], z~N(0,1/K), rho=2.6; updates m=n=8192"}
+    for K in (1024, 4096, 8192):
+        rng = np.random.default_rng(K)
+        d = torch.as_tensor(np.sort(rng.uniform(1e-3, 1.0, K) ** 2), device="cuda")
+        z = torch.as_tensor(rng.standard_normal(K) / np.sqrt(K), device="cuda")
+        row = {}
+        for name, ctx in ctxs.items():
+            for _ in range(3):
+                svdu.secular(d, z, 2.6, ctx=ctx, check=False)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                svdu.secular(d, z, 2.6, ctx=ctx, check=False)
+            e1.record()
+            torch.cuda.synchronize()
+            _, _, its = svdu.secular(d, z, 2.6, ctx=ctx)
+            row[name] = {"ms": e0.elapsed_time(e1) / reps, "mean_iterations": float(its.float().mean())}
+        res[f"secular_K{K}"] = row
+    args = haar_inputs(torch, S, 8192, 8192, 8192)
+    for path, pname in ((svdu.SVDU_PATH_FMM, "fmm"), (svdu.SVDU_PATH_DIRECT, "direct")):
+        md, od = _time_update(svdu, torch, args, reps=3, path=path, eps=1e-10, ctx=ctxs["direct_sums"])
+        mf, of = _time_update(svdu, torch, args, reps=3, path=path, eps=1e-10)
+        res[f"update_8192_{pname}_path"] = {
+            "direct_sums_ms": md, "far_field_ms": mf,
+            "sigma_max_abs_diff": (of[1] - od[1]).abs().max().item(),
+            "vectors_max_abs_diff": max((of[0] - od[0]).abs().max().item(), (of[2] - od[2]).abs().max().item())}
+        del od, of
+    for c in ctxs.values():
+        c.close()
+    return res
+
+
 def batched_workload(torch, count=512, seed=4):
     """512 independent problems: m log-uniform in [64, 1024], n = m + U{0..m},
     sigma ~ U[0.01, 10] descending, Haar U and V, a, b ~ N(0, 1/n)."""
@@ -421,7 +466,8 @@ def measure_serving(svdu, torch, arrival_s=4.0, rate=2000.0, workers=3, sustain_
     stated rate for `arrival_s` seconds (the offered load far exceeds the
     device, so the backlog grows; requests still queued when arrivals end are
     dropped), then at 70 % of the throughput measured there, drained, so that
-    latency is interpretable. Factors: one Haar pair per size; every matrix of
+    latency is interpretable; both again with requests for orders >= 4096 on
+    the FMM path. Factors: one Haar pair per size; every matrix of
     that size gets its own orthogonal factors from it by a random permutation
     of rows and of columns and random column signs; sigma ~ U[0.1, 10]
     descending; a, b ~ N(0, 1/n) from a pool of 16 pairs per size."""
@@ -502,6 +548,8 @@ def measure_serving(svdu, torch, arrival_s=4.0, rate=2000.0, workers=3, sustain_
     sus = 0.7 * res["stated_rate"]["updates_per_s"]
     res["sustainable_rate"] = run(sus, sustain_s, drain=True)
     res["stated_rate_fmm_n_ge_4096"] = run(rate, arrival_s, drain=False, fmm_min_n=4096)
+    sus_f = 0.7 * res["stated_rate_fmm_n_ge_4096"]["updates_per_s"]
+    res["sustainable_rate_fmm_n_ge_4096"] = run(sus_f, sustain_s, drain=True, fmm_min_n=4096)
     return res
 
 
@@ -532,7 +580,7 @@ def main():
                     help="seconds of arrivals at the stated rate (50 s: the 100k-request stream at 2000/s)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other workloads (m=n=256 latency, m=n=4096 direct vs FMM, m=4096 n=8192 "
-                         "precision forms, FMM order sweep)")
+                         "precision forms, FMM order sweep, secular far field)")
     ap.add_argument("--serving-only", action="store_true", help="measure only the serving form")
     ap.add_argument("--batch-reps", type=int, default=5, help="timed launches of the batched workload")
     ap.add_argument("--batched-only", action="store_true",
@@ -698,6 +746,8 @@ def main():
         cf["m4096_n8192_precision"] = measure_config_3a(svdu, torch)
         print("[bench] FMM order sweep ...", file=sys.stderr, flush=True)
         cf["fmm_order_sweep"] = measure_fmm_order_sweep(svdu, torch)
+        print("[bench] secular sums: direct vs far field ...", file=sys.stderr, flush=True)
+        cf["secular_far_field"] = measure_secular_far_field(svdu, torch)
     if not args.no_serving:
         print("[bench] serving form ...", file=sys.stderr, flush=True)
         out.setdefault("forms", {})["serving"] = measure_serving(svdu, torch, arrival_s=args.serving_window)

@@ -74,6 +74,16 @@ extern "C" {
 #define SVDU_OPT_PERSISTENT 4    /* 1: products of svdu_rank1_update and svdu_rank1_update_batched use the
                                     persistent schedule (see SVDU_BATCH_PERSISTENT); default 0 */
 #define SVDU_OPT_SLICES 6        /* slices S of SVDU_PREC_SLICED_INT8: 6, 7 (default) or 8 */
+#define SVDU_OPT_SECULAR_FMM 7   /* 1 (default): for eigenproblems of order above 2048 the secular sums
+                                    (Section 3.1) take their far field from Chebyshev interpolants sampled
+                                    once per eigen-update, for each leaf of 64 consecutive poles (32
+                                    points; a pole is far from a leaf when its distance is at least the
+                                    leaf's width); near poles and the extreme root beyond the last pole
+                                    take the direct sums. Every iterate then costs O(leaf + p) instead of
+                                    O(K). Roots agree with the direct sums to rounding. Orders up to 2048
+                                    take the direct sums. 0: direct sums for every order. 2: the far field
+                                    at every order (for tests; slower below 2048). Other values:
+                                    SVDU_EINVAL. */
 #define SVDU_OPT_REFINE 5        /* 1 (default): FP64 results get the close-cluster refinement (not in the
                                     paper): for consecutive sigma^ with relative gaps <= 1e-6, in clusters
                                     of up to 8 and up to min(m, 128) columns in all, the block

@@ -35,6 +35,7 @@ SVDU_OPT_TILE_SHAPE = 3
 SVDU_OPT_PERSISTENT = 4
 SVDU_OPT_REFINE = 5
 SVDU_OPT_SLICES = 6
+SVDU_OPT_SECULAR_FMM = 7
 SVDU_TILE_128x128 = 0
 SVDU_TILE_64x128 = 1
 SVDU_TILE_128x64 = 2

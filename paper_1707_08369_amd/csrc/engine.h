@@ -31,6 +31,8 @@ void default_shape_table(int (&t)[kNumPrec][kShapeBuckets]);
 
 struct Options {
   int maxit = 200;                          // secular iteration cap
+  int secular_ff = 1;                       // SVDU_OPT_SECULAR_FMM: 0 direct sums, 1 far field above
+                                            // order 2048, 2 far field at every order
   bool refine = true;                       // close-cluster refinement of FP64 results
   bool persistent = false;                  // persistent product schedule
   int forced_shape = -1;                    // -1: the table
@@ -201,6 +203,7 @@ void write_blob(const std::vector<char>& blob, char* dst, hipStream_t st);
 enum : int { kStepAll = 0, kStepUpToRoots = 1, kStepProductsOnward = 2 };
 struct Sched {
   int maxit = 200;
+  int secular_ff = 1;
   bool persistent = false;
   bool refine = true;
   int grid_cap[kNumPrec][kNumShapes] = {};   // [precision][shape]

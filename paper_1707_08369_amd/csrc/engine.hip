@@ -306,7 +306,7 @@ StageLevel build_level(const std::vector<Stage>& st_in, const std::vector<TmvJob
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return st_in[x].N > st_in[y].N; });
   std::vector<Stage> st;
   std::vector<TmvJob> tv;
-  std::vector<int> bw, bt, bs, bq;
+  std::vector<int> bw, bt, bs, bq, bl;
   for (int i : order) {
     st.push_back(st_in[i]);
     tv.push_back(i < (int)tv_in.size() ? tv_in[i] : TmvJob{0, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}});
@@ -314,8 +314,9 @@ StageLevel build_level(const std::vector<Stage>& st_in, const std::vector<TmvJob
     bt.push_back(cdiv(st_in[i].N, 256));
     bs.push_back(st_in[i].N <= kGroupMaxN ? cdiv(st_in[i].N, 256 / kSmallGroup) : cdiv(st_in[i].N, 4));
     bq.push_back(cdiv(bs.back(), 4));
+    bl.push_back(cdiv(st_in[i].N, kSfLeaf) + 1);   // leaves, then the extreme root
   }
-  const std::vector<int> ow = prefix(bw), ot = prefix(bt), os = prefix(bs), oq = prefix(bq);
+  const std::vector<int> ow = prefix(bw), ot = prefix(bt), os = prefix(bs), oq = prefix(bq), ol = prefix(bl);
   StageLevel S;
   S.n = (int)st.size();
   S.st = B.put(st);
@@ -324,10 +325,12 @@ StageLevel build_level(const std::vector<Stage>& st_in, const std::vector<TmvJob
   S.boff_t = B.put(ot);
   S.boff_i = B.put(os);
   S.boff_s = B.put(oq);
+  S.boff_l = B.put(ol);
   S.blocks_w = ow.back();
   S.blocks_t = ot.back();
   S.blocks_i = os.back();
   S.blocks_s = oq.back();
+  S.blocks_l = ol.back();
   for (const Stage& x : st) S.nmax = std::max(S.nmax, x.N);
   return S;
 }
@@ -634,7 +637,7 @@ void enqueue_plan(const Plan& P, const Sched& S, int part, hipStream_t st) {
     S.mark(1, st);
     if (P.prob.n > 0) hipLaunchKernelGGL(prob_setup_kernel, dim3(P.prob.n), dim3(1024), 0, st, P.prob);
     for (int lev = 0; lev < 2; ++lev) {
-      launch_stage_level(P.lev[lev], S.maxit, st);
+      launch_stage_level(P.lev[lev], S.maxit, S.secular_ff, st);
       launch_cauchy_tmatvec_level(P.lev[lev], st);
     }
     if (P.prob.blocks_n > 0)
@@ -759,6 +762,7 @@ int TimingRing::read(double* ms, int max_calls) {
 Sched sched_of(svdu_ctx* ctx, const Options& o, bool persistent, bool timed) {
   Sched S;
   S.maxit = o.maxit;
+  S.secular_ff = o.secular_ff;
   S.refine = o.refine;
   S.persistent = persistent;
   if (ctx && persistent && !ctx->have_caps) {

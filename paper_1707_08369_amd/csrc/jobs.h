@@ -44,6 +44,8 @@ struct TmvJob {
 // the same arithmetic alone and in a batch.
 constexpr int kGroupMaxN = 2048;
 constexpr int kSmallGroup = 16;
+// Poles per leaf of the far-field form of the secular solve (one block per leaf).
+constexpr int kSfLeaf = 64;
 
 struct StageLevel {
   int n = 0;
@@ -53,7 +55,8 @@ struct StageLevel {
   const int* boff_t = nullptr;   // ceil(N / 256) blocks per job
   const int* boff_i = nullptr;   // item kernels: ceil(N / (256 / kSmallGroup)) if N <= kGroupMaxN, else ceil(N / 4)
   const int* boff_s = nullptr;   // secular kernel: ceil(item blocks / 4) blocks of 1024 threads per job
-  int blocks_w = 0, blocks_t = 0, blocks_i = 0, blocks_s = 0;
+  const int* boff_l = nullptr;   // far-field secular kernel: ceil(N / kSfLeaf) + 1 blocks per job
+  int blocks_w = 0, blocks_t = 0, blocks_i = 0, blocks_s = 0, blocks_l = 0;
   int nmax = 0;                  // largest order of the level (host side)
 };
 
@@ -204,9 +207,12 @@ int gemv_chunks(int R);
 size_t gemv_t_scratch_elems(int R, int N, int nv);
 // Deflation, secular roots, Loewner weights, column norms, descriptors of
 // every eigen-update of a level.
-void launch_stage_level(const StageLevel& L, int maxit, hipStream_t st);
+// far_field (SVDU_OPT_SECULAR_FMM): 0 the secular roots from the direct sums;
+// 1 with the far field from per-leaf interpolants for orders above
+// kGroupMaxN; 2 with it at every order.
+void launch_stage_level(const StageLevel& L, int maxit, int far_field, hipStream_t st);
 // The secular solve alone (svdu_secular).
-void launch_secular_level(const StageLevel& L, int maxit, hipStream_t st);
+void launch_secular_level(const StageLevel& L, int maxit, int far_field, hipStream_t st);
 // y = C~^T x for the TmvJobs of a level.
 void launch_cauchy_tmatvec_level(const StageLevel& L, hipStream_t st);
 // X_out = X C~ for every job of the list, in tile shape `shape` (TileShape),

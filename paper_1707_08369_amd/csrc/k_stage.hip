@@ -313,6 +313,93 @@ __device__ inline SecSums secular_sums_t(const Reflect<LDS>& R, double sc, int i
   return SecSums{group_sum<G>(psi), group_sum<G>(dpsi), group_sum<G>(phi), group_sum<G>(dphi)};
 }
 
+// ---------------------------------------------------------------------------
+// Secular sums with the far field from Chebyshev interpolants (the option
+// SVDU_OPT_SECULAR_FMM). Section 3.1 of the paper rules the FMM out for the
+// secular equation because the evaluation points (the iterates) are not known
+// in advance; they are, however, known to stay in the gap of their root, and
+// the sources (poles and weights) are fixed. So the far field is sampled
+// once per eigen-update around the gaps, in the spirit of the fast multipole
+// method, and every iterate evaluates it in O(p):
+//  * the poles of the (reflected) problem fall into leaves of kSfLeaf
+//    consecutive poles. Leaf l's interval T runs from its first pole to the
+//    first pole of the next leaf (the last leaf: to the last pole), so every
+//    root of the leaf lies in T, except the extreme root beyond the last pole.
+//    That one is solved with the direct sums (its interval, up to
+//    d_{K-1} + rho sum w, can be wider than all the poles together);
+//  * a pole at distance >= |T| from T is far. Far poles left of T are all
+//    below every root of the leaf (they enter psi), far poles right of it all
+//    above (they enter phi). Each of psi, psi', phi, phi' over the far poles
+//    is analytic around T with its nearest singularity |T| away, so its
+//    interpolant at kSfP Chebyshev points of T converges like (3 + sqrt 8)^-p;
+//    it is evaluated in the barycentric form from the node values, which
+//    keeps its rounding at a few units (the coefficient form loses about p);
+//  * the near poles form one contiguous range [kl, kr] (the leaf and its
+//    neighbours within |T|), summed directly with the pole-relative
+//    differences of the direct form.
+// Nodes and evaluation points are formed as offsets from the leaf's first
+// pole, so a leaf far from the origin keeps its relative resolution.
+// ---------------------------------------------------------------------------
+constexpr int kSfP = 32;      // Chebyshev points of the far-field interpolants (kSfLeaf poles per leaf)
+
+struct SfLeaf {
+  double h, hinv;       // half-width of T and its reciprocal
+  int k0, kl, kr;       // first pole of the leaf; near range [kl, kr]
+  double t[kSfP];       // Chebyshev points of the first kind on [-1, 1]
+  double lam[kSfP];     // their barycentric weights (-1)^q sin((2q + 1) pi / 2p)
+  double f[4][kSfP];    // psi, psi', phi, phi' of the far poles at the points
+};
+
+// Sums at x = po + tau as secular_sums_t, with the poles outside [kl, kr]
+// taken from the leaf's interpolants: lane `sub` of the group adds points sub
+// and sub + 16 to the barycentric numerators and denominator.
+template <bool REFL, bool SC, int G, bool LDS>
+__device__ inline SecSums secular_sums_ff(const Reflect<LDS>& R, double sc, int i, double po, double tau, int sub,
+                                          const SfLeaf& f, double plo) {
+  static_assert(G == 16 && kSfP == 2 * G, "two interpolation points per lane");
+  double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+  bool tiny = false;
+  secular_range<REFL, SC, false, G, LDS>(R, sc, f.kl + sub, i + 1, po, tau, &psi, &dpsi, &tiny);
+  secular_range<REFL, SC, false, G, LDS>(R, sc, i + 1 + sub, f.kr + 1, po, tau, &phi, &dphi, &tiny);
+  if (group_any<G>(tiny)) {
+    psi = dpsi = phi = dphi = 0.0;
+    secular_range<REFL, SC, true, G, LDS>(R, sc, f.kl + sub, i + 1, po, tau, &psi, &dpsi, &tiny);
+    secular_range<REFL, SC, true, G, LDS>(R, sc, i + 1 + sub, f.kr + 1, po, tau, &phi, &dphi, &tiny);
+  }
+  // the iterate in the coordinate of T, from offsets to the leaf's first pole
+  const double t = (((po - plo) + tau) - f.h) * f.hinv;
+  double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0, den = 0.0;
+  const double dt0 = t - f.t[sub], dt1 = t - f.t[sub + G];
+  // Within 2^-60 of a point (in the coordinate of T, where every far sum
+  // changes by at most half its size per unit) that point's values are the
+  // result to far below rounding, and the quotient below could overflow.
+  const bool hit0 = fabs(dt0) < 0x1p-60, hit1 = fabs(dt1) < 0x1p-60;
+  if (group_any<G>(hit0 || hit1)) {
+    const int q = hit0 ? sub : sub + G;
+    const bool h = hit0 || hit1;
+    n0 = h ? f.f[0][q] : 0.0;
+    n1 = h ? f.f[1][q] : 0.0;
+    n2 = h ? f.f[2][q] : 0.0;
+    n3 = h ? f.f[3][q] : 0.0;
+    den = h ? 1.0 : 0.0;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int q = sub + e * G;
+      const double r = f.lam[q] * recip_fast(e == 0 ? dt0 : dt1);
+      n0 = __builtin_fma(r, f.f[0][q], n0);
+      n1 = __builtin_fma(r, f.f[1][q], n1);
+      n2 = __builtin_fma(r, f.f[2][q], n2);
+      n3 = __builtin_fma(r, f.f[3][q], n3);
+      den += r;
+    }
+  }
+  den = group_sum<G>(den);
+  const double dinv = 1.0 / den;
+  return SecSums{group_sum<G>(psi) + group_sum<G>(n0) * dinv, group_sum<G>(dpsi) + group_sum<G>(n1) * dinv,
+                 group_sum<G>(phi) + group_sum<G>(n2) * dinv, group_sum<G>(dphi) + group_sum<G>(n3) * dinv};
+}
+
 // A power of two near |x| (x finite and nonzero), else 1. Lengths divided by it
 // and derivatives multiplied by it scale exactly, so the quadratics below keep
 // their coefficients at the scale of the secular function itself: without it
@@ -321,6 +408,17 @@ __device__ inline SecSums secular_sums_t(const Reflect<LDS>& R, double sc, int i
 __device__ inline double length_unit(double x) {
   if (!(x != 0.0) || !isfinite(x)) return 1.0;
   return ldexp(1.0, ilogb(x));
+}
+
+// The unit S of the secular iteration: a power of two near the largest |pole|
+// when that lies outside [2^-500, 2^500], else 1. Poles and weights divided by
+// S (exactly) keep every sum and quadratic away from overflow and underflow;
+// the roots are scaled back at the end.
+template <bool LDS>
+__device__ inline double secular_unit(const Reflect<LDS>& R) {
+  const double pmax = fmax(fabs(R.ld(R.g)), fabs(R.ld(R.g + R.K - 1)));   // the poles ascend
+  const bool scaled = pmax != 0.0 && (pmax < 0x1p-500 || pmax > 0x1p500);
+  return scaled ? fmax(length_unit(pmax), 0x1p-1000) : 1.0;
 }
 
 // Root of c x^2 - a x + b = 0 inside (lo, hi); returns false when none is.
@@ -352,11 +450,12 @@ __device__ inline bool quad_root_in(double c, double a, double b, double lo, dou
 // by bisection. Root `idx` belongs to an aligned group of G lanes of the wave
 // (G = 64: the whole wave), which splits the sums over its lanes; every lane
 // of the group takes the same decisions from the same reduced sums.
-template <int G, bool LDS>
+// FF: the sums take their far field from the leaf `lf` (secular_sums_ff).
+template <int G, bool LDS, bool FF = false>
 __device__ void secular_body(const int* __restrict__ Kdev, const double* __restrict__ g,
                              const double* __restrict__ W2, const double* __restrict__ rhop,
                              int* __restrict__ org, double* __restrict__ tau_out, int* __restrict__ iters,
-                             int* status, int maxit, int idx) {
+                             int* status, int maxit, int idx, const SfLeaf* lf = nullptr) {
   if (*status & kStFatal) return;
   const int K = *Kdev;
   const int sub = threadIdx.x & (G - 1);
@@ -366,22 +465,27 @@ __device__ void secular_body(const int* __restrict__ Kdev, const double* __restr
   const double rho = fabs(rho0);
   const double rinv = 1.0 / rho;
   const int i = R.refl ? K - 1 - idx : idx;  // root index in the reflected problem
-  // Work in units of S, a power of two near the largest |pole|, when that lies
-  // outside [2^-500, 2^500]: poles and weights divided by S (exactly) keep
-  // every sum and quadratic away from overflow and underflow; the roots are
-  // scaled back at the end. In between S = 1 and nothing is rescaled.
-  const double pmax = fmax(fabs(R.ld(g)), fabs(R.ld(g + K - 1)));   // the poles ascend
-  const bool scaled = pmax != 0.0 && (pmax < 0x1p-500 || pmax > 0x1p500);
-  const double S = scaled ? fmax(length_unit(pmax), 0x1p-1000) : 1.0;
+  // work in units of S (secular_unit); in between S = 1 and nothing is rescaled
+  const double S = secular_unit(R);
+  const bool scaled = S != 1.0;
   const double sc = 1.0 / S;
   auto pole = [&](int k) { return R.pole(k) * sc; };
   auto wt = [&](int k) { return R.wt(k) * sc; };
+  const double plo = FF ? pole(lf->k0) : 0.0;
   auto sums = [&](double po, double tau) -> SecSums {
-    if (scaled)
-      return R.refl ? secular_sums_t<true, true, G, LDS>(R, sc, i, po, tau, sub)
-                    : secular_sums_t<false, true, G, LDS>(R, sc, i, po, tau, sub);
-    return R.refl ? secular_sums_t<true, false, G, LDS>(R, sc, i, po, tau, sub)
-                  : secular_sums_t<false, false, G, LDS>(R, sc, i, po, tau, sub);
+    if constexpr (FF) {
+      if (scaled)
+        return R.refl ? secular_sums_ff<true, true, G, LDS>(R, sc, i, po, tau, sub, *lf, plo)
+                      : secular_sums_ff<false, true, G, LDS>(R, sc, i, po, tau, sub, *lf, plo);
+      return R.refl ? secular_sums_ff<true, false, G, LDS>(R, sc, i, po, tau, sub, *lf, plo)
+                    : secular_sums_ff<false, false, G, LDS>(R, sc, i, po, tau, sub, *lf, plo);
+    } else {
+      if (scaled)
+        return R.refl ? secular_sums_t<true, true, G, LDS>(R, sc, i, po, tau, sub)
+                      : secular_sums_t<false, true, G, LDS>(R, sc, i, po, tau, sub);
+      return R.refl ? secular_sums_t<true, false, G, LDS>(R, sc, i, po, tau, sub)
+                    : secular_sums_t<false, false, G, LDS>(R, sc, i, po, tau, sub);
+    }
   };
 
   int o;
@@ -686,6 +790,152 @@ __global__ __launch_bounds__(BT) void secular_kernel(StageLevel L, int maxit) {
   }
 }
 
+// Far-field form of the secular kernel, for levels with an order above
+// kGroupMaxN: one block of kSfThreads per leaf, then one more per job for the
+// extreme root. A leaf's block first builds the
+// leaf's interval, near range and interpolation data (sf_setup), then its
+// kSfThreads / 16 = kSfLeaf groups of 16 lanes solve the leaf's roots with
+// secular_sums_ff. The extreme root's block solves that root with the direct
+// sums on one wave, from an LDS copy of the poles as in the secular kernel.
+constexpr int kSfThreads = 1024;
+static_assert(kSfThreads / 16 == kSfLeaf && kSmallGroup == 16, "one 16-lane group per root of a leaf");
+static_assert(kSfThreads == 32 * kSfP, "one thread per (point, pole stride) pair");
+
+// Interval, near range and interpolation data of leaf k0 of the stage's
+// reflected problem (K live poles, k0 < K - 1), in units of the secular
+// iteration. The poles pass through LDS in chunks of kSfChunk; each is
+// classified on the way (far below T, far above T, or near) and its far terms
+// are added at the 32 points. The poles ascend, so the far poles below T are
+// the first nl and those above it the last nr, and the near range is
+// [nl, K - 1 - nr]. LDS: red 4 * 32 * 33 doubles, sp and sw kSfChunk doubles
+// each, cnt 2 ints.
+constexpr int kSfChunk = 2048;
+constexpr int kSfRed = 4 * 32 * 33;
+
+__device__ void sf_setup(const Stage& s, int K, int k0, SfLeaf* lf, double* red, double* sp, double* sw, int* cnt) {
+  const double rho0 = *s.rho;
+  const Reflect<false> R{s.g, s.W2, K, rho0 < 0.0};
+  const double sc = 1.0 / secular_unit(R);
+  auto pole = [&](int k) { return R.pole(k) * sc; };
+  auto wt = [&](int k) { return R.wt(k) * sc; };
+  const int t = threadIdx.x;
+  const double lo = pole(k0);
+  if (t < 2) cnt[t] = 0;
+  const double w = pole(min(k0 + kSfLeaf, K - 1)) - lo;
+  // far sums at the Chebyshev points x_q = lo + h (1 + t_q): point q = t % 32,
+  // poles j = t / 32, t / 32 + 32, ... of each chunk
+  const int q = t & (kSfP - 1), r = t >> 5;
+  const double tq = cospi((double)(2 * q + 1) / (2.0 * kSfP));
+  const double xo = 0.5 * w * (1.0 + tq);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int nl = 0, nr = 0;
+  for (int c0 = 0; c0 < K; c0 += kSfChunk) {
+    const int n = min(kSfChunk, K - c0);
+    __syncthreads();   // the previous chunk is consumed
+    for (int j = t; j < n; j += kSfThreads) {
+      sp[j] = pole(c0 + j);
+      sw[j] = wt(c0 + j);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int j = r; j < n; j += 32) {
+      const double off = sp[j] - lo;
+      const bool fl = off <= -w, fr = off >= 2.0 * w;
+      const bool far = fl || fr;
+      const double D = far ? off - xo : 1.0;   // far: |D| >= |T|
+      const double rd = far ? (recip_tiny(D) ? 1.0 / D : recip_fast(D)) : 0.0;
+      const double v = sw[j] * rd;
+      const double dv = v * rd;
+      s0 += fl ? v : 0.0;
+      s1 += fl ? dv : 0.0;
+      s2 += fr ? v : 0.0;
+      s3 += fr ? dv : 0.0;
+      nl += fl ? 1 : 0;
+      nr += fr ? 1 : 0;
+    }
+  }
+  red[(0 * 32 + r) * 33 + q] = s0;
+  red[(1 * 32 + r) * 33 + q] = s1;
+  red[(2 * 32 + r) * 33 + q] = s2;
+  red[(3 * 32 + r) * 33 + q] = s3;
+  if (q == 0) {   // every pole was seen by the 32 threads of one r; count it once
+    atomicAdd(&cnt[0], nl);
+    atomicAdd(&cnt[1], nr);
+  }
+  if (r == 0) {
+    lf->t[q] = tq;
+    const double sq = sinpi((double)(2 * q + 1) / (2.0 * kSfP));
+    lf->lam[q] = (q & 1) ? -sq : sq;
+  }
+  __syncthreads();
+  if (t < 4 * kSfP) {
+    const int a = t >> 5, qq = t & 31;
+    double f = 0.0;
+    for (int v = 0; v < 32; ++v) f += red[(a * 32 + v) * 33 + qq];
+    lf->f[a][qq] = f;
+  }
+  if (t == 0) {
+    lf->k0 = k0;
+    lf->kl = cnt[0];
+    lf->kr = K - 1 - cnt[1];
+    lf->h = 0.5 * w;
+    lf->hinv = 2.0 / w;
+  }
+  __syncthreads();
+}
+
+static_assert(kSfRed + 2 * kSfChunk <= 2 * kSecLdsN, "the setup's LDS fits the pole copy's");
+
+// direct_max: jobs of order up to this take the direct sums.
+__global__ __launch_bounds__(kSfThreads) void secular_ff_kernel(StageLevel L, int maxit, int direct_max) {
+  __shared__ double lds[2 * kSecLdsN];   // setup: red, sp, sw; extreme root: poles, then weights
+  __shared__ int cnt[2];
+  __shared__ SfLeaf lf;
+  const int j = find_job(L.boff_l, L.n, blockIdx.x);
+  const Stage s = L.st[j];
+  if (*s.status & kStFatal) return;   // set before this launch only: uniform over the block
+  const int K = min(max(*s.counts, 0), s.N);
+  if (K <= 0) return;
+  const int b = blockIdx.x - L.boff_l[j];
+  if (s.N <= direct_max) {
+    // orders up to kGroupMaxN (direct_max) keep the direct sums with the item
+    // layout of secular_kernel (groups of kSmallGroup lanes, 64 roots per
+    // block), so a problem's roots do not depend on what shares the launch
+    if (b * kSfLeaf >= K) return;
+    for (int e = threadIdx.x; e < K; e += blockDim.x) {
+      lds[e] = gld(s.g + e);
+      lds[kSecLdsN + e] = gld(s.W2 + e);
+    }
+    __syncthreads();
+    secular_body<kSmallGroup, true>(s.counts, lds, lds + kSecLdsN, s.rho, s.org, s.tau, s.iters, s.status, maxit,
+                                    b * kSfLeaf + (int)(threadIdx.x / kSmallGroup));
+    return;
+  }
+  const bool refl = *s.rho < 0.0;
+  if (b == (s.N + kSfLeaf - 1) / kSfLeaf) {   // the extreme root, K - 1 of the reflected problem
+    const int idx = refl ? 0 : K - 1;
+    if (s.N <= kSecLdsN) {
+      for (int e = threadIdx.x; e < K; e += blockDim.x) {
+        lds[e] = gld(s.g + e);
+        lds[kSecLdsN + e] = gld(s.W2 + e);
+      }
+      __syncthreads();
+      if (threadIdx.x < 64)
+        secular_body<64, true>(s.counts, lds, lds + kSecLdsN, s.rho, s.org, s.tau, s.iters, s.status, maxit, idx);
+    } else if (threadIdx.x < 64) {
+      secular_body<64, false>(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, idx);
+    }
+    return;
+  }
+  const int k0 = b * kSfLeaf;
+  if (k0 >= K - 1) return;   // no root of this leaf but the extreme one
+  sf_setup(s, K, k0, &lf, lds, lds + kSfRed, lds + kSfRed + kSfChunk, cnt);
+  const int i = k0 + (threadIdx.x >> 4);   // root of the reflected problem
+  if (i >= K - 1) return;
+  secular_body<16, false, true>(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit,
+                                refl ? K - 1 - i : i, &lf);
+}
+
 // Block shapes and the LDS copy of the poles as in the secular kernel; the
 // roots' origins and offsets stream from global memory.
 template <int BT>
@@ -742,18 +992,24 @@ __global__ __launch_bounds__(256) void merge_kernel(StageLevel L) {
   merge_body(s, (blockIdx.x - L.boff_t[j]) * 256 + threadIdx.x);
 }
 
-void launch_secular_level(const StageLevel& L, int maxit, hipStream_t st) {
+void launch_secular_level(const StageLevel& L, int maxit, int far_field, hipStream_t st) {
   if (L.blocks_i <= 0) return;
+  // far_field 1: the far-field form above kGroupMaxN; 2: at every order
+  if (far_field == 2 || (far_field == 1 && L.nmax > kGroupMaxN)) {
+    const int direct_max = far_field == 2 ? 0 : kGroupMaxN;
+    hipLaunchKernelGGL(secular_ff_kernel, dim3(L.blocks_l), dim3(kSfThreads), 0, st, L, maxit, direct_max);
+    return;
+  }
   if (L.nmax <= kGroupMaxN)
     hipLaunchKernelGGL(secular_kernel<256>, dim3(L.blocks_i), dim3(256), 0, st, L, maxit);
   else
     hipLaunchKernelGGL(secular_kernel<1024>, dim3(L.blocks_s), dim3(1024), 0, st, L, maxit);
 }
 
-void launch_stage_level(const StageLevel& L, int maxit, hipStream_t st) {
+void launch_stage_level(const StageLevel& L, int maxit, int far_field, hipStream_t st) {
   if (L.n <= 0 || L.blocks_w <= 0) return;
   hipLaunchKernelGGL(deflate_kernel, dim3(L.n), dim3(kDeflThreads), 0, st, L);
-  launch_secular_level(L, maxit, st);
+  launch_secular_level(L, maxit, far_field, st);
   if (L.nmax <= kGroupMaxN)
     hipLaunchKernelGGL(loewner_kernel<256>, dim3(L.blocks_i), dim3(256), 0, st, L);
   else

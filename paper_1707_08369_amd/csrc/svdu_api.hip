@@ -396,7 +396,7 @@ int svdu_eig_update(svdu_ctx* ctx, int R, int N, const double* X, int ldx, const
   hipLaunchKernelGGL(set_scalar, dim3(1), dim3(64), 0, st, s.rho, rho, E.status);
   hipLaunchKernelGGL(identity_map, dim3((N + 255) / 256), dim3(256), 0, st, N, s.col_of);
   write_blob(blob, E.tables, st);
-  launch_stage_level(lev, ctx->opt.maxit, st);
+  launch_stage_level(lev, ctx->opt.maxit, ctx->opt.secular_ff, st);
   if (path == SVDU_PATH_FMM) {
     const int Rs[1] = {R};
     const double* Xs[1] = {X};
@@ -460,7 +460,7 @@ int svdu_secular(svdu_ctx* ctx, int K, const double* d, const double* z, double 
   hipLaunchKernelGGL(set_scalar, dim3(1), dim3(64), 0, st, rhod, rho, status);
   hipLaunchKernelGGL(square_kernel, dim3((K + 255) / 256), dim3(256), 0, st, K, z, w2, Kdev, K);
   write_blob(blob, tables, st);
-  launch_secular_level(lev, ctx->opt.maxit, st);
+  launch_secular_level(lev, ctx->opt.maxit, ctx->opt.secular_ff, st);
   return hip_ok();
 }
 
@@ -492,6 +492,12 @@ int svdu_set_option(svdu_ctx* ctx, int option, int value) {
     if (value < kMinSlices || value > kMaxSlices) return SVDU_EINVAL;
     const int old = o.slices;
     o.slices = value;
+    return old;
+  }
+  if (option == SVDU_OPT_SECULAR_FMM) {
+    if (value < 0 || value > 2) return SVDU_EINVAL;
+    const int old = o.secular_ff;
+    o.secular_ff = value;
     return old;
   }
   if (option == SVDU_OPT_TIMING) return ctx->ring.set(value != 0);

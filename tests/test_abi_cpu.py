@@ -168,6 +168,11 @@ def test_options(lib, ctx):
     assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SLICES, 5) == svdu.SVDU_EINVAL
     assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SLICES, 9) == svdu.SVDU_EINVAL
     assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SLICES, 7) == 8
+    assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SECULAR_FMM, 0) == 1     # on above order 2048 by default
+    assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SECULAR_FMM, 2) == 0
+    assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SECULAR_FMM, 3) == svdu.SVDU_EINVAL
+    assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SECULAR_FMM, -1) == svdu.SVDU_EINVAL
+    assert svdu.svdu_set_option(ctx, svdu.SVDU_OPT_SECULAR_FMM, 1) == 2
 
 
 def _table(ctx, prec, new=None):
