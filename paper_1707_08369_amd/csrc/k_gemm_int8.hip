@@ -234,10 +234,21 @@ __device__ __forceinline__ void i8_tile_order(int t, int tiles_m, int tiles_n, i
   *tn = w / gm;
 }
 
+// A block of kI8Threads (8 waves) computes a kI8BM x kI8BN tile; wave w owns
+// rows 16 w .. 16 w + 15 and all kI8BN columns, so its S x 4 accumulators take
+// 112 registers and two waves fit on each SIMD: while one waits for its next
+// slices the other keeps the matrix cores busy. The S slice tiles of C~ for a
+// k step are staged in LDS (double-buffered, one barrier per k step); each
+// wave streams its own X slices from global memory one k step ahead.
+constexpr int kI8Threads = 512;
+
 template <int S>
-__global__ __launch_bounds__(256, 1) void gemm_i8_kernel(I8List L) {
+__global__ __launch_bounds__(kI8Threads, 1) void gemm_i8_kernel(I8List L) {
   constexpr int TILE = S * 64;          // v4i per (block, k step) group of S slice tiles
-  __shared__ v4i Bs[2][4 * TILE];
+  constexpr int NBT = 4 * TILE;         // v4i of C~ slices per k step
+  constexpr int NB = (NBT + kI8Threads - 1) / kI8Threads;
+  static_assert(kI8BM == 16 * (kI8Threads / 64) && kI8BN == 64, "one 16-row block per wave, 4 column blocks");
+  __shared__ v4i Bs[2][NBT];
   const int jb = find_job(L.boff, L.n, blockIdx.x);
   const I8Job J = L.job[jb];
   if (*J.d.status & kStFatal) return;
@@ -256,57 +267,49 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_kernel(I8List L) {
       double* rhs = reinterpret_cast<double*>(&Bs[0][0]);
       int* js = reinterpret_cast<int*>(rhs + SM);
       double* dots = reinterpret_cast<double*>(js + SM);
-      copy_path<kI8BM, 256, 1, SM>(J, tm * kI8BM, tn * kI8BN, cc, cl, cp, rhs, js, dots);
+      copy_path<kI8BM, kI8Threads, 1, SM>(J, tm * kI8BM, tn * kI8BN, cc, cl, cp, rhs, js, dots);
       return;
     }
   }
   const int KB = J.KB;
   const v4i* A = reinterpret_cast<const v4i*>(J.A);
   const v4i* B = reinterpret_cast<const v4i*>(J.B);
-  const int rb0 = tm * (kI8BM / 16) + 2 * wave, cb0 = tn * (kI8BN / 16);
-  const v4i* ap0 = A + (size_t)rb0 * KB * TILE + lane;
-  const v4i* ap1 = ap0 + (size_t)KB * TILE;
-  // this thread's share of the block's B fragments: elements tid + 256 i of the
-  // 4 TILE of a k step (column block c = e / TILE, offset e % TILE)
-  const v4i* bp[S];
+  const int rb = tm * (kI8BM / 16) + wave, cb0 = tn * (kI8BN / 16);
+  const v4i* ap = A + (size_t)rb * KB * TILE + lane;
+  // this thread's share of the block's C~ fragments: elements tid + kI8Threads i
+  // of the NBT of a k step (column block c = e / TILE, offset e % TILE)
+  const v4i* bp[NB];
 #pragma unroll
-  for (int i = 0; i < S; ++i) {
-    const int e = tid + 256 * i, c = e / TILE;
+  for (int i = 0; i < NB; ++i) {
+    const int e = min(tid + kI8Threads * i, NBT - 1), c = e / TILE;
     bp[i] = B + (size_t)(cb0 + c) * KB * TILE + (e - c * TILE);
   }
 
-  v4i acc[S][2][4];
+  v4i acc[S][4];
 #pragma unroll
   for (int g = 0; g < S; ++g)
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[g][r][c] = v4i{0, 0, 0, 0};
+    for (int c = 0; c < 4; ++c) acc[g][c] = v4i{0, 0, 0, 0};
 
   // The loads of step kb + 1 are issued right after the barrier of step kb and
   // consumed at the top of step kb + 1, so no wait for them falls inside the
   // MFMA sequence (nor for the first step's loads, issued the same way).
-  v4i a[2][S], an[2][S], bn[S];
+  v4i a[S], an[S], bn[NB];
   auto load_next = [&](int kb) {
     const size_t o = (size_t)kb * TILE;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      an[0][s] = gld(ap0 + o + s * 64);
-      an[1][s] = gld(ap1 + o + s * 64);
-    }
+    for (int s = 0; s < S; ++s) an[s] = gld(ap + o + s * 64);
 #pragma unroll
-    for (int i = 0; i < S; ++i) bn[i] = gld(bp[i] + o);
+    for (int i = 0; i < NB; ++i) bn[i] = gld(bp[i] + o);
   };
   load_next(0);
   for (int kb = 0; kb < KB; ++kb) {
     v4i* Bc = Bs[kb & 1];
 #pragma unroll
-    for (int i = 0; i < S; ++i) Bc[tid + 256 * i] = bn[i];
+    for (int i = 0; i < NB; ++i)
+      if (NBT % kI8Threads == 0 || tid + kI8Threads * i < NBT) Bc[tid + kI8Threads * i] = bn[i];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      a[0][s] = an[0][s];
-      a[1][s] = an[1][s];
-    }
+    for (int s = 0; s < S; ++s) a[s] = an[s];
     __syncthreads();
     if (kb + 1 < KB) load_next(kb + 1);
 #pragma unroll
@@ -317,15 +320,13 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_kernel(I8List L) {
 #pragma unroll
       for (int s = 0; s + t < S; ++s)
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-          for (int c = 0; c < 4; ++c)
-            acc[s + t][r][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[r][s], b[c], acc[s + t][r][c], 0, 0, 0);
+        for (int c = 0; c < 4; ++c)
+          acc[s + t][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[s], b[c], acc[s + t][c], 0, 0, 0);
     }
   }
 
   // epilogue: sum_g acc_g 2^(-7 g) by Horner in FP64, times 2^(Ex + Ec - 12)
-  const int row0 = tm * kI8BM + 32 * wave + 4 * (lane >> 4);
+  const int row0 = tm * kI8BM + 16 * wave + 4 * (lane >> 4);
   const int colx = tn * kI8BN + (lane & 15);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -334,16 +335,14 @@ __global__ __launch_bounds__(256, 1) void gemm_i8_kernel(I8List L) {
     const int ec = gld(J.eb + col) - 12;
     const double sc = J.d.colscale ? gld(J.d.colscale + col) : 1.0;
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int v = 0; v < 4; ++v) {
+      const int row = row0 + v;
+      if (row >= J.R) continue;
+      double x = (double)acc[S - 1][c][v];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = row0 + 16 * r + v;
-        if (row >= J.R) continue;
-        double x = (double)acc[S - 1][r][c][v];
-#pragma unroll
-        for (int g = S - 2; g >= 0; --g) x = __builtin_fma(x, 0x1p-7, (double)acc[g][r][c][v]);
-        gst(J.Xo + (size_t)row * J.ldo + col, sc * __builtin_amdgcn_ldexp(x, gld(J.ea + row) + ec));
-      }
+      for (int g = S - 2; g >= 0; --g) x = __builtin_fma(x, 0x1p-7, (double)acc[g][c][v]);
+      gst(J.Xo + (size_t)row * J.ldo + col, sc * __builtin_amdgcn_ldexp(x, gld(J.ea + row) + ec));
+    }
   }
 }
 
@@ -370,9 +369,9 @@ void launch_slice_c(const SliceCList& L, int S, hipStream_t st) {
 void launch_gemm_i8(const I8List& L, int S, hipStream_t st) {
   if (L.n <= 0 || L.blocks <= 0) return;
   switch (S) {
-    case 6: hipLaunchKernelGGL(gemm_i8_kernel<6>, dim3(L.blocks), dim3(256), 0, st, L); break;
-    case 8: hipLaunchKernelGGL(gemm_i8_kernel<8>, dim3(L.blocks), dim3(256), 0, st, L); break;
-    default: hipLaunchKernelGGL(gemm_i8_kernel<7>, dim3(L.blocks), dim3(256), 0, st, L); break;
+    case 6: hipLaunchKernelGGL(gemm_i8_kernel<6>, dim3(L.blocks), dim3(kI8Threads), 0, st, L); break;
+    case 8: hipLaunchKernelGGL(gemm_i8_kernel<8>, dim3(L.blocks), dim3(kI8Threads), 0, st, L); break;
+    default: hipLaunchKernelGGL(gemm_i8_kernel<7>, dim3(L.blocks), dim3(kI8Threads), 0, st, L); break;
   }
 }
 
