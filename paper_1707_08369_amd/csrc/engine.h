@@ -9,6 +9,7 @@
 
 #include <string.h>
 
+#include <functional>
 #include <vector>
 
 #include "../../include/svdu.h"
@@ -93,8 +94,10 @@ struct Layout {
   int *rf_info, *rf_start, *rf_size, *rf_off, *rf_idx;
   double *rf_Yu, *rf_Yv, *rf_T, *rf_W, *rf_beta;
   Stage st[4];                    // L+, L-, R+, R-
-  double* fmm_work;               // FMM path only
+  double* fmm_work;               // FMM path only (the right-hand products; the single eigen-update)
   size_t fmm_elems;
+  double* fmm_work_l;             // FMM path: the left-hand products, which run beside the right-hand ones
+  size_t fmm_elems_l;
   char* fmm_plan;
   size_t fmm_plan_bytes;
   size_t bytes;
@@ -214,8 +217,10 @@ struct Sched {
   }
 };
 // Enqueues the sequence (or a part of it: the FMM path runs the products
-// itself between the two parts).
-void enqueue_plan(const Plan& P, const Sched& S, int part, hipStream_t st);
+// itself between the two parts). after_level, when given, is called once the
+// work of each eigen-update level is enqueued (level 0, then 1).
+void enqueue_plan(const Plan& P, const Sched& S, int part, hipStream_t st,
+                  const std::function<void(int)>* after_level = nullptr);
 
 // Gathers the status words of the plan's updates into out[0..n-1] (device).
 void enqueue_status_gather(const Plan& P, int* out, hipStream_t st);
@@ -233,6 +238,17 @@ struct svdu_ctx {
   svdu::TimingRing ring;
   bool have_caps = false;
   int grid_cap[svdu::kNumPrec][svdu::kNumShapes] = {};
+  // a second stream for the FMM path's right-hand products (default priority),
+  // forked from and joined to the caller's stream with two events; these and
+  // the events below are created on first use
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t roots[2] = {nullptr, nullptr};   // the FMM path's root copies of each level are done
+  // pinned host memory for the FMM path's copies of the roots (grown on
+  // demand; every copy into it has completed when a call returns)
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  ~svdu_ctx();
 };
 
 namespace svdu {

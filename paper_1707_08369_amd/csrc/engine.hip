@@ -110,7 +110,7 @@ Layout carve_update(void* base, int m, int n, int path, int precision) {
   L.renorm_v = c.take<double>(s32 ? renorm_scratch_elems(n, n) : 0);
   for (int k = 0; k < 4; ++k) carve_stage(c, L.st[k], k < 2 ? m : n);
   const bool fmm = path == SVDU_PATH_FMM;
-  L.TL = fmm ? nullptr : c.take<double>((size_t)m * m);   // the FMM path runs the sides in turn through TR
+  L.TL = c.take<double>((size_t)m * m);
   L.TR = c.take<double>((size_t)n * n);
   const bool i8 = precision == SVDU_PREC_SLICED_INT8;
   for (int k = 0; k < 2; ++k) {
@@ -137,6 +137,8 @@ Layout carve_update(void* base, int m, int n, int path, int precision) {
   L.rf_beta = c.take<double>(km);
   L.fmm_elems = fmm ? fmm_workspace_elems(n, n) : 0;
   L.fmm_work = c.take<double>(L.fmm_elems);
+  L.fmm_elems_l = fmm ? fmm_workspace_elems(m, m) : 0;
+  L.fmm_work_l = c.take<double>(L.fmm_elems_l);
   L.fmm_plan_bytes = fmm ? 4 * fmm_plan_bytes(n) : 0;
   L.fmm_plan = c.take<char>(L.fmm_plan_bytes);
   L.bytes = c.off + 256;
@@ -627,7 +629,8 @@ void write_blob(const std::vector<char>& blob, char* dst, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // the sequence
 // ---------------------------------------------------------------------------
-void enqueue_plan(const Plan& P, const Sched& S, int part, hipStream_t st) {
+void enqueue_plan(const Plan& P, const Sched& S, int part, hipStream_t st,
+                  const std::function<void(int)>* after_level) {
   const bool s32 = P.precision == SVDU_PREC_SPLIT32;
   if (part != kStepProductsOnward) {
     S.mark(0, st);
@@ -639,6 +642,7 @@ void enqueue_plan(const Plan& P, const Sched& S, int part, hipStream_t st) {
     for (int lev = 0; lev < 2; ++lev) {
       launch_stage_level(P.lev[lev], S.maxit, S.secular_ff, st);
       launch_cauchy_tmatvec_level(P.lev[lev], st);
+      if (after_level) (*after_level)(lev);
     }
     if (P.prob.blocks_n > 0)
       hipLaunchKernelGGL(prob_finalize_kernel, dim3(P.prob.blocks_n), dim3(256), 0, st, P.prob);
@@ -710,6 +714,19 @@ int gemm_split32_grid_cap(int shape);
 int gemm_grid_cap(int shape, int precision) {
   return precision == SVDU_PREC_SPLIT32 ? gemm_split32_grid_cap(shape) : gemm_f64_grid_cap(shape);
 }
+
+}  // namespace svdu
+
+svdu_ctx::~svdu_ctx() {
+  if (aux) (void)hipStreamDestroy(aux);   // work already enqueued on it still completes
+  if (fork) (void)hipEventDestroy(fork);
+  if (join) (void)hipEventDestroy(join);
+  for (hipEvent_t e : roots)
+    if (e) (void)hipEventDestroy(e);
+  if (pinned) (void)hipHostFree(pinned);
+}
+
+namespace svdu {
 
 // ---------------------------------------------------------------------------
 // timing ring of a context

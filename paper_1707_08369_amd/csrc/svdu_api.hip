@@ -68,21 +68,49 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
 
 int hip_ok() { return hipGetLastError() == hipSuccess ? SVDU_OK : SVDU_EHIP; }
 
-// Host copies of one stage's roots, for the FMM plans.
+// Host copies of one stage's roots, for the FMM plans: views into host
+// memory that the caller owns.
 struct HostRoots {
-  int counts[4];
-  std::vector<double> g, tau;
-  std::vector<int> org;
+  int* counts;   // 4
+  double* g;     // N
+  double* tau;   // N
+  int* org;      // N
 };
 
-void enqueue_root_copies(const Stage& s, HostRoots* h, hipStream_t st) {
-  h->g.resize(s.N);
-  h->tau.resize(s.N);
-  h->org.resize(s.N);
-  (void)hipMemcpyAsync(h->counts, s.counts, sizeof(h->counts), hipMemcpyDeviceToHost, st);
-  (void)hipMemcpyAsync(h->g.data(), s.g, s.N * sizeof(double), hipMemcpyDeviceToHost, st);
-  (void)hipMemcpyAsync(h->tau.data(), s.tau, s.N * sizeof(double), hipMemcpyDeviceToHost, st);
-  (void)hipMemcpyAsync(h->org.data(), s.org, s.N * sizeof(int), hipMemcpyDeviceToHost, st);
+// Host memory for the roots of one stage of order N: counts, g, tau, org.
+static size_t host_roots_bytes(int N) { return ((size_t)16 + 20 * (size_t)N + 255) & ~size_t(255); }
+
+static HostRoots host_roots_at(char* p, int N) {
+  HostRoots h;
+  h.counts = reinterpret_cast<int*>(p);
+  h.g = reinterpret_cast<double*>(p + 16);
+  h.tau = h.g + N;
+  h.org = reinterpret_cast<int*>(h.tau + N);
+  return h;
+}
+
+void enqueue_root_copies(const Stage& s, const HostRoots& h, hipStream_t st) {
+  (void)hipMemcpyAsync(h.counts, s.counts, 4 * sizeof(int), hipMemcpyDeviceToHost, st);
+  (void)hipMemcpyAsync(h.g, s.g, s.N * sizeof(double), hipMemcpyDeviceToHost, st);
+  (void)hipMemcpyAsync(h.tau, s.tau, s.N * sizeof(double), hipMemcpyDeviceToHost, st);
+  (void)hipMemcpyAsync(h.org, s.org, s.N * sizeof(int), hipMemcpyDeviceToHost, st);
+}
+
+// The tree plan of one product from the host copies of its stage's roots
+// (appended to blob). The host reads indices that the device produced: they
+// are checked before use, so inconsistent device results give an error
+// instead of a host fault.
+int prepare_plan(const Stage& s, const HostRoots& h, double eps, std::vector<char>* blob, FmmPrepared* pp) {
+  const int K = h.counts[0];
+  if (K < 0 || K > s.N) return SVDU_EHIP;
+  std::vector<double> mu(K);
+  for (int i = 0; i < K; ++i) {
+    const int o = h.org[i];
+    if (o < 0 || o >= K) return SVDU_EHIP;
+    mu[i] = h.g[o] + h.tau[i];
+  }
+  fmm_prepare(K, h.g, mu.data(), eps, blob, pp);
+  return SVDU_OK;
 }
 
 // Products through the FMM for a list of eigen-updates. One host round
@@ -91,56 +119,149 @@ void enqueue_root_copies(const Stage& s, HostRoots* h, hipStream_t st) {
 int fmm_products_impl(int nst, Stage* stages, const int* Rs, const double* const* Xs, const int* ldxs,
                       double* const* Xos, const int* ldos, const double* const* scales, const int* status_dev,
                       double* work, size_t work_elems, char* plan_dev, size_t plan_bytes, double eps,
-                      const int* marks, const Sched* S, hipStream_t st) {
+                      hipStream_t st) {
+  std::vector<size_t> at(nst + 1, 0);
+  for (int k = 0; k < nst; ++k) at[k + 1] = at[k] + host_roots_bytes(stages[k].N);
+  std::vector<double> mem((at[nst] + 7) / 8);   // 8-byte aligned; the call waits for its copies below
   std::vector<HostRoots> h(nst);
   int status = 0;
   (void)hipMemcpyAsync(&status, status_dev, sizeof(int), hipMemcpyDeviceToHost, st);
-  for (int k = 0; k < nst; ++k) enqueue_root_copies(stages[k], &h[k], st);
+  for (int k = 0; k < nst; ++k) {
+    h[k] = host_roots_at(reinterpret_cast<char*>(mem.data()) + at[k], stages[k].N);
+    enqueue_root_copies(stages[k], h[k], st);
+  }
   if (hipStreamSynchronize(st) != hipSuccess) return SVDU_EHIP;
   if (status & kStFatal) return SVDU_OK;   // reported by svdu_get_status
   std::vector<char> blob;
   std::vector<FmmPrepared> prep(nst);
-  for (int k = 0; k < nst; ++k) {
-    // The host reads indices that the device produced: check them before use,
-    // so that inconsistent device results give an error instead of a host fault.
-    const int K = h[k].counts[0];
-    if (K < 0 || K > stages[k].N) return SVDU_EHIP;
-    std::vector<double> mu(K);
-    for (int i = 0; i < K; ++i) {
-      const int o = h[k].org[i];
-      if (o < 0 || o >= K) return SVDU_EHIP;
-      mu[i] = h[k].g[o] + h[k].tau[i];
-    }
-    fmm_prepare(K, h[k].g.data(), mu.data(), eps, &blob, &prep[k]);
-  }
+  for (int k = 0; k < nst; ++k)
+    if (const int rc = prepare_plan(stages[k], h[k], eps, &blob, &prep[k])) return rc;
   if (blob.size() > plan_bytes) return SVDU_ENOMEM;
   if (!blob.empty()) {
     if (hipMemcpyAsync(plan_dev, blob.data(), blob.size(), hipMemcpyHostToDevice, st) != hipSuccess) return SVDU_EHIP;
     if (hipStreamSynchronize(st) != hipSuccess) return SVDU_EHIP;   // blob is a host temporary
   }
-  for (int k = 0; k < nst; ++k) {
+  for (int k = 0; k < nst; ++k)
     if (fmm_launch(Rs[k], Xs[k], ldxs[k], stages[k], prep[k], plan_dev, Xos[k], ldos[k], scales[k], work,
                    work_elems, st) != 0)
       return SVDU_ENOMEM;
-    if (marks && marks[k] >= 0 && S) S->mark(marks[k], st);
-  }
   return SVDU_OK;
 }
 
-int fmm_products(const Update& u, const Plan& P, double eps, const Sched& S, hipStream_t st) {
+// The whole update on the FMM path, from the projections to the products
+// (the caller enqueues the rest). The products run by level: U C~_L+ -> TL
+// and V C~_R+ -> TR, then TL C~_L- -> U^ and TR C~_R- diag(s) -> V^. A level's
+// roots are copied to the host as soon as its eigen-updates are enqueued, so
+// the host builds the first level's tree plans while the device runs the
+// second level's eigen-updates, and the second level's plans while it runs
+// the first level's products. Within a level the right-hand product runs on
+// the context's second stream (with its own work buffer) beside the left-hand
+// one, so that the many small launches of the two tree passes overlap.
+// The context's second stream and the events of the FMM path (made on first
+// use, on the context's device, which is current).
+static bool fmm_sync_objects(svdu_ctx* ctx) {
+  auto event = [](hipEvent_t* e) {
+    if (!*e && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) *e = nullptr;
+    return *e != nullptr;
+  };
+  if (!ctx->aux && hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess) ctx->aux = nullptr;
+  const bool ev = event(&ctx->fork) && event(&ctx->join) && event(&ctx->roots[0]) && event(&ctx->roots[1]);
+  return ctx->aux && ev;
+}
+
+int fmm_update(svdu_ctx* ctx, const Update& u, const Plan& P, double eps, const Sched& S, hipStream_t st) {
   const Layout& L = u.L;
-  // all four products in one host round trip; the two sides use TR in turn,
-  // which stream order makes safe
-  Stage st4[4] = {P.host_stages[0], P.host_stages[1], P.host_stages[2], P.host_stages[3]};
-  const int Rs[4] = {u.m, u.m, u.n, u.n};
-  const double* Xs[4] = {u.U, L.TR, u.V, L.TR};
-  const int ldx[4] = {u.ldu, u.m, u.ldv, u.n};
-  double* Xo[4] = {L.TR, u.U_out, L.TR, u.V_out};
-  const int ldo[4] = {u.m, u.ldu_out, u.n, u.ldv_out};
-  const double* sc[4] = {nullptr, nullptr, nullptr, L.signs};
-  const int marks[4] = {-1, 3, -1, 4};
-  return fmm_products_impl(4, st4, Rs, Xs, ldx, Xo, ldo, sc, L.status, L.fmm_work, L.fmm_elems, L.fmm_plan,
-                           L.fmm_plan_bytes, eps, marks, &S, st);
+  if (!fmm_sync_objects(ctx)) return SVDU_EHIP;
+  struct LevelHost {
+    HostRoots h[2];   // the left and the right eigen-update of the level
+    int* status;
+    hipEvent_t ev;
+  } H[2];
+  // pinned host memory for the copies, so that they do not hold up the host
+  // while it enqueues the next level: 256 bytes of status words, then the roots
+  size_t need = 256;
+  for (int k = 0; k < 4; ++k) need += host_roots_bytes(P.host_stages[k].N);
+  if (need > ctx->pinned_bytes) {
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    if (hipHostMalloc(&ctx->pinned, need, hipHostMallocDefault) != hipSuccess) {
+      ctx->pinned = nullptr;
+      return SVDU_EHIP;
+    }
+    ctx->pinned_bytes = need;
+  }
+  {
+    char* p = static_cast<char*>(ctx->pinned);
+    H[0].ev = ctx->roots[0];
+    H[1].ev = ctx->roots[1];
+    H[0].status = reinterpret_cast<int*>(p);
+    H[1].status = H[0].status + 1;
+    size_t at = 256;
+    for (int lev = 0; lev < 2; ++lev)
+      for (int side = 0; side < 2; ++side) {
+        const int N = P.host_stages[2 * side + lev].N;
+        H[lev].h[side] = host_roots_at(p + at, N);
+        at += host_roots_bytes(N);
+      }
+  }
+  const std::function<void(int)> copy_roots = [&](int lev) {
+    (void)hipMemcpyAsync(H[lev].status, L.status, sizeof(int), hipMemcpyDeviceToHost, st);
+    for (int side = 0; side < 2; ++side) enqueue_root_copies(P.host_stages[2 * side + lev], H[lev].h[side], st);
+    (void)hipEventRecord(H[lev].ev, st);
+  };
+  enqueue_plan(P, S, kStepUpToRoots, st, &copy_roots);
+  int rc = SVDU_OK;
+  size_t off = 0;
+  for (int lev = 0; lev < 2; ++lev) {
+    if (hipEventSynchronize(H[lev].ev) != hipSuccess) {
+      rc = SVDU_EHIP;
+      break;
+    }
+    if (*H[lev].status & kStFatal) break;   // reported by svdu_get_status
+    std::vector<char> blob;
+    FmmPrepared prep[2];
+    for (int side = 0; side < 2 && rc == SVDU_OK; ++side)
+      rc = prepare_plan(P.host_stages[2 * side + lev], H[lev].h[side], eps, &blob, &prep[side]);
+    if (rc != SVDU_OK) break;
+    if (off + blob.size() > L.fmm_plan_bytes) {
+      rc = SVDU_ENOMEM;
+      break;
+    }
+    char* plan = L.fmm_plan + off;
+    if (!blob.empty()) {
+      if (hipMemcpyAsync(plan, blob.data(), blob.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {   // blob is a host temporary
+        rc = SVDU_EHIP;
+        break;
+      }
+    }
+    off += (blob.size() + 255) & ~size_t(255);
+    if (hipEventRecord(ctx->fork, st) != hipSuccess || hipStreamWaitEvent(ctx->aux, ctx->fork, 0) != hipSuccess) {
+      rc = SVDU_EHIP;
+      break;
+    }
+    for (int side = 0; side < 2 && rc == SVDU_OK; ++side) {
+      const bool left = side == 0;
+      const int N = left ? u.m : u.n;
+      const double* X = lev == 0 ? (left ? u.U : u.V) : (left ? L.TL : L.TR);
+      const int ldx = lev == 0 ? (left ? u.ldu : u.ldv) : N;
+      double* Xo = lev == 0 ? (left ? L.TL : L.TR) : (left ? u.U_out : u.V_out);
+      const int ldo = lev == 0 ? N : (left ? u.ldu_out : u.ldv_out);
+      const double* sc = (lev == 1 && !left) ? L.signs : nullptr;
+      if (fmm_launch(N, X, ldx, P.host_stages[2 * side + lev], prep[side], plan, Xo, ldo, sc,
+                     left ? L.fmm_work_l : L.fmm_work, left ? L.fmm_elems_l : L.fmm_elems,
+                     left ? st : ctx->aux) != 0)
+        rc = SVDU_ENOMEM;
+    }
+    // join even after an error: nothing on the second stream may outlive the call's stream order
+    if (hipEventRecord(ctx->join, ctx->aux) != hipSuccess || hipStreamWaitEvent(st, ctx->join, 0) != hipSuccess)
+      rc = SVDU_EHIP;
+    if (rc == SVDU_OK) S.mark(3 + lev, st);
+  }
+  // the root copies write the pinned buffer: let every one finish before the call returns
+  for (LevelHost& x : H) (void)hipEventSynchronize(x.ev);
+  return rc;
 }
 
 // Single-update workspace: the update's layout, then 2 kNumShapes tile
@@ -239,8 +360,7 @@ int svdu_rank1_update(svdu_ctx* ctx, int m, int n, const double* U, int ldu, con
   write_blob(blob, W.tables, st);
   const Sched S = sched_of(ctx, ctx->opt, ctx->opt.persistent, true);
   if (path == SVDU_PATH_FMM) {
-    enqueue_plan(P, S, kStepUpToRoots, st);
-    const int rc = fmm_products(u, P, eps, S, st);
+    const int rc = fmm_update(ctx, u, P, eps, S, st);
     if (rc != SVDU_OK) return rc;
     enqueue_plan(P, S, kStepProductsOnward, st);
   } else {
@@ -405,7 +525,7 @@ int svdu_eig_update(svdu_ctx* ctx, int R, int N, const double* X, int ldx, const
     const int ldos[1] = {ldo};
     const double* sc[1] = {nullptr};
     const int rc = fmm_products_impl(1, &s, Rs, Xs, ldxs, Xos, ldos, sc, E.status, E.fmm_work, E.fmm_elems,
-                                     E.fmm_plan, E.fmm_plan_bytes, eps, nullptr, nullptr, st);
+                                     E.fmm_plan, E.fmm_plan_bytes, eps, st);
     if (rc != SVDU_OK) return rc;
   } else {
     launch_gemm_f64(G, shape, false, 0, st);
