@@ -324,9 +324,12 @@ __device__ inline SecSums secular_sums_t(const Reflect<LDS>& R, double sc, int i
 //  * the poles of the (reflected) problem fall into leaves of kSfLeaf
 //    consecutive poles. Leaf l's interval T runs from its first pole to the
 //    first pole of the next leaf (the last leaf: to the last pole), so every
-//    root of the leaf lies in T, except the extreme root beyond the last pole.
-//    That one is solved with the direct sums (its interval, up to
-//    d_{K-1} + rho sum w, can be wider than all the poles together);
+//    root of the leaf lies in T. Two roots are solved with the direct sums
+//    instead: the extreme root beyond the last pole (its interval, up to
+//    d_{K-1} + rho sum w, can be wider than all the poles together) and the
+//    root between the first two poles (after an update with rho > 0 the top
+//    eigenvalue can sit far above the rest, and the next update, with
+//    rho < 0, sees it reflected as its first pole). Leaf 0 starts at pole 1;
 //  * a pole at distance >= |T| from T is far. Far poles left of T are all
 //    below every root of the leaf (they enter psi), far poles right of it all
 //    above (they enter phi). Each of psi, psi', phi, phi' over the far poles
@@ -792,18 +795,19 @@ __global__ __launch_bounds__(BT) void secular_kernel(StageLevel L, int maxit) {
 
 // Far-field form of the secular kernel, for levels with an order above
 // kGroupMaxN: one block of kSfThreads per leaf, then one more per job for the
-// extreme root. A leaf's block first builds the
-// leaf's interval, near range and interpolation data (sf_setup), then its
+// two roots of the direct sums. A leaf's block first builds the leaf's
+// interval, near range and interpolation data (sf_setup), then its
 // kSfThreads / 16 = kSfLeaf groups of 16 lanes solve the leaf's roots with
-// secular_sums_ff. The extreme root's block solves that root with the direct
-// sums on one wave, from an LDS copy of the poles as in the secular kernel.
+// secular_sums_ff. The last block solves the extreme root (wave 0) and the
+// root between the first two poles (wave 1) with the direct sums, from an LDS
+// copy of the poles as in the secular kernel.
 constexpr int kSfThreads = 1024;
 static_assert(kSfThreads / 16 == kSfLeaf && kSmallGroup == 16, "one 16-lane group per root of a leaf");
 static_assert(kSfThreads == 32 * kSfP, "one thread per (point, pole stride) pair");
 
-// Interval, near range and interpolation data of leaf k0 of the stage's
-// reflected problem (K live poles, k0 < K - 1), in units of the secular
-// iteration. The poles pass through LDS in chunks of kSfChunk; each is
+// Interval T = [pole a, pole b] (a < b), near range and interpolation data of
+// a leaf of the stage's reflected problem (K live poles), in units of the
+// secular iteration. The poles pass through LDS in chunks of kSfChunk; each is
 // classified on the way (far below T, far above T, or near) and its far terms
 // are added at the 32 points. The poles ascend, so the far poles below T are
 // the first nl and those above it the last nr, and the near range is
@@ -812,16 +816,17 @@ static_assert(kSfThreads == 32 * kSfP, "one thread per (point, pole stride) pair
 constexpr int kSfChunk = 2048;
 constexpr int kSfRed = 4 * 32 * 33;
 
-__device__ void sf_setup(const Stage& s, int K, int k0, SfLeaf* lf, double* red, double* sp, double* sw, int* cnt) {
+__device__ void sf_setup(const Stage& s, int K, int a, int b, SfLeaf* lf, double* red, double* sp, double* sw,
+                         int* cnt) {
   const double rho0 = *s.rho;
   const Reflect<false> R{s.g, s.W2, K, rho0 < 0.0};
   const double sc = 1.0 / secular_unit(R);
   auto pole = [&](int k) { return R.pole(k) * sc; };
   auto wt = [&](int k) { return R.wt(k) * sc; };
   const int t = threadIdx.x;
-  const double lo = pole(k0);
+  const double lo = pole(a);
   if (t < 2) cnt[t] = 0;
-  const double w = pole(min(k0 + kSfLeaf, K - 1)) - lo;
+  const double w = pole(b) - lo;
   // far sums at the Chebyshev points x_q = lo + h (1 + t_q): point q = t % 32,
   // poles j = t / 32, t / 32 + 32, ... of each chunk
   const int q = t & (kSfP - 1), r = t >> 5;
@@ -875,7 +880,7 @@ __device__ void sf_setup(const Stage& s, int K, int k0, SfLeaf* lf, double* red,
     lf->f[a][qq] = f;
   }
   if (t == 0) {
-    lf->k0 = k0;
+    lf->k0 = a;
     lf->kl = cnt[0];
     lf->kr = K - 1 - cnt[1];
     lf->h = 0.5 * w;
@@ -912,26 +917,32 @@ __global__ __launch_bounds__(kSfThreads) void secular_ff_kernel(StageLevel L, in
     return;
   }
   const bool refl = *s.rho < 0.0;
-  if (b == (s.N + kSfLeaf - 1) / kSfLeaf) {   // the extreme root, K - 1 of the reflected problem
-    const int idx = refl ? 0 : K - 1;
+  if (b == (s.N + kSfLeaf - 1) / kSfLeaf) {
+    // the direct sums: wave 0 the extreme root K - 1, wave 1 root 0 (roots of the reflected problem)
+    const int w = threadIdx.x >> 6;
+    const int i = w == 0 ? K - 1 : 0;
+    const bool mine = w < 2 && (w == 0 || K > 1);
+    const int idx = refl ? K - 1 - i : i;
     if (s.N <= kSecLdsN) {
       for (int e = threadIdx.x; e < K; e += blockDim.x) {
         lds[e] = gld(s.g + e);
         lds[kSecLdsN + e] = gld(s.W2 + e);
       }
       __syncthreads();
-      if (threadIdx.x < 64)
+      if (mine)
         secular_body<64, true>(s.counts, lds, lds + kSecLdsN, s.rho, s.org, s.tau, s.iters, s.status, maxit, idx);
-    } else if (threadIdx.x < 64) {
+    } else if (mine) {
       secular_body<64, false>(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit, idx);
     }
     return;
   }
+  // this leaf's roots of the far-field form: [r0, r1) without 0 and K - 1
   const int k0 = b * kSfLeaf;
-  if (k0 >= K - 1) return;   // no root of this leaf but the extreme one
-  sf_setup(s, K, k0, &lf, lds, lds + kSfRed, lds + kSfRed + kSfChunk, cnt);
+  const int r0 = max(k0, 1), r1 = min(k0 + kSfLeaf, K - 1);
+  if (r0 >= r1) return;
+  sf_setup(s, K, r0, r1, &lf, lds, lds + kSfRed, lds + kSfRed + kSfChunk, cnt);
   const int i = k0 + (threadIdx.x >> 4);   // root of the reflected problem
-  if (i >= K - 1) return;
+  if (i < r0 || i >= r1) return;
   secular_body<16, false, true>(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit,
                                 refl ? K - 1 - i : i, &lf);
 }

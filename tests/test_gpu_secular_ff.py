@@ -56,6 +56,12 @@ def _poles(K, kind, rng):
     if kind == "pairs":     # close pairs one part in 1e11 apart
         base = np.sort(rng.uniform(0.1, 1.0, (K + 1) // 2))
         return np.sort(np.concatenate([base, base * (1 + 2e-11)]))[:K]
+    if kind == "top_outlier":
+        # the spectrum after an update with rho > 0: the top pole far above the
+        # rest (with rho < 0 the reflected problem sees it as its first pole)
+        d = np.sort(rng.uniform(0.0, 1.0, K))
+        d[-1] = 4.0
+        return d
     # a tight cluster of most poles inside a wide spread: near ranges of the
     # cluster's neighbours cover most poles
     nc = (3 * K) // 4
@@ -78,7 +84,7 @@ def _check_roots(d, z, rho, org_g, tau_g):
 
 @pytest.mark.parametrize("K", [1, 2, 63, 64, 65, 200, 1000, 3000])
 @pytest.mark.parametrize("rho", [0.8, -0.8])
-@pytest.mark.parametrize("kind", ["uniform", "geometric", "pairs", "cluster"])
+@pytest.mark.parametrize("kind", ["uniform", "geometric", "pairs", "cluster", "top_outlier"])
 def test_far_field_roots_match_oracle(lib, ffctx, K, rho, kind):
     rng = np.random.default_rng(K + 100)
     d = _poles(K, kind, rng)

@@ -2,8 +2,9 @@
 
 The far-field form (SVDU_OPT_SECULAR_FMM) splits the poles into leaves of 64
 consecutive poles. Leaf l's interval T runs from its first pole to the next
-leaf's first pole (the last leaf: to the last pole; the extreme root beyond it
-takes the direct sums). Poles at least |T| from T are far: those below T enter psi and those
+leaf's first pole (the last leaf: to the last pole; leaf 0 from the second
+pole: the extreme root beyond the last pole and the root between the first two
+poles take the direct sums). Poles at least |T| from T are far: those below T enter psi and those
 above it phi for every root of the leaf. The four far sums psi, psi', phi, phi'
 are sampled at 32 Chebyshev points of the first kind on T and interpolated in
 the barycentric form. This file restates that construction in numpy and
@@ -25,7 +26,7 @@ LEAF, P = 64, 32
 
 def _leaf(d, k0):
     K = d.shape[0]
-    lo = d[k0]
+    lo = d[max(k0, 1)]
     wd = d[min(k0 + LEAF, K - 1)] - lo
     off = d - lo
     kl = int(np.argmax(off > -wd))                    # first near pole
@@ -97,6 +98,10 @@ def _spectrum(kind, K, rng):
     if kind == "pairs":
         base = np.sort(rng.uniform(0.1, 1.0, K // 2))
         return np.sort(np.concatenate([base, base * (1 + 2e-11)]))
+    if kind == "first_outlier":   # reflected spectrum after an update with rho > 0
+        d = np.sort(rng.uniform(0.0, 1.0, K))
+        d[0] = -3.0
+        return d
     nc = (3 * K) // 4
     cl = 1.0 + 1e-9 * (np.arange(nc) + 0.5 * rng.uniform(0.0, 1.0, nc)) / nc
     return np.sort(np.concatenate([cl, rng.uniform(0, 10, K - nc)]))
@@ -114,7 +119,7 @@ def _leaf_errors(kind, rng, form):
         k0 = leaf * LEAF
         lo, wd, kl, kr = _leaf(d, k0)
         # the near range holds the leaf and the next pole; far poles are >= |T| away
-        assert kl <= k0 and kr >= min(k0 + LEAF, K - 1)
+        assert kl <= max(k0, 1) and kr >= min(k0 + LEAF, K - 1)
         assert np.all(lo - d[:kl] >= wd * (1 - 1e-15))
         assert np.all(d[kr + 1:] - (lo + wd) >= wd * (1 - 1e-15))
         h = 0.5 * wd
@@ -130,7 +135,7 @@ def _leaf_errors(kind, rng, form):
     return worst
 
 
-@pytest.mark.parametrize("kind", ["uniform", "geometric", "pairs", "cluster"])
+@pytest.mark.parametrize("kind", ["uniform", "geometric", "pairs", "cluster", "first_outlier"])
 def test_far_field_interpolants_are_at_rounding_level(kind):
     assert _leaf_errors(kind, np.random.default_rng(11), "bary") <= 2e-15
 
