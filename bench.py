@@ -163,7 +163,8 @@ def measure_forms(svdu, torch, U, sigma, V, A_vecs, B_vecs, Uo, so, Vo, stream, 
         def run(k):
             svdu.rank1_update(U, sigma, V, A_vecs[k], B_vecs[k], eps=1e-10, path=path, precision=prec,
                               out=(Uo, so, Vo), workspace=wsf, want_defl=False, stream=stream, check=False, ctx=ctx)
-        run(0)
+        for _ in range(3):   # a fresh context and workspace: the first calls of a form run slower
+            run(0)
         torch.cuda.synchronize()
         ctx.set_option(svdu.SVDU_OPT_TIMING, 1)
         t0 = time.perf_counter()
