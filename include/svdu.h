@@ -325,9 +325,10 @@ int svdu_rank1_update_batched(svdu_ctx* ctx, int count, const svdu_problem* prob
 
 /* ---- tile-shape autotuner --------------------------------------------------
  * For each size bucket up to max_n (<= 8192 recommended), times the product
- * kernel of every tile shape on the same set of synthetic products of order
- * N (the bucket's upper end, or max_n), as many as make 4096 tiles of
- * 128 x 128 (16 per compute unit, so every shape runs on a full device), and stores the
+ * kernel of every tile shape on the same set of synthetic products of four
+ * orders spread over the bucket (up to its upper end, or max_n), each as many
+ * times as make 1024 tiles of 128 x 128 (4096 in all, 16 per compute unit, so
+ * every shape runs on a full device), and stores the
  * fastest shape in the table of `ctx` used by every later call of that
  * precision made with it. times_ms (host, SVDU_TILE_BUCKETS x SVDU_TILE_SHAPES, may be NULL) receives the
  * best of three timed launches per shape (-1 for buckets above max_n), table

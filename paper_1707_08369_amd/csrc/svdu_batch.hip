@@ -41,6 +41,7 @@ namespace {
 int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 constexpr int kTuneTiles = 4096;                       // tuning workload per bucket, in 128 x 128 tiles
+constexpr int kTuneOrders = 4;                         // orders per bucket, spread over it up to its top
 constexpr size_t kTuneOutElems = (size_t)1 << 26;      // 512 MiB of outputs: 4096 tiles of any N <= 8192
 
 // Batch workspace: status words, tile counters, tables, then one update layout per problem.
@@ -386,36 +387,52 @@ int svdu_autotune(svdu_ctx* ctx, int precision, int max_n, double* times_ms, int
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SVDU_EHIP;
   int rc = SVDU_OK;
   for (int bk = 0; bk < kShapeBuckets && rc == SVDU_OK; ++bk) {
-    const int N = std::min(64 << bk, max_n);
-    if (bk > 0 && (64 << (bk - 1)) >= max_n) {   // bucket beyond max_n: keep the table entry
+    const int hi = std::min(64 << bk, max_n), lo = bk == 0 ? 0 : (64 << (bk - 1));
+    if (bk > 0 && lo >= max_n) {   // bucket beyond max_n: keep the table entry
       if (times_ms)
         for (int s = 0; s < kNumShapes; ++s) times_ms[bk * kNumShapes + s] = -1.0;
       if (table) table[bk] = tab[bk];
       continue;
     }
-    // the same set of products for every shape: 4096 tiles of 128 x 128 (16 per
-    // compute unit), so that every shape sees the device full
-    const int tiles128 = cdiv(N, 128) * cdiv(N, 128);
-    int count = std::max(1, cdiv(kTuneTiles, tiles128));
-    count = (int)std::min<size_t>((size_t)count, out_elems / ((size_t)N * N));
-    d = CauchyDesc{N, rg, rzeta, rh, rcl, ctype, co, ctau, ccs, ccl, cmem, ch, nullptr, status};
+    // the same set of products for every shape, of kTuneOrders orders spread
+    // over the bucket (a shape's ragged last tile row costs differently at
+    // different orders), each as many times as make kTuneTiles / kTuneOrders
+    // tiles of 128 x 128, so that every shape sees the device full
+    std::vector<int> Ns, counts;
+    size_t used = 0;
+    for (int j = 0; j < kTuneOrders; ++j) {
+      const int N = std::max(1, lo + ((hi - lo) * (j + 1) + kTuneOrders - 1) / kTuneOrders);
+      const int tiles128 = cdiv(N, 128) * cdiv(N, 128);
+      int count = std::max(1, cdiv(kTuneTiles / kTuneOrders, tiles128));
+      count = (int)std::min<size_t>((size_t)count, (out_elems - used) / ((size_t)N * N));
+      if (count < 1) continue;
+      Ns.push_back(N);
+      counts.push_back(count);
+      used += (size_t)count * N * N;
+    }
     double best = 1e30;
     int best_s = tab[bk];
     for (int s = 0; s < kNumShapes; ++s) {
       std::vector<GemmJob> jobs;
-      for (int k = 0; k < count; ++k) {
-        GemmJob J{};
-        J.R = N;
-        J.ldx = N;
-        J.ldo = N;
-        J.vec_a = (N % 2) == 0 ? 1 : 0;
-        J.shape = run_shape(s, precision == SVDU_PREC_SPLIT32);
-        J.tiles_n = cdiv(N, shape_bn(J.shape));
-        J.tiles = cdiv(N, shape_bm(J.shape)) * J.tiles_n;
-        J.X = X;
-        J.Xo = Xo + (size_t)k * N * N;
-        J.d = d;
-        jobs.push_back(J);
+      size_t off = 0;
+      for (size_t o = 0; o < Ns.size(); ++o) {
+        const int N = Ns[o];
+        d = CauchyDesc{N, rg, rzeta, rh, rcl, ctype, co, ctau, ccs, ccl, cmem, ch, nullptr, status};
+        for (int k = 0; k < counts[o]; ++k) {
+          GemmJob J{};
+          J.R = N;
+          J.ldx = N;
+          J.ldo = N;
+          J.vec_a = (N % 2) == 0 ? 1 : 0;
+          J.shape = run_shape(s, precision == SVDU_PREC_SPLIT32);
+          J.tiles_n = cdiv(N, shape_bn(J.shape));
+          J.tiles = cdiv(N, shape_bm(J.shape)) * J.tiles_n;
+          J.X = X;
+          J.Xo = Xo + off;
+          J.d = d;
+          jobs.push_back(J);
+          off += (size_t)N * N;
+        }
       }
       std::vector<char> blob;
       BlobWriter B{&blob, tables};

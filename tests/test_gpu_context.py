@@ -123,3 +123,79 @@ def test_server_keeps_the_options_of_its_creation(lib):
             srv.close()
     finally:
         ctx.close()
+
+
+def _fmm_problem(seed, m, n):
+    rng = np.random.default_rng(seed)
+    return [S.haar_torch(m, seed=seed, device="cuda"), dev(S.sigma_uniform(m, 1e-3, 1.0, rng)),
+            S.haar_torch(n, seed=seed + 1, device="cuda"), dev(rng.standard_normal(m) / np.sqrt(n)),
+            dev(rng.standard_normal(n) / np.sqrt(n))]
+
+
+def _run_fmm(lib, ctx, args, stream, reps):
+    outs = []
+    with torch.cuda.stream(stream):
+        for _ in range(reps):
+            Uo, so, Vo, _ = lib.rank1_update(*args, path=lib.SVDU_PATH_FMM, eps=1e-10, ctx=ctx, stream=stream,
+                                             want_defl=False)
+            outs.append((Uo, so, Vo))
+    stream.synchronize()
+    return outs
+
+
+def test_fmm_path_two_contexts_two_threads_bitwise(lib):
+    """The FMM path forks its right-hand products onto a second stream of the
+    context and joins them back, and copies roots into the context's pinned
+    memory: two contexts driving it at once from two threads, each on its own
+    stream, give bitwise their single-thread results (order 3000, so the
+    secular roots take the far-field form too)."""
+    ca, cb = lib.Context(), lib.Context()
+    try:
+        pa, pb = _fmm_problem(31, 3000, 3000), _fmm_problem(41, 2500, 3100)
+        sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+        ref_a = _run_fmm(lib, ca, pa, sa, 1)[0]
+        ref_b = _run_fmm(lib, cb, pb, sb, 1)[0]
+        # against the direct path of the same inputs
+        for p, ref in ((pa, ref_a), (pb, ref_b)):
+            Ud, sd, Vd, _ = lib.rank1_update(*p, want_defl=False)
+            assert float((ref[1] - sd).abs().max()) <= 1e-13 * float(sd[0])
+            assert float((ref[0] - Ud).abs().max()) <= 1e-9 and float((ref[2] - Vd).abs().max()) <= 1e-9
+        got = {}
+
+        def worker(name, ctx, args, stream):
+            got[name] = _run_fmm(lib, ctx, args, stream, 3)
+
+        ta = threading.Thread(target=worker, args=("a", ca, pa, sa))
+        tb = threading.Thread(target=worker, args=("b", cb, pb, sb))
+        ta.start()
+        tb.start()
+        ta.join()
+        tb.join()
+        for name, ref in (("a", ref_a), ("b", ref_b)):
+            assert len(got[name]) == 3
+            for o in got[name]:
+                for x, y in zip(o, ref):
+                    assert torch.equal(x, y), name
+    finally:
+        ca.close()
+        cb.close()
+
+
+def test_fmm_path_context_reused_across_orders(lib):
+    """One context's pinned root buffer grows with the order; calls of
+    different orders in a row match fresh contexts' results bitwise."""
+    ctx = lib.Context()
+    try:
+        s = torch.cuda.current_stream()
+        for m, seed in ((500, 51), (3000, 52), (500, 53)):
+            p = _fmm_problem(seed, m, m)
+            got = _run_fmm(lib, ctx, p, s, 1)[0]
+            fresh = lib.Context()
+            try:
+                ref = _run_fmm(lib, fresh, p, s, 1)[0]
+            finally:
+                fresh.close()
+            for x, y in zip(got, ref):
+                assert torch.equal(x, y), m
+    finally:
+        ctx.close()
