@@ -139,10 +139,9 @@ size_t svdu_workspace_bytes(int m, int n, int path, int precision);
  *  path        SVDU_PATH_DIRECT or SVDU_PATH_FMM. The FMM path copies the
  *              roots of each level of eigen-updates to the host to build its
  *              trees (the call waits for them, and returns once the second
- *              level's products are enqueued); it runs the right-hand
- *              products on a second stream of the context, forked from and
- *              joined to `stream` with events. It works with SVDU_PREC_FP64
- *              only.
+ *              level's products are enqueued); it runs part of its products
+ *              on two more streams of the context, forked from and joined to
+ *              `stream` with events. It works with SVDU_PREC_FP64 only.
  *  precision   SVDU_PREC_FP64, SVDU_PREC_SPLIT32 or SVDU_PREC_SLICED_INT8 (the
  *              last two on SVDU_PATH_DIRECT only; SVDU_PREC_SLICED_INT8 for
  *              n <= 32768, above which its INT32 sums could overflow:
@@ -260,7 +259,8 @@ int svdu_secular(svdu_ctx* ctx, int K, const double* d, const double* z, double 
  * updates (deflation, secular roots, weights, signs, singular values), 2 and
  * 3 the products X C~ (direct path: first level U C~_L+ and V C~_R+, then
  * second level U~ C~_L- and V~ C~_R-, with the column rescaling of the
- * precision form; the FMM path the same levels), 4 the flag copies.
+ * precision form; on the FMM path the first level's products partly run
+ * beside phase 1, so phase 2 holds what remains of them), 4 the flag copies.
  * Waits for those events. Returns the number of calls filled, or SVDU_EHIP. */
 int svdu_timing_read(svdu_ctx* ctx, double* ms, int max_calls);
 

@@ -238,12 +238,16 @@ struct svdu_ctx {
   svdu::TimingRing ring;
   bool have_caps = false;
   int grid_cap[svdu::kNumPrec][svdu::kNumShapes] = {};
-  // a second stream for the FMM path's right-hand products (default priority),
-  // forked from and joined to the caller's stream with two events; these and
-  // the events below are created on first use
-  hipStream_t aux = nullptr;
+  // two more streams for the FMM path's products (default priority), forked
+  // from and joined to the caller's stream with events; all are created on
+  // first use
+  hipStream_t aux = nullptr, aux2 = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
   hipEvent_t roots[2] = {nullptr, nullptr};   // the FMM path's root copies of each level are done
+  hipEvent_t up0 = nullptr;                   // the first level's plans are uploaded (on aux)
+  hipEvent_t done_a = nullptr, done_b = nullptr;   // the first level's products are done (aux, aux2)
+  hipEvent_t uploaded = nullptr;              // every plan upload of the last call has read the pinned memory
+  bool upload_pending = false;
   // pinned host memory for the FMM path's copies of the roots (grown on
   // demand; every copy into it has completed when a call returns)
   void* pinned = nullptr;

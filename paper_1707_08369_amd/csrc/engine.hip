@@ -718,10 +718,11 @@ int gemm_grid_cap(int shape, int precision) {
 }  // namespace svdu
 
 svdu_ctx::~svdu_ctx() {
-  if (aux) (void)hipStreamDestroy(aux);   // work already enqueued on it still completes
-  if (fork) (void)hipEventDestroy(fork);
-  if (join) (void)hipEventDestroy(join);
-  for (hipEvent_t e : roots)
+  // the pinned memory may still be read by the last call's plan upload
+  if (upload_pending && uploaded) (void)hipEventSynchronize(uploaded);
+  for (hipStream_t s : {aux, aux2})
+    if (s) (void)hipStreamDestroy(s);   // work already enqueued on it still completes
+  for (hipEvent_t e : {fork, join, roots[0], roots[1], up0, done_a, done_b, uploaded})
     if (e) (void)hipEventDestroy(e);
   if (pinned) (void)hipHostFree(pinned);
 }

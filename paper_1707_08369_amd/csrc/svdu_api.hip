@@ -148,39 +148,56 @@ int fmm_products_impl(int nst, Stage* stages, const int* Rs, const double* const
   return SVDU_OK;
 }
 
-// The whole update on the FMM path, from the projections to the products
-// (the caller enqueues the rest). The products run by level: U C~_L+ -> TL
-// and V C~_R+ -> TR, then TL C~_L- -> U^ and TR C~_R- diag(s) -> V^. A level's
-// roots are copied to the host as soon as its eigen-updates are enqueued, so
-// the host builds the first level's tree plans while the device runs the
-// second level's eigen-updates, and the second level's plans while it runs
-// the first level's products. Within a level the right-hand product runs on
-// the context's second stream (with its own work buffer) beside the left-hand
-// one, so that the many small launches of the two tree passes overlap.
-// The context's second stream and the events of the FMM path (made on first
+// The context's other streams and the events of the FMM path (made on first
 // use, on the context's device, which is current).
 static bool fmm_sync_objects(svdu_ctx* ctx) {
   auto event = [](hipEvent_t* e) {
     if (!*e && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) *e = nullptr;
     return *e != nullptr;
   };
-  if (!ctx->aux && hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess) ctx->aux = nullptr;
-  const bool ev = event(&ctx->fork) && event(&ctx->join) && event(&ctx->roots[0]) && event(&ctx->roots[1]);
-  return ctx->aux && ev;
+  auto stream = [](hipStream_t* s) {
+    if (!*s && hipStreamCreateWithFlags(s, hipStreamNonBlocking) != hipSuccess) *s = nullptr;
+    return *s != nullptr;
+  };
+  const bool ss = stream(&ctx->aux) && stream(&ctx->aux2);
+  const bool ev = event(&ctx->fork) && event(&ctx->join) && event(&ctx->roots[0]) && event(&ctx->roots[1]) &&
+                  event(&ctx->up0) && event(&ctx->done_a) && event(&ctx->done_b) && event(&ctx->uploaded);
+  return ss && ev;
 }
 
+// The whole update on the FMM path, from the projections to the products
+// (the caller enqueues the rest). The products run by level: U C~_L+ -> TL
+// and V C~_R+ -> TR, then TL C~_L- -> U^ and TR C~_R- diag(s) -> V^. The tree
+// plans are built on the host from the roots, so each level's roots are
+// copied into pinned host memory as soon as its eigen-updates are enqueued:
+//  * level 0: once its roots arrive, the host builds its plans while the
+//    device runs the level-1 eigen-updates; the plans are uploaded and the
+//    two products run on the context's two other streams, beside those
+//    eigen-updates (they only read U, V and the level-0 descriptors);
+//  * level 1: the host builds its plans while the level-0 products run; the
+//    caller's stream uploads them, waits for the level-0 products, and runs
+//    the left-hand product while the second stream runs the right-hand one.
+// Every stream is joined back into the caller's stream before the call
+// returns, also after an error. Results do not depend on the overlap.
 int fmm_update(svdu_ctx* ctx, const Update& u, const Plan& P, double eps, const Sched& S, hipStream_t st) {
   const Layout& L = u.L;
   if (!fmm_sync_objects(ctx)) return SVDU_EHIP;
+  if (ctx->upload_pending) {   // the last call's uploads read the pinned memory
+    if (hipEventSynchronize(ctx->uploaded) != hipSuccess) return SVDU_EHIP;
+    ctx->upload_pending = false;
+  }
   struct LevelHost {
     HostRoots h[2];   // the left and the right eigen-update of the level
     int* status;
     hipEvent_t ev;
+    char* blob;       // pinned staging of the level's plans
   } H[2];
-  // pinned host memory for the copies, so that they do not hold up the host
-  // while it enqueues the next level: 256 bytes of status words, then the roots
+  // pinned host memory: 256 bytes of status words, the roots, then one plan
+  // staging area per level
+  const size_t half = (L.fmm_plan_bytes / 2) & ~size_t(255);   // the plans of one level (two products)
   size_t need = 256;
   for (int k = 0; k < 4; ++k) need += host_roots_bytes(P.host_stages[k].N);
+  need += 2 * half;
   if (need > ctx->pinned_bytes) {
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     ctx->pinned = nullptr;
@@ -204,6 +221,8 @@ int fmm_update(svdu_ctx* ctx, const Update& u, const Plan& P, double eps, const 
         H[lev].h[side] = host_roots_at(p + at, N);
         at += host_roots_bytes(N);
       }
+    H[0].blob = p + at;
+    H[1].blob = p + at + half;
   }
   const std::function<void(int)> copy_roots = [&](int lev) {
     (void)hipMemcpyAsync(H[lev].status, L.status, sizeof(int), hipMemcpyDeviceToHost, st);
@@ -211,54 +230,91 @@ int fmm_update(svdu_ctx* ctx, const Update& u, const Plan& P, double eps, const 
     (void)hipEventRecord(H[lev].ev, st);
   };
   enqueue_plan(P, S, kStepUpToRoots, st, &copy_roots);
+  // one product of level lev, side 0 (left) or 1 (right)
+  auto product = [&](int lev, int side, const FmmPrepared& pp, const char* plan, hipStream_t s) {
+    const bool left = side == 0;
+    const int N = left ? u.m : u.n;
+    const double* X = lev == 0 ? (left ? u.U : u.V) : (left ? L.TL : L.TR);
+    const int ldx = lev == 0 ? (left ? u.ldu : u.ldv) : N;
+    double* Xo = lev == 0 ? (left ? L.TL : L.TR) : (left ? u.U_out : u.V_out);
+    const int ldo = lev == 0 ? N : (left ? u.ldu_out : u.ldv_out);
+    const double* sc = (lev == 1 && !left) ? L.signs : nullptr;
+    return fmm_launch(N, X, ldx, P.host_stages[2 * side + lev], pp, plan, Xo, ldo, sc,
+                      left ? L.fmm_work_l : L.fmm_work, left ? L.fmm_elems_l : L.fmm_elems, s) == 0
+               ? SVDU_OK
+               : SVDU_ENOMEM;
+  };
+  // the plans of level lev from its roots, staged in pinned memory; size in *bytes
+  auto plans = [&](int lev, FmmPrepared (&prep)[2], size_t* bytes) {
+    std::vector<char> blob;
+    for (int side = 0; side < 2; ++side)
+      if (const int rc = prepare_plan(P.host_stages[2 * side + lev], H[lev].h[side], eps, &blob, &prep[side]))
+        return rc;
+    if (blob.size() > half) return SVDU_ENOMEM;
+    if (!blob.empty()) memcpy(H[lev].blob, blob.data(), blob.size());
+    *bytes = blob.size();
+    return SVDU_OK;
+  };
   int rc = SVDU_OK;
-  size_t off = 0;
-  for (int lev = 0; lev < 2; ++lev) {
-    if (hipEventSynchronize(H[lev].ev) != hipSuccess) {
+  bool level0 = false;   // level-0 work was enqueued on the other streams
+  do {
+    // level 0, on the two other streams
+    if (hipEventSynchronize(H[0].ev) != hipSuccess) {
       rc = SVDU_EHIP;
       break;
     }
-    if (*H[lev].status & kStFatal) break;   // reported by svdu_get_status
-    std::vector<char> blob;
-    FmmPrepared prep[2];
-    for (int side = 0; side < 2 && rc == SVDU_OK; ++side)
-      rc = prepare_plan(P.host_stages[2 * side + lev], H[lev].h[side], eps, &blob, &prep[side]);
-    if (rc != SVDU_OK) break;
-    if (off + blob.size() > L.fmm_plan_bytes) {
-      rc = SVDU_ENOMEM;
+    if (*H[0].status & kStFatal) break;   // reported by svdu_get_status
+    FmmPrepared prep0[2];
+    size_t bytes0 = 0;
+    if ((rc = plans(0, prep0, &bytes0)) != SVDU_OK) break;
+    level0 = true;
+    if (hipStreamWaitEvent(ctx->aux, H[0].ev, 0) != hipSuccess ||
+        (bytes0 && hipMemcpyAsync(L.fmm_plan, H[0].blob, bytes0, hipMemcpyHostToDevice, ctx->aux) != hipSuccess) ||
+        hipEventRecord(ctx->up0, ctx->aux) != hipSuccess || hipStreamWaitEvent(ctx->aux2, ctx->up0, 0) != hipSuccess) {
+      rc = SVDU_EHIP;
       break;
     }
-    char* plan = L.fmm_plan + off;
-    if (!blob.empty()) {
-      if (hipMemcpyAsync(plan, blob.data(), blob.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess) {   // blob is a host temporary
-        rc = SVDU_EHIP;
-        break;
-      }
+    if ((rc = product(0, 0, prep0[0], L.fmm_plan, ctx->aux)) != SVDU_OK) break;
+    if ((rc = product(0, 1, prep0[1], L.fmm_plan, ctx->aux2)) != SVDU_OK) break;
+    // level 1, forked from the caller's stream
+    if (hipEventSynchronize(H[1].ev) != hipSuccess) {
+      rc = SVDU_EHIP;
+      break;
     }
-    off += (blob.size() + 255) & ~size_t(255);
+    if (*H[1].status & kStFatal) break;
+    FmmPrepared prep1[2];
+    size_t bytes1 = 0;
+    if ((rc = plans(1, prep1, &bytes1)) != SVDU_OK) break;
+    char* plan1 = L.fmm_plan + half;
+    if (bytes1 && hipMemcpyAsync(plan1, H[1].blob, bytes1, hipMemcpyHostToDevice, st) != hipSuccess) {
+      rc = SVDU_EHIP;
+      break;
+    }
+    if (hipEventRecord(ctx->done_a, ctx->aux) != hipSuccess || hipEventRecord(ctx->done_b, ctx->aux2) != hipSuccess ||
+        hipStreamWaitEvent(st, ctx->done_a, 0) != hipSuccess || hipStreamWaitEvent(st, ctx->done_b, 0) != hipSuccess) {
+      rc = SVDU_EHIP;
+      break;
+    }
+    level0 = false;   // joined
+    S.mark(3, st);
     if (hipEventRecord(ctx->fork, st) != hipSuccess || hipStreamWaitEvent(ctx->aux, ctx->fork, 0) != hipSuccess) {
       rc = SVDU_EHIP;
       break;
     }
-    for (int side = 0; side < 2 && rc == SVDU_OK; ++side) {
-      const bool left = side == 0;
-      const int N = left ? u.m : u.n;
-      const double* X = lev == 0 ? (left ? u.U : u.V) : (left ? L.TL : L.TR);
-      const int ldx = lev == 0 ? (left ? u.ldu : u.ldv) : N;
-      double* Xo = lev == 0 ? (left ? L.TL : L.TR) : (left ? u.U_out : u.V_out);
-      const int ldo = lev == 0 ? N : (left ? u.ldu_out : u.ldv_out);
-      const double* sc = (lev == 1 && !left) ? L.signs : nullptr;
-      if (fmm_launch(N, X, ldx, P.host_stages[2 * side + lev], prep[side], plan, Xo, ldo, sc,
-                     left ? L.fmm_work_l : L.fmm_work, left ? L.fmm_elems_l : L.fmm_elems,
-                     left ? st : ctx->aux) != 0)
-        rc = SVDU_ENOMEM;
-    }
-    // join even after an error: nothing on the second stream may outlive the call's stream order
+    rc = product(1, 0, prep1[0], plan1, st);
+    if (rc == SVDU_OK) rc = product(1, 1, prep1[1], plan1, ctx->aux);
     if (hipEventRecord(ctx->join, ctx->aux) != hipSuccess || hipStreamWaitEvent(st, ctx->join, 0) != hipSuccess)
       rc = SVDU_EHIP;
-    if (rc == SVDU_OK) S.mark(3 + lev, st);
+    if (rc == SVDU_OK) S.mark(4, st);
+  } while (false);
+  if (level0) {   // an exit between the levels: join the other streams all the same
+    (void)hipEventRecord(ctx->done_a, ctx->aux);
+    (void)hipEventRecord(ctx->done_b, ctx->aux2);
+    (void)hipStreamWaitEvent(st, ctx->done_a, 0);
+    (void)hipStreamWaitEvent(st, ctx->done_b, 0);
   }
+  // every upload has been enqueued before this point on a stream the caller's now waits for
+  if (hipEventRecord(ctx->uploaded, st) == hipSuccess) ctx->upload_pending = true;
   // the root copies write the pinned buffer: let every one finish before the call returns
   for (LevelHost& x : H) (void)hipEventSynchronize(x.ev);
   return rc;

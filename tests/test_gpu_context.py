@@ -199,3 +199,29 @@ def test_fmm_path_context_reused_across_orders(lib):
                 assert torch.equal(x, y), m
     finally:
         ctx.close()
+
+
+def test_fmm_path_error_exit_then_reuse(lib):
+    """A non-finite input stops the FMM path before its products (the status
+    word is read with the first level's roots); the call reports
+    SVDU_ENONFINITE, and the same context's next call is bitwise a fresh
+    context's."""
+    ctx = lib.Context()
+    try:
+        p = _fmm_problem(61, 2300, 2300)
+        bad = list(p)
+        bad[3] = p[3].clone()
+        bad[3][7] = float("nan")
+        with pytest.raises(lib.SvduError) as e:
+            lib.rank1_update(*bad, path=lib.SVDU_PATH_FMM, eps=1e-10, ctx=ctx, want_defl=False)
+        assert e.value.code == lib.SVDU_ENONFINITE
+        got = lib.rank1_update(*p, path=lib.SVDU_PATH_FMM, eps=1e-10, ctx=ctx, want_defl=False)
+        fresh = lib.Context()
+        try:
+            ref = lib.rank1_update(*p, path=lib.SVDU_PATH_FMM, eps=1e-10, ctx=fresh, want_defl=False)
+        finally:
+            fresh.close()
+        for x, y in zip(got[:3], ref[:3]):
+            assert torch.equal(x, y)
+    finally:
+        ctx.close()
