@@ -370,6 +370,27 @@ def measure_secular_far_field(svdu, torch, reps=20):
     return res
 
 
+def measure_fmm_crossover(svdu, torch, sizes=(256, 512, 1024, 2048, 4096, 8192)):
+    """Direct against FMM product path (eps = 1e-10) as the order grows (the
+    analogue of the paper's comparison of the direct and the fast product):
+    m = n, sigma ~ U[1e-3, 1], Haar factors; time per update on each path,
+    their ratio, and the FMM result's largest difference from the direct one.
+    The crossover is the smallest order from which the FMM path is faster."""
+    import synth_inputs as S
+    rows = []
+    for N in sizes:
+        args = haar_inputs(torch, S, N, N, 7000 + N)
+        reps = 20 if N <= 1024 else (5 if N <= 4096 else 3)
+        md, od = _time_update(svdu, torch, args, reps=reps)
+        mf, of = _time_update(svdu, torch, args, reps=reps, path=svdu.SVDU_PATH_FMM, eps=1e-10)
+        err = max((of[0] - od[0]).abs().max().item(), (of[2] - od[2]).abs().max().item())
+        rows.append({"n": N, "direct_ms": md, "fmm_ms": mf, "fmm_speedup": md / mf, "fmm_vs_direct_max_abs": err})
+        del args, od, of
+    faster = [r["n"] for r in rows if r["fmm_speedup"] > 1.0]
+    return {"workload": "m=n, sigma~U[1e-3,1], haar U,V, a,b~N(0,1/n), fp64, direct vs fmm eps=1e-10",
+            "orders": rows, "fmm_faster_from_n": min(faster) if faster else None}
+
+
 def batched_workload(torch, count=512, seed=4):
     """512 independent problems: m log-uniform in [64, 1024], n = m + U{0..m},
     sigma ~ U[0.01, 10] descending, Haar U and V, a, b ~ N(0, 1/n)."""
@@ -581,7 +602,7 @@ def main():
                     help="seconds of arrivals at the stated rate (50 s: the 100k-request stream at 2000/s)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other workloads (m=n=256 latency, m=n=4096 direct vs FMM, m=4096 n=8192 "
-                         "precision forms, FMM order sweep, secular far field)")
+                         "precision forms, FMM order sweep, secular far field, direct vs FMM crossover)")
     ap.add_argument("--serving-only", action="store_true", help="measure only the serving form")
     ap.add_argument("--batch-reps", type=int, default=5, help="timed launches of the batched workload")
     ap.add_argument("--batched-only", action="store_true",
@@ -749,6 +770,8 @@ def main():
         cf["fmm_order_sweep"] = measure_fmm_order_sweep(svdu, torch)
         print("[bench] secular sums: direct vs far field ...", file=sys.stderr, flush=True)
         cf["secular_far_field"] = measure_secular_far_field(svdu, torch)
+        print("[bench] direct vs FMM crossover ...", file=sys.stderr, flush=True)
+        cf["fmm_crossover"] = measure_fmm_crossover(svdu, torch)
     if not args.no_serving:
         print("[bench] serving form ...", file=sys.stderr, flush=True)
         out.setdefault("forms", {})["serving"] = measure_serving(svdu, torch, arrival_s=args.serving_window)
