@@ -32,6 +32,8 @@
 // B[l / 16][l % 16]; result register v holds D[l / 16 + 4 v][l % 16].
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "cauchy_tile.h"
 #include "copy_path.h"
 #include "jobs.h"
@@ -89,18 +91,24 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
     for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
   double aA[MB][4], aB[MB][4], bg[RPW][NC];
+  // X of the half-step at k index k0: 16-byte loads (aligned rows, the whole
+  // step in range), or element loads with the tail zeroed
+  auto loadA_vec = [&](int k0, double (&a)[MB][4]) {
+    const int kb = k0 + kq;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const double2 v0 = gld2(xr[mb] + kb);
+      const double2 v1 = gld2(xr[mb] + kb + 2);
+      a[mb][0] = v0.x;
+      a[mb][1] = v0.y;
+      a[mb][2] = v1.x;
+      a[mb][3] = v1.y;
+    }
+  };
   auto loadA = [&](int k0, double (&a)[MB][4]) {
     const int kb = k0 + kq;
     if (J.vec_a && k0 + kBK <= N) {   // block-uniform: the whole step is in range
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const double2 v0 = gld2(xr[mb] + kb);
-        const double2 v1 = gld2(xr[mb] + kb + 2);
-        a[mb][0] = v0.x;
-        a[mb][1] = v0.y;
-        a[mb][2] = v1.x;
-        a[mb][3] = v1.y;
-      }
+      loadA_vec(k0, a);
     } else {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
@@ -132,14 +140,42 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
   // Half-step hs covers k in [16 hs, 16 hs + 16). The LDS buffers hold KH
   // half-steps each; half-step hs is row block hs % KH of buffer (hs / KH) % 2.
   auto bufof = [&](int hs) { return (((hs / KH) & 1) ? Bs1 : Bs0) + (hs % KH) * kBK * BN; };
+  // Row descriptors (zeta, g) of the C~ rows a wave generates in half-step
+  // hs (rows (hs + KH) kBK + RPW wave + r). On the all-live path of the
+  // 8-wave tile (PRE) they are loaded one half-step ahead, before that step's
+  // X: loads complete in the order issued as far as the wait counter is
+  // concerned, so a wait for the descriptors of this half-step never waits
+  // for the X of the next one, and X has a whole half-step to arrive. The
+  // 4-wave tiles have no registers to spare for them and load them where
+  // they are used.
+  constexpr bool PRE = LIVE && W == 8;
+  auto load_desc = [&](int hs, double (&z)[RPW], double (&g)[RPW]) {
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int j = (hs + KH) * kBK + RPW * wave + r, jj = j < N ? j : N - 1;
+      const double zl = gld(d.rzeta + jj);
+      z[r] = (j < N) ? zl : 0.0;
+      g[r] = gld(d.rg + jj);
+    }
+  };
   // one half-step: MFMAs on (a, C~ of hs) interleaved with generating
-  // half-step hs + KH; one barrier per KH half-steps
-  auto step = [&](const double (&a)[MB][4], int hs) {
+  // half-step hs + KH; one barrier per KH half-steps. Issues the descriptor
+  // loads of half-step hs + 1 (into zn, gn) and then X of the half-step at
+  // k index kpre (into an, if kpre >= 0). With VEC (std::true_type; the
+  // 8-wave tile) the X load is a full 16-byte step with no branch, so the
+  // wait counts the compiler places follow the issue order above.
+  auto step = [&](auto VEC, const double (&a)[MB][4], int hs, double (&an)[MB][4], int kpre,
+                  const double (&zc)[RPW], const double (&gc)[RPW], double (&zn)[RPW], double (&gn)[RPW]) {
     const double* Bcur = bufof(hs);
     double* Bnext = bufof(hs + KH);
     const int kn = (hs + KH) * kBK;
     double mind = 1.0;
     const int jb = kn + RPW * wave;
+    if (PRE) load_desc(hs + 1, zn, gn);
+    if constexpr (decltype(VEC)::value)
+      loadA_vec(kpre, an);
+    else if (kpre >= 0)
+      loadA(kpre, an);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       double bf[NB];
@@ -151,8 +187,10 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
         for (int mb = 0; mb < MB; ++mb)
           acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb][s], bf[nb], acc[mb][nb], 0, 0, 0);
       if (s % SPR == SPR - 1) {
+        const int r = s / SPR;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) bg[s / SPR][c] = prod_entry<LIVE>(d, jb + s / SPR, N, cc[c], &mind);
+        for (int c = 0; c < NC; ++c)
+          bg[r][c] = PRE ? prod_live_entry(zc[r], gc[r], cc[c], &mind) : prod_entry<LIVE>(d, jb + r, N, cc[c], &mind);
       }
     }
     if (LIVE && __any(mind < 0x1p-1000)) fix_tiny(jb);
@@ -172,17 +210,36 @@ __device__ __forceinline__ void gemm_f64_body(const GemmJob& J, int m0, int n0, 
     if (LIVE && __any(mind < 0x1p-1000)) fix_tiny(h * kBK + RPW * wave);
     store_b(bufof(h));
   }
+  double zA[RPW], gA[RPW], zB[RPW], gB[RPW];
+  if (PRE) load_desc(0, zA, gA);
   loadA(0, aA);
   __syncthreads();
   int kc = 0;
-  for (; kc + 2 <= nk; kc += 2) {
-    loadA((kc + 1) * kBK, aB);
-    step(aA, kc);
-    const int k2 = (kc + 2 < nk) ? (kc + 2) * kBK : (kc + 1) * kBK;
-    loadA(k2, aA);
-    step(aB, kc + 1);
+  if constexpr (W == 8) {
+    if (J.vec_a) {
+      // pairs of half-steps whose X loads (half-steps kc + 1, kc + 2) are full 16-k steps
+      const int nv = N / kBK;
+      for (; kc + 3 <= nv; kc += 2) {
+        step(std::true_type{}, aA, kc, aB, (kc + 1) * kBK, zA, gA, zB, gB);
+        step(std::true_type{}, aB, kc + 1, aA, (kc + 2) * kBK, zB, gB, zA, gA);
+      }
+    }
+    for (; kc + 2 <= nk; kc += 2) {
+      step(std::false_type{}, aA, kc, aB, (kc + 1) * kBK, zA, gA, zB, gB);
+      const int k2 = (kc + 2 < nk) ? (kc + 2) * kBK : (kc + 1) * kBK;
+      step(std::false_type{}, aB, kc + 1, aA, k2, zB, gB, zA, gA);
+    }
+  } else {
+    // 4-wave tiles: X of the next half-step is loaded ahead of each step
+    for (; kc + 2 <= nk; kc += 2) {
+      loadA((kc + 1) * kBK, aB);
+      step(std::false_type{}, aA, kc, aB, -1, zA, gA, zB, gB);
+      const int k2 = (kc + 2 < nk) ? (kc + 2) * kBK : (kc + 1) * kBK;
+      loadA(k2, aA);
+      step(std::false_type{}, aB, kc + 1, aA, -1, zB, gB, zA, gA);
+    }
   }
-  if (kc < nk) step(aA, kc);
+  if (kc < nk) step(std::false_type{}, aA, kc, aB, -1, zA, gA, zB, gB);
 
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
