@@ -742,7 +742,7 @@ def main():
         # GEMM roofline below only describes the direct path
         "roofline": None if not plain else {
             "bound": "mfma",
-            "kernel": "gemm_cauchy_f64_kernel<2, 2, 2, 8> (256x128 tiles on 8 waves, 32-k LDS stages)",
+            "kernel": "gemm_cauchy_f64_kernel<2, 2, 4, 8> (256x128 tiles on 8 waves, 64-k LDS stages)",
             "achieved": achieved,
             "peak": FP64_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",

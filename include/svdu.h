@@ -69,8 +69,8 @@ extern "C" {
 #define SVDU_OPT_TIMING 2        /* 1: record phase timings of svdu_rank1_update (resets the record) */
 #define SVDU_OPT_TILE_SHAPE 3    /* -1 (default): tile shape of the products from the tuning table;
                                     0..5 force SVDU_TILE_* (results are bitwise the same for every shape;
-                                    the precision form runs SVDU_TILE_128x128_K32 and
-                                    SVDU_TILE_256x128_K32 as 128 x 128) */
+                                    the split-FP32 precision form runs SVDU_TILE_128x128_K32 and
+                                    SVDU_TILE_256x128_K64 as 128 x 128) */
 #define SVDU_OPT_PERSISTENT 4    /* 1: products of svdu_rank1_update and svdu_rank1_update_batched use the
                                     persistent schedule (see SVDU_BATCH_PERSISTENT); default 0 */
 #define SVDU_OPT_SLICES 6        /* slices S of SVDU_PREC_SLICED_INT8: 6, 7 (default) or 8 */
@@ -97,7 +97,7 @@ extern "C" {
 #define SVDU_TILE_128x64 2
 #define SVDU_TILE_64x64 3
 #define SVDU_TILE_128x128_K32 4  /* 128 x 128, C~ staged 32 k rows at a time (one barrier per 32 k) */
-#define SVDU_TILE_256x128_K32 5  /* 256 x 128 on 8 waves, 32-k stages: each generated C~ entry serves 256 rows */
+#define SVDU_TILE_256x128_K64 5  /* 256 x 128 on 8 waves, 64-k stages: each generated C~ entry serves 256 rows */
 #define SVDU_TILE_SHAPES 6
 #define SVDU_TILE_BUCKETS 8      /* tuning-table buckets by order N: (0,64], (64,128], ..., (4096, inf) */
 

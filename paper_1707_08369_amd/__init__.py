@@ -41,7 +41,7 @@ SVDU_TILE_64x128 = 1
 SVDU_TILE_128x64 = 2
 SVDU_TILE_64x64 = 3
 SVDU_TILE_128x128_K32 = 4
-SVDU_TILE_256x128_K32 = 5
+SVDU_TILE_256x128_K64 = 5
 SVDU_TILE_SHAPES = 6
 SVDU_TILE_BUCKETS = 8
 SVDU_BATCH_PERSISTENT = 1

@@ -90,17 +90,17 @@ __device__ __forceinline__ double gen_entry(const CauchyDesc& d, int j, int N, c
 // Tile shapes of the product kernels: W waves stacked along M, each wave
 // 16 MB rows (MB = 1 or 2 MFMA blocks of 16) by 64 NC columns (NC = 1 or 2).
 // kT128x128k32: 128 x 128 with LDS tiles of 32 k rows, one barrier per 32 k.
-// kT256x128k32: 8 waves of 32 x 128 (256 x 128), 32-k LDS tiles; every
-// generated C~ entry serves 256 rows of X.
+// kT256x128k64: 8 waves of 32 x 128 (256 x 128), LDS tiles of 64 k rows
+// (one barrier per 64 k); every generated C~ entry serves 256 rows of X.
 enum TileShape : int {
-  kT128x128 = 0, kT64x128 = 1, kT128x64 = 2, kT64x64 = 3, kT128x128k32 = 4, kT256x128k32 = 5, kNumShapes = 6
+  kT128x128 = 0, kT64x128 = 1, kT128x64 = 2, kT64x64 = 3, kT128x128k32 = 4, kT256x128k64 = 5, kNumShapes = 6
 };
 __host__ __device__ constexpr int shape_bm(int s) {
-  return (s == kT64x128 || s == kT64x64) ? 64 : (s == kT256x128k32 ? 256 : 128);
+  return (s == kT64x128 || s == kT64x64) ? 64 : (s == kT256x128k64 ? 256 : 128);
 }
 __host__ __device__ constexpr int shape_bn(int s) { return (s == kT128x64 || s == kT64x64) ? 64 : 128; }
 // The shape a product actually runs with. The split-FP32 kernel has no
-// 32-k or 8-wave variant and runs those shapes as 128 x 128.
+// staged or 8-wave variant and runs those shapes as 128 x 128.
 __host__ __device__ constexpr int run_shape(int s, bool split32) {
   return (split32 && s >= kT128x128k32) ? kT128x128 : s;
 }

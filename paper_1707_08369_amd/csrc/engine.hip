@@ -689,7 +689,7 @@ void enqueue_status_gather(const Plan& P, int* out, hipStream_t st) {
 // ---------------------------------------------------------------------------
 void default_shape_table(int (&t)[kNumPrec][kShapeBuckets]) {
   static const int def[kNumPrec][kShapeBuckets] = {
-      {kT64x64, kT128x128, kT128x64, kT128x64, kT128x128, kT256x128k32, kT256x128k32, kT256x128k32},
+      {kT64x64, kT128x128, kT128x64, kT128x64, kT128x128, kT256x128k64, kT256x128k64, kT256x128k64},
       {kT64x64, kT64x64, kT64x64, kT64x64, kT64x64, kT64x128, kT128x128, kT128x128}};
   memcpy(t, def, sizeof(def));
 }

@@ -371,7 +371,7 @@ void launch_gemm_f64(const GemmList& L, int shape, bool persistent, int grid_cap
     case kT128x64: launch_shape<2, 1, 1, 4>(L, persistent, grid_cap, st); break;
     case kT64x64: launch_shape<1, 1, 1, 4>(L, persistent, grid_cap, st); break;
     case kT128x128k32: launch_shape<2, 2, 2, 4>(L, persistent, grid_cap, st); break;
-    case kT256x128k32: launch_shape<2, 2, 2, 8>(L, persistent, grid_cap, st); break;
+    case kT256x128k64: launch_shape<2, 2, 4, 8>(L, persistent, grid_cap, st); break;
     default: launch_shape<2, 2, 1, 4>(L, persistent, grid_cap, st); break;
   }
 }
@@ -397,7 +397,7 @@ int gemm_f64_grid_cap(int shape) {
     case kT128x64: return resident_blocks_gemm_f64_grid_cap<2, 1, 1, 4>();
     case kT64x64: return resident_blocks_gemm_f64_grid_cap<1, 1, 1, 4>();
     case kT128x128k32: return resident_blocks_gemm_f64_grid_cap<2, 2, 2, 4>();
-    case kT256x128k32: return resident_blocks_gemm_f64_grid_cap<2, 2, 2, 8>();
+    case kT256x128k64: return resident_blocks_gemm_f64_grid_cap<2, 2, 4, 8>();
     default: return resident_blocks_gemm_f64_grid_cap<2, 2, 1, 4>();
   }
 }
