@@ -15,6 +15,8 @@
 //    which keeps C~ orthogonal to working precision.
 #include <math.h>
 
+#include <type_traits>
+
 #include "device_util.h"
 #include "jobs.h"
 #include "svdu_internal.h"
@@ -832,33 +834,50 @@ __device__ void sf_setup(const Stage& s, int K, int a, int b, SfLeaf* lf, double
   const int q = t & (kSfP - 1), r = t >> 5;
   const double tq = cospi((double)(2 * q + 1) / (2.0 * kSfP));
   const double xo = 0.5 * w * (1.0 + tq);
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int nl = 0, nr = 0;
-  for (int c0 = 0; c0 < K; c0 += kSfChunk) {
-    const int n = min(kSfChunk, K - c0);
-    __syncthreads();   // the previous chunk is consumed
-    for (int j = t; j < n; j += kSfThreads) {
-      sp[j] = pole(c0 + j);
-      sw[j] = wt(c0 + j);
-    }
-    __syncthreads();
+  double s0, s1, s2, s3;
+  int nl, nr;
+  // One pass over the poles. The fast pass takes every reciprocal from
+  // recip_fast, with no branch per pole; if any |D| of the block is below its
+  // range (a far pole is at least |T| away, so only for |T| near 2^-1000) the
+  // block repeats the pass with true divisions for those.
+  auto pass = [&](auto EXACT) {
+    s0 = s1 = s2 = s3 = 0.0;
+    nl = nr = 0;
+    bool tiny = false;
+    for (int c0 = 0; c0 < K; c0 += kSfChunk) {
+      const int n = min(kSfChunk, K - c0);
+      __syncthreads();   // the previous chunk is consumed
+      for (int j = t; j < n; j += kSfThreads) {
+        sp[j] = pole(c0 + j);
+        sw[j] = wt(c0 + j);
+      }
+      __syncthreads();
 #pragma unroll 4
-    for (int j = r; j < n; j += 32) {
-      const double off = sp[j] - lo;
-      const bool fl = off <= -w, fr = off >= 2.0 * w;
-      const bool far = fl || fr;
-      const double D = far ? off - xo : 1.0;   // far: |D| >= |T|
-      const double rd = far ? (recip_tiny(D) ? 1.0 / D : recip_fast(D)) : 0.0;
-      const double v = sw[j] * rd;
-      const double dv = v * rd;
-      s0 += fl ? v : 0.0;
-      s1 += fl ? dv : 0.0;
-      s2 += fr ? v : 0.0;
-      s3 += fr ? dv : 0.0;
-      nl += fl ? 1 : 0;
-      nr += fr ? 1 : 0;
+      for (int j = r; j < n; j += 32) {
+        const double off = sp[j] - lo;
+        const bool fl = off <= -w, fr = off >= 2.0 * w;
+        const bool far = fl || fr;
+        const double D = far ? off - xo : 1.0;   // far: |D| >= |T|
+        double rd;
+        if constexpr (decltype(EXACT)::value) {
+          rd = far ? (recip_tiny(D) ? 1.0 / D : recip_fast(D)) : 0.0;
+        } else {
+          tiny |= recip_tiny(D);
+          rd = far ? recip_fast(D) : 0.0;
+        }
+        const double v = sw[j] * rd;
+        const double dv = v * rd;
+        s0 += fl ? v : 0.0;
+        s1 += fl ? dv : 0.0;
+        s2 += fr ? v : 0.0;
+        s3 += fr ? dv : 0.0;
+        nl += fl ? 1 : 0;
+        nr += fr ? 1 : 0;
+      }
     }
-  }
+    return tiny;
+  };
+  if (__syncthreads_or(pass(std::false_type{}))) pass(std::true_type{});
   red[(0 * 32 + r) * 33 + q] = s0;
   red[(1 * 32 + r) * 33 + q] = s1;
   red[(2 * 32 + r) * 33 + q] = s2;
