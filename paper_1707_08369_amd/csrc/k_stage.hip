@@ -961,6 +961,19 @@ __global__ __launch_bounds__(kSfThreads) void secular_ff_kernel(StageLevel L, in
   if (r0 >= r1) return;
   sf_setup(s, K, r0, r1, &lf, lds, lds + kSfRed, lds + kSfRed + kSfChunk, cnt);
   const int i = k0 + (threadIdx.x >> 4);   // root of the reflected problem
+  if (s.N <= kSecLdsN) {
+    // the setup's LDS is free again (sf_setup ends with a barrier): the
+    // iterates read every pole and weight from an LDS copy, as the direct sums do
+    for (int e = threadIdx.x; e < K; e += blockDim.x) {
+      lds[e] = gld(s.g + e);
+      lds[kSecLdsN + e] = gld(s.W2 + e);
+    }
+    __syncthreads();
+    if (i < r0 || i >= r1) return;
+    secular_body<16, true, true>(s.counts, lds, lds + kSecLdsN, s.rho, s.org, s.tau, s.iters, s.status, maxit,
+                                 refl ? K - 1 - i : i, &lf);
+    return;
+  }
   if (i < r0 || i >= r1) return;
   secular_body<16, false, true>(s.counts, s.g, s.W2, s.rho, s.org, s.tau, s.iters, s.status, maxit,
                                 refl ? K - 1 - i : i, &lf);
