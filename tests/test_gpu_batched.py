@@ -152,11 +152,12 @@ def test_batched_per_problem_status(lib):
 
 
 @pytest.mark.parametrize("shape", [0, 1, 2, 3, 4, 5])
-@pytest.mark.parametrize("m,n", [(300, 457), (301, 333)])
+@pytest.mark.parametrize("m,n", [(300, 457), (301, 333), (20, 37)])
 def test_tile_shapes_give_identical_results(lib, shape, m, n):
     """Every tile shape gives the same bits. 300 x 457: 16-byte rows of X and
     ragged last k steps (full vector steps, then element steps); 301 x 333: odd
-    leading dimensions, so X is read element by element throughout."""
+    leading dimensions, so X is read element by element throughout; 20 x 37:
+    fewer k steps than one LDS stage holds."""
     P = S.make_problem(m, n, "uniform", seed=7)
     args = (dev(P.U), dev(P.sigma), dev(P.V), dev(P.a), dev(P.b))
     old = lib.set_option(lib.SVDU_OPT_TILE_SHAPE, 0)
